@@ -1,0 +1,220 @@
+"""Benchmark: sliding-window group-by over Zipf-skewed streams on one MI355X.
+
+Workload (one "step" = one batch through the whole per-batch path: histogram,
+plan, scatter, per-group update, emit): 10,000 groups, window W=1000,
+batches of 1,048,576 int32 (key, value) tuples, keys Zipf(s) over
+[0, 10000) with hot ranks randomly permuted, values uniform in [0, 1e6).
+All batches are generated on the device and resident in HBM before timing.
+
+Reported: tuples/s and algorithmic HBM GB/s for s in {0, 0.5, 1, 1.5, 2},
+balanced vs static partition, p50/p99 batch latency.  The headline value
+is s=1.5, balanced.  The roofline object is for the longest-running kernel
+of the headline run (HIP events around its launches); the cpu_baseline is
+the CPU oracle timed on a bounded sample of the same headline batches.
+
+Algorithmic bytes per batch (what the method must move): every key and value
+read once (8 B per tuple), and per touched group the surviving tuples
+written to its ring (4 B each), the evicted values read (4 B each, only
+while a group's batch is shorter than its window), its state read and
+written (32 B) and its result emitted (24 B).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SWEEP = (0.0, 0.5, 1.0, 1.5, 2.0)
+HEADLINE_S = 1.5
+METRIC = "tuples/sec and HBM GB/s at Zipf s=0..2, balanced vs static; p99 batch latency"
+
+
+def algorithmic_bytes(torch, keys_list, groups, window, n):
+    """Exact algorithmic bytes of each batch (list), from the batch's key
+    histogram and the window fill before it."""
+    dev = keys_list[0].device
+    cnt = torch.zeros(groups, dtype=torch.int64, device=dev)
+    out = []
+    for keys in keys_list:
+        k = torch.bincount(keys.to(torch.int64), minlength=groups)
+        touched = k > 0
+        m = torch.minimum(k, torch.tensor(window, device=dev))
+        e = torch.where(k < window, torch.clamp(cnt + k - window, min=0), torch.zeros_like(k))
+        per_group = (4 * m + 4 * e + 32 + 24) * touched
+        out.append(8 * n + int(per_group.sum().item()))
+        cnt = torch.minimum(cnt + k, torch.tensor(window, device=dev))
+    return out
+
+
+def run_mode(torch, cq, batches, cfg, mode, warmup, steps, kernel_times=False):
+    """Warm up, then time `steps` batches (push + emit) with no host syncs in
+    between.  Returns a dict of measurements."""
+    dev = batches[0][0].device
+    q = cq.Query(cfg.groups, cfg.window, partition=mode, reserve=cfg.batch)
+    cap = min(cfg.groups, cfg.batch)
+    ids = torch.empty(cap, dtype=torch.int32, device=dev)
+    sums = torch.empty(cap, dtype=torch.int64, device=dev)
+    counts = torch.empty(cap, dtype=torch.int32, device=dev)
+    avgs = torch.empty(cap, dtype=torch.float64, device=dev)
+    nt = torch.empty(1, dtype=torch.int64, device=dev)
+    for b in range(warmup):
+        k, v = batches[b]
+        q.push(k, v)
+        q.results_into(ids, sums, counts, avgs, nt)
+    torch.cuda.synchronize()
+    if kernel_times:
+        q.set_telemetry(cq.TELEMETRY_KERNEL_TIMES)
+        q.kernel_times()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        k, v = batches[warmup + i]
+        starts[i].record()
+        q.push(k, v)
+        q.results_into(ids, sums, counts, avgs, nt)
+        ends[i].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    res = {"wall_s": wall, "lat_ms": lat}
+    if kernel_times:
+        res["kernels"] = q.kernel_times()
+        q.set_telemetry(0)
+    res["plan"] = q.batch_plan()
+    q.close()
+    return res
+
+
+def cpu_baseline(batches_host, cfg, budget_s):
+    """The CPU oracle (one thread) over the first batches of the headline
+    stream until about `budget_s` seconds of work."""
+    from oracle import RingOracle
+    ora = RingOracle(cfg.groups, cfg.window)
+    done, t = 0, 0.0
+    for k, v in batches_host:
+        t0 = time.perf_counter()
+        ora.push(k, v)
+        t += time.perf_counter() - t0
+        done += 1
+        if t >= budget_s:
+            break
+    ora.close()
+    return done, t
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of CPU-oracle work for the cpu_baseline sample")
+    ap.add_argument("--sweep", default=",".join(str(s) for s in SWEEP))
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not "
+              "supported (the path would shard groups by owner across GPUs, see the "
+              "design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1309_0634_amd as cq
+    from workloads import DeviceStream, skew
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    sweep = [float(x) for x in args.sweep.split(",")]
+    rows = []
+    headline = None
+    for s in sweep:
+        cfg = skew(s, batches=args.warmup + args.steps)
+        ds = DeviceStream(cfg, dev)
+        batches = [ds.batch(b) for b in range(args.warmup + args.steps)]
+        torch.cuda.synchronize()
+        bytes_per = algorithmic_bytes(torch, [k for k, _ in batches], cfg.groups, cfg.window,
+                                      cfg.batch)
+        timed_bytes = sum(bytes_per[args.warmup:])
+        for mode, name in ((cq.PARTITION_BALANCED, "balanced"), (cq.PARTITION_STATIC, "static")):
+            is_head = (s == HEADLINE_S and mode == cq.PARTITION_BALANCED)
+            r = run_mode(torch, cq, batches, cfg, mode, args.warmup, args.steps,
+                         kernel_times=is_head)
+            tuples = args.steps * cfg.batch
+            row = {
+                "s": s, "partition": name,
+                "tuples_per_s": tuples / r["wall_s"],
+                "alg_GBps": timed_bytes / r["wall_s"] / 1e9,
+                "ms_per_batch": 1e3 * r["wall_s"] / args.steps,
+                "p50_batch_ms": float(np.percentile(r["lat_ms"], 50)),
+                "p99_batch_ms": float(np.percentile(r["lat_ms"], 99)),
+                "alg_MB_per_batch": timed_bytes / args.steps / 1e6,
+                "heavy_groups": int(r["plan"]["heavy_groups"]),
+                "touched": int(r["plan"]["touched"]),
+            }
+            rows.append(row)
+            print(json.dumps({"progress": row}), file=sys.stderr, flush=True)
+            if is_head:
+                headline = (row, r, timed_bytes, cfg, batches)
+        if not (s == HEADLINE_S):
+            del batches
+            torch.cuda.empty_cache()
+
+    if headline is None:
+        print("bench.py: the sweep must include s=1.5", file=sys.stderr)
+        sys.exit(2)
+    row, r, timed_bytes, cfg, batches = headline
+    kern = r["kernels"]
+    dom = max(kern, key=lambda k: kern[k][0])
+    dom_ms, dom_launches = kern[dom]
+    avg_bytes = timed_bytes / args.steps
+    achieved = avg_bytes / (dom_ms / dom_launches * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": dom, "kernel_avg_us": round(1e3 * dom_ms / dom_launches, 2),
+                "kernel_times_ms": {k: round(v[0], 3) for k, v in kern.items()}}
+    cpu = None
+    if not args.no_cpu:
+        host = ((k.cpu().numpy(), v.cpu().numpy()) for k, v in batches)
+        done, t = cpu_baseline(host, cfg, args.cpu_budget)
+        cpu = {"value": done * cfg.batch / t, "unit": "tuples/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {done} batches of the s=1.5 stream (1,048,576 tuples each), "
+                         f"C oracle, one thread, {t:.1f} s",
+               "host_cpus": os.cpu_count()}
+    out = {
+        "metric": METRIC,
+        "value": row["tuples_per_s"],
+        "unit": "tuples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": row["ms_per_batch"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "zipf_skew_g10000_w1000_n1048576_s1.5_balanced",
+                   "groups": cfg.groups, "window": cfg.window, "batch": cfg.batch,
+                   "zipf_s": HEADLINE_S, "partition": "balanced", "parallelism": "1gpu"},
+        "alg_GBps": row["alg_GBps"],
+        "p50_batch_ms": row["p50_batch_ms"],
+        "p99_batch_ms": row["p99_batch_ms"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "sweep": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

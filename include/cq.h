@@ -1,0 +1,214 @@
+/*
+ * cq.h -- continuous sliding-window group-by aggregation on MI355X (gfx950).
+ *
+ * One query maintains, for every group id g in [0, groups), a count window
+ * holding the last `window` integer values seen for g, and its SUM, COUNT
+ * and AVG.  Tuples arrive in batches of (key, value) int32 pairs.  This is
+ * the continuous aggregate query of Koutsoumpakis, Koutsoumpakis and
+ * Gounaris, "Skew Handling in Aggregate Streaming Queries on GPUs" (ADMS
+ * 2013): tuples are (group identifier id, integer attr) pairs and the
+ * aggregate of a group depends on the last values received for it under a
+ * fixed-size window (Section 3, problem statement); the stream is processed
+ * in iterations of fixed-size batches (Section 3.1); a full window discards
+ * its oldest value (Section 3.2).  Groups are spread over GPU workers by a
+ * load balancer decided on the device from the batch's own key histogram
+ * (the paper decides on the CPU and applies it one iteration late,
+ * Section 3.1 and Section 4).
+ *
+ * Conventions for every call:
+ *   - plain C types only; device pointers are HIP device (or managed)
+ *     addresses; `stream` is a hipStream_t passed as void* (NULL = the
+ *     default stream);
+ *   - calls on one query are stream-ordered and must be issued on one
+ *     stream (or ordered by the caller); a query is not thread-safe;
+ *     distinct queries are independent;
+ *   - no call throws; every call returns a CQ_* status code.
+ *
+ * Semantics taken where the paper is silent:
+ *   - within a batch, arrival order is array order;
+ *   - results are produced once per batch, for every group the batch
+ *     touched, in ascending group id, with the value after that group's last
+ *     tuple in the batch;
+ *   - a window that is not yet full aggregates the values present:
+ *     COUNT = min(window, tuples seen), AVG = (double)SUM / (double)COUNT,
+ *     one IEEE-754 binary64 round-to-nearest division of exact integers;
+ *   - SUM is exact in int64 (|SUM| <= window * 2^31 < 2^53).
+ */
+#ifndef CQ_H
+#define CQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Aggregate selection bits for cq_create.  All three are always maintained;
+ * the mask records what the caller asked for. */
+#define CQ_SUM   1u
+#define CQ_COUNT 2u
+#define CQ_AVG   4u
+
+/* Status codes. */
+#define CQ_OK             0
+#define CQ_ERR_INVALID   -1   /* bad argument; nothing was enqueued       */
+#define CQ_ERR_OOM       -2   /* device memory short; nothing leaked      */
+#define CQ_ERR_KEY_RANGE -3   /* the batch held a key outside [0, groups) */
+#define CQ_ERR_HIP       -4   /* a HIP runtime call failed                */
+
+/* Work assignment of the per-group phase (see cq_set_partition). */
+#define CQ_PARTITION_BALANCED 0
+#define CQ_PARTITION_STATIC   1
+
+/* Largest batch accepted by cq_push_batch. */
+#define CQ_MAX_BATCH (1ll << 30)
+/* Largest window accepted by cq_create (keeps (double)SUM exact). */
+#define CQ_MAX_WINDOW ((1 << 22) - 1)
+
+typedef struct cq_query cq_query;
+
+/*
+ * cq_create -- a new query with `groups` group ids and a window of `window`
+ * tuples per group (Section 3: group identifier, integer attribute, fixed
+ * size window; Section 3.2: one window per group in device memory).
+ *   groups     : 1 .. 2^31-1; keys must lie in [0, groups).
+ *   window     : 1 .. CQ_MAX_WINDOW.
+ *   aggregates : non-empty subset of CQ_SUM | CQ_COUNT | CQ_AVG.
+ *   out        : receives the handle.
+ * Allocates the window store (groups * window * 4 bytes) and the per-group
+ * state on the current HIP device, zero-filled; the library owns them until
+ * cq_destroy.  Returns CQ_OK, CQ_ERR_INVALID, CQ_ERR_OOM (nothing leaked,
+ * *out = NULL) or CQ_ERR_HIP.
+ */
+int cq_create(int64_t groups, int32_t window, uint32_t aggregates, cq_query **out);
+
+/*
+ * cq_reserve -- size the per-batch scratch for batches of up to `max_batch`
+ * tuples now, so that no later cq_push_batch allocates (cq_push_batch grows
+ * the scratch on demand otherwise, synchronizing the query's last stream
+ * first).  Returns CQ_OK, CQ_ERR_INVALID or CQ_ERR_OOM.
+ */
+int cq_reserve(cq_query *q, int64_t max_batch);
+
+/*
+ * cq_set_partition -- how groups are assigned to GPU workers in the
+ * per-group phase (Section 4 load balancing; Section 5.1 initial
+ * assignment).
+ *   CQ_PARTITION_BALANCED (default): every batch, light groups are packed
+ *     into workgroups by tuple count and every heavy group gets its own
+ *     workgroup, decided on the device from the batch's histogram;
+ *   CQ_PARTITION_STATIC: `workers` workgroups (0 = 1024), worker w owns the
+ *     equal, consecutive group range [w*groups/workers, (w+1)*groups/workers)
+ *     -- the paper's initial assignment with balancing turned off.
+ * Results are identical in every mode.  Takes effect at the next push.
+ * Returns CQ_OK or CQ_ERR_INVALID.
+ */
+int cq_set_partition(cq_query *q, int32_t mode, int32_t workers);
+
+/*
+ * cq_push_batch -- apply one batch of n tuples (Section 3.1: one iteration
+ * over a batch; Section 3.2: each tuple enters its group's window, a full
+ * window discarding its oldest value).
+ *   keys, values : caller-owned device arrays of n int32 each (SoA); they
+ *                  must stay valid and unchanged until the enqueued work has
+ *                  completed; the library keeps no reference after that.
+ *   n            : 0 .. CQ_MAX_BATCH; n = 0 is a valid batch touching nothing.
+ *   stream       : hipStream_t (void*), NULL = default stream.
+ * Enqueues the whole update on `stream` and returns without waiting for the
+ * device (unless the scratch must grow, see cq_reserve).  Host-side errors
+ * (q NULL, n out of range, NULL arrays with n > 0) return CQ_ERR_INVALID and
+ * enqueue nothing.  A key outside [0, groups) is found on the device: the
+ * whole batch is rejected, the windows are left unchanged, and the next
+ * cq_results reports it.
+ */
+int cq_push_batch(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n,
+                  void *stream);
+
+/*
+ * cq_results -- write the results of the most recently pushed batch, one
+ * entry per group the batch touched, in ascending group id.
+ *   ids       : device int32[cap]  group id          (may be NULL)
+ *   sums      : device int64[cap]  SUM of the window (may be NULL)
+ *   counts    : device int32[cap]  COUNT             (may be NULL)
+ *   avgs      : device double[cap] AVG               (may be NULL)
+ *   n_touched : device int64[1]    number of entries written (required)
+ * with cap >= min(groups, n of that batch).  Stream-ordered after the push;
+ * returns CQ_OK without waiting for the device.  If that batch was rejected
+ * for a bad key, *n_touched receives CQ_ERR_KEY_RANGE (negative) and the
+ * arrays are not written.  Before any push, *n_touched = 0.  The next push
+ * replaces what this call reads.
+ */
+int cq_results(cq_query *q, int32_t *ids, int64_t *sums, int32_t *counts, double *avgs,
+               int64_t *n_touched, void *stream);
+
+/*
+ * cq_status -- wait for the query's last stream and return the status of the
+ * most recent batch: CQ_OK or CQ_ERR_KEY_RANGE (or CQ_ERR_HIP).
+ */
+int cq_status(cq_query *q);
+
+/*
+ * cq_destroy -- wait for the query's last stream, then free everything.
+ * NULL is a no-op returning CQ_OK.
+ */
+int cq_destroy(cq_query *q);
+
+/* Static description of a status code. */
+const char *cq_strerror(int code);
+
+/* ---------------- measurement (not needed for results) ---------------- */
+
+/* Telemetry flags for cq_set_telemetry. */
+#define CQ_TELEMETRY_KERNEL_TIMES 1 /* HIP events around every kernel launch */
+#define CQ_TELEMETRY_WORKERS      2 /* per-workgroup (hardware id, start, end,
+                                       tuples) records of the per-group phase */
+
+/* Kernel kinds reported by cq_kernel_times, in this order. */
+#define CQ_KERNEL_HIST    0
+#define CQ_KERNEL_PLAN    1
+#define CQ_KERNEL_SCATTER 2
+#define CQ_KERNEL_UPDATE  3
+#define CQ_KERNEL_EMIT    4
+#define CQ_KERNEL_KINDS   5
+
+/*
+ * cq_set_telemetry -- turn measurement on (flags) or off (0).  Imbalance
+ * is what the paper's balancing corrects (Section 1; Section 3.1 detects it
+ * from tuples per thread); these records make it measurable on the device.
+ * Returns CQ_OK, CQ_ERR_INVALID or CQ_ERR_OOM.
+ */
+int cq_set_telemetry(cq_query *q, int32_t flags);
+
+/*
+ * cq_kernel_times -- wait for the query's last stream; for every kernel
+ * kind k < nkinds, write the summed duration in milliseconds of its launches
+ * since the previous call to ms[k] and their number to launches[k]
+ * (host arrays); then start counting afresh.  Needs
+ * CQ_TELEMETRY_KERNEL_TIMES.  Returns CQ_OK, CQ_ERR_INVALID or CQ_ERR_HIP.
+ */
+int cq_kernel_times(cq_query *q, double *ms, int64_t *launches, int32_t nkinds);
+
+/*
+ * cq_worker_trace -- wait for the query's last stream and copy the
+ * per-workgroup records of the most recent batch's per-group phase into the
+ * host array `rec` (cap records of 6 int64: raw HW_ID register, XCC id,
+ * start tick, end tick, tuples handled, items handled; ticks of the
+ * constant 100 MHz device clock).  *count receives the number of records
+ * available.  Needs CQ_TELEMETRY_WORKERS.
+ */
+int cq_worker_trace(cq_query *q, int64_t *rec, int64_t cap, int64_t *count);
+
+/*
+ * cq_batch_plan -- wait for the query's last stream and copy the most
+ * recent batch's partition summary into the host array `out` (9 int64):
+ * light buckets, heavy groups, light tuples, heavy tuples, touched groups,
+ * heavy run descriptors, status, arrival tiles, and the library's sticky
+ * internal-consistency bits (0 unless a kernel found a plan breaking its own
+ * size bounds and skipped work rather than overrun a buffer).
+ */
+int cq_batch_plan(cq_query *q, int64_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

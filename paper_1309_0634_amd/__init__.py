@@ -1,0 +1,200 @@
+"""Python binding of libcq (include/cq.h): sliding-window group-by on MI355X.
+
+Argument marshalling only.  Every step of the update runs in the HIP
+kernels of ``libcq.so``; torch tensors are used for device memory and the
+stream handle.  The binding fails loudly when the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIBRARY = os.path.join(PKG, "libcq.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "cq.h")
+
+SUM, COUNT, AVG = 1, 2, 4
+OK, ERR_INVALID, ERR_OOM, ERR_KEY_RANGE, ERR_HIP = 0, -1, -2, -3, -4
+PARTITION_BALANCED, PARTITION_STATIC = 0, 1
+TELEMETRY_KERNEL_TIMES, TELEMETRY_WORKERS = 1, 2
+KERNEL_KINDS = ("hist", "plan", "scatter", "update", "emit")
+MAX_BATCH = 1 << 30
+MAX_WINDOW = (1 << 22) - 1
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+class CQError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        msg = strerror(code) if _lib is not None else f"status {code}"
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+        self.code = code
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libcq.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBRARY):
+            raise ImportError(f"{LIBRARY} is missing: build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIBRARY)
+        P, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+        pi64 = ctypes.POINTER(ctypes.c_int64)
+        pdbl = ctypes.POINTER(ctypes.c_double)
+        sig = {
+            "cq_create": ([i64, i32, u32, ctypes.POINTER(P)], ctypes.c_int),
+            "cq_reserve": ([P, i64], ctypes.c_int),
+            "cq_set_partition": ([P, i32, i32], ctypes.c_int),
+            "cq_push_batch": ([P, P, P, i64, P], ctypes.c_int),
+            "cq_results": ([P, P, P, P, P, P, P], ctypes.c_int),
+            "cq_status": ([P], ctypes.c_int),
+            "cq_destroy": ([P], ctypes.c_int),
+            "cq_strerror": ([ctypes.c_int], ctypes.c_char_p),
+            "cq_set_telemetry": ([P, i32], ctypes.c_int),
+            "cq_kernel_times": ([P, pdbl, pi64, i32], ctypes.c_int),
+            "cq_worker_trace": ([P, pi64, i64, pi64], ctypes.c_int),
+            "cq_batch_plan": ([P, pi64], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().cq_strerror(code).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise CQError(rc, what)
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _dptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Query:
+    """One continuous query: ``groups`` group ids, a ``window``-tuple window
+    per group (cq_create)."""
+
+    def __init__(self, groups: int, window: int, aggregates: int = SUM | COUNT | AVG,
+                 partition: int = PARTITION_BALANCED, workers: int = 0,
+                 reserve: int = 0):
+        L = lib()
+        h = ctypes.c_void_p()
+        _check(L.cq_create(int(groups), int(window), int(aggregates), ctypes.byref(h)),
+               "cq_create")
+        self._h = h
+        self.groups = int(groups)
+        self.window = int(window)
+        self.last_n = 0
+        if partition != PARTITION_BALANCED or workers:
+            self.set_partition(partition, workers)
+        if reserve:
+            _check(L.cq_reserve(self._h, int(reserve)), "cq_reserve")
+
+    # -- lifecycle ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            rc = lib().cq_destroy(self._h)
+            self._h = None
+            _check(rc, "cq_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- configuration -----------------------------------------------------
+    def set_partition(self, mode: int, workers: int = 0):
+        _check(lib().cq_set_partition(self._h, int(mode), int(workers)), "cq_set_partition")
+
+    def reserve(self, max_batch: int):
+        _check(lib().cq_reserve(self._h, int(max_batch)), "cq_reserve")
+
+    def set_telemetry(self, flags: int):
+        _check(lib().cq_set_telemetry(self._h, int(flags)), "cq_set_telemetry")
+
+    # -- the hot path ------------------------------------------------------
+    def push(self, keys, values, stream=None):
+        """Enqueue one batch: ``keys``/``values`` are int32 device tensors."""
+        n = keys.numel()
+        if values.numel() != n:
+            raise ValueError("keys and values differ in length")
+        if n and (keys.dtype != values.dtype or not keys.is_cuda or not values.is_cuda
+                  or not keys.is_contiguous() or not values.is_contiguous()):
+            raise ValueError("keys and values must be contiguous int32 device tensors")
+        _check(lib().cq_push_batch(self._h, _dptr(keys) if n else None,
+                                   _dptr(values) if n else None, int(n),
+                                   _stream_handle(stream)), "cq_push_batch")
+        self.last_n = int(n)
+
+    def results_into(self, ids, sums, counts, avgs, n_touched, stream=None):
+        """Enqueue the emission of the last batch's results into caller
+        device tensors (any of ids/sums/counts/avgs may be None)."""
+        _check(lib().cq_results(self._h, _dptr(ids), _dptr(sums), _dptr(counts), _dptr(avgs),
+                                _dptr(n_touched), _stream_handle(stream)), "cq_results")
+
+    def results(self, stream=None):
+        """Host-synchronising convenience: (ids, sums, counts, avgs) as CPU
+        tensors; raises CQError(ERR_KEY_RANGE) for a rejected batch."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        cap = max(1, min(self.groups, self.last_n))
+        ids = torch.empty(cap, dtype=torch.int32, device=dev)
+        sums = torch.empty(cap, dtype=torch.int64, device=dev)
+        counts = torch.empty(cap, dtype=torch.int32, device=dev)
+        avgs = torch.empty(cap, dtype=torch.float64, device=dev)
+        nt = torch.empty(1, dtype=torch.int64, device=dev)
+        self.results_into(ids, sums, counts, avgs, nt, stream)
+        m = int(nt.cpu().item())
+        if m < 0:
+            raise CQError(m, "batch")
+        return ids[:m].cpu(), sums[:m].cpu(), counts[:m].cpu(), avgs[:m].cpu()
+
+    def status(self) -> int:
+        return lib().cq_status(self._h)
+
+    # -- measurement -------------------------------------------------------
+    def kernel_times(self):
+        """{kind: (ms, launches)} since the previous call (syncs)."""
+        ms = (ctypes.c_double * len(KERNEL_KINDS))()
+        ln = (ctypes.c_int64 * len(KERNEL_KINDS))()
+        _check(lib().cq_kernel_times(self._h, ms, ln, len(KERNEL_KINDS)), "cq_kernel_times")
+        return {k: (ms[i], ln[i]) for i, k in enumerate(KERNEL_KINDS)}
+
+    def worker_trace(self):
+        """Per-workgroup records of the last batch's per-group phase as a list
+        of (hw_id, xcc_id, t_start, t_end, tuples, items) tuples."""
+        cnt = ctypes.c_int64(0)
+        _check(lib().cq_worker_trace(self._h, None, 0, ctypes.byref(cnt)), "cq_worker_trace")
+        m = cnt.value
+        buf = (ctypes.c_int64 * (6 * max(m, 1)))()
+        _check(lib().cq_worker_trace(self._h, buf, m, ctypes.byref(cnt)), "cq_worker_trace")
+        return [tuple(buf[6 * i:6 * i + 6]) for i in range(m)]
+
+    def batch_plan(self):
+        out = (ctypes.c_int64 * 9)()
+        _check(lib().cq_batch_plan(self._h, out), "cq_batch_plan")
+        keys = ("light_buckets", "heavy_groups", "light_tuples", "heavy_tuples",
+                "touched", "heavy_runs", "status", "tiles", "fault")
+        return dict(zip(keys, list(out)))

@@ -1,0 +1,437 @@
+// C-ABI runtime: query objects, device memory, per-batch launch sequence,
+// telemetry.  See include/cq.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "cq.h"
+#include "cq_internal.h"
+
+using namespace cq;
+
+namespace {
+
+struct TimedLaunch {
+    hipEvent_t start, stop;
+    int kind;
+};
+
+}  // namespace
+
+struct cq_query {
+    int device = 0;
+    uint32_t aggregates = 0;
+    State st{};
+    Scratch sc{};
+    int mode = CQ_PARTITION_BALANCED;
+    int32_t workers = 1024;
+    int64_t cap_n = 0;          // batch capacity of the per-batch scratch
+    int64_t last_n = 0;         // size of the most recent batch
+    int32_t last_tiles = 0;
+    int last_mode = CQ_PARTITION_BALANCED;
+    int32_t last_workers = 0;
+    hipStream_t last_stream = nullptr;
+    bool pushed = false;
+    int32_t telemetry = 0;
+    int64_t trace_cap = 0;      // records the trace buffer holds
+    std::vector<TimedLaunch> live;
+    std::vector<hipEvent_t> spare;
+    double ms[CQ_KERNEL_KINDS] = {0};
+    int64_t launches[CQ_KERNEL_KINDS] = {0};
+};
+
+namespace {
+
+int from_hip(hipError_t e) {
+    if (e == hipSuccess) return CQ_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return CQ_ERR_OOM;
+    return CQ_ERR_HIP;
+}
+
+template <typename T>
+int dalloc(T **p, int64_t count) {
+    *p = nullptr;
+    if (count < 1) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * (size_t)count);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return from_hip(e);
+    }
+    return CQ_OK;
+}
+
+template <typename T>
+void dfree(T *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+// Makes the query's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+void free_batch_scratch(cq_query *q) {
+    dfree(q->sc.hkey);
+    dfree(q->sc.hpre);
+    dfree(q->sc.hdb);
+    dfree(q->sc.hruns);
+    dfree(q->sc.desc);
+    dfree(q->sc.bkey);
+    dfree(q->sc.sdat);
+    q->cap_n = 0;
+}
+
+void free_all(cq_query *q) {
+    free_batch_scratch(q);
+    dfree(q->st.ring);
+    dfree(q->st.pos);
+    dfree(q->st.cnt);
+    dfree(q->st.sum);
+    dfree(q->sc.k);
+    dfree(q->sc.lpre);
+    dfree(q->sc.hcum);
+    dfree(q->sc.cursor);
+    dfree(q->sc.touched);
+    dfree(q->sc.partials);
+    dfree(q->sc.flag);
+    dfree(q->sc.fault);
+    dfree(q->sc.tot);
+    dfree(q->sc.trace);
+    for (auto &t : q->live) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    for (auto e : q->spare) (void)hipEventDestroy(e);
+    q->live.clear();
+    q->spare.clear();
+}
+
+int64_t tiles_of(int64_t n) { return (n + TILE - 1) / TILE; }
+
+// Per-batch scratch for batches of up to n tuples.
+int alloc_batch_scratch(cq_query *q, int64_t n) {
+    const int64_t T = tiles_of(n);
+    const int64_t nh = n / HEAVY_MIN + 1;
+    const int64_t nl = (n + LIGHT_BUDGET - 1) / LIGHT_BUDGET + 1;
+    const int64_t ndesc = std::min(n, nh * T) + 1;
+    int rc = CQ_OK;
+    if (rc == CQ_OK) rc = dalloc(&q->sc.hkey, nh);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.hpre, nh + 1);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.hdb, nh);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.hruns, nh);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.desc, ndesc);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.bkey, nl + 1);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.sdat, n);
+    if (rc != CQ_OK) {
+        free_batch_scratch(q);
+        return rc;
+    }
+    q->cap_n = n;
+    return CQ_OK;
+}
+
+int ensure_capacity(cq_query *q, int64_t n) {
+    if (n <= q->cap_n) return CQ_OK;
+    // The old scratch may still be read by enqueued work.
+    if (q->pushed) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return from_hip(e);
+    }
+    free_batch_scratch(q);
+    // round up to whole tiles so that small growth steps do not reallocate
+    const int64_t want = std::max<int64_t>(tiles_of(n) * TILE, 1);
+    return alloc_batch_scratch(q, want);
+}
+
+int ensure_trace(cq_query *q, int64_t records) {
+    if (records <= q->trace_cap) return CQ_OK;
+    dfree(q->sc.trace);
+    int rc = dalloc(&q->sc.trace, 6 * records);
+    if (rc != CQ_OK) {
+        q->trace_cap = 0;
+        return rc;
+    }
+    q->trace_cap = records;
+    return CQ_OK;
+}
+
+hipEvent_t take_event(cq_query *q) {
+    if (!q->spare.empty()) {
+        hipEvent_t e = q->spare.back();
+        q->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch one kernel step, bracketed by events when kernel timing is on.
+template <typename F>
+int timed(cq_query *q, int kind, hipStream_t s, F &&launch) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (q->telemetry & CQ_TELEMETRY_KERNEL_TIMES) {
+        a = take_event(q);
+        b = take_event(q);
+        if (a && b) (void)hipEventRecord(a, s);
+    }
+    hipError_t e = launch();
+    if (a && b) {
+        (void)hipEventRecord(b, s);
+        q->live.push_back({a, b, kind});
+    } else {
+        if (a) q->spare.push_back(a);
+        if (b) q->spare.push_back(b);
+    }
+    return from_hip(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cq_strerror(int code) {
+    switch (code) {
+        case CQ_OK: return "success";
+        case CQ_ERR_INVALID: return "invalid argument";
+        case CQ_ERR_OOM: return "out of device memory";
+        case CQ_ERR_KEY_RANGE: return "batch rejected: key outside [0, groups)";
+        case CQ_ERR_HIP: return "HIP runtime error";
+        default: return "unknown status code";
+    }
+}
+
+int cq_create(int64_t groups, int32_t window, uint32_t aggregates, cq_query **out) {
+    if (!out) return CQ_ERR_INVALID;
+    *out = nullptr;
+    if (groups < 1 || groups > INT32_MAX - 1 || window < 1 || window > CQ_MAX_WINDOW)
+        return CQ_ERR_INVALID;
+    if (aggregates == 0 || (aggregates & ~(CQ_SUM | CQ_COUNT | CQ_AVG)) != 0)
+        return CQ_ERR_INVALID;
+    cq_query *q = new (std::nothrow) cq_query();
+    if (!q) return CQ_ERR_OOM;
+    if (hipGetDevice(&q->device) != hipSuccess) {
+        delete q;
+        return CQ_ERR_HIP;
+    }
+    q->aggregates = aggregates;
+    q->st.G = groups;
+    q->st.W = window;
+    const int64_t G = groups;
+    const int64_t nblk = (G + PLAN_CHUNK - 1) / PLAN_CHUNK;
+    int rc = dalloc(&q->st.ring, G * (int64_t)window);
+    if (rc == CQ_OK) rc = dalloc(&q->st.pos, G);
+    if (rc == CQ_OK) rc = dalloc(&q->st.cnt, G);
+    if (rc == CQ_OK) rc = dalloc(&q->st.sum, G);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.k, G);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.lpre, G + 1);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.hcum, G + 1);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.cursor, G);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.touched, G);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.partials, nblk * PLAN_FIELDS);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.flag, 1);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.fault, 1);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.tot, 1);
+    hipError_t e = hipSuccess;
+    if (rc == CQ_OK) {
+        // zero-filled windows: never-written slots read as 0, so the first
+        // W insertions of a group subtract nothing
+        e = hipMemset(q->st.ring, 0, sizeof(int32_t) * (size_t)(G * (int64_t)window));
+        if (e == hipSuccess) e = hipMemset(q->st.pos, 0, sizeof(int32_t) * (size_t)G);
+        if (e == hipSuccess) e = hipMemset(q->st.cnt, 0, sizeof(int32_t) * (size_t)G);
+        if (e == hipSuccess) e = hipMemset(q->st.sum, 0, sizeof(int64_t) * (size_t)G);
+        if (e == hipSuccess) e = hipMemset(q->sc.k, 0, sizeof(int32_t) * (size_t)G);
+        if (e == hipSuccess) e = hipMemset(q->sc.flag, 0, sizeof(int32_t));
+        if (e == hipSuccess) e = hipMemset(q->sc.fault, 0, sizeof(int32_t));
+        if (e == hipSuccess) e = hipMemset(q->sc.tot, 0, sizeof(PlanTotals));
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        rc = from_hip(e);
+    }
+    if (rc != CQ_OK) {
+        free_all(q);
+        delete q;
+        return rc;
+    }
+    *out = q;
+    return CQ_OK;
+}
+
+int cq_reserve(cq_query *q, int64_t max_batch) {
+    if (!q || max_batch < 0 || max_batch > CQ_MAX_BATCH) return CQ_ERR_INVALID;
+    DeviceGuard g(q->device);
+    return ensure_capacity(q, std::max<int64_t>(max_batch, 1));
+}
+
+int cq_set_partition(cq_query *q, int32_t mode, int32_t workers) {
+    if (!q) return CQ_ERR_INVALID;
+    if (mode != CQ_PARTITION_BALANCED && mode != CQ_PARTITION_STATIC) return CQ_ERR_INVALID;
+    if (workers < 0 || workers > (1 << 20)) return CQ_ERR_INVALID;
+    q->mode = mode;
+    q->workers = workers ? workers : 1024;
+    return CQ_OK;
+}
+
+int cq_push_batch(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n,
+                  void *stream) {
+    if (!q || n < 0 || n > CQ_MAX_BATCH) return CQ_ERR_INVALID;
+    if (n > 0 && (!keys || !values)) return CQ_ERR_INVALID;
+    DeviceGuard guard(q->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int rc = ensure_capacity(q, std::max<int64_t>(n, 1));
+    if (rc != CQ_OK) return rc;
+    const int64_t upd_grid = update_grid(n, q->mode, q->workers);
+    if (q->telemetry & CQ_TELEMETRY_WORKERS) {
+        rc = ensure_trace(q, upd_grid);
+        if (rc != CQ_OK) return rc;
+    }
+    Scratch sc = q->sc;
+    if (!(q->telemetry & CQ_TELEMETRY_WORKERS)) sc.trace = nullptr;
+    q->last_stream = s;
+    q->pushed = true;
+    q->last_n = n;
+    q->last_mode = q->mode;
+    q->last_workers = q->workers;
+    if (n == 0) {
+        q->last_tiles = 0;
+        return from_hip(launch_reset_totals(sc, s));
+    }
+    const int64_t G = q->st.G;
+    const int32_t T = (int32_t)tiles_of(n);
+    q->last_tiles = T;
+    rc = timed(q, CQ_KERNEL_HIST, s, [&] { return launch_hist(keys, n, G, sc, s); });
+    if (rc == CQ_OK)
+        rc = timed(q, CQ_KERNEL_PLAN, s, [&] { return launch_plan(G, T, sc, s); });
+    if (rc == CQ_OK)
+        rc = timed(q, CQ_KERNEL_SCATTER, s,
+                   [&] { return launch_scatter(keys, values, n, G, sc, s); });
+    if (rc == CQ_OK)
+        rc = timed(q, CQ_KERNEL_UPDATE, s, [&] {
+            return launch_update(q->st, sc, n, T, q->mode, q->workers, s);
+        });
+    return rc;
+}
+
+int cq_results(cq_query *q, int32_t *ids, int64_t *sums, int32_t *counts, double *avgs,
+               int64_t *n_touched, void *stream) {
+    if (!q || !n_touched) return CQ_ERR_INVALID;
+    DeviceGuard guard(q->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int64_t cap = std::min<int64_t>(q->st.G, q->last_n);
+    int rc = timed(q, CQ_KERNEL_EMIT, s, [&] {
+        return launch_emit(q->st, q->sc, cap, ids, sums, counts, avgs, n_touched, s);
+    });
+    q->last_stream = s;
+    q->pushed = true;
+    return rc;
+}
+
+int cq_status(cq_query *q) {
+    if (!q) return CQ_ERR_INVALID;
+    DeviceGuard guard(q->device);
+    hipError_t e = hipStreamSynchronize(q->last_stream);
+    if (e != hipSuccess) return from_hip(e);
+    PlanTotals t;
+    e = hipMemcpy(&t, q->sc.tot, sizeof(t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return from_hip(e);
+    return t.status;
+}
+
+int cq_destroy(cq_query *q) {
+    if (!q) return CQ_OK;
+    DeviceGuard guard(q->device);
+    int rc = CQ_OK;
+    if (q->pushed) rc = from_hip(hipStreamSynchronize(q->last_stream));
+    free_all(q);
+    delete q;
+    return rc;
+}
+
+int cq_set_telemetry(cq_query *q, int32_t flags) {
+    if (!q || (flags & ~(CQ_TELEMETRY_KERNEL_TIMES | CQ_TELEMETRY_WORKERS)) != 0)
+        return CQ_ERR_INVALID;
+    q->telemetry = flags;
+    return CQ_OK;
+}
+
+int cq_kernel_times(cq_query *q, double *ms, int64_t *launches, int32_t nkinds) {
+    if (!q || nkinds < 0 || (nkinds > 0 && (!ms || !launches))) return CQ_ERR_INVALID;
+    DeviceGuard guard(q->device);
+    int rc = CQ_OK;
+    for (auto &t : q->live) {
+        hipError_t e = hipEventSynchronize(t.stop);
+        float el = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&el, t.start, t.stop);
+        if (e != hipSuccess) {
+            rc = from_hip(e);
+        } else {
+            q->ms[t.kind] += el;
+            q->launches[t.kind] += 1;
+        }
+        q->spare.push_back(t.start);
+        q->spare.push_back(t.stop);
+    }
+    q->live.clear();
+    for (int k = 0; k < nkinds && k < CQ_KERNEL_KINDS; ++k) {
+        ms[k] = q->ms[k];
+        launches[k] = q->launches[k];
+    }
+    for (int k = 0; k < CQ_KERNEL_KINDS; ++k) {
+        q->ms[k] = 0;
+        q->launches[k] = 0;
+    }
+    return rc;
+}
+
+int cq_worker_trace(cq_query *q, int64_t *rec, int64_t cap, int64_t *count) {
+    if (!q || !count || cap < 0 || (cap > 0 && !rec)) return CQ_ERR_INVALID;
+    DeviceGuard guard(q->device);
+    *count = 0;
+    if (!(q->telemetry & CQ_TELEMETRY_WORKERS) || !q->sc.trace || q->last_n == 0) return CQ_OK;
+    hipError_t e = hipStreamSynchronize(q->last_stream);
+    if (e != hipSuccess) return from_hip(e);
+    const int64_t have = std::min(q->trace_cap, update_grid(q->last_n, q->last_mode, q->last_workers));
+    *count = have;
+    const int64_t m = std::min(have, cap);
+    if (m > 0) {
+        e = hipMemcpy(rec, q->sc.trace, sizeof(int64_t) * 6 * (size_t)m, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return from_hip(e);
+    }
+    return CQ_OK;
+}
+
+int cq_batch_plan(cq_query *q, int64_t *out) {
+    if (!q || !out) return CQ_ERR_INVALID;
+    DeviceGuard guard(q->device);
+    hipError_t e = hipStreamSynchronize(q->last_stream);
+    if (e != hipSuccess) return from_hip(e);
+    PlanTotals t;
+    e = hipMemcpy(&t, q->sc.tot, sizeof(t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return from_hip(e);
+    out[0] = t.n_light_buckets;
+    out[1] = t.n_heavy;
+    out[2] = t.light_tuples;
+    out[3] = t.heavy_tuples;
+    out[4] = t.n_touched;
+    out[5] = t.n_desc;
+    out[6] = t.status;
+    out[7] = t.tiles;
+    int32_t fault = 0;
+    e = hipMemcpy(&fault, q->sc.fault, sizeof(fault), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return from_hip(e);
+    out[8] = fault;
+    return CQ_OK;
+}
+
+}  // extern "C"

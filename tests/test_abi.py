@@ -1,0 +1,81 @@
+"""The C-ABI library loads, exports every symbol its header declares, and
+rejects bad host-side arguments before touching the device (CPU only)."""
+import ctypes
+import re
+
+import pytest
+
+import paper_1309_0634_amd as cq
+
+
+def _declared_functions():
+    src = open(cq.HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(cq_\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    try:
+        return cq.lib()
+    except ImportError:
+        import __graft_entry__
+        __graft_entry__.build()
+        return cq.lib()
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("cq_create", "cq_push_batch", "cq_results", "cq_destroy", "cq_strerror"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_strerror(L):
+    assert cq.strerror(cq.OK) == "success"
+    assert "key" in cq.strerror(cq.ERR_KEY_RANGE)
+    assert cq.strerror(12345) == "unknown status code"
+
+
+def test_create_rejects_bad_arguments_without_device(L):
+    h = ctypes.c_void_p()
+    for groups, window, aggs in [(0, 10, 7), (-5, 10, 7), (10, 0, 7), (10, -1, 7),
+                                 (10, cq.MAX_WINDOW + 1, 7), (10, 10, 0), (10, 10, 8),
+                                 (1 << 31, 10, 7)]:
+        assert L.cq_create(groups, window, aggs, ctypes.byref(h)) == cq.ERR_INVALID
+        assert h.value is None
+    assert L.cq_create(10, 10, 7, None) == cq.ERR_INVALID
+
+
+def test_null_handles_are_rejected(L):
+    assert L.cq_push_batch(None, None, None, 0, None) == cq.ERR_INVALID
+    assert L.cq_results(None, None, None, None, None, None, None) == cq.ERR_INVALID
+    assert L.cq_set_partition(None, 0, 0) == cq.ERR_INVALID
+    assert L.cq_reserve(None, 10) == cq.ERR_INVALID
+    assert L.cq_status(None) == cq.ERR_INVALID
+    assert L.cq_set_telemetry(None, 1) == cq.ERR_INVALID
+    assert L.cq_batch_plan(None, None) == cq.ERR_INVALID
+    assert L.cq_destroy(None) == cq.OK
+
+
+def test_binding_names_match_header():
+    for name in ("cq_create", "cq_reserve", "cq_set_partition", "cq_push_batch", "cq_results",
+                 "cq_status", "cq_destroy", "cq_strerror", "cq_set_telemetry",
+                 "cq_kernel_times", "cq_worker_trace", "cq_batch_plan"):
+        assert name in _declared_functions()
+
+
+def test_header_constants_match_binding():
+    src = open(cq.HEADER).read()
+
+    def val(name):
+        m = re.search(r"#define\s+%s\s+\(?(-?\w+)" % name, src)
+        return int(m.group(1).rstrip("u"), 0)
+
+    assert val("CQ_SUM") == cq.SUM and val("CQ_COUNT") == cq.COUNT and val("CQ_AVG") == cq.AVG
+    assert val("CQ_ERR_KEY_RANGE") == cq.ERR_KEY_RANGE
+    assert val("CQ_PARTITION_STATIC") == cq.PARTITION_STATIC
