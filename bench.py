@@ -58,7 +58,7 @@ def run_mode(torch, cq, batches, cfg, mode, warmup, steps, kernel_times=False):
     """Warm up, then time `steps` batches (push + emit) with no host syncs in
     between.  Returns a dict of measurements."""
     dev = batches[0][0].device
-    q = cq.Query(cfg.groups, cfg.window, partition=mode, reserve=cfg.batch)
+    q = cq.Query(cfg.groups, cfg.window, partition=mode)
     cap = min(cfg.groups, cfg.batch)
     ids = torch.empty(cap, dtype=torch.int32, device=dev)
     sums = torch.empty(cap, dtype=torch.int64, device=dev)
@@ -67,8 +67,7 @@ def run_mode(torch, cq, batches, cfg, mode, warmup, steps, kernel_times=False):
     nt = torch.empty(1, dtype=torch.int64, device=dev)
     for b in range(warmup):
         k, v = batches[b]
-        q.push(k, v)
-        q.results_into(ids, sums, counts, avgs, nt)
+        q.push_results_into(k, v, ids, sums, counts, avgs, nt)
     torch.cuda.synchronize()
     if kernel_times:
         q.set_telemetry(cq.TELEMETRY_KERNEL_TIMES)
@@ -80,8 +79,7 @@ def run_mode(torch, cq, batches, cfg, mode, warmup, steps, kernel_times=False):
     for i in range(steps):
         k, v = batches[warmup + i]
         starts[i].record()
-        q.push(k, v)
-        q.results_into(ids, sums, counts, avgs, nt)
+        q.push_results_into(k, v, ids, sums, counts, avgs, nt)
         ends[i].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -159,6 +157,7 @@ def main():
                 "p99_batch_ms": float(np.percentile(r["lat_ms"], 99)),
                 "alg_MB_per_batch": timed_bytes / args.steps / 1e6,
                 "heavy_groups": int(r["plan"]["heavy_groups"]),
+                "buckets": int(r["plan"]["buckets"]),
                 "touched": int(r["plan"]["touched"]),
             }
             rows.append(row)

@@ -83,10 +83,10 @@ typedef struct cq_query cq_query;
 int cq_create(int64_t groups, int32_t window, uint32_t aggregates, cq_query **out);
 
 /*
- * cq_reserve -- size the per-batch scratch for batches of up to `max_batch`
- * tuples now, so that no later cq_push_batch allocates (cq_push_batch grows
- * the scratch on demand otherwise, synchronizing the query's last stream
- * first).  Returns CQ_OK, CQ_ERR_INVALID or CQ_ERR_OOM.
+ * cq_reserve -- kept for callers that size buffers up front: every working
+ * buffer is sized by cq_create (batches run in fixed-size sub-batches), so
+ * no later call allocates.  Returns CQ_OK or CQ_ERR_INVALID (q NULL or
+ * max_batch outside 0 .. CQ_MAX_BATCH).
  */
 int cq_reserve(cq_query *q, int64_t max_batch);
 
@@ -97,9 +97,12 @@ int cq_reserve(cq_query *q, int64_t max_batch);
  *   CQ_PARTITION_BALANCED (default): every batch, light groups are packed
  *     into workgroups by tuple count and every heavy group gets its own
  *     workgroup, decided on the device from the batch's histogram;
- *   CQ_PARTITION_STATIC: `workers` workgroups (0 = 1024), worker w owns the
- *     equal, consecutive group range [w*groups/workers, (w+1)*groups/workers)
- *     -- the paper's initial assignment with balancing turned off.
+ *   CQ_PARTITION_STATIC: `workers` workers (0 = 1024), worker w owns the
+ *     equal, consecutive group range [ceil(w*groups/workers),
+ *     ceil((w+1)*groups/workers)) and processes every tuple of its groups
+ *     -- the paper's initial assignment with balancing turned off
+ *     (Section 5.1).  Needs workers <= 1536 and at most 2048 groups per
+ *     worker.
  * Results are identical in every mode.  Takes effect at the next push.
  * Returns CQ_OK or CQ_ERR_INVALID.
  */
@@ -142,6 +145,17 @@ int cq_results(cq_query *q, int32_t *ids, int64_t *sums, int32_t *counts, double
                int64_t *n_touched, void *stream);
 
 /*
+ * cq_push_batch_results -- cq_push_batch followed by cq_results into the
+ * given device buffers, with the same arguments and the same results; the
+ * per-group phase writes the results itself, saving the separate emission
+ * launch.  For callers that want every batch's results (the per-batch
+ * output of Section 3.1 iterations).
+ */
+int cq_push_batch_results(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n,
+                          int32_t *ids, int64_t *sums, int32_t *counts, double *avgs,
+                          int64_t *n_touched, void *stream);
+
+/*
  * cq_status -- wait for the query's last stream and return the status of the
  * most recent batch: CQ_OK or CQ_ERR_KEY_RANGE (or CQ_ERR_HIP).
  */
@@ -160,16 +174,18 @@ const char *cq_strerror(int code);
 
 /* Telemetry flags for cq_set_telemetry. */
 #define CQ_TELEMETRY_KERNEL_TIMES 1 /* HIP events around every kernel launch */
+#define CQ_TELEMETRY_PHASES       4 /* device clock at fixed points inside each
+                                       kernel, per workgroup (cq_phase_trace) */
 #define CQ_TELEMETRY_WORKERS      2 /* per-workgroup (hardware id, start, end,
                                        tuples) records of the per-group phase */
 
-/* Kernel kinds reported by cq_kernel_times, in this order. */
-#define CQ_KERNEL_HIST    0
-#define CQ_KERNEL_PLAN    1
-#define CQ_KERNEL_SCATTER 2
-#define CQ_KERNEL_UPDATE  3
-#define CQ_KERNEL_EMIT    4
-#define CQ_KERNEL_KINDS   5
+/* Launch kinds reported by cq_kernel_times, in this order. */
+#define CQ_KERNEL_HIST_PLAN 0 /* histogram + balancer plan           */
+#define CQ_KERNEL_PASS      1 /* tile-local reorder by bucket        */
+#define CQ_KERNEL_UPDATE    2 /* per-group evict + insert + aggregate */
+#define CQ_KERNEL_EMIT      3 /* separate result emission            */
+#define CQ_KERNEL_OTHER     4 /* whole-batch checks and collection   */
+#define CQ_KERNEL_KINDS     5
 
 /*
  * cq_set_telemetry -- turn measurement on (flags) or off (0).  Imbalance
@@ -199,12 +215,23 @@ int cq_kernel_times(cq_query *q, double *ms, int64_t *launches, int32_t nkinds);
 int cq_worker_trace(cq_query *q, int64_t *rec, int64_t cap, int64_t *count);
 
 /*
+ * cq_phase_trace -- wait for the query's last stream and copy the phase
+ * clocks of the most recent sub-batch for one kernel `kind` (0: histogram +
+ * plan, 1: reorder pass, 2: per-group update) into the host array `out`
+ * (cap records of 8 int64 device-clock ticks, one record per workgroup, 0 =
+ * not reached).  *count receives the number of records available (4096).
+ * Needs CQ_TELEMETRY_PHASES.  Returns CQ_OK, CQ_ERR_INVALID or CQ_ERR_HIP.
+ */
+int cq_phase_trace(cq_query *q, int32_t kind, int64_t *out, int64_t cap, int64_t *count);
+
+/*
  * cq_batch_plan -- wait for the query's last stream and copy the most
  * recent batch's partition summary into the host array `out` (9 int64):
- * light buckets, heavy groups, light tuples, heavy tuples, touched groups,
- * heavy run descriptors, status, arrival tiles, and the library's sticky
- * internal-consistency bits (0 unless a kernel found a plan breaking its own
- * size bounds and skipped work rather than overrun a buffer).
+ * light buckets, heavy groups, light tuples, touched groups (whole batch),
+ * buckets (light + heavy, or static workers), touched groups of the last
+ * sub-batch, status, reorder tiles of the last sub-batch, and the library's
+ * sticky internal-consistency bits (0 unless a kernel found a plan breaking
+ * its own size bounds and skipped work rather than overrun a buffer).
  */
 int cq_batch_plan(cq_query *q, int64_t *out);
 

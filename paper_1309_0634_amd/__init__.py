@@ -17,8 +17,8 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "cq.h")
 SUM, COUNT, AVG = 1, 2, 4
 OK, ERR_INVALID, ERR_OOM, ERR_KEY_RANGE, ERR_HIP = 0, -1, -2, -3, -4
 PARTITION_BALANCED, PARTITION_STATIC = 0, 1
-TELEMETRY_KERNEL_TIMES, TELEMETRY_WORKERS = 1, 2
-KERNEL_KINDS = ("hist", "plan", "scatter", "update", "emit")
+TELEMETRY_KERNEL_TIMES, TELEMETRY_WORKERS, TELEMETRY_PHASES = 1, 2, 4
+KERNEL_KINDS = ("hist_plan", "pass", "update", "emit", "other")
 MAX_BATCH = 1 << 30
 MAX_WINDOW = (1 << 22) - 1
 
@@ -49,6 +49,7 @@ def lib() -> ctypes.CDLL:
             "cq_set_partition": ([P, i32, i32], ctypes.c_int),
             "cq_push_batch": ([P, P, P, i64, P], ctypes.c_int),
             "cq_results": ([P, P, P, P, P, P, P], ctypes.c_int),
+            "cq_push_batch_results": ([P, P, P, i64, P, P, P, P, P, P], ctypes.c_int),
             "cq_status": ([P], ctypes.c_int),
             "cq_destroy": ([P], ctypes.c_int),
             "cq_strerror": ([ctypes.c_int], ctypes.c_char_p),
@@ -56,6 +57,7 @@ def lib() -> ctypes.CDLL:
             "cq_kernel_times": ([P, pdbl, pi64, i32], ctypes.c_int),
             "cq_worker_trace": ([P, pi64, i64, pi64], ctypes.c_int),
             "cq_batch_plan": ([P, pi64], ctypes.c_int),
+            "cq_phase_trace": ([P, i32, pi64, i64, pi64], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -148,6 +150,18 @@ class Query:
                                    _stream_handle(stream)), "cq_push_batch")
         self.last_n = int(n)
 
+    def push_results_into(self, keys, values, ids, sums, counts, avgs, n_touched, stream=None):
+        """Enqueue one batch and the emission of its results into caller
+        device tensors (cq_push_batch_results)."""
+        n = keys.numel()
+        if values.numel() != n:
+            raise ValueError("keys and values differ in length")
+        _check(lib().cq_push_batch_results(
+            self._h, _dptr(keys) if n else None, _dptr(values) if n else None, int(n),
+            _dptr(ids), _dptr(sums), _dptr(counts), _dptr(avgs), _dptr(n_touched),
+            _stream_handle(stream)), "cq_push_batch_results")
+        self.last_n = int(n)
+
     def results_into(self, ids, sums, counts, avgs, n_touched, stream=None):
         """Enqueue the emission of the last batch's results into caller
         device tensors (any of ids/sums/counts/avgs may be None)."""
@@ -192,9 +206,21 @@ class Query:
         _check(lib().cq_worker_trace(self._h, buf, m, ctypes.byref(cnt)), "cq_worker_trace")
         return [tuple(buf[6 * i:6 * i + 6]) for i in range(m)]
 
+    def phase_trace(self, kind: int):
+        """Phase clocks of the last sub-batch for kernel `kind` (0 histogram +
+        plan, 1 reorder pass, 2 update): list of 8-tuples per workgroup."""
+        cnt = ctypes.c_int64(0)
+        _check(lib().cq_phase_trace(self._h, int(kind), None, 0, ctypes.byref(cnt)),
+               "cq_phase_trace")
+        m = cnt.value
+        buf = (ctypes.c_int64 * (8 * max(m, 1)))()
+        _check(lib().cq_phase_trace(self._h, int(kind), buf, m, ctypes.byref(cnt)),
+               "cq_phase_trace")
+        return [tuple(buf[8 * i:8 * i + 8]) for i in range(m)]
+
     def batch_plan(self):
         out = (ctypes.c_int64 * 9)()
         _check(lib().cq_batch_plan(self._h, out), "cq_batch_plan")
-        keys = ("light_buckets", "heavy_groups", "light_tuples", "heavy_tuples",
-                "touched", "heavy_runs", "status", "tiles", "fault")
+        keys = ("light_buckets", "heavy_groups", "light_tuples", "touched", "buckets",
+                "sub_touched", "status", "tiles", "fault")
         return dict(zip(keys, list(out)))

@@ -7,104 +7,149 @@
 
 namespace cq {
 
-// ---------------------------------------------------------------- tuning --
-// Arrival tiles: the histogram and scatter kernels each take TILE
-// consecutive tuples per 256-thread workgroup (ITEMS per thread).
-constexpr int TILE = 2048;
-constexpr int TILE_THREADS = 256;
-constexpr int ITEMS = TILE / TILE_THREADS;
-// A group with at least HEAVY_MIN tuples in a batch is heavy: it gets its
-// own work item whose cost is bounded by the window, not by its tuples.
-constexpr int HEAVY_MIN = 1024;
-// Light groups are packed into buckets of about LIGHT_BUDGET tuples; a bucket
-// holds fewer than LIGHT_BUDGET + HEAVY_MIN <= LCAP tuples.
-constexpr int LIGHT_BUDGET = 1024;
-constexpr int LCAP = 2048;
-// Heavy run descriptors cached in LDS (beyond this they are re-read).
-constexpr int DESC_CACHE = 2048;
-// LDS counters indexed directly by key when groups <= DIRECT_MAX_G;
-// otherwise an open-addressing LDS hash table with HASH_SLOTS slots.
-constexpr int DIRECT_MAX_G = 12288;
-constexpr int HASH_LOG = 12;
-constexpr int HASH_SLOTS = 1 << HASH_LOG;
-static_assert(HASH_SLOTS >= 2 * TILE, "hash load factor must stay <= 1/2");
-static_assert(LIGHT_BUDGET + HEAVY_MIN <= LCAP, "light bucket bound");
-// Plan (scan over groups): PLAN_THREADS threads x PLAN_KPT keys per block.
+// ---------------------------------------------------------------- sizes --
+// A batch is processed in sub-batches of at most SUB tuples (windows after
+// B1 then B2 equal windows after B1||B2, so this is exact); results are
+// emitted once, after the last sub-batch.
+constexpr int SUB = 1 << 20;
+
+// Histogram: arrival tiles of HIST_THREADS threads, HIST_KPT keys per thread
+// (loaded together); per-tile counters are
+// LDS arrays indexed by key while groups <= HIST_DIRECT_MAX_G, otherwise an
+// open-addressing LDS hash of HIST_HASH_SLOTS slots over HIST_HASH_TILE tuples.
+constexpr int HIST_THREADS = 1024;
+constexpr int HIST_KPT = 32;
+constexpr int HIST_TILE = HIST_THREADS * HIST_KPT;
+constexpr int HIST_DIRECT_MAX_G = 32768;
+constexpr int HIST_HASH_TILE = 8192;
+constexpr int HIST_HASH_LOG = 14;
+constexpr int HIST_HASH_SLOTS = 1 << HIST_HASH_LOG;
+static_assert(HIST_HASH_SLOTS >= 2 * HIST_HASH_TILE, "hash load factor <= 1/2");
+
+// Plan (scan over groups): PLAN_THREADS x PLAN_KPT groups per block; one
+// block (fused into the histogram's last block) when G <= PLAN_CHUNK.
 constexpr int PLAN_THREADS = 1024;
-constexpr int PLAN_KPT = 16;
+constexpr int PLAN_KPT = 32;
 constexpr int PLAN_CHUNK = PLAN_THREADS * PLAN_KPT;
-constexpr int PLAN_FIELDS = 5;
-// Per-group phase workgroups.
+constexpr int PLAN_FIELDS = 3;   // light tuples, heavy groups, touched groups
+
+// Balanced assignment: a group with >= HEAVY_MIN tuples in a sub-batch is
+// heavy and becomes a bucket of its own; light groups are packed, in id
+// order, into buckets of about LIGHT_BUDGET tuples (fewer than LIGHT_BUDGET
+// + HEAVY_MIN).
+constexpr int HEAVY_MIN = 1024;
+constexpr int LIGHT_BUDGET = 1024;
+constexpr int LIGHT_CAP = LIGHT_BUDGET + HEAVY_MIN;
+constexpr int LIGHT_BITS = 11;   // positions inside a light bucket
+static_assert(LIGHT_CAP <= (1 << LIGHT_BITS), "light positions must fit the match bits");
+constexpr int NB_MAX = SUB / LIGHT_BUDGET + SUB / HEAVY_MIN + 2;
+constexpr int NB_BITS = 12;
+static_assert(NB_MAX < (1 << NB_BITS), "bucket ids must fit the match bits");
+
+// Multisplit pass: tiles of PASS_TILE tuples, PASS_WAVES waves, each wave a
+// contiguous chunk of PASS_TILE / PASS_WAVES tuples in 64-lane rounds.
+constexpr int PASS_TILE = 4096;
+constexpr int PASS_WAVES = 8;
+constexpr int PASS_THREADS = 64 * PASS_WAVES;
+constexpr int PASS_ROUNDS = PASS_TILE / PASS_THREADS;
+constexpr int PASS_TILES_MAX = SUB / PASS_TILE;
+static_assert(PASS_TILE / PASS_WAVES < 65536, "per-wave counters are 16-bit");
+
+// Per-group phase.
 constexpr int UPD_THREADS = 256;
-constexpr int UPD_MAX_GRID = 4096;
+// Static assignment: one wave per worker, four workers per workgroup; a
+// worker owns at most STATIC_KEYS_MAX groups.
+constexpr int STATIC_WORKERS_PER_WG = 4;
+constexpr int STATIC_KEYS_MAX = 2048;
 constexpr int EMIT_THREADS = 256;
 
-// Descriptor of one heavy run: the tuples of one heavy group that one
-// arrival tile staged contiguously.  x = first staged slot; y = tile << 12 |
-// (count - 1).
-constexpr int RUN_COUNT_BITS = 12;
-static_assert(TILE <= (1 << RUN_COUNT_BITS), "run count field");
-
-// Totals of the most recent batch's plan (device resident).
+// Totals of the most recent (sub-)batch plan (device resident).
 struct PlanTotals {
     int32_t n_light_buckets;
     int32_t n_heavy;
-    int32_t light_tuples;
-    int32_t heavy_tuples;
-    int32_t n_touched;
-    int32_t n_desc;
-    int32_t status;   // 0 or CQ_ERR_KEY_RANGE
-    int32_t tiles;
+    int32_t light_tuples;   // tuples in light buckets
+    int32_t n_touched;      // groups touched by the whole batch (final list)
+    int32_t status;         // 0 or CQ_ERR_KEY_RANGE
+    int32_t n_buckets;      // light + heavy (balanced) or workers (static)
+    int32_t tiles;          // multisplit tiles of the last sub-batch
+    int32_t sub_touched;    // groups touched by the last sub-batch
 };
-
-// Bits of the device-side fault word (Scratch::fault): set when a kernel
-// finds a plan that breaks one of its own size bounds and skips the work
-// instead of overrunning a buffer.  Never set by a correct plan.
-constexpr int32_t FAULT_LIGHT_SIZE = 1;
-constexpr int32_t FAULT_HEAVY_CHUNK = 2;
 
 // Window store and per-group state.
 struct State {
     int64_t G;
     int32_t W;
-    int32_t *ring;   // G x W values, row g is group g's ring
-    int32_t *pos;    // G: next write slot of the ring (= tuples seen mod W)
+    int32_t *ring;   // G x W values; row g is group g's ring
+    int32_t *pos;    // G: next ring slot (= tuples seen mod W)
     int32_t *cnt;    // G: values in the window (<= W)
     int64_t *sum;    // G: exact window sum
 };
 
-// Per-batch working buffers.
+// Working buffers.
 struct Scratch {
-    int32_t *k;         // G   key histogram; zero between batches
-    int32_t *lpre;      // G+1 exclusive prefix of light-group tuple counts
-    int32_t *hcum;      // G+1 exclusive prefix of heavy flags (heavy index)
-    int32_t *cursor;    // G   scatter cursor: next staged slot of the group
-    int32_t *touched;   // G   touched group ids, ascending
+    // per group (G or G+1 entries)
+    int32_t *k;         // histogram of the current sub-batch; zero between uses
+    int32_t *lpre;      // G+1: exclusive prefix of tuples staged in light buckets
+    int32_t *bucket;    // bucket of each touched group
+    int32_t *pold;      // ring slot of each touched group before the sub-batch
+    int32_t *tidx;      // output position of each touched group
+    int32_t *stamp;     // batch sequence number that last touched the group
+    int32_t *touched;   // touched group ids, ascending
+    // per bucket / heavy group
+    int32_t *bstart;    // light bucket -> first group; [n_light] = G
     int32_t *hkey;      // heavy index -> group
-    int32_t *hpre;      // heavy index -> first staged slot (relative); +1 end
-    int32_t *hdb;       // heavy index -> first descriptor
-    int32_t *hruns;     // heavy index -> descriptors written
-    int2 *desc;         // heavy run descriptors
-    int32_t *bkey;      // light bucket -> first group; [n_buckets] = G
-    int2 *sdat;         // n staged (arrival index, value) pairs
-    int32_t *partials;  // plan block partials (PLAN_FIELDS per block)
-    int32_t *flag;      // [1] bad-key flag raised by the histogram
-    int32_t *fault;     // [1] sticky FAULT_* bits (see above)
-    PlanTotals *tot;    // plan totals
+    // multisplit output
+    int2 *sdat;         // SUB staged (key, value), tile-major, bucket-sorted per tile
+    int32_t *rowstart;  // [tile][n_buckets + 1] bucket starts inside each tile
+    // control
+    int32_t *partials;  // plan block partials
+    int32_t *bad;       // batch sequence number of the last batch with a bad key
+    uint32_t *done;     // histogram blocks finished (last one plans)
+    int32_t *fault;     // sticky internal-consistency bits
+    PlanTotals *tot;
     int64_t *trace;     // optional per-workgroup records (6 int64 each)
+    int64_t *phase;     // optional phase clocks [kind][block][PHASE_SLOTS]
 };
 
-// Launchers (each enqueues on `s` and returns the HIP launch status).
-hipError_t launch_hist(const int32_t *keys, int64_t n, int64_t G, Scratch sc, hipStream_t s);
-hipError_t launch_plan(int64_t G, int32_t tiles, Scratch sc, hipStream_t s);
-hipError_t launch_scatter(const int32_t *keys, const int32_t *values, int64_t n, int64_t G,
-                          Scratch sc, hipStream_t s);
-hipError_t launch_update(State st, Scratch sc, int64_t n, int32_t tiles, int mode,
-                         int32_t workers, hipStream_t s);
-hipError_t launch_emit(State st, Scratch sc, int64_t cap, int32_t *ids, int64_t *sums,
-                       int32_t *counts, double *avgs, int64_t *n_touched, hipStream_t s);
+// Phase clocks (telemetry): kernels of kind PHASE_* record the device clock
+// at fixed points, per workgroup, for the first PHASE_BLOCKS workgroups.
+constexpr int PHASE_HIST_PLAN = 0;
+constexpr int PHASE_PASS = 1;
+constexpr int PHASE_UPDATE = 2;
+constexpr int PHASE_KINDS = 3;
+constexpr int PHASE_BLOCKS = 4096;
+constexpr int PHASE_SLOTS = 8;
+
+// Result destination of an emitting launch (all may be null).
+struct Out {
+    int32_t *ids;
+    int64_t *sums;
+    int32_t *counts;
+    double *avgs;
+    int64_t *n_touched;
+};
+
+constexpr int32_t FAULT_LIGHT_SIZE = 1;
+constexpr int32_t FAULT_BUCKETS = 2;
+constexpr int32_t FAULT_STATIC_KEYS = 4;
+
+enum Mode { MODE_BALANCED = 0, MODE_STATIC = 1 };
+
+// Launch sequence pieces (each enqueues on `s`, returns the launch status).
+hipError_t launch_validate(const int32_t *keys, int64_t n, int64_t G, int32_t seq, Scratch sc,
+                           hipStream_t s);
+hipError_t launch_hist_plan(const int32_t *keys, int64_t n, State st, Scratch sc, int32_t seq,
+                            int mode, int32_t workers, hipStream_t s);
+hipError_t launch_pass(const int32_t *keys, const int32_t *values, int64_t n, Scratch sc,
+                       hipStream_t s);
+hipError_t launch_update(State st, Scratch sc, int64_t n, int mode, int32_t workers, Out out,
+                         hipStream_t s);
+hipError_t launch_collect_touched(int64_t G, int32_t seq, Scratch sc, hipStream_t s);
+hipError_t launch_emit(State st, Scratch sc, int64_t cap, Out out, hipStream_t s);
 hipError_t launch_reset_totals(Scratch sc, hipStream_t s);
-// Workgroups launched by launch_update (one trace record each).
+// Workgroups of the per-group phase (one trace record each).
 int64_t update_grid(int64_t n, int mode, int32_t workers);
+// Histogram kernels launched by launch_hist_plan for a sub-batch of n.
+int64_t hist_blocks(int64_t n, int64_t G);
 
 }  // namespace cq

@@ -1,51 +1,52 @@
-// HIP kernels for gfx950 (CDNA4, wave64): one batch of the continuous
-// sliding-window group-by aggregate.
+// HIP kernels for gfx950 (CDNA4, wave64): one sub-batch (<= SUB tuples) of
+// the continuous sliding-window group-by aggregate.
 //
-// Per batch, in stream order:
-//   k_hist     arrival tiles -> key histogram k[g]; flags keys outside
-//              [0, G) (tuples are (id, attr), Section 3; a bad batch is
-//              rejected whole);
-//   k_plan_*   scans over the groups: light/heavy split, touched list,
-//              light buckets packed by tuple count, heavy work items -- the
-//              load balancer, decided from this batch's exact histogram
-//              (the paper's coordinator moves groups between threads on the
-//              CPU with a one-iteration delay, Section 3.1 and Section 4);
-//   k_scatter  arrival tiles -> every tuple staged with its arrival index in
-//              its group's segment (the paper's reordered data matrix,
-//              Section 3.1, grouped by group instead of by thread); one
-//              global reservation per (tile, group); heavy groups also get a
-//              run descriptor per tile;
-//   k_update_* the per-group phase: each group's surviving tuples (its last
-//              W in arrival order) go to its ring slots; the evicted slot
-//              values are subtracted and the new ones added (Section 3.2:
-//              a full window discards its oldest value, nextPos moves on);
-//   k_emit     (from cq_results) the touched groups' SUM, COUNT, AVG in
-//              ascending id.
+// Three launches per sub-batch, in stream order:
 //
-// The path is integer work bounded by memory traffic: no MFMA.
-#include "cq_internal.h"
+//   k_hist_plan  arrival tiles count keys in LDS; the last tile to finish
+//                plans the sub-batch: the load balancer (Section 4 moves
+//                groups between workers from per-worker tuple counts; here
+//                the exact per-group counts of this very batch decide, with
+//                no one-iteration delay).  Light groups are packed in id
+//                order into buckets of about LIGHT_BUDGET tuples, every
+//                group with >= HEAVY_MIN tuples becomes a bucket of its own,
+//                and each touched group's ring pointer moves on (Section 3.2:
+//                nextPos advances as values enter the window).
+//   k_pass       arrival tiles reorder their tuples by bucket, stably, in
+//                LDS and write them back contiguously: the paper's two-pass
+//                linear reorder (Section 3.1), done per tile so that no tile
+//                waits on another.
+//   k_update_*   the per-group phase: a bucket's tuples are read tile by
+//                tile (arrival order); every tuple among its group's last W
+//                goes to ring slot (pos + rank) mod W, and the group's sum
+//                gains (new value - value overwritten), i.e. the evicted
+//                value is subtracted (Section 3.2: a full window discards its
+//                oldest value).  Results are emitted in ascending group id.
+//
+// Integer work bounded by memory traffic and latency: no MFMA.
+#include <algorithm>
+
 #include "cq.h"
+#include "cq_internal.h"
 
 namespace cq {
 
 // ------------------------------------------------------------ utilities --
 
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    return (lane_id() == 0) ? 0ull : (~0ull >> (64 - lane_id()));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
 __device__ __forceinline__ int wave_incl_add(int v) {
-    const int lane = threadIdx.x & 63;
+    const int lane = lane_id();
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         int t = __shfl_up(v, o, 64);
         if (lane >= o) v += t;
-    }
-    return v;
-}
-
-__device__ __forceinline__ unsigned long long wave_incl_max_u64(unsigned long long v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        unsigned long long t = __shfl_up(v, o, 64);
-        if (lane >= o && t > v) v = t;
     }
     return v;
 }
@@ -56,17 +57,11 @@ __device__ __forceinline__ long long wave_sum_ll(long long v) {
     return v;
 }
 
-__device__ __forceinline__ int wave_sum_int(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Exclusive block scan of F ints per thread; `lds` holds F * (waves) ints.
-// Returns the block totals in `total`.  Contains barriers: call uniformly.
+// Exclusive block scan of F ints per thread; `lds` holds F * waves ints.
+// Returns the block totals in `total`.  Barriers inside: call uniformly.
 template <int F>
 __device__ void block_excl_scan(int (&v)[F], int (&total)[F], int *lds) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = lane_id(), wid = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
     int incl[F];
 #pragma unroll
@@ -94,24 +89,27 @@ __device__ void block_excl_scan(int (&v)[F], int (&total)[F], int *lds) {
     __syncthreads();
 }
 
-// Block sum of an int; `lds` holds >= waves ints.  Barriers inside.
-__device__ int block_sum_int(int v, int *lds) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int nw = blockDim.x >> 6;
-    v = wave_sum_int(v);
-    if (lane == 0) lds[wid] = v;
+// Exclusive scan of a[0, m) in LDS (in place), a[m] = total.  Each thread
+// scans a contiguous piece.  Barriers inside.
+__device__ void block_excl_scan_array(int32_t *a, int m, int *lds) {
+    const int per = (m + blockDim.x - 1) / blockDim.x;
+    const int b0 = min(m, (int)threadIdx.x * per), b1 = min(m, b0 + per);
+    int f[1] = {0}, t[1];
+    for (int i = b0; i < b1; ++i) f[0] += a[i];
+    block_excl_scan<1>(f, t, lds);
+    for (int i = b0; i < b1; ++i) {
+        const int x = a[i];
+        a[i] = f[0];
+        f[0] += x;
+    }
+    if (threadIdx.x == 0) a[m] = t[0];
     __syncthreads();
-    int t = 0;
-    for (int w = 0; w < nw; ++w) t += lds[w];
-    __syncthreads();
-    return t;
 }
 
 __device__ long long block_sum_ll(long long v, long long *lds) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int nw = blockDim.x >> 6;
+    const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     v = wave_sum_ll(v);
-    if (lane == 0) lds[wid] = v;
+    if (lane_id() == 0) lds[wid] = v;
     __syncthreads();
     long long t = 0;
     for (int w = 0; w < nw; ++w) t += lds[w];
@@ -119,582 +117,471 @@ __device__ long long block_sum_ll(long long v, long long *lds) {
     return t;
 }
 
-// Inclusive max-scan of a[0, size) in LDS (unsigned 64-bit).  Each thread
-// scans a contiguous piece, then pieces are combined across the block.
-__device__ void block_incl_max_scan_u64(unsigned long long *a, int size,
-                                        unsigned long long *lds_w) {
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int nw = blockDim.x >> 6;
-    const int per = (size + blockDim.x - 1) / blockDim.x;
-    const int b0 = min(size, tid * per), b1 = min(size, b0 + per);
-    unsigned long long m = 0;
-    for (int i = b0; i < b1; ++i) {
-        unsigned long long x = a[i];
-        if (x > m) m = x;
-        a[i] = m;
+// Largest r in [0, m) with pre[r] <= p (pre ascending, pre[0] = 0 <= p).
+__device__ __forceinline__ int upper_run(const int32_t *pre, int m, int p) {
+    int lo = 0, hi = m - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= p) lo = mid; else hi = mid - 1;
     }
-    unsigned long long incl = wave_incl_max_u64(m);
-    if (lane == 63) lds_w[wid] = incl;
-    __syncthreads();
-    unsigned long long before = 0;
-    for (int w = 0; w < wid; ++w)
-        if (lds_w[w] > before) before = lds_w[w];
-    unsigned long long prev = __shfl_up(incl, 1, 64);
-    if (lane > 0 && prev > before) before = prev;
-    for (int i = b0; i < b1; ++i)
-        if (a[i] < before) a[i] = before;
-    __syncthreads();
-    (void)nw;
+    return lo;
 }
 
-// In-LDS bitonic sort, ascending, of key[0, P2) (P2 a power of two), with an
-// optional int payload.  Barriers inside; P2 must be uniform.
-template <bool PAYLOAD>
-__device__ void bitonic_sort(unsigned long long *key, int32_t *val, int P2) {
-    for (int k = 2; k <= P2; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = threadIdx.x; t < (P2 >> 1); t += blockDim.x) {
-                const int lo = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-                const int hi = lo + j;
-                const bool asc = (lo & k) == 0;
-                unsigned long long a = key[lo], b = key[hi];
-                if ((a > b) == asc) {
-                    key[lo] = b;
-                    key[hi] = a;
-                    if (PAYLOAD) {
-                        int32_t x = val[lo];
-                        val[lo] = val[hi];
-                        val[hi] = x;
-                    }
-                }
+// Records the device clock for phase `slot` of this workgroup (thread 0).
+__device__ __forceinline__ void phase_mark(const Scratch &sc, int kind, int slot) {
+    if (sc.phase && threadIdx.x == 0 && blockIdx.x < PHASE_BLOCKS)
+        sc.phase[((int64_t)kind * PHASE_BLOCKS + blockIdx.x) * PHASE_SLOTS + slot] =
+            (int64_t)wall_clock64();
+}
+
+__device__ __forceinline__ int32_t load_coherent(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// -------------------------------------------------------- plan (per key) --
+// Fields scanned over groups: light tuples, heavy groups, touched groups.
+__device__ __forceinline__ void key_fields(int32_t kg, int mode, int (&f)[PLAN_FIELDS]) {
+    const bool heavy = mode == MODE_BALANCED && kg >= HEAVY_MIN;
+    f[0] = (kg > 0 && !heavy) ? kg : 0;
+    f[1] = heavy ? 1 : 0;
+    f[2] = kg > 0 ? 1 : 0;
+}
+
+__device__ __forceinline__ int32_t static_worker(int64_t g, int64_t G, int32_t workers) {
+    return (int32_t)((g * workers) / G);
+}
+
+// Plan of one touched group g with kg tuples, from the exclusive running
+// field values x_ex (light tuples, heavy index, output position) and its
+// current ring pointer po / count c: moves the ring pointer and count on (the
+// update reads the old pointer from pold) and assigns the group's bucket.
+__device__ __forceinline__ void plan_group(const State &st, const Scratch &sc, int64_t g,
+                                           int32_t kg, const int (&x_ex)[PLAN_FIELDS],
+                                           int32_t po, int32_t c, int32_t n_light, int32_t seq,
+                                           int mode, int32_t workers) {
+    const int32_t W = st.W;
+    sc.stamp[g] = seq;
+    sc.tidx[g] = x_ex[2];
+    sc.touched[x_ex[2]] = (int32_t)g;
+    sc.pold[g] = po;
+    st.pos[g] = (int32_t)(((uint32_t)po + (uint32_t)kg) % (uint32_t)W);
+    st.cnt[g] = (int32_t)min((int64_t)W, (int64_t)c + kg);
+    // a sub-batch at least as long as the window replaces it whole: the new
+    // sum is the sum of the survivors alone
+    if (kg >= W) st.sum[g] = 0;
+    if (mode == MODE_STATIC) {
+        sc.bucket[g] = static_worker(g, st.G, workers);
+    } else if (kg >= HEAVY_MIN) {
+        sc.bucket[g] = n_light + x_ex[1];
+        sc.hkey[x_ex[1]] = (int32_t)g;
+    } else {
+        // light buckets: bucket m starts at the group whose staged range
+        // [L, L + k) contains position m * LIGHT_BUDGET
+        const int32_t L = x_ex[0];
+        sc.bucket[g] = (L + kg - 1) / LIGHT_BUDGET;
+        const int32_t m = (L + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
+        if ((int64_t)m * LIGHT_BUDGET <= (int64_t)L + kg - 1) sc.bstart[m] = (int32_t)g;
+    }
+}
+
+// Groups of a plan block are split into one contiguous range per wave; lanes
+// take consecutive groups, 64 per round, so every load and store of the plan
+// is coalesced, and prefixes inside a round come from wave shuffles.
+constexpr int PLAN_BATCH = 8;  // rounds whose inputs are fetched together
+
+__device__ __forceinline__ void wave_range(int64_t gb, int64_t ge, int64_t &c0, int64_t &c1) {
+    const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6;
+    const int64_t per = ((ge - gb + nw - 1) / nw + 63) / 64 * 64;
+    c0 = min(ge, gb + wv * per);
+    c1 = min(ge, c0 + per);
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Field totals of this wave's range (same value in every lane).
+__device__ void plan_wave_totals(const int32_t *__restrict__ k, int64_t gb, int64_t ge, int mode,
+                                 int (&tot)[PLAN_FIELDS]) {
+    int64_t c0, c1;
+    wave_range(gb, ge, c0, c1);
+    int f[PLAN_FIELDS] = {0, 0, 0};
+    for (int64_t r0 = c0; r0 < c1; r0 += 64 * PLAN_BATCH) {
+        int32_t kv[PLAN_BATCH];
+#pragma unroll
+        for (int j = 0; j < PLAN_BATCH; ++j) {
+            const int64_t g = r0 + j * 64 + lane_id();
+            kv[j] = g < c1 ? k[g] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < PLAN_BATCH; ++j) {
+            int x[PLAN_FIELDS];
+            key_fields(kv[j], mode, x);
+#pragma unroll
+            for (int q = 0; q < PLAN_FIELDS; ++q) f[q] += x[q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < PLAN_FIELDS; ++q) tot[q] = wave_sum(f[q]);
+}
+
+// Exclusive scan of the waves' totals across the block: each wave gets its
+// offset in `off`, every thread the block totals in `btot`.  Barriers inside.
+__device__ void plan_block_offsets(const int (&wtot)[PLAN_FIELDS], int (&off)[PLAN_FIELDS],
+                                   int (&btot)[PLAN_FIELDS], int *lds) {
+    const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6;
+    if (lane_id() == 0)
+#pragma unroll
+        for (int q = 0; q < PLAN_FIELDS; ++q) lds[wv * PLAN_FIELDS + q] = wtot[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PLAN_FIELDS; ++q) {
+        int before = 0, all = 0;
+        for (int w = 0; w < nw; ++w) {
+            const int x = lds[w * PLAN_FIELDS + q];
+            if (w < wv) before += x;
+            all += x;
+        }
+        off[q] = before;
+        btot[q] = all;
+    }
+    __syncthreads();
+}
+
+// Writes the plan of this wave's range, starting from running values `run`
+// (the exclusive prefix at the range start); clears the histogram.
+__device__ void plan_wave_write(const State &st, const Scratch &sc, int64_t gb, int64_t ge,
+                                int (&run)[PLAN_FIELDS], int32_t n_light, int32_t seq, int mode,
+                                int32_t workers, bool ok) {
+    int64_t c0, c1;
+    wave_range(gb, ge, c0, c1);
+    const int lane = lane_id();
+    for (int64_t r0 = c0; r0 < c1; r0 += 64 * PLAN_BATCH) {
+        int32_t kv[PLAN_BATCH], pv[PLAN_BATCH], cv[PLAN_BATCH];
+#pragma unroll
+        for (int j = 0; j < PLAN_BATCH; ++j) {
+            const int64_t g = r0 + j * 64 + lane;
+            const bool in = g < c1;
+            kv[j] = in ? sc.k[g] : 0;
+            pv[j] = (in && ok) ? st.pos[g] : 0;
+            cv[j] = (in && ok) ? st.cnt[g] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < PLAN_BATCH; ++j) {
+            const int64_t g = r0 + j * 64 + lane;
+            const int32_t kg = kv[j];
+            if (kg) sc.k[g] = 0;
+            int x[PLAN_FIELDS], ex[PLAN_FIELDS];
+            key_fields(kg, mode, x);
+#pragma unroll
+            for (int q = 0; q < PLAN_FIELDS; ++q) {
+                const int incl = wave_incl_add(x[q]);
+                ex[q] = run[q] + incl - x[q];
+                run[q] += __shfl(incl, 63, 64);
             }
-            __syncthreads();
+            if (ok && g < c1) {
+                sc.lpre[g] = ex[0];
+                if (kg > 0) plan_group(st, sc, g, kg, ex, pv[j], cv[j], n_light, seq, mode, workers);
+            }
         }
     }
 }
 
-__device__ __forceinline__ int next_pow2(int x) {
-    int p = 1;
-    while (p < x) p <<= 1;
-    return p;
+// Totals of the plan; thread 0 only.
+__device__ void plan_publish(const State &st, const Scratch &sc, const int (&tot)[PLAN_FIELDS],
+                             int32_t status, int mode, int32_t workers) {
+    const int32_t nl = mode == MODE_STATIC ? 0 : (tot[0] + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
+    PlanTotals t;
+    t.n_light_buckets = nl;
+    t.n_heavy = tot[1];
+    t.light_tuples = tot[0];
+    t.n_touched = tot[2];
+    t.status = status;
+    t.n_buckets = mode == MODE_STATIC ? workers : nl + tot[1];
+    t.tiles = 0;
+    t.sub_touched = tot[2];
+    *sc.tot = t;
+    if (!status) {
+        if (mode != MODE_STATIC) sc.bstart[nl] = (int32_t)st.G;
+        sc.lpre[st.G] = tot[0];
+        if (t.n_buckets > NB_MAX) atomicOr(sc.fault, FAULT_BUCKETS);
+    }
 }
 
-// Arrival-tile loader: item j of thread t is tuple base + 4*(j/4*256 + t) +
-// j%4, so every wave reads 1 KiB contiguous per vector load.
-__device__ __forceinline__ int64_t tile_index(int64_t base, int j) {
-    return base + 4 * ((int64_t)(j >> 2) * TILE_THREADS + threadIdx.x) + (j & 3);
-}
-
-__device__ __forceinline__ void load_tile(const int32_t *__restrict__ p, int64_t base,
-                                          int64_t n, bool vec, int32_t (&v)[ITEMS]) {
+// ----------------------------------------------------- k_hist_plan (small G)
+// Histogram blocks of HIST_THREADS threads over HIST_TILE consecutive tuples
+// each (every thread's keys loaded together), LDS counters indexed by key;
+// the block that finishes last plans the whole sub-batch (G <= PLAN_CHUNK).
+__global__ __launch_bounds__(HIST_THREADS) void k_hist_plan_small(
+    const int32_t *__restrict__ keys, int64_t n, bool vec, State st, Scratch sc, int32_t seq,
+    int mode, int32_t workers) {
+    extern __shared__ int32_t cntr[];
+    __shared__ int red[PLAN_FIELDS * (HIST_THREADS / 64)];
+    __shared__ int last;
+    const int tid = threadIdx.x;
+    const int G = (int)st.G;
+    phase_mark(sc, PHASE_HIST_PLAN, 0);
+    for (int g = tid; g < G; g += HIST_THREADS) cntr[g] = 0;
+    const int64_t base = (int64_t)blockIdx.x * HIST_TILE;
+    int32_t v[HIST_KPT];
 #pragma unroll
-    for (int q = 0; q < ITEMS / 4; ++q) {
-        const int64_t i0 = base + 4 * ((int64_t)q * TILE_THREADS + threadIdx.x);
-        if (vec && i0 + 3 < n) {
-            int4 x = *reinterpret_cast<const int4 *>(p + i0);
-            v[4 * q + 0] = x.x;
-            v[4 * q + 1] = x.y;
-            v[4 * q + 2] = x.z;
-            v[4 * q + 3] = x.w;
+    for (int j = 0; j < HIST_KPT / 4; ++j) {
+        const int64_t i = base + 4 * ((int64_t)j * HIST_THREADS + tid);
+        if (vec && i + 3 < n) {
+            const int4 x = *reinterpret_cast<const int4 *>(keys + i);
+            v[4 * j] = x.x; v[4 * j + 1] = x.y; v[4 * j + 2] = x.z; v[4 * j + 3] = x.w;
         } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[4 * q + e] = (i0 + e < n) ? p[i0 + e] : 0;
-        }
-    }
-}
-
-// Open-addressing LDS hash: slot holding `key` (inserted if absent).  Keys
-// are >= 0; empty slots hold -1.  At most TILE distinct keys per tile and
-// HASH_SLOTS >= 2*TILE, so a free slot is always found.
-__device__ __forceinline__ int hash_slot(int32_t *hk, int32_t key) {
-    uint32_t h = ((uint32_t)key * 2654435761u) >> (32 - HASH_LOG);
-    while (true) {
-        int32_t prev = atomicCAS(&hk[h], -1, key);
-        if (prev == -1 || prev == key) return (int)h;
-        h = (h + 1) & (HASH_SLOTS - 1);
-    }
-}
-
-// --------------------------------------------------------------- k_hist --
-// One arrival tile per workgroup: count keys in LDS (indexed directly, or
-// through the hash for large G), then one global atomic per distinct key.
-template <bool DIRECT>
-__global__ __launch_bounds__(TILE_THREADS) void k_hist(const int32_t *__restrict__ keys,
-                                                       int64_t n, int64_t G, bool vec,
-                                                       int32_t *__restrict__ k,
-                                                       int32_t *__restrict__ flag) {
-    extern __shared__ int32_t lds[];
-    const int tid = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * TILE;
-    int32_t kv[ITEMS];
-    load_tile(keys, base, n, vec, kv);
-    int32_t *hk = lds, *hc = lds + HASH_SLOTS;
-    if (DIRECT) {
-        for (int g = tid; g < (int)G; g += TILE_THREADS) lds[g] = 0;
-    } else {
-        for (int s = tid; s < HASH_SLOTS; s += TILE_THREADS) {
-            hk[s] = -1;
-            hc[s] = 0;
+            for (int e = 0; e < 4; ++e) v[4 * j + e] = (i + e < n) ? keys[i + e] : 0;
         }
     }
     __syncthreads();
     int bad = 0;
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        if (tile_index(base, j) >= n) continue;
-        const int32_t key = kv[j];
-        if (key < 0 || (int64_t)key >= G) {
-            bad = 1;
-            continue;
+    for (int j = 0; j < HIST_KPT / 4; ++j) {
+        const int64_t i = base + 4 * ((int64_t)j * HIST_THREADS + tid);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (i + e >= n) continue;
+            const int32_t key = v[4 * j + e];
+            if (key < 0 || key >= G) bad = 1;
+            else atomicAdd(&cntr[key], 1);
         }
-        if (DIRECT)
-            atomicAdd(&lds[key], 1);
-        else
-            atomicAdd(&hc[hash_slot(hk, key)], 1);
     }
     if (__syncthreads_or(bad)) {
-        if (tid == 0) atomicOr(flag, 1);
+        if (tid == 0) atomicExch(sc.bad, seq);
     }
-    if (DIRECT) {
-        for (int g = tid; g < (int)G; g += TILE_THREADS) {
-            const int32_t c = lds[g];
-            if (c) atomicAdd(&k[g], c);
-        }
-    } else {
-        for (int s = tid; s < HASH_SLOTS; s += TILE_THREADS) {
-            const int32_t key = hk[s];
-            if (key >= 0) atomicAdd(&k[key], hc[s]);
-        }
+    phase_mark(sc, PHASE_HIST_PLAN, 1);
+    for (int g = tid; g < G; g += HIST_THREADS) {
+        const int32_t c = cntr[g];
+        if (c) atomicAdd(&sc.k[g], c);
     }
+    __threadfence();
+    __syncthreads();
+    phase_mark(sc, PHASE_HIST_PLAN, 2);
+    if (tid == 0) last = atomicAdd(sc.done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    phase_mark(sc, PHASE_HIST_PLAN, 3);
+    // acquire: every block's counts (and bad-key mark) are visible below
+    __threadfence();
+    if (tid == 0) *sc.done = 0;
+
+    // ---- plan (this block only) ----
+    const int32_t status = load_coherent(sc.bad) == seq ? CQ_ERR_KEY_RANGE : 0;
+    int wtot[PLAN_FIELDS], off[PLAN_FIELDS], tot[PLAN_FIELDS];
+    plan_wave_totals(sc.k, 0, G, mode, wtot);
+    plan_block_offsets(wtot, off, tot, red);
+    phase_mark(sc, PHASE_HIST_PLAN, 4);
+    const int32_t nl = mode == MODE_STATIC ? 0 : (tot[0] + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
+    if (tid == 0) plan_publish(st, sc, tot, status, mode, workers);
+    plan_wave_write(st, sc, 0, G, off, nl, seq, mode, workers, status == 0);
+    __syncthreads();
+    phase_mark(sc, PHASE_HIST_PLAN, 5);
 }
 
-// --------------------------------------------------------------- k_plan --
-// Per group g with k_g tuples in this batch:
-//   light (0 < k_g < HEAVY_MIN) -> field 0 (tuples), packed into buckets;
-//   heavy (k_g >= HEAVY_MIN)    -> fields 1 (index), 2 (tuples), 4 (runs);
-//   touched (k_g > 0)           -> field 3 (output position).
-__device__ __forceinline__ void key_fields(int32_t kg, int32_t tiles, int (&f)[PLAN_FIELDS]) {
-    const bool heavy = kg >= HEAVY_MIN;
-    const bool light = kg > 0 && !heavy;
-    f[0] = light ? kg : 0;
-    f[1] = heavy ? 1 : 0;
-    f[2] = heavy ? kg : 0;
-    f[3] = kg > 0 ? 1 : 0;
-    f[4] = heavy ? min(tiles, kg) : 0;
-}
-
-// Sums of the fields over this thread's PLAN_KPT consecutive groups.
-__device__ void plan_thread_sums(const int32_t *__restrict__ k, int64_t g0, int64_t G,
-                                 int32_t tiles, int (&f)[PLAN_FIELDS]) {
-#pragma unroll
-    for (int i = 0; i < PLAN_FIELDS; ++i) f[i] = 0;
-    for (int i = 0; i < PLAN_KPT; ++i) {
-        const int64_t g = g0 + i;
-        if (g >= G) break;
-        int x[PLAN_FIELDS];
-        key_fields(k[g], tiles, x);
-#pragma unroll
-        for (int q = 0; q < PLAN_FIELDS; ++q) f[q] += x[q];
+// ------------------------------------------------ histogram (large G) --
+// HIST_HASH_TILE tuples per block; an LDS hash table aggregates equal keys,
+// then one global atomic per distinct key.
+__device__ __forceinline__ int hash_slot(int32_t *hk, int32_t key) {
+    uint32_t h = ((uint32_t)key * 2654435761u) >> (32 - HIST_HASH_LOG);
+    while (true) {
+        const int32_t prev = atomicCAS(&hk[h], -1, key);
+        if (prev == -1 || prev == key) return (int)h;
+        h = (h + 1) & (HIST_HASH_SLOTS - 1);
     }
 }
 
-// Write the per-group plan for this thread's groups, starting from the
-// exclusive running values `run`; zero the histogram for the next batch.
-__device__ void plan_thread_write(int32_t *__restrict__ k, int64_t g0, int64_t G,
-                                  int32_t tiles, int (&run)[PLAN_FIELDS],
-                                  int32_t light_total, const Scratch &sc) {
-    for (int i = 0; i < PLAN_KPT; ++i) {
-        const int64_t g = g0 + i;
-        if (g >= G) break;
-        const int32_t kg = k[g];
-        k[g] = 0;
-        int x[PLAN_FIELDS];
-        key_fields(kg, tiles, x);
-        sc.lpre[g] = run[0];
-        sc.hcum[g] = run[1];
-        if (kg > 0) sc.touched[run[3]] = (int32_t)g;
-        if (x[0]) {
-            sc.cursor[g] = run[0];
-            // Light buckets: bucket m starts at the group whose staged range
-            // [L, L + k_g) contains position m * LIGHT_BUDGET.
-            const int32_t L = run[0];
-            const int32_t m = (L + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
-            if ((int64_t)m * LIGHT_BUDGET <= (int64_t)L + kg - 1) sc.bkey[m] = (int32_t)g;
-        } else if (x[1]) {
-            const int32_t h = run[1];
-            sc.hkey[h] = (int32_t)g;
-            sc.hpre[h] = run[2];
-            sc.hdb[h] = run[4];
-            sc.hruns[h] = 0;
-            sc.cursor[g] = light_total + run[2];
-        }
-#pragma unroll
-        for (int q = 0; q < PLAN_FIELDS; ++q) run[q] += x[q];
+__global__ __launch_bounds__(HIST_THREADS) void k_hist_hash(const int32_t *__restrict__ keys,
+                                                            int64_t n, int64_t G, int32_t seq,
+                                                            Scratch sc) {
+    extern __shared__ int32_t lds[];
+    int32_t *hk = lds, *hc = lds + HIST_HASH_SLOTS;
+    const int tid = threadIdx.x;
+    for (int s = tid; s < HIST_HASH_SLOTS; s += HIST_THREADS) {
+        hk[s] = -1;
+        hc[s] = 0;
+    }
+    __syncthreads();
+    const int64_t b0 = (int64_t)blockIdx.x * HIST_HASH_TILE;
+    const int64_t b1 = min(n, b0 + HIST_HASH_TILE);
+    int bad = 0;
+    for (int64_t i = b0 + tid; i < b1; i += HIST_THREADS) {
+        const int32_t key = keys[i];
+        if (key < 0 || (int64_t)key >= G) bad = 1;
+        else atomicAdd(&hc[hash_slot(hk, key)], 1);
+    }
+    if (__syncthreads_or(bad)) {
+        if (tid == 0) atomicExch(sc.bad, seq);
+    }
+    for (int s = tid; s < HIST_HASH_SLOTS; s += HIST_THREADS) {
+        const int32_t key = hk[s];
+        if (key >= 0) atomicAdd(&sc.k[key], hc[s]);
     }
 }
 
-// Totals -> PlanTotals and sentinels; takes the bad-key flag of the batch.
-__device__ void plan_publish(int (&tot)[PLAN_FIELDS], int64_t G, int32_t tiles,
-                             const Scratch &sc) {
-    const int32_t nl = (tot[0] + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
-    PlanTotals t;
-    t.n_light_buckets = nl;
-    t.n_heavy = tot[1];
-    t.light_tuples = tot[0];
-    t.heavy_tuples = tot[2];
-    t.n_touched = tot[3];
-    t.n_desc = tot[4];
-    t.status = *sc.flag ? CQ_ERR_KEY_RANGE : 0;
-    t.tiles = tiles;
-    *sc.tot = t;
-    *sc.flag = 0;
-    sc.bkey[nl] = (int32_t)G;
-    sc.lpre[G] = tot[0];
-    sc.hcum[G] = tot[1];
-    sc.hpre[tot[1]] = tot[2];
-}
-
-// Whole plan in one workgroup (G <= PLAN_CHUNK).
-__global__ __launch_bounds__(PLAN_THREADS) void k_plan_single(int64_t G, int32_t tiles,
-                                                              Scratch sc) {
-    __shared__ int lds[PLAN_FIELDS * (PLAN_THREADS / 64)];
-    const int64_t g0 = (int64_t)threadIdx.x * PLAN_KPT;
-    int f[PLAN_FIELDS], tot[PLAN_FIELDS];
-    plan_thread_sums(sc.k, g0, G, tiles, f);
-    block_excl_scan<PLAN_FIELDS>(f, tot, lds);
-    if (threadIdx.x == 0) plan_publish(tot, G, tiles, sc);
-    plan_thread_write(sc.k, g0, G, tiles, f, tot[0], sc);
-}
-
-// Multi-block plan, phase 1: block sums.
-__global__ __launch_bounds__(PLAN_THREADS) void k_plan_reduce(int64_t G, int32_t tiles,
-                                                              Scratch sc) {
-    __shared__ int lds[PLAN_FIELDS * (PLAN_THREADS / 64)];
-    const int64_t g0 = (int64_t)blockIdx.x * PLAN_CHUNK + (int64_t)threadIdx.x * PLAN_KPT;
-    int f[PLAN_FIELDS], tot[PLAN_FIELDS];
-    plan_thread_sums(sc.k, g0, G, tiles, f);
-    block_excl_scan<PLAN_FIELDS>(f, tot, lds);
+// Plan over large G in three launches: block sums, a scan of the block
+// sums, and the per-group writes.
+__global__ __launch_bounds__(PLAN_THREADS) void k_plan_reduce(int64_t G, int mode, Scratch sc) {
+    __shared__ int red[PLAN_FIELDS * (PLAN_THREADS / 64)];
+    const int64_t gb = (int64_t)blockIdx.x * PLAN_CHUNK, ge = min(G, gb + PLAN_CHUNK);
+    int wtot[PLAN_FIELDS], off[PLAN_FIELDS], tot[PLAN_FIELDS];
+    plan_wave_totals(sc.k, gb, ge, mode, wtot);
+    plan_block_offsets(wtot, off, tot, red);
     if (threadIdx.x == 0)
         for (int q = 0; q < PLAN_FIELDS; ++q) sc.partials[blockIdx.x * PLAN_FIELDS + q] = tot[q];
 }
 
-// Phase 2 (one workgroup): exclusive scan of the block sums, totals.
-__global__ __launch_bounds__(PLAN_THREADS) void k_plan_scan(int32_t nblk, int64_t G,
-                                                            int32_t tiles, Scratch sc) {
-    __shared__ int lds[PLAN_FIELDS * (PLAN_THREADS / 64)];
+__global__ __launch_bounds__(PLAN_THREADS) void k_plan_scan(int32_t nblk, State st, Scratch sc,
+                                                            int32_t seq, int mode,
+                                                            int32_t workers) {
+    __shared__ int red[PLAN_FIELDS * (PLAN_THREADS / 64)];
     const int per = (nblk + PLAN_THREADS - 1) / PLAN_THREADS;
     const int b0 = min(nblk, (int)threadIdx.x * per), b1 = min(nblk, b0 + per);
-    int f[PLAN_FIELDS] = {0, 0, 0, 0, 0}, tot[PLAN_FIELDS];
+    int f[PLAN_FIELDS] = {0, 0, 0}, tot[PLAN_FIELDS];
     for (int b = b0; b < b1; ++b)
         for (int q = 0; q < PLAN_FIELDS; ++q) f[q] += sc.partials[b * PLAN_FIELDS + q];
-    block_excl_scan<PLAN_FIELDS>(f, tot, lds);
+    block_excl_scan<PLAN_FIELDS>(f, tot, red);
     for (int b = b0; b < b1; ++b)
         for (int q = 0; q < PLAN_FIELDS; ++q) {
             const int x = sc.partials[b * PLAN_FIELDS + q];
             sc.partials[b * PLAN_FIELDS + q] = f[q];
             f[q] += x;
         }
-    if (threadIdx.x == 0) plan_publish(tot, G, tiles, sc);
+    if (threadIdx.x == 0) {
+        const int32_t status = *sc.bad == seq ? CQ_ERR_KEY_RANGE : 0;
+        plan_publish(st, sc, tot, status, mode, workers);
+    }
 }
 
-// Phase 3: per-group outputs from the block offsets.
-__global__ __launch_bounds__(PLAN_THREADS) void k_plan_down(int64_t G, int32_t tiles,
-                                                            Scratch sc) {
-    __shared__ int lds[PLAN_FIELDS * (PLAN_THREADS / 64)];
-    const int64_t g0 = (int64_t)blockIdx.x * PLAN_CHUNK + (int64_t)threadIdx.x * PLAN_KPT;
-    int f[PLAN_FIELDS], tot[PLAN_FIELDS];
-    plan_thread_sums(sc.k, g0, G, tiles, f);
-    block_excl_scan<PLAN_FIELDS>(f, tot, lds);
+__global__ __launch_bounds__(PLAN_THREADS) void k_plan_down(State st, Scratch sc, int32_t seq,
+                                                            int mode, int32_t workers) {
+    __shared__ int red[PLAN_FIELDS * (PLAN_THREADS / 64)];
+    const int64_t G = st.G;
+    const int64_t gb = (int64_t)blockIdx.x * PLAN_CHUNK, ge = min(G, gb + PLAN_CHUNK);
+    int wtot[PLAN_FIELDS], off[PLAN_FIELDS], tot[PLAN_FIELDS];
+    plan_wave_totals(sc.k, gb, ge, mode, wtot);
+    plan_block_offsets(wtot, off, tot, red);
 #pragma unroll
-    for (int q = 0; q < PLAN_FIELDS; ++q) f[q] += sc.partials[blockIdx.x * PLAN_FIELDS + q];
-    plan_thread_write(sc.k, g0, G, tiles, f, sc.tot->light_tuples, sc);
+    for (int q = 0; q < PLAN_FIELDS; ++q) off[q] += sc.partials[blockIdx.x * PLAN_FIELDS + q];
+    const PlanTotals t = *sc.tot;
+    plan_wave_write(st, sc, gb, ge, off, t.n_light_buckets, seq, mode, workers, t.status == 0);
 }
 
-// ------------------------------------------------------------ k_scatter --
-// One arrival tile per workgroup.  Count the tile's tuples per group in LDS
-// (the returned old count is the tuple's place inside the tile's run), then
-// reserve each group's run with one global atomic on its cursor, and stage
-// (arrival index, value) pairs there.  Runs of heavy groups are recorded as
-// descriptors so the per-group phase can find the group's last tuples.
-template <bool DIRECT>
-__global__ __launch_bounds__(TILE_THREADS) void k_scatter(const int32_t *__restrict__ keys,
-                                                          const int32_t *__restrict__ values,
-                                                          int64_t n, int64_t G, bool vec,
-                                                          Scratch sc) {
-    if (sc.tot->status) return;
-    extern __shared__ int32_t lds[];
-    const int tid = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * TILE;
-    int32_t kv[ITEMS], vv[ITEMS], loc[ITEMS], slot[ITEMS];
-    load_tile(keys, base, n, vec, kv);
-    load_tile(values, base, n, vec, vv);
-    int32_t *hk = lds, *hc = lds + HASH_SLOTS;
-    if (DIRECT) {
-        for (int g = tid; g < (int)G; g += TILE_THREADS) lds[g] = 0;
-    } else {
-        for (int s = tid; s < HASH_SLOTS; s += TILE_THREADS) {
-            hk[s] = -1;
-            hc[s] = 0;
-        }
+// Whole-batch key check (used when a batch spans several sub-batches, so
+// that a bad key anywhere rejects the batch before any state changes).
+__global__ void k_validate(const int32_t *__restrict__ keys, int64_t n, int64_t G, int32_t seq,
+                           Scratch sc) {
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t key = keys[i];
+        if (key < 0 || (int64_t)key >= G) bad = 1;
     }
-    __syncthreads();
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicExch(sc.bad, seq);
+}
+
+// --------------------------------------------------------------- k_pass --
+// One arrival tile of PASS_TILE tuples per workgroup.  Wave w owns tuples
+// [w*1024, (w+1)*1024) of the tile, visited in 64-lane rounds; every tuple
+// learns its rank among the wave's earlier tuples of the same bucket from
+// ballots over the bucket id bits (lanes of one bucket find each other)
+// plus a per-wave counter.  Waves then combine into tile-wide bucket
+// offsets, the tile is reordered in LDS and written back contiguously, and
+// the tile's bucket starts are recorded.  Tiles never wait on each other.
+__global__ __launch_bounds__(PASS_THREADS) void k_pass(const int32_t *__restrict__ keys,
+                                                       const int32_t *__restrict__ values,
+                                                       int64_t n, Scratch sc) {
+    __shared__ uint16_t wc[PASS_WAVES][NB_MAX];
+    __shared__ int32_t ts[NB_MAX + 1];
+    __shared__ int2 stage[PASS_TILE];
+    __shared__ int red[PASS_WAVES];
+    const PlanTotals t = *sc.tot;
+    if (t.status) return;
+    const int NB = t.n_buckets;
+    if (NB > NB_MAX) return;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const int64_t base = (int64_t)blockIdx.x * PASS_TILE;
+    const int tile_n = (int)min((int64_t)PASS_TILE, n - base);
+    phase_mark(sc, PHASE_PASS, 0);
+    for (int i = tid; i < PASS_WAVES * NB; i += PASS_THREADS) wc[i / NB][i % NB] = 0;
+    int32_t key[PASS_ROUNDS], val[PASS_ROUNDS], bk[PASS_ROUNDS], lr[PASS_ROUNDS];
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        if (tile_index(base, j) >= n) continue;
-        if (DIRECT) {
-            slot[j] = kv[j];
-            loc[j] = atomicAdd(&lds[kv[j]], 1);
-        } else {
-            slot[j] = hash_slot(hk, kv[j]);
-            loc[j] = atomicAdd(&hc[slot[j]], 1);
-        }
+    for (int r = 0; r < PASS_ROUNDS; ++r) {
+        const int64_t i = base + wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane;
+        const bool valid = i < n;
+        key[r] = valid ? keys[i] : 0;
+        val[r] = valid ? values[i] : 0;
     }
-    __syncthreads();
-    const int nslots = DIRECT ? (int)G : HASH_SLOTS;
-    int32_t *cnt = DIRECT ? lds : hc;
-    for (int s = tid; s < nslots; s += TILE_THREADS) {
-        const int32_t c = cnt[s];
-        if (!c) continue;
-        const int32_t g = DIRECT ? s : hk[s];
-        const int32_t start = atomicAdd(&sc.cursor[g], c);
-        if (sc.lpre[g + 1] == sc.lpre[g]) {  // not light: heavy
-            const int32_t h = sc.hcum[g];
-            const int32_t d = atomicAdd(&sc.hruns[h], 1);
-            sc.desc[sc.hdb[h] + d] =
-                make_int2(start, (int32_t)(blockIdx.x << RUN_COUNT_BITS) | (c - 1));
-        }
-        cnt[s] = start;
-    }
-    __syncthreads();
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const int64_t i = tile_index(base, j);
-        if (i >= n) continue;
-        sc.sdat[cnt[slot[j]] + loc[j]] = make_int2((int32_t)i, vv[j]);
+    for (int r = 0; r < PASS_ROUNDS; ++r) {
+        const int64_t i = base + wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane;
+        bk[r] = (i < n) ? sc.bucket[key[r]] : NB;
+        lr[r] = 0;
     }
+    __syncthreads();
+    phase_mark(sc, PHASE_PASS, 1);
+#pragma unroll
+    for (int r = 0; r < PASS_ROUNDS; ++r) {
+        const int b = bk[r];
+        const bool valid = (unsigned)b < (unsigned)NB;
+        uint64_t m = ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < NB_BITS; ++bit) {
+            const bool on = (b >> bit) & 1;
+            const uint64_t bb = ballot(on);
+            m &= on ? bb : ~bb;
+        }
+        if (valid) {
+            const uint64_t below = m & lanemask_lt();
+            const int c = wc[wave][b];
+            lr[r] = c + __popcll(below);
+            if (below == 0) wc[wave][b] = (uint16_t)(c + __popcll(m));
+        }
+    }
+    __syncthreads();
+    phase_mark(sc, PHASE_PASS, 2);
+    // per bucket: tile count, and each wave's offset inside the bucket
+    for (int b = tid; b < NB; b += PASS_THREADS) {
+        int s = 0;
+#pragma unroll
+        for (int w = 0; w < PASS_WAVES; ++w) {
+            const int c = wc[w][b];
+            wc[w][b] = (uint16_t)s;
+            s += c;
+        }
+        ts[b] = s;
+    }
+    __syncthreads();
+    block_excl_scan_array(ts, NB, red);
+    phase_mark(sc, PHASE_PASS, 3);
+#pragma unroll
+    for (int r = 0; r < PASS_ROUNDS; ++r) {
+        const int b = bk[r];
+        if ((unsigned)b < (unsigned)NB) stage[ts[b] + wc[wave][b] + lr[r]] = make_int2(key[r], val[r]);
+    }
+    __syncthreads();
+    int2 *dst = sc.sdat + base;
+    for (int i = tid; i < tile_n; i += PASS_THREADS) dst[i] = stage[i];
+    int32_t *row = sc.rowstart + (int64_t)blockIdx.x * (NB + 1);
+    for (int b = tid; b <= NB; b += PASS_THREADS) row[b] = ts[b];
+    phase_mark(sc, PHASE_PASS, 4);
 }
 
 // ------------------------------------------------------------- k_update --
-// Shared memory carved per path (bytes).
-constexpr int SMEM_BYTES = 57408;
-// light path
-constexpr int L_SK = 0;                       // u64[LCAP] (group << 32 | arrival)
-constexpr int L_SV = L_SK + 8 * LCAP;         // i32[LCAP] values
-constexpr int L_SEG = L_SV + 4 * LCAP;        // u64[LCAP] (group+1 << 32 | first pos)
-constexpr int L_ACC = L_SEG + 8 * LCAP;       // i64[LCAP] per-group sum deltas
-static_assert(L_ACC + 8 * LCAP <= SMEM_BYTES, "light LDS");
-// heavy path
-constexpr int HCH = TILE;                      // elements staged per chunk
-constexpr int H_BUF = 0;                       // u64[HCH] (arrival << 32 | value)
-constexpr int H_DC = H_BUF + 8 * HCH;          // int2[DESC_CACHE]
-constexpr int H_LIST = H_DC + 8 * DESC_CACHE;  // int2[HCH] runs of the chunk
-constexpr int H_LOFF = H_LIST + 8 * HCH;       // i32[HCH + 1] run offsets
-static_assert(H_LOFF + 4 * (HCH + 1) + 16 <= SMEM_BYTES, "heavy LDS");
 
-__device__ __forceinline__ void finalize_group(const State &st, int32_t g, int64_t kg,
-                                               long long delta) {
-    const int64_t c = (int64_t)st.cnt[g] + kg;
-    st.cnt[g] = (int32_t)(c < st.W ? c : st.W);
-    st.pos[g] = (int32_t)(((uint32_t)st.pos[g] + (uint32_t)kg) % (uint32_t)st.W);
-    st.sum[g] += delta;
+__device__ __forceinline__ void emit_one(const Out &out, int32_t j, int32_t g, int64_t s,
+                                         int32_t c) {
+    if (out.ids) out.ids[j] = g;
+    if (out.sums) out.sums[j] = s;
+    if (out.counts) out.counts[j] = c;
+    if (out.avgs) out.avgs[j] = (double)s / (double)c;
 }
 
-// Light groups [a, b): their staged tuples are contiguous, [lpre[a],
-// lpre[b]), fewer than LCAP.  Sort each group's tuples by arrival index in
-// LDS, then every tuple among the group's last W goes to ring slot
-// (pos + rank) mod W, adding (new - old slot value) to the group's sum.
-__device__ int light_chunk(int32_t a, int32_t b, const State &st, const Scratch &sc,
-                           char *smem, unsigned long long *lds_w) {
-    const int tid = threadIdx.x;
-    const int32_t s0 = sc.lpre[a];
-    const int size = sc.lpre[b] - s0;
-    if (size <= 0) return 0;
-    if (size > LCAP) {  // impossible for a well-formed plan
-        if (threadIdx.x == 0) atomicOr(sc.fault, FAULT_LIGHT_SIZE);
-        return 0;
-    }
-    unsigned long long *sk = reinterpret_cast<unsigned long long *>(smem + L_SK);
-    int32_t *sv = reinterpret_cast<int32_t *>(smem + L_SV);
-    unsigned long long *seg = reinterpret_cast<unsigned long long *>(smem + L_SEG);
-    long long *acc = reinterpret_cast<long long *>(smem + L_ACC);
-    const int P2 = next_pow2(size);
-    for (int p = tid; p < size; p += blockDim.x) {
-        seg[p] = 0;
-        acc[p] = 0;
-    }
-    __syncthreads();
-    // mark where each light group's staged range starts ...
-    for (int32_t g = a + tid; g < b; g += blockDim.x) {
-        const int32_t l0 = sc.lpre[g], l1 = sc.lpre[g + 1];
-        if (l1 > l0)
-            seg[l0 - s0] = ((unsigned long long)(uint32_t)(g - a + 1) << 32) | (uint32_t)(l0 - s0);
-    }
-    __syncthreads();
-    // ... and spread the mark over the range
-    block_incl_max_scan_u64(seg, size, lds_w);
-    for (int p = tid; p < P2; p += blockDim.x) {
-        if (p < size) {
-            const int2 e = sc.sdat[s0 + p];
-            const uint32_t gl = (uint32_t)(seg[p] >> 32) - 1;
-            sk[p] = ((unsigned long long)gl << 32) | (uint32_t)e.x;
-            sv[p] = e.y;
-        } else {
-            sk[p] = ~0ull;
-        }
-    }
-    __syncthreads();
-    bitonic_sort<true>(sk, sv, P2);
-    const int32_t W = st.W;
-    for (int p = tid; p < size; p += blockDim.x) {
-        const int32_t g = a + (int32_t)(sk[p] >> 32);
-        const int p0 = (int)(uint32_t)seg[p];
-        const int32_t kg = sc.lpre[g + 1] - sc.lpre[g];
-        const int32_t r = p - p0;
-        const int32_t need = kg < W ? kg : W;
-        if (r >= kg - need) {
-            const uint32_t slot = ((uint32_t)st.pos[g] + (uint32_t)r) % (uint32_t)W;
-            int32_t *cell = st.ring + (int64_t)g * W + slot;
-            const int32_t old = *cell;
-            const int32_t v = sv[p];
-            *cell = v;
-            atomicAdd(reinterpret_cast<unsigned long long *>(&acc[p0]),
-                      (unsigned long long)((long long)v - (long long)old));
-        }
-    }
-    __syncthreads();
-    for (int p = tid; p < size; p += blockDim.x) {
-        const unsigned long long s = seg[p];
-        const int p0 = (int)(uint32_t)s;
-        if (p == p0) {
-            const int32_t g = a + (int32_t)(s >> 32) - 1;
-            finalize_group(st, g, sc.lpre[g + 1] - sc.lpre[g], acc[p]);
-        }
-    }
-    __syncthreads();
-    return size;
-}
-
-// Tuples of heavy item i staged in tiles >= tau.
-__device__ int heavy_tail_count(int32_t tau, int nd, bool cached, const int2 *dc,
-                                const int2 *D, int *lds_i) {
-    int s = 0;
-    for (int d = threadIdx.x; d < nd; d += blockDim.x) {
-        const int2 x = cached ? dc[d] : D[d];
-        if ((x.y >> RUN_COUNT_BITS) >= tau) s += (x.y & ((1 << RUN_COUNT_BITS) - 1)) + 1;
-    }
-    return block_sum_int(s, lds_i);
-}
-
-// Heavy group (k_g >= HEAVY_MIN): only its last min(k_g, W) tuples matter.
-// Walk its runs from the last arrival tile backwards in chunks of at most
-// one tile's worth of tuples, sort each chunk by arrival index, and write
-// the survivors.  Cost is bounded by the window plus one tile, whatever k_g.
-__device__ int heavy_item(int32_t i, const State &st, const Scratch &sc, int32_t tiles,
-                          char *smem, int *lds_i, long long *lds_ll) {
-    const int tid = threadIdx.x;
-    const int32_t h = sc.hkey[i];
-    const int32_t kh = sc.hpre[i + 1] - sc.hpre[i];
-    const int32_t W = st.W;
-    const int32_t need = kh < W ? kh : W;
-    const int nd = sc.hruns[i];
-    const int2 *D = sc.desc + sc.hdb[i];
-    unsigned long long *buf = reinterpret_cast<unsigned long long *>(smem + H_BUF);
-    int2 *dc = reinterpret_cast<int2 *>(smem + H_DC);
-    int2 *list = reinterpret_cast<int2 *>(smem + H_LIST);
-    int32_t *loff = reinterpret_cast<int32_t *>(smem + H_LOFF);
-    int32_t *nlist = loff + HCH + 1;
-    const bool cached = nd <= DESC_CACHE;
-    if (cached)
-        for (int d = tid; d < nd; d += blockDim.x) dc[d] = D[d];
-    __syncthreads();
-    const int32_t pos_h = st.pos[h];
-    long long acc = 0;
-    int done = 0;
-    int32_t hi = tiles, s_hi = 0;
-    for (int guard = 0; s_hi < need && hi > 0 && guard <= tiles; ++guard) {
-        // smallest tau with (tuples in tiles [tau, hi)) <= HCH
-        int32_t lo_t = 0, hi_t = hi - 1;
-        while (lo_t < hi_t) {
-            const int32_t mid = (lo_t + hi_t) >> 1;
-            if (heavy_tail_count(mid, nd, cached, dc, D, lds_i) - s_hi <= HCH)
-                hi_t = mid;
-            else
-                lo_t = mid + 1;
-        }
-        const int32_t tau = lo_t;
-        const int32_t s_tau = heavy_tail_count(tau, nd, cached, dc, D, lds_i);
-        const int C = s_tau - s_hi;
-        if (C <= 0 || C > HCH) {  // impossible for a well-formed plan
-            if (tid == 0) atomicOr(sc.fault, FAULT_HEAVY_CHUNK);
-            break;
-        }
-        // runs of the chunk
-        if (tid == 0) *nlist = 0;
-        __syncthreads();
-        for (int d = tid; d < nd; d += blockDim.x) {
-            const int2 x = cached ? dc[d] : D[d];
-            const int32_t t = x.y >> RUN_COUNT_BITS;
-            if (t >= tau && t < hi)
-                list[atomicAdd(nlist, 1)] = make_int2(x.x, (x.y & ((1 << RUN_COUNT_BITS) - 1)) + 1);
-        }
-        __syncthreads();
-        const int nl = *nlist;
-        {   // offsets of the runs inside the chunk
-            const int per = (nl + blockDim.x - 1) / blockDim.x;
-            const int b0 = min(nl, tid * per), b1 = min(nl, b0 + per);
-            int f[1] = {0}, t[1];
-            for (int r = b0; r < b1; ++r) f[0] += list[r].y;
-            block_excl_scan<1>(f, t, lds_i);
-            for (int r = b0; r < b1; ++r) {
-                loff[r] = f[0];
-                f[0] += list[r].y;
-            }
-            if (tid == 0) loff[nl] = t[0];
-        }
-        __syncthreads();
-        const int P2 = next_pow2(C);
-        for (int e = tid; e < P2; e += blockDim.x) {
-            if (e < C) {
-                int lo = 0, up = nl - 1;  // run r with loff[r] <= e < loff[r+1]
-                while (lo < up) {
-                    const int mid = (lo + up + 1) >> 1;
-                    if (loff[mid] <= e) lo = mid; else up = mid - 1;
-                }
-                const int2 x = sc.sdat[list[lo].x + (e - loff[lo])];
-                buf[e] = ((unsigned long long)(uint32_t)x.x << 32) | (uint32_t)x.y;
-            } else {
-                buf[e] = ~0ull;
-            }
-        }
-        __syncthreads();
-        bitonic_sort<false>(buf, nullptr, P2);
-        const int32_t rank0 = kh - s_tau;
-        for (int p = tid; p < C; p += blockDim.x) {
-            const int32_t rank = rank0 + p;
-            if (rank >= kh - need) {
-                const int32_t v = (int32_t)(uint32_t)buf[p];
-                const uint32_t slot = ((uint32_t)pos_h + (uint32_t)rank) % (uint32_t)W;
-                int32_t *cell = st.ring + (int64_t)h * W + slot;
-                const int32_t old = *cell;
-                *cell = v;
-                acc += (long long)v - (long long)old;
-            }
-        }
-        __syncthreads();
-        done += C;
-        s_hi = s_tau;
-        hi = tau;
-    }
-    const long long delta = block_sum_ll(acc, lds_ll);
-    if (tid == 0) finalize_group(st, h, kh, delta);
-    __syncthreads();
-    return done;
-}
-
-__device__ __forceinline__ void trace_begin(unsigned long long &t0) { t0 = wall_clock64(); }
-
-__device__ __forceinline__ void trace_end(int64_t *trace, unsigned long long t0,
-                                          int64_t tuples, int64_t items) {
+__device__ __forceinline__ void trace_record(int64_t *trace, unsigned long long t0,
+                                             int64_t tuples, int64_t items) {
     if (!trace || threadIdx.x != 0) return;
     const unsigned long long t1 = wall_clock64();
     const uint32_t hwid = __builtin_amdgcn_s_getreg((31 << 11) | (0 << 6) | 4);
@@ -708,87 +595,418 @@ __device__ __forceinline__ void trace_end(int64_t *trace, unsigned long long t0,
     r[5] = items;
 }
 
-// Balanced assignment: work items are the plan's light buckets followed by
-// the heavy groups; workgroups stride over them.
-__global__ __launch_bounds__(UPD_THREADS) void k_update_balanced(State st, Scratch sc,
-                                                                 int32_t tiles) {
-    __shared__ __align__(16) char smem[SMEM_BYTES];
-    __shared__ int lds_i[64];
-    __shared__ long long lds_ll[16];
-    __shared__ unsigned long long lds_w[16];
-    unsigned long long t0;
-    trace_begin(t0);
-    int64_t tuples = 0, items = 0;
-    if (!sc.tot->status) {
-        const int32_t nl = sc.tot->n_light_buckets;
-        const int32_t total = nl + sc.tot->n_heavy;
-        for (int32_t it = blockIdx.x; it < total; it += gridDim.x) {
-            if (it < nl)
-                tuples += light_chunk(sc.bkey[it], sc.bkey[it + 1], st, sc, smem, lds_w);
-            else
-                tuples += heavy_item(it - nl, st, sc, tiles, smem, lds_i, lds_ll);
-            ++items;
-        }
+// The runs of bucket b (one per tile, in tile order = arrival order): rs[t]
+// = first staged slot, rp[t] = tuples of the bucket in tiles before t,
+// rp[tiles] = bucket size.  Barriers inside.
+__device__ int bucket_runs(const Scratch &sc, int b, int NB, int tiles, int32_t *rs,
+                           int32_t *rp, int *red) {
+    for (int t = threadIdx.x; t < tiles; t += blockDim.x) {
+        const int32_t *row = sc.rowstart + (int64_t)t * (NB + 1);
+        const int32_t s = row[b], e = row[b + 1];
+        rs[t] = t * PASS_TILE + s;
+        rp[t] = e - s;
     }
-    trace_end(sc.trace, t0, tuples, items);
+    __syncthreads();
+    block_excl_scan_array(rp, tiles, red);
+    return rp[tiles];
 }
 
-// Static assignment: worker w owns groups [w*G/P, (w+1)*G/P) and handles all
-// of them itself -- light groups in LDS-sized pieces, then its heavy groups.
-__global__ __launch_bounds__(UPD_THREADS) void k_update_static(State st, Scratch sc,
-                                                               int32_t tiles, int32_t workers) {
-    __shared__ __align__(16) char smem[SMEM_BYTES];
-    __shared__ int lds_i[64];
-    __shared__ long long lds_ll[16];
-    __shared__ unsigned long long lds_w[16];
-    unsigned long long t0;
-    trace_begin(t0);
-    int64_t tuples = 0, items = 0;
-    if (!sc.tot->status) {
-        const int64_t G = st.G;
-        const int32_t g0 = (int32_t)(G * blockIdx.x / workers);
-        const int32_t g1 = (int32_t)(G * (blockIdx.x + 1) / workers);
-        int32_t a = g0;
-        while (a < g1) {
-            // largest b in (a, g1] whose light tuples [lpre[a], lpre[b]) fit
-            int32_t lo = a + 1, hi = g1;
-            const int32_t la = sc.lpre[a];
-            while (lo < hi) {
-                const int32_t mid = lo + (hi - lo + 1) / 2;
-                if (sc.lpre[mid] - la <= LCAP) lo = mid; else hi = mid - 1;
-            }
-            tuples += light_chunk(a, lo, st, sc, smem, lds_w);
-            ++items;
-            a = lo;
+// LDS layout of the balanced per-group phase (bytes).
+constexpr int U_RS = 0;                                  // i32[PASS_TILES_MAX]
+constexpr int U_RP = U_RS + 4 * PASS_TILES_MAX;          // i32[PASS_TILES_MAX + 1]
+constexpr int U_EK = U_RP + 4 * (PASS_TILES_MAX + 4);    // i32[LIGHT_CAP] keys
+constexpr int U_EV = U_EK + 4 * LIGHT_CAP;               // i32[LIGHT_CAP] values
+constexpr int U_PZ = U_EV + 4 * LIGHT_CAP;               // i32[LIGHT_CAP] group start in bucket
+constexpr int U_LR = U_PZ + 4 * LIGHT_CAP;               // i32[LIGHT_CAP] rank inside wave chunk
+constexpr int U_HD = U_LR + 4 * LIGHT_CAP;               // i32[LIGHT_CAP] group at its start
+constexpr int U_CW = U_HD + 4 * LIGHT_CAP;               // u16[UPD_WAVES][LIGHT_CAP]
+constexpr int UPD_WAVES = UPD_THREADS / 64;
+constexpr int U_ACC = U_CW + 2 * UPD_WAVES * LIGHT_CAP;  // i64[LIGHT_CAP] sum deltas
+constexpr int U_BYTES = U_ACC + 8 * LIGHT_CAP;
+
+// Light bucket b: groups [bstart[b], bstart[b+1]) packed by the plan, fewer
+// than LIGHT_CAP tuples, read in arrival order.  Each wave takes a
+// contiguous chunk; in every 64-lane round the lanes holding the same group
+// find each other with ballots over the group's start position, so a
+// tuple's rank among its group's earlier tuples is exact and stable.  Every
+// tuple among its group's last W goes to ring slot (pos + rank) mod W.
+__device__ int light_bucket(int b, int size, int tiles, const State &st, const Scratch &sc,
+                            const Out &out, char *smem) {
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+    const int32_t *rs = reinterpret_cast<const int32_t *>(smem + U_RS);
+    const int32_t *rp = reinterpret_cast<const int32_t *>(smem + U_RP);
+    int32_t *ek = reinterpret_cast<int32_t *>(smem + U_EK);
+    int32_t *ev = reinterpret_cast<int32_t *>(smem + U_EV);
+    int32_t *pz = reinterpret_cast<int32_t *>(smem + U_PZ);
+    int32_t *lr = reinterpret_cast<int32_t *>(smem + U_LR);
+    int32_t *hd = reinterpret_cast<int32_t *>(smem + U_HD);
+    uint16_t *cw = reinterpret_cast<uint16_t *>(smem + U_CW);
+    long long *acc = reinterpret_cast<long long *>(smem + U_ACC);
+    const int32_t a = sc.bstart[b];
+    const int32_t z = sc.bstart[b + 1];
+    const int32_t s0 = sc.lpre[a];
+    if (size <= 0) return 0;
+    if (size > LIGHT_CAP || sc.lpre[z] - s0 != size) {
+        if (tid == 0) atomicOr(sc.fault, FAULT_LIGHT_SIZE);
+        return 0;
+    }
+    for (int p = tid; p < size; p += blockDim.x) {
+        const int r = upper_run(rp, tiles, p);
+        const int2 e = sc.sdat[rs[r] + (p - rp[r])];
+        const int32_t g = e.x;
+        int32_t p0 = -1;
+        if (g >= a && g < z) {
+            const int32_t l0 = sc.lpre[g];
+            if (sc.lpre[g + 1] > l0) p0 = l0 - s0;
         }
-        for (int32_t i = sc.hcum[g0]; i < sc.hcum[g1]; ++i) {
-            tuples += heavy_item(i, st, sc, tiles, smem, lds_i, lds_ll);
-            ++items;
+        if (p0 < 0 || p0 >= size) {  // impossible for a well-formed plan
+            atomicOr(sc.fault, FAULT_LIGHT_SIZE);
+            p0 = -1;
+        }
+        ek[p] = g;
+        ev[p] = e.y;
+        pz[p] = p0;
+        hd[p] = -1;
+        acc[p] = 0;
+    }
+    for (int i = tid; i < UPD_WAVES * size; i += blockDim.x) cw[(i / size) * LIGHT_CAP + i % size] = 0;
+    __syncthreads();
+    phase_mark(sc, PHASE_UPDATE, 2);
+    // ranks inside each wave's chunk of the arrival order
+    const int chunk = (size + UPD_WAVES - 1) / UPD_WAVES;
+    const int c0 = min(size, wv * chunk), c1 = min(size, c0 + chunk);
+    uint16_t *mycw = cw + wv * LIGHT_CAP;
+    for (int r0 = c0; r0 < c1; r0 += 64) {
+        const int p = r0 + lane;
+        const bool valid = p < c1 && pz[p] >= 0;
+        const int p0 = valid ? pz[p] : 0;
+        uint64_t m = ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < LIGHT_BITS; ++bit) {
+            const bool on = (p0 >> bit) & 1;
+            const uint64_t bb = ballot(on);
+            m &= on ? bb : ~bb;
+        }
+        if (valid) {
+            const uint64_t below = m & lanemask_lt();
+            const int c = mycw[p0];
+            lr[p] = c + __popcll(below);
+            if (below == 0) mycw[p0] = (uint16_t)(c + __popcll(m));
         }
     }
-    trace_end(sc.trace, t0, tuples, items);
+    __syncthreads();
+    // each group's count per wave -> the wave's offset inside the group
+    for (int i = tid; i < size; i += blockDim.x) {
+        int sacc = 0;
+#pragma unroll
+        for (int w = 0; w < UPD_WAVES; ++w) {
+            const int c = cw[w * LIGHT_CAP + i];
+            cw[w * LIGHT_CAP + i] = (uint16_t)sacc;
+            sacc += c;
+        }
+    }
+    __syncthreads();
+    const int32_t W = st.W;
+    phase_mark(sc, PHASE_UPDATE, 3);
+    for (int p = tid; p < size; p += blockDim.x) {
+        const int p0 = pz[p];
+        if (p0 < 0) continue;
+        const int w = p / chunk;
+        const int32_t g = ek[p];
+        const int32_t rank = cw[w * LIGHT_CAP + p0] + lr[p];
+        const int32_t kg = sc.lpre[g + 1] - sc.lpre[g];
+        if (rank == 0) hd[p0] = g;
+        const int32_t need = kg < W ? kg : W;
+        if (rank >= kg - need && rank < kg) {
+            const uint32_t slot = ((uint32_t)sc.pold[g] + (uint32_t)rank) % (uint32_t)W;
+            int32_t *cell = st.ring + (int64_t)g * W + slot;
+            const int32_t old = kg >= W ? 0 : *cell;
+            const int32_t v = ev[p];
+            *cell = v;
+            atomicAdd(reinterpret_cast<unsigned long long *>(&acc[p0]),
+                      (unsigned long long)((long long)v - (long long)old));
+        }
+    }
+    __syncthreads();
+    phase_mark(sc, PHASE_UPDATE, 4);
+    for (int i = tid; i < size; i += blockDim.x) {
+        const int32_t g = hd[i];
+        if (g >= 0) {
+            const int64_t s = st.sum[g] + acc[i];
+            st.sum[g] = s;
+            if (out.n_touched) emit_one(out, sc.tidx[g], g, s, st.cnt[g]);
+        }
+    }
+    __syncthreads();
+    return size;
+}
+
+// Heavy bucket (one group, size >= HEAVY_MIN tuples): only its last
+// min(size, W) tuples survive; they are read straight from their runs.
+__device__ int heavy_bucket(int h, int size, int tiles, const State &st, const Scratch &sc,
+                            const Out &out, char *smem, long long *red_ll) {
+    const int tid = threadIdx.x;
+    const int32_t *rs = reinterpret_cast<const int32_t *>(smem + U_RS);
+    const int32_t *rp = reinterpret_cast<const int32_t *>(smem + U_RP);
+    const int32_t g = sc.hkey[h];
+    const int32_t W = st.W;
+    const int32_t need = size < W ? size : W;
+    const bool full = size >= W;
+    const uint32_t po = (uint32_t)sc.pold[g];
+    long long acc = 0;
+    for (int p = size - need + tid; p < size; p += blockDim.x) {
+        const int r = upper_run(rp, tiles, p);
+        const int32_t v = sc.sdat[rs[r] + (p - rp[r])].y;
+        const uint32_t slot = (po + (uint32_t)p) % (uint32_t)W;
+        int32_t *cell = st.ring + (int64_t)g * W + slot;
+        const int32_t old = full ? 0 : *cell;
+        *cell = v;
+        acc += (long long)v - (long long)old;
+    }
+    const long long delta = block_sum_ll(acc, red_ll);
+    if (tid == 0) {
+        const int64_t s = st.sum[g] + delta;
+        st.sum[g] = s;
+        if (out.n_touched) emit_one(out, sc.tidx[g], g, s, st.cnt[g]);
+    }
+    __syncthreads();
+    return need;
+}
+
+__global__ __launch_bounds__(UPD_THREADS) void k_update_balanced(State st, Scratch sc, int tiles,
+                                                                 Out out) {
+    __shared__ __align__(16) char smem[U_BYTES];
+    __shared__ int red[UPD_THREADS / 64];
+    __shared__ long long red_ll[UPD_THREADS / 64];
+    const unsigned long long t0 = wall_clock64();
+    const PlanTotals t = *sc.tot;
+    if (t.status) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && out.n_touched) *out.n_touched = t.status;
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && out.n_touched) *out.n_touched = t.n_touched;
+    int64_t tuples = 0, items = 0;
+    const int NB = t.n_buckets;
+    int32_t *rs = reinterpret_cast<int32_t *>(smem + U_RS);
+    int32_t *rp = reinterpret_cast<int32_t *>(smem + U_RP);
+    phase_mark(sc, PHASE_UPDATE, 0);
+    for (int b = blockIdx.x; b < NB; b += gridDim.x) {
+        const int size = bucket_runs(sc, b, NB, tiles, rs, rp, red);
+        if (b == (int)blockIdx.x) phase_mark(sc, PHASE_UPDATE, 1);
+        if (b < t.n_light_buckets)
+            tuples += light_bucket(b, size, tiles, st, sc, out, smem);
+        else
+            tuples += heavy_bucket(b - t.n_light_buckets, size, tiles, st, sc, out, smem, red_ll);
+        ++items;
+    }
+    phase_mark(sc, PHASE_UPDATE, 5);
+    trace_record(sc.trace, t0, tuples, items);
+}
+
+// Static assignment: worker w (one wave) owns groups [g0(w), g0(w+1)) and
+// streams all of their tuples in arrival order, 64 at a time; lanes holding
+// the same group find each other with ballots and a per-group counter gives
+// ranks.  A worker's time grows with the tuples of its groups.
+constexpr int S_RS = 0;                                                   // i32[4][T]
+constexpr int S_RP = S_RS + 4 * STATIC_WORKERS_PER_WG * PASS_TILES_MAX;   // i32[4][T+1]
+constexpr int S_CTR = S_RP + 4 * STATIC_WORKERS_PER_WG * (PASS_TILES_MAX + 1);
+constexpr int S_ACC = S_CTR + 4 * STATIC_WORKERS_PER_WG * STATIC_KEYS_MAX + 16;
+constexpr int S_BYTES = S_ACC + 8 * STATIC_WORKERS_PER_WG * STATIC_KEYS_MAX;
+
+__device__ __forceinline__ int32_t static_first(int64_t w, int64_t G, int32_t workers) {
+    return (int32_t)((w * G + workers - 1) / workers);
+}
+
+__global__ __launch_bounds__(UPD_THREADS) void k_update_static(State st, Scratch sc, int tiles,
+                                                               int32_t workers, Out out) {
+    __shared__ __align__(16) char smem[S_BYTES];
+    __shared__ long long tend[STATIC_WORKERS_PER_WG];
+    __shared__ long long tsum[STATIC_WORKERS_PER_WG];
+    const unsigned long long t0 = wall_clock64();
+    const PlanTotals t = *sc.tot;
+    if (t.status) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && out.n_touched) *out.n_touched = t.status;
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && out.n_touched) *out.n_touched = t.n_touched;
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    const int64_t w = (int64_t)blockIdx.x * STATIC_WORKERS_PER_WG + wv;
+    const int NB = t.n_buckets;
+    const int64_t G = st.G;
+    const int32_t W = st.W;
+    int32_t *rs = reinterpret_cast<int32_t *>(smem + S_RS) + wv * PASS_TILES_MAX;
+    int32_t *rp = reinterpret_cast<int32_t *>(smem + S_RP) + wv * (PASS_TILES_MAX + 1);
+    int32_t *ctr = reinterpret_cast<int32_t *>(smem + S_CTR) + wv * STATIC_KEYS_MAX;
+    long long *acc = reinterpret_cast<long long *>(smem + S_ACC) + wv * STATIC_KEYS_MAX;
+    int64_t tuples = 0;
+    if (w < workers && w < NB) {
+        const int32_t g0 = static_first(w, G, workers), g1 = static_first(w + 1, G, workers);
+        const int nk = g1 - g0;
+        if (nk > STATIC_KEYS_MAX) {
+            if (lane == 0) atomicOr(sc.fault, FAULT_STATIC_KEYS);
+        } else {
+            for (int i = lane; i < nk; i += 64) {
+                ctr[i] = 0;
+                acc[i] = 0;
+            }
+            // runs of bucket w, and a wave-wide exclusive scan of their sizes
+            int carry = 0;
+            for (int tb = 0; tb < tiles; tb += 64) {
+                const int tt = tb + lane;
+                int len = 0;
+                if (tt < tiles) {
+                    const int32_t *row = sc.rowstart + (int64_t)tt * (NB + 1);
+                    const int32_t s = row[w], e = row[w + 1];
+                    rs[tt] = tt * PASS_TILE + s;
+                    len = e - s;
+                }
+                const int incl = wave_incl_add(len);
+                if (tt < tiles) rp[tt] = carry + incl - len;
+                carry += __shfl(incl, 63, 64);
+            }
+            if (lane == 0) rp[tiles] = carry;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int size = carry;
+            tuples = size;
+            for (int c0 = 0; c0 < size; c0 += 64) {
+                const int p = c0 + lane;
+                bool valid = p < size;
+                int32_t g = g0, v = 0;
+                if (valid) {
+                    const int r = upper_run(rp, tiles, p);
+                    const int2 e = sc.sdat[rs[r] + (p - rp[r])];
+                    g = e.x;
+                    v = e.y;
+                }
+                int loc = g - g0;
+                if (valid && (loc < 0 || loc >= nk)) {  // impossible for a well-formed plan
+                    atomicOr(sc.fault, FAULT_STATIC_KEYS);
+                    loc = 0;
+                    valid = false;
+                }
+                int rank = 0;
+                uint64_t active = ballot(valid);
+                while (active) {
+                    const int leader = __ffsll((unsigned long long)active) - 1;
+                    const int kl = __shfl(loc, leader, 64);
+                    const bool mine = valid && loc == kl;
+                    const uint64_t m = ballot(mine);
+                    const int c = ctr[kl];
+                    if (mine) rank = c + __popcll(m & lanemask_lt());
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    if (lane == leader) ctr[kl] = c + __popcll(m);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    active &= ~m;
+                }
+                if (valid) {
+                    const int32_t kg = sc.lpre[g + 1] - sc.lpre[g];
+                    const int32_t need = kg < W ? kg : W;
+                    if (rank >= kg - need) {
+                        const uint32_t slot =
+                            ((uint32_t)sc.pold[g] + (uint32_t)rank) % (uint32_t)W;
+                        int32_t *cell = st.ring + (int64_t)g * W + slot;
+                        const int32_t old = kg >= W ? 0 : *cell;
+                        *cell = v;
+                        atomicAdd(reinterpret_cast<unsigned long long *>(&acc[loc]),
+                                  (unsigned long long)((long long)v - (long long)old));
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int i = lane; i < nk; i += 64) {
+                const int32_t g = g0 + i;
+                if (sc.lpre[g + 1] - sc.lpre[g] > 0) {
+                    const int64_t s = st.sum[g] + acc[i];
+                    st.sum[g] = s;
+                    if (out.n_touched) emit_one(out, sc.tidx[g], g, s, st.cnt[g]);
+                }
+            }
+        }
+    }
+    // one record per workgroup: its last worker's end and all its tuples
+    if (lane == 0) {
+        tend[wv] = (long long)wall_clock64();
+        tsum[wv] = tuples;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && sc.trace) {
+        long long e = 0, s = 0;
+        for (int i = 0; i < STATIC_WORKERS_PER_WG; ++i) {
+            e = tend[i] > e ? tend[i] : e;
+            s += tsum[i];
+        }
+        const uint32_t hwid = __builtin_amdgcn_s_getreg((31 << 11) | (0 << 6) | 4);
+        const uint32_t xcc = __builtin_amdgcn_s_getreg((15 << 11) | (0 << 6) | 20);
+        int64_t *r = sc.trace + 6 * (int64_t)blockIdx.x;
+        r[0] = hwid;
+        r[1] = xcc;
+        r[2] = (int64_t)t0;
+        r[3] = e;
+        r[4] = s;
+        r[5] = STATIC_WORKERS_PER_WG;
+    }
+}
+
+// ---------------------------------------------- touched list (multi-sub) --
+__global__ __launch_bounds__(PLAN_THREADS) void k_touch_reduce(int64_t G, int32_t seq,
+                                                               Scratch sc) {
+    __shared__ int red[PLAN_THREADS / 64];
+    const int64_t g0 = (int64_t)blockIdx.x * PLAN_CHUNK + (int64_t)threadIdx.x * PLAN_KPT;
+    int f[1] = {0}, t[1];
+    for (int i = 0; i < PLAN_KPT; ++i)
+        if (g0 + i < G && sc.stamp[g0 + i] == seq) ++f[0];
+    block_excl_scan<1>(f, t, red);
+    if (threadIdx.x == 0) sc.partials[blockIdx.x] = t[0];
+}
+
+__global__ __launch_bounds__(PLAN_THREADS) void k_touch_scan(int32_t nblk, Scratch sc) {
+    __shared__ int red[PLAN_THREADS / 64];
+    const int per = (nblk + PLAN_THREADS - 1) / PLAN_THREADS;
+    const int b0 = min(nblk, (int)threadIdx.x * per), b1 = min(nblk, b0 + per);
+    int f[1] = {0}, t[1];
+    for (int b = b0; b < b1; ++b) f[0] += sc.partials[b];
+    block_excl_scan<1>(f, t, red);
+    for (int b = b0; b < b1; ++b) {
+        const int x = sc.partials[b];
+        sc.partials[b] = f[0];
+        f[0] += x;
+    }
+    if (threadIdx.x == 0) sc.tot->n_touched = t[0];
+}
+
+__global__ __launch_bounds__(PLAN_THREADS) void k_touch_write(int64_t G, int32_t seq,
+                                                              Scratch sc) {
+    __shared__ int red[PLAN_THREADS / 64];
+    const int64_t g0 = (int64_t)blockIdx.x * PLAN_CHUNK + (int64_t)threadIdx.x * PLAN_KPT;
+    int f[1] = {0}, t[1];
+    for (int i = 0; i < PLAN_KPT; ++i)
+        if (g0 + i < G && sc.stamp[g0 + i] == seq) ++f[0];
+    block_excl_scan<1>(f, t, red);
+    int j = f[0] + sc.partials[blockIdx.x];
+    for (int i = 0; i < PLAN_KPT; ++i)
+        if (g0 + i < G && sc.stamp[g0 + i] == seq) sc.touched[j++] = (int32_t)(g0 + i);
 }
 
 // --------------------------------------------------------------- k_emit --
-__global__ __launch_bounds__(EMIT_THREADS) void k_emit(State st, Scratch sc, int32_t *ids,
-                                                       int64_t *sums, int32_t *counts,
-                                                       double *avgs, int64_t *n_touched) {
+// Results of the most recent batch from the state, in touched-list order.
+__global__ __launch_bounds__(EMIT_THREADS) void k_emit(State st, Scratch sc, Out out) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t status = sc.tot->status;
     if (status) {
-        if (gid == 0) *n_touched = status;
+        if (gid == 0) *out.n_touched = status;
         return;
     }
     const int32_t nt = sc.tot->n_touched;
-    if (gid == 0) *n_touched = nt;
+    if (gid == 0) *out.n_touched = nt;
     for (int64_t j = gid; j < nt; j += (int64_t)gridDim.x * blockDim.x) {
         const int32_t g = sc.touched[j];
-        const int64_t s = st.sum[g];
-        const int32_t c = st.cnt[g];
-        if (ids) ids[j] = g;
-        if (sums) sums[j] = s;
-        if (counts) counts[j] = c;
-        if (avgs) avgs[j] = (double)s / (double)c;
+        emit_one(out, (int32_t)j, g, st.sum[g], st.cnt[g]);
     }
 }
 
@@ -801,74 +1019,82 @@ __global__ void k_reset_totals(Scratch sc) {
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
-hipError_t launch_hist(const int32_t *keys, int64_t n, int64_t G, Scratch sc, hipStream_t s) {
-    const int64_t tiles = (n + TILE - 1) / TILE;
-    const bool direct = G <= DIRECT_MAX_G;
-    const size_t lds = direct ? (size_t)G * 4 : (size_t)2 * HASH_SLOTS * 4;
-    if (direct)
-        hipLaunchKernelGGL(k_hist<true>, dim3((unsigned)tiles), dim3(TILE_THREADS), lds, s, keys,
-                           n, G, aligned16(keys), sc.k, sc.flag);
-    else
-        hipLaunchKernelGGL(k_hist<false>, dim3((unsigned)tiles), dim3(TILE_THREADS), lds, s, keys,
-                           n, G, aligned16(keys), sc.k, sc.flag);
+int64_t hist_blocks(int64_t n, int64_t G) {
+    (void)G;
+    return std::max<int64_t>(1, (n + HIST_TILE - 1) / HIST_TILE);
+}
+
+hipError_t launch_validate(const int32_t *keys, int64_t n, int64_t G, int32_t seq, Scratch sc,
+                           hipStream_t s) {
+    int64_t grid = (n + 4095) / 4096;
+    grid = std::max<int64_t>(1, std::min<int64_t>(grid, 2048));
+    hipLaunchKernelGGL(k_validate, dim3((unsigned)grid), dim3(256), 0, s, keys, n, G, seq, sc);
     return hipGetLastError();
 }
 
-hipError_t launch_plan(int64_t G, int32_t tiles, Scratch sc, hipStream_t s) {
-    const int64_t nblk = (G + PLAN_CHUNK - 1) / PLAN_CHUNK;
-    if (nblk == 1) {
-        hipLaunchKernelGGL(k_plan_single, dim3(1), dim3(PLAN_THREADS), 0, s, G, tiles, sc);
-    } else {
-        hipLaunchKernelGGL(k_plan_reduce, dim3((unsigned)nblk), dim3(PLAN_THREADS), 0, s, G,
-                           tiles, sc);
-        hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(PLAN_THREADS), 0, s, (int32_t)nblk, G,
-                           tiles, sc);
-        hipLaunchKernelGGL(k_plan_down, dim3((unsigned)nblk), dim3(PLAN_THREADS), 0, s, G,
-                           tiles, sc);
+hipError_t launch_hist_plan(const int32_t *keys, int64_t n, State st, Scratch sc, int32_t seq,
+                            int mode, int32_t workers, hipStream_t s) {
+    const int64_t G = st.G;
+    if (G <= PLAN_CHUNK && G <= HIST_DIRECT_MAX_G) {
+        const int64_t grid = hist_blocks(n, G);
+        hipLaunchKernelGGL(k_hist_plan_small, dim3((unsigned)grid), dim3(HIST_THREADS),
+                           (size_t)G * 4, s, keys, n, aligned16(keys), st, sc, seq, mode,
+                           workers);
+        return hipGetLastError();
     }
+    const int64_t tiles = std::max<int64_t>((n + HIST_HASH_TILE - 1) / HIST_HASH_TILE, 1);
+    hipLaunchKernelGGL(k_hist_hash, dim3((unsigned)tiles), dim3(HIST_THREADS),
+                       (size_t)2 * HIST_HASH_SLOTS * 4, s, keys, n, G, seq, sc);
+    const int64_t nblk = (G + PLAN_CHUNK - 1) / PLAN_CHUNK;
+    hipLaunchKernelGGL(k_plan_reduce, dim3((unsigned)nblk), dim3(PLAN_THREADS), 0, s, G, mode,
+                       sc);
+    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(PLAN_THREADS), 0, s, (int32_t)nblk, st, sc, seq,
+                       mode, workers);
+    hipLaunchKernelGGL(k_plan_down, dim3((unsigned)nblk), dim3(PLAN_THREADS), 0, s, st, sc, seq,
+                       mode, workers);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const int32_t *keys, const int32_t *values, int64_t n, int64_t G,
-                          Scratch sc, hipStream_t s) {
-    const int64_t tiles = (n + TILE - 1) / TILE;
-    const bool direct = G <= DIRECT_MAX_G;
-    const bool vec = aligned16(keys) && aligned16(values);
-    const size_t lds = direct ? (size_t)G * 4 : (size_t)2 * HASH_SLOTS * 4;
-    if (direct)
-        hipLaunchKernelGGL(k_scatter<true>, dim3((unsigned)tiles), dim3(TILE_THREADS), lds, s,
-                           keys, values, n, G, vec, sc);
-    else
-        hipLaunchKernelGGL(k_scatter<false>, dim3((unsigned)tiles), dim3(TILE_THREADS), lds, s,
-                           keys, values, n, G, vec, sc);
+hipError_t launch_pass(const int32_t *keys, const int32_t *values, int64_t n, Scratch sc,
+                       hipStream_t s) {
+    const int64_t tiles = (n + PASS_TILE - 1) / PASS_TILE;
+    hipLaunchKernelGGL(k_pass, dim3((unsigned)tiles), dim3(PASS_THREADS), 0, s, keys, values, n,
+                       sc);
     return hipGetLastError();
 }
 
 int64_t update_grid(int64_t n, int mode, int32_t workers) {
-    if (mode == CQ_PARTITION_STATIC) return workers;
-    const int64_t items = (n + LIGHT_BUDGET - 1) / LIGHT_BUDGET + n / HEAVY_MIN + 1;
-    return items < UPD_MAX_GRID ? items : UPD_MAX_GRID;
+    if (mode == MODE_STATIC) return (workers + STATIC_WORKERS_PER_WG - 1) / STATIC_WORKERS_PER_WG;
+    const int64_t nb = (n + LIGHT_BUDGET - 1) / LIGHT_BUDGET + n / HEAVY_MIN + 1;
+    return std::max<int64_t>(1, std::min<int64_t>(nb, NB_MAX));
 }
 
-hipError_t launch_update(State st, Scratch sc, int64_t n, int32_t tiles, int mode,
-                         int32_t workers, hipStream_t s) {
+hipError_t launch_update(State st, Scratch sc, int64_t n, int mode, int32_t workers, Out out,
+                         hipStream_t s) {
+    const int tiles = (int)((n + PASS_TILE - 1) / PASS_TILE);
     const int64_t grid = update_grid(n, mode, workers);
-    if (mode == CQ_PARTITION_STATIC)
+    if (mode == MODE_STATIC)
         hipLaunchKernelGGL(k_update_static, dim3((unsigned)grid), dim3(UPD_THREADS), 0, s, st, sc,
-                           tiles, workers);
+                           tiles, workers, out);
     else
         hipLaunchKernelGGL(k_update_balanced, dim3((unsigned)grid), dim3(UPD_THREADS), 0, s, st,
-                           sc, tiles);
+                           sc, tiles, out);
     return hipGetLastError();
 }
 
-hipError_t launch_emit(State st, Scratch sc, int64_t cap, int32_t *ids, int64_t *sums,
-                       int32_t *counts, double *avgs, int64_t *n_touched, hipStream_t s) {
+hipError_t launch_collect_touched(int64_t G, int32_t seq, Scratch sc, hipStream_t s) {
+    const int64_t nblk = (G + PLAN_CHUNK - 1) / PLAN_CHUNK;
+    hipLaunchKernelGGL(k_touch_reduce, dim3((unsigned)nblk), dim3(PLAN_THREADS), 0, s, G, seq,
+                       sc);
+    hipLaunchKernelGGL(k_touch_scan, dim3(1), dim3(PLAN_THREADS), 0, s, (int32_t)nblk, sc);
+    hipLaunchKernelGGL(k_touch_write, dim3((unsigned)nblk), dim3(PLAN_THREADS), 0, s, G, seq, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(State st, Scratch sc, int64_t cap, Out out, hipStream_t s) {
     int64_t grid = (cap + EMIT_THREADS - 1) / EMIT_THREADS;
-    if (grid < 1) grid = 1;
-    if (grid > 1024) grid = 1024;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)grid), dim3(EMIT_THREADS), 0, s, st, sc, ids, sums,
-                       counts, avgs, n_touched);
+    grid = std::max<int64_t>(1, std::min<int64_t>(grid, 1024));
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)grid), dim3(EMIT_THREADS), 0, s, st, sc, out);
     return hipGetLastError();
 }
 

@@ -25,17 +25,16 @@ struct cq_query {
     uint32_t aggregates = 0;
     State st{};
     Scratch sc{};
-    int mode = CQ_PARTITION_BALANCED;
+    int mode = MODE_BALANCED;
     int32_t workers = 1024;
-    int64_t cap_n = 0;          // batch capacity of the per-batch scratch
+    int32_t seq = 0;            // batch sequence number (device-side epochs)
     int64_t last_n = 0;         // size of the most recent batch
-    int32_t last_tiles = 0;
-    int last_mode = CQ_PARTITION_BALANCED;
-    int32_t last_workers = 0;
+    int last_mode = MODE_BALANCED;
+    int32_t last_workers = 1024;
     hipStream_t last_stream = nullptr;
     bool pushed = false;
     int32_t telemetry = 0;
-    int64_t trace_cap = 0;      // records the trace buffer holds
+    int64_t trace_cap = 0;
     std::vector<TimedLaunch> live;
     std::vector<hipEvent_t> spare;
     double ms[CQ_KERNEL_KINDS] = {0};
@@ -82,33 +81,29 @@ struct DeviceGuard {
     }
 };
 
-void free_batch_scratch(cq_query *q) {
-    dfree(q->sc.hkey);
-    dfree(q->sc.hpre);
-    dfree(q->sc.hdb);
-    dfree(q->sc.hruns);
-    dfree(q->sc.desc);
-    dfree(q->sc.bkey);
-    dfree(q->sc.sdat);
-    q->cap_n = 0;
-}
-
 void free_all(cq_query *q) {
-    free_batch_scratch(q);
     dfree(q->st.ring);
     dfree(q->st.pos);
     dfree(q->st.cnt);
     dfree(q->st.sum);
     dfree(q->sc.k);
     dfree(q->sc.lpre);
-    dfree(q->sc.hcum);
-    dfree(q->sc.cursor);
+    dfree(q->sc.bucket);
+    dfree(q->sc.pold);
+    dfree(q->sc.tidx);
+    dfree(q->sc.stamp);
     dfree(q->sc.touched);
+    dfree(q->sc.bstart);
+    dfree(q->sc.hkey);
+    dfree(q->sc.sdat);
+    dfree(q->sc.rowstart);
     dfree(q->sc.partials);
-    dfree(q->sc.flag);
+    dfree(q->sc.bad);
+    dfree(q->sc.done);
     dfree(q->sc.fault);
     dfree(q->sc.tot);
     dfree(q->sc.trace);
+    dfree(q->sc.phase);
     for (auto &t : q->live) {
         (void)hipEventDestroy(t.start);
         (void)hipEventDestroy(t.stop);
@@ -116,43 +111,6 @@ void free_all(cq_query *q) {
     for (auto e : q->spare) (void)hipEventDestroy(e);
     q->live.clear();
     q->spare.clear();
-}
-
-int64_t tiles_of(int64_t n) { return (n + TILE - 1) / TILE; }
-
-// Per-batch scratch for batches of up to n tuples.
-int alloc_batch_scratch(cq_query *q, int64_t n) {
-    const int64_t T = tiles_of(n);
-    const int64_t nh = n / HEAVY_MIN + 1;
-    const int64_t nl = (n + LIGHT_BUDGET - 1) / LIGHT_BUDGET + 1;
-    const int64_t ndesc = std::min(n, nh * T) + 1;
-    int rc = CQ_OK;
-    if (rc == CQ_OK) rc = dalloc(&q->sc.hkey, nh);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.hpre, nh + 1);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.hdb, nh);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.hruns, nh);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.desc, ndesc);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.bkey, nl + 1);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.sdat, n);
-    if (rc != CQ_OK) {
-        free_batch_scratch(q);
-        return rc;
-    }
-    q->cap_n = n;
-    return CQ_OK;
-}
-
-int ensure_capacity(cq_query *q, int64_t n) {
-    if (n <= q->cap_n) return CQ_OK;
-    // The old scratch may still be read by enqueued work.
-    if (q->pushed) {
-        hipError_t e = hipDeviceSynchronize();
-        if (e != hipSuccess) return from_hip(e);
-    }
-    free_batch_scratch(q);
-    // round up to whole tiles so that small growth steps do not reallocate
-    const int64_t want = std::max<int64_t>(tiles_of(n) * TILE, 1);
-    return alloc_batch_scratch(q, want);
 }
 
 int ensure_trace(cq_query *q, int64_t records) {
@@ -178,7 +136,7 @@ hipEvent_t take_event(cq_query *q) {
     return e;
 }
 
-// Launch one kernel step, bracketed by events when kernel timing is on.
+// Launch one step, bracketed by events when kernel timing is on.
 template <typename F>
 int timed(cq_query *q, int kind, hipStream_t s, F &&launch) {
     hipEvent_t a = nullptr, b = nullptr;
@@ -196,6 +154,76 @@ int timed(cq_query *q, int kind, hipStream_t s, F &&launch) {
         if (b) q->spare.push_back(b);
     }
     return from_hip(e);
+}
+
+bool static_ok(int64_t G, int32_t workers) {
+    if (workers < 1 || workers > NB_MAX - 2) return false;
+    return (G + workers - 1) / workers <= STATIC_KEYS_MAX;
+}
+
+// The whole per-batch sequence; `out` non-null means emit into it.
+int push(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n, hipStream_t s,
+         const Out *out) {
+    if (q->mode == MODE_STATIC && !static_ok(q->st.G, q->workers)) return CQ_ERR_INVALID;
+    const int64_t nsub = (n + SUB - 1) / SUB;
+    const int64_t upd_grid = update_grid(std::min<int64_t>(std::max<int64_t>(n, 1), SUB), q->mode,
+                                         q->workers);
+    int rc = CQ_OK;
+    if (q->telemetry & CQ_TELEMETRY_WORKERS) {
+        rc = ensure_trace(q, upd_grid);
+        if (rc != CQ_OK) return rc;
+    }
+    if ((q->telemetry & CQ_TELEMETRY_PHASES) && !q->sc.phase) {
+        rc = dalloc(&q->sc.phase, (int64_t)PHASE_KINDS * PHASE_BLOCKS * PHASE_SLOTS);
+        if (rc != CQ_OK) return rc;
+        (void)hipMemset(q->sc.phase, 0,
+                        sizeof(int64_t) * (size_t)PHASE_KINDS * PHASE_BLOCKS * PHASE_SLOTS);
+    }
+    Scratch sc = q->sc;
+    if (!(q->telemetry & CQ_TELEMETRY_WORKERS)) sc.trace = nullptr;
+    if (!(q->telemetry & CQ_TELEMETRY_PHASES)) sc.phase = nullptr;
+    q->last_stream = s;
+    q->pushed = true;
+    q->last_n = n;
+    q->last_mode = q->mode;
+    q->last_workers = q->workers;
+    const int32_t seq = ++q->seq;
+    if (n == 0) {
+        rc = from_hip(launch_reset_totals(sc, s));
+        if (rc == CQ_OK && out)
+            rc = timed(q, CQ_KERNEL_EMIT, s, [&] { return launch_emit(q->st, sc, 1, *out, s); });
+        return rc;
+    }
+    const int64_t G = q->st.G;
+    if (nsub > 1)
+        rc = timed(q, CQ_KERNEL_OTHER, s,
+                   [&] { return launch_validate(keys, n, G, seq, sc, s); });
+    const Out none = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    for (int64_t b = 0; b < nsub && rc == CQ_OK; ++b) {
+        const int64_t off = b * SUB;
+        const int64_t m = std::min<int64_t>(SUB, n - off);
+        const Out o = (out && nsub == 1) ? *out : none;
+        rc = timed(q, CQ_KERNEL_HIST_PLAN, s, [&] {
+            return launch_hist_plan(keys + off, m, q->st, sc, seq, q->mode, q->workers, s);
+        });
+        if (rc == CQ_OK)
+            rc = timed(q, CQ_KERNEL_PASS, s,
+                       [&] { return launch_pass(keys + off, values + off, m, sc, s); });
+        if (rc == CQ_OK)
+            rc = timed(q, CQ_KERNEL_UPDATE, s, [&] {
+                return launch_update(q->st, sc, m, q->mode, q->workers, o, s);
+            });
+    }
+    if (rc == CQ_OK && nsub > 1) {
+        rc = timed(q, CQ_KERNEL_OTHER, s,
+                   [&] { return launch_collect_touched(G, seq, sc, s); });
+        if (rc == CQ_OK && out) {
+            const int64_t cap = std::min<int64_t>(G, n);
+            rc = timed(q, CQ_KERNEL_EMIT, s,
+                       [&] { return launch_emit(q->st, sc, cap, *out, s); });
+        }
+    }
+    return rc;
 }
 
 }  // namespace
@@ -237,11 +265,18 @@ int cq_create(int64_t groups, int32_t window, uint32_t aggregates, cq_query **ou
     if (rc == CQ_OK) rc = dalloc(&q->st.sum, G);
     if (rc == CQ_OK) rc = dalloc(&q->sc.k, G);
     if (rc == CQ_OK) rc = dalloc(&q->sc.lpre, G + 1);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.hcum, G + 1);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.cursor, G);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.bucket, G);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.pold, G);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.tidx, G);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.stamp, G);
     if (rc == CQ_OK) rc = dalloc(&q->sc.touched, G);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.bstart, NB_MAX + 1);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.hkey, NB_MAX);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.sdat, SUB);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.rowstart, (int64_t)PASS_TILES_MAX * (NB_MAX + 1));
     if (rc == CQ_OK) rc = dalloc(&q->sc.partials, nblk * PLAN_FIELDS);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.flag, 1);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.bad, 1);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.done, 1);
     if (rc == CQ_OK) rc = dalloc(&q->sc.fault, 1);
     if (rc == CQ_OK) rc = dalloc(&q->sc.tot, 1);
     hipError_t e = hipSuccess;
@@ -253,7 +288,11 @@ int cq_create(int64_t groups, int32_t window, uint32_t aggregates, cq_query **ou
         if (e == hipSuccess) e = hipMemset(q->st.cnt, 0, sizeof(int32_t) * (size_t)G);
         if (e == hipSuccess) e = hipMemset(q->st.sum, 0, sizeof(int64_t) * (size_t)G);
         if (e == hipSuccess) e = hipMemset(q->sc.k, 0, sizeof(int32_t) * (size_t)G);
-        if (e == hipSuccess) e = hipMemset(q->sc.flag, 0, sizeof(int32_t));
+        if (e == hipSuccess) e = hipMemset(q->sc.stamp, 0, sizeof(int32_t) * (size_t)G);
+        if (e == hipSuccess) e = hipMemset(q->sc.bucket, 0, sizeof(int32_t) * (size_t)G);
+        if (e == hipSuccess) e = hipMemset(q->sc.lpre, 0, sizeof(int32_t) * (size_t)(G + 1));
+        if (e == hipSuccess) e = hipMemset(q->sc.bad, 0, sizeof(int32_t));
+        if (e == hipSuccess) e = hipMemset(q->sc.done, 0, sizeof(uint32_t));
         if (e == hipSuccess) e = hipMemset(q->sc.fault, 0, sizeof(int32_t));
         if (e == hipSuccess) e = hipMemset(q->sc.tot, 0, sizeof(PlanTotals));
         if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -269,17 +308,20 @@ int cq_create(int64_t groups, int32_t window, uint32_t aggregates, cq_query **ou
 }
 
 int cq_reserve(cq_query *q, int64_t max_batch) {
+    // every working buffer is sized at cq_create (batches are processed in
+    // fixed-size sub-batches), so there is nothing left to reserve
     if (!q || max_batch < 0 || max_batch > CQ_MAX_BATCH) return CQ_ERR_INVALID;
-    DeviceGuard g(q->device);
-    return ensure_capacity(q, std::max<int64_t>(max_batch, 1));
+    return CQ_OK;
 }
 
 int cq_set_partition(cq_query *q, int32_t mode, int32_t workers) {
     if (!q) return CQ_ERR_INVALID;
     if (mode != CQ_PARTITION_BALANCED && mode != CQ_PARTITION_STATIC) return CQ_ERR_INVALID;
-    if (workers < 0 || workers > (1 << 20)) return CQ_ERR_INVALID;
-    q->mode = mode;
-    q->workers = workers ? workers : 1024;
+    if (workers < 0) return CQ_ERR_INVALID;
+    const int32_t w = workers ? workers : 1024;
+    if (mode == CQ_PARTITION_STATIC && !static_ok(q->st.G, w)) return CQ_ERR_INVALID;
+    q->mode = mode == CQ_PARTITION_STATIC ? MODE_STATIC : MODE_BALANCED;
+    q->workers = w;
     return CQ_OK;
 }
 
@@ -288,39 +330,17 @@ int cq_push_batch(cq_query *q, const int32_t *keys, const int32_t *values, int64
     if (!q || n < 0 || n > CQ_MAX_BATCH) return CQ_ERR_INVALID;
     if (n > 0 && (!keys || !values)) return CQ_ERR_INVALID;
     DeviceGuard guard(q->device);
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    int rc = ensure_capacity(q, std::max<int64_t>(n, 1));
-    if (rc != CQ_OK) return rc;
-    const int64_t upd_grid = update_grid(n, q->mode, q->workers);
-    if (q->telemetry & CQ_TELEMETRY_WORKERS) {
-        rc = ensure_trace(q, upd_grid);
-        if (rc != CQ_OK) return rc;
-    }
-    Scratch sc = q->sc;
-    if (!(q->telemetry & CQ_TELEMETRY_WORKERS)) sc.trace = nullptr;
-    q->last_stream = s;
-    q->pushed = true;
-    q->last_n = n;
-    q->last_mode = q->mode;
-    q->last_workers = q->workers;
-    if (n == 0) {
-        q->last_tiles = 0;
-        return from_hip(launch_reset_totals(sc, s));
-    }
-    const int64_t G = q->st.G;
-    const int32_t T = (int32_t)tiles_of(n);
-    q->last_tiles = T;
-    rc = timed(q, CQ_KERNEL_HIST, s, [&] { return launch_hist(keys, n, G, sc, s); });
-    if (rc == CQ_OK)
-        rc = timed(q, CQ_KERNEL_PLAN, s, [&] { return launch_plan(G, T, sc, s); });
-    if (rc == CQ_OK)
-        rc = timed(q, CQ_KERNEL_SCATTER, s,
-                   [&] { return launch_scatter(keys, values, n, G, sc, s); });
-    if (rc == CQ_OK)
-        rc = timed(q, CQ_KERNEL_UPDATE, s, [&] {
-            return launch_update(q->st, sc, n, T, q->mode, q->workers, s);
-        });
-    return rc;
+    return push(q, keys, values, n, reinterpret_cast<hipStream_t>(stream), nullptr);
+}
+
+int cq_push_batch_results(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n,
+                          int32_t *ids, int64_t *sums, int32_t *counts, double *avgs,
+                          int64_t *n_touched, void *stream) {
+    if (!q || n < 0 || n > CQ_MAX_BATCH || !n_touched) return CQ_ERR_INVALID;
+    if (n > 0 && (!keys || !values)) return CQ_ERR_INVALID;
+    DeviceGuard guard(q->device);
+    const Out out = {ids, sums, counts, avgs, n_touched};
+    return push(q, keys, values, n, reinterpret_cast<hipStream_t>(stream), &out);
 }
 
 int cq_results(cq_query *q, int32_t *ids, int64_t *sums, int32_t *counts, double *avgs,
@@ -329,9 +349,8 @@ int cq_results(cq_query *q, int32_t *ids, int64_t *sums, int32_t *counts, double
     DeviceGuard guard(q->device);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int64_t cap = std::min<int64_t>(q->st.G, q->last_n);
-    int rc = timed(q, CQ_KERNEL_EMIT, s, [&] {
-        return launch_emit(q->st, q->sc, cap, ids, sums, counts, avgs, n_touched, s);
-    });
+    const Out out = {ids, sums, counts, avgs, n_touched};
+    int rc = timed(q, CQ_KERNEL_EMIT, s, [&] { return launch_emit(q->st, q->sc, cap, out, s); });
     q->last_stream = s;
     q->pushed = true;
     return rc;
@@ -359,7 +378,8 @@ int cq_destroy(cq_query *q) {
 }
 
 int cq_set_telemetry(cq_query *q, int32_t flags) {
-    if (!q || (flags & ~(CQ_TELEMETRY_KERNEL_TIMES | CQ_TELEMETRY_WORKERS)) != 0)
+    if (!q || (flags & ~(CQ_TELEMETRY_KERNEL_TIMES | CQ_TELEMETRY_WORKERS |
+                         CQ_TELEMETRY_PHASES)) != 0)
         return CQ_ERR_INVALID;
     q->telemetry = flags;
     return CQ_OK;
@@ -401,11 +421,31 @@ int cq_worker_trace(cq_query *q, int64_t *rec, int64_t cap, int64_t *count) {
     if (!(q->telemetry & CQ_TELEMETRY_WORKERS) || !q->sc.trace || q->last_n == 0) return CQ_OK;
     hipError_t e = hipStreamSynchronize(q->last_stream);
     if (e != hipSuccess) return from_hip(e);
-    const int64_t have = std::min(q->trace_cap, update_grid(q->last_n, q->last_mode, q->last_workers));
+    const int64_t have = std::min(
+        q->trace_cap,
+        update_grid(std::min<int64_t>(q->last_n, SUB), q->last_mode, q->last_workers));
     *count = have;
     const int64_t m = std::min(have, cap);
     if (m > 0) {
         e = hipMemcpy(rec, q->sc.trace, sizeof(int64_t) * 6 * (size_t)m, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return from_hip(e);
+    }
+    return CQ_OK;
+}
+
+int cq_phase_trace(cq_query *q, int32_t kind, int64_t *out, int64_t cap, int64_t *count) {
+    if (!q || !count || kind < 0 || kind >= PHASE_KINDS || cap < 0 || (cap > 0 && !out))
+        return CQ_ERR_INVALID;
+    DeviceGuard guard(q->device);
+    *count = 0;
+    if (!(q->telemetry & CQ_TELEMETRY_PHASES) || !q->sc.phase) return CQ_OK;
+    hipError_t e = hipStreamSynchronize(q->last_stream);
+    if (e != hipSuccess) return from_hip(e);
+    *count = PHASE_BLOCKS;
+    const int64_t m = std::min<int64_t>(PHASE_BLOCKS, cap);
+    if (m > 0) {
+        e = hipMemcpy(out, q->sc.phase + (int64_t)kind * PHASE_BLOCKS * PHASE_SLOTS,
+                      sizeof(int64_t) * PHASE_SLOTS * (size_t)m, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return from_hip(e);
     }
     return CQ_OK;
@@ -419,17 +459,17 @@ int cq_batch_plan(cq_query *q, int64_t *out) {
     PlanTotals t;
     e = hipMemcpy(&t, q->sc.tot, sizeof(t), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return from_hip(e);
-    out[0] = t.n_light_buckets;
-    out[1] = t.n_heavy;
-    out[2] = t.light_tuples;
-    out[3] = t.heavy_tuples;
-    out[4] = t.n_touched;
-    out[5] = t.n_desc;
-    out[6] = t.status;
-    out[7] = t.tiles;
     int32_t fault = 0;
     e = hipMemcpy(&fault, q->sc.fault, sizeof(fault), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return from_hip(e);
+    out[0] = t.n_light_buckets;
+    out[1] = t.n_heavy;
+    out[2] = t.light_tuples;
+    out[3] = t.n_touched;
+    out[4] = t.n_buckets;
+    out[5] = t.sub_touched;
+    out[6] = t.status;
+    out[7] = (std::min<int64_t>(q->last_n, SUB) + PASS_TILE - 1) / PASS_TILE;
     out[8] = fault;
     return CQ_OK;
 }

@@ -94,9 +94,10 @@ def test_heavy_groups_with_large_window():
         p.close()
 
 
-@pytest.mark.parametrize("G", [1000, 12288, 12289, 100_000])
+@pytest.mark.parametrize("G", [1000, 32768, 32769, 100_000])
 def test_histogram_paths(G):
-    """Direct-indexed LDS counters (G <= 12288) and the LDS hash (larger G)."""
+    """Direct-indexed LDS counters with the plan fused into the histogram
+    (G <= 32768), and the LDS hash with the three-launch plan (larger G)."""
     note(f"case: histogram path G={G}")
     rng = np.random.default_rng(G)
     p = Pair(G, 64)
@@ -229,7 +230,9 @@ def test_skew_sorted_ids_worst_case_for_static():
 
 
 def test_partition_plan_matches_histogram():
-    """The plan's totals equal what numpy computes from the histogram."""
+    """The balancer's plan equals what numpy derives from the histogram:
+    groups with >= 1024 tuples are heavy buckets, the rest are packed into
+    buckets of 1024 tuples."""
     note("case: plan totals")
     cfg = skew(1.5)
     q = cq.Query(cfg.groups, cfg.window)
@@ -240,14 +243,62 @@ def test_partition_plan_matches_histogram():
         kk = np.bincount(k, minlength=cfg.groups)
         light = (kk > 0) & (kk < 1024)
         heavy = kk >= 1024
-        tiles = (len(k) + 2047) // 2048
-        assert plan["touched"] == int((kk > 0).sum())
+        nl = (int(kk[light].sum()) + 1023) // 1024
+        assert plan["touched"] == int((kk > 0).sum()) == plan["sub_touched"]
         assert plan["heavy_groups"] == int(heavy.sum())
         assert plan["light_tuples"] == int(kk[light].sum())
-        assert plan["heavy_tuples"] == int(kk[heavy].sum())
-        assert plan["light_buckets"] == (int(kk[light].sum()) + 1023) // 1024
-        assert plan["heavy_runs"] == int(np.minimum(kk[heavy], tiles).sum())
-        assert plan["tiles"] == tiles and plan["fault"] == 0
+        assert plan["light_buckets"] == nl
+        assert plan["buckets"] == nl + int(heavy.sum())
+        assert plan["tiles"] == (len(k) + 4095) // 4096 and plan["fault"] == 0
+    q.set_partition(cq.PARTITION_STATIC, 100)
+    k, v = host_batch(cfg, 3)
+    q.push(to_dev(k), to_dev(v))
+    plan = q.batch_plan()
+    assert plan["buckets"] == 100 and plan["heavy_groups"] == 0
+    assert plan["light_tuples"] == len(k)
+    q.close()
+
+
+def test_fused_push_results_matches_split_calls():
+    """cq_push_batch_results gives the same results as cq_push_batch then
+    cq_results, also across sub-batch boundaries."""
+    note("case: fused push+results")
+    import torch
+    rng = np.random.default_rng(21)
+    G, W = 3000, 64
+    a = Pair(G, W)
+    q = cq.Query(G, W)
+    dev = device()
+    for b, n in enumerate([100, 70_000, (1 << 20) + 5, 3 * (1 << 20) - 7, 0, 12]):
+        k = rng.integers(0, G, n).astype(np.int32)
+        k[: n // 2] = rng.integers(0, 5, n // 2)
+        v = rng.integers(-50, 50, n).astype(np.int32)
+        dk, dv = to_dev(k), to_dev(v)
+        want = a.step(k, v, f"split n={n}", dkeys=dk, dvalues=dv)
+        cap = max(1, min(G, n))
+        ids = torch.empty(cap, dtype=torch.int32, device=dev)
+        sums = torch.empty(cap, dtype=torch.int64, device=dev)
+        cnts = torch.empty(cap, dtype=torch.int32, device=dev)
+        avgs = torch.empty(cap, dtype=torch.float64, device=dev)
+        nt = torch.empty(1, dtype=torch.int64, device=dev)
+        q.push_results_into(dk, dv, ids, sums, cnts, avgs, nt)
+        m = int(nt.item())
+        got = (ids[:m].cpu(), sums[:m].cpu(), cnts[:m].cpu(), avgs[:m].cpu())
+        for x, y in zip(got, want):
+            assert np.array_equal(x.numpy().view(np.int64) if x.dtype == torch.float64 else x.numpy(),
+                                  y.numpy().view(np.int64) if y.dtype == torch.float64 else y.numpy())
+    a.close()
+    q.close()
+
+
+def test_static_partition_limits():
+    note("case: static limits")
+    q = cq.Query(1 << 20, 4)
+    with pytest.raises(cq.CQError):
+        q.set_partition(cq.PARTITION_STATIC, 100)   # more than 2048 groups per worker
+    with pytest.raises(cq.CQError):
+        q.set_partition(cq.PARTITION_STATIC, 5000)  # more workers than buckets
+    q.set_partition(cq.PARTITION_STATIC, 1024)
     q.close()
 
 
