@@ -21,8 +21,10 @@ written (32 B) and its result emitted (24 B).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -93,6 +95,39 @@ def run_mode(torch, cq, batches, cfg, mode, warmup, steps, kernel_times=False):
     return res
 
 
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1309_0634_amd", "csrc", "cq_kernels.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` recorded from rocprofv3 FETCH_SIZE and
+    WRITE_SIZE counters in profiles/traffic_<kernel>.md, or None when that
+    record was taken on a different kernel source than the one built now."""
+    path = os.path.join(PROFILES, f"traffic_{kernel}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (m_sha and m_b):
+        return None
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    return float(m_b.group(1)) if sha == m_sha.group(1) else None
+
+
+def copy_calibration(torch, mib: int):
+    """One plain device-to-device copy of `mib` MiB, so that a profiler run
+    of this command also shows what the traffic counters read for a kernel
+    of known size."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def cpu_baseline(batches_host, cfg, budget_s):
     """The CPU oracle (one thread) over the first batches of the headline
     stream until about `budget_s` seconds of work."""
@@ -119,6 +154,8 @@ def main():
                     help="seconds of CPU-oracle work for the cpu_baseline sample")
     ap.add_argument("--sweep", default=",".join(str(s) for s in SWEEP))
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not "
@@ -132,6 +169,8 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.calibrate:
+        copy_calibration(torch, args.calibrate)
     sweep = [float(x) for x in args.sweep.split(",")]
     rows = []
     headline = None
@@ -177,8 +216,9 @@ def main():
     dom_ms, dom_launches = kern[dom]
     avg_bytes = timed_bytes / args.steps
     achieved = avg_bytes / (dom_ms / dom_launches * 1e-3) / 1e9
+    traffic = measured_traffic(dom)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom, "kernel_avg_us": round(1e3 * dom_ms / dom_launches, 2),
                 "kernel_times_ms": {k: round(v[0], 3) for k, v in kern.items()}}
     cpu = None

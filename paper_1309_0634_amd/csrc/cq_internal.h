@@ -32,6 +32,7 @@ constexpr int PLAN_THREADS = 1024;
 constexpr int PLAN_KPT = 32;
 constexpr int PLAN_CHUNK = PLAN_THREADS * PLAN_KPT;
 constexpr int PLAN_FIELDS = 3;   // light tuples, heavy groups, touched groups
+static_assert(PLAN_THREADS == HIST_THREADS, "the last histogram block runs the plan");
 
 // Balanced assignment: a group with >= HEAVY_MIN tuples in a sub-batch is
 // heavy and becomes a bucket of its own; light groups are packed, in id
@@ -57,6 +58,8 @@ static_assert(PASS_TILE / PASS_WAVES < 65536, "per-wave counters are 16-bit");
 
 // Per-group phase.
 constexpr int UPD_THREADS = 256;
+// Accelerator complex dies (each with its own L2) of the target device.
+constexpr int XCDS = 8;
 // Static assignment: one wave per worker, four workers per workgroup; a
 // worker owns at most STATIC_KEYS_MAX groups.
 constexpr int STATIC_WORKERS_PER_WG = 4;
@@ -106,6 +109,7 @@ struct Scratch {
     int32_t *bad;       // batch sequence number of the last batch with a bad key
     uint32_t *done;     // histogram blocks finished (last one plans)
     int32_t *fault;     // sticky internal-consistency bits
+    int32_t *hot;       // [2] most frequent groups of the last planned sub-batch
     PlanTotals *tot;
     int64_t *trace;     // optional per-workgroup records (6 int64 each)
     int64_t *phase;     // optional phase clocks [kind][block][PHASE_SLOTS]

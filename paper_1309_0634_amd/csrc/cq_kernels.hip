@@ -41,15 +41,21 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
-__device__ __forceinline__ int wave_incl_add(int v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-    }
-    return v;
+// Inclusive prefix sum over the 64 lanes of a wave with DPP row shifts and
+// row broadcasts (GFX9 cross-lane data movement), without LDS traffic: four
+// shifted adds give prefixes inside each row of 16 lanes, two broadcasts
+// carry row totals forward.  Lanes with no source add 0.
+__device__ __forceinline__ int wave_incl_add(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
 }
+
+__device__ __forceinline__ int wave_total(int incl) { return __builtin_amdgcn_readlane(incl, 63); }
 
 __device__ __forceinline__ long long wave_sum_ll(long long v) {
 #pragma unroll
@@ -162,7 +168,7 @@ __device__ __forceinline__ void plan_group(const State &st, const Scratch &sc, i
     const int32_t W = st.W;
     sc.stamp[g] = seq;
     sc.tidx[g] = x_ex[2];
-    sc.touched[x_ex[2]] = (int32_t)g;
+    if ((uint32_t)x_ex[2] < (uint64_t)st.G) sc.touched[x_ex[2]] = (int32_t)g;
     sc.pold[g] = po;
     st.pos[g] = (int32_t)(((uint32_t)po + (uint32_t)kg) % (uint32_t)W);
     st.cnt[g] = (int32_t)min((int64_t)W, (int64_t)c + kg);
@@ -173,120 +179,148 @@ __device__ __forceinline__ void plan_group(const State &st, const Scratch &sc, i
         sc.bucket[g] = static_worker(g, st.G, workers);
     } else if (kg >= HEAVY_MIN) {
         sc.bucket[g] = n_light + x_ex[1];
-        sc.hkey[x_ex[1]] = (int32_t)g;
+        if ((uint32_t)x_ex[1] < (uint32_t)NB_MAX) sc.hkey[x_ex[1]] = (int32_t)g;
     } else {
         // light buckets: bucket m starts at the group whose staged range
         // [L, L + k) contains position m * LIGHT_BUDGET
         const int32_t L = x_ex[0];
         sc.bucket[g] = (L + kg - 1) / LIGHT_BUDGET;
         const int32_t m = (L + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
-        if ((int64_t)m * LIGHT_BUDGET <= (int64_t)L + kg - 1) sc.bstart[m] = (int32_t)g;
+        if ((int64_t)m * LIGHT_BUDGET <= (int64_t)L + kg - 1 && (uint32_t)m < (uint32_t)NB_MAX)
+            sc.bstart[m] = (int32_t)g;
     }
 }
 
-// Groups of a plan block are split into one contiguous range per wave; lanes
-// take consecutive groups, 64 per round, so every load and store of the plan
-// is coalesced, and prefixes inside a round come from wave shuffles.
-constexpr int PLAN_BATCH = 8;  // rounds whose inputs are fetched together
+// A plan block walks its groups in chunks of PLAN_CHUNK_G consecutive ids;
+// inside a chunk each wave owns PLAN_R rounds of 64 consecutive groups (lane
+// = group), all loaded before use, so every load and store is coalesced.
+// Prefixes come from DPP wave scans of two packed fields (light tuples;
+// heavy flag | touched flag << 16), wave totals meet in LDS, and a running
+// carry links the chunks.
+constexpr int PLAN_R = 10;
+constexpr int PLAN_CHUNK_G = (PLAN_THREADS / 64) * PLAN_R * 64;
 
-__device__ __forceinline__ void wave_range(int64_t gb, int64_t ge, int64_t &c0, int64_t &c1) {
-    const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6;
-    const int64_t per = ((ge - gb + nw - 1) / nw + 63) / 64 * 64;
-    c0 = min(ge, gb + wv * per);
-    c1 = min(ge, c0 + per);
+// Top two (count << 32 | group) pairs of this thread's groups.
+struct Top2 {
+    unsigned long long a = 0, b = 0;
+    __device__ void add(unsigned long long x) {
+        if (x > a) { b = a; a = x; } else if (x > b) { b = x; }
+    }
+};
+
+__device__ __forceinline__ void top2_wave(Top2 &t) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long xa = __shfl_xor(t.a, o, 64), xb = __shfl_xor(t.b, o, 64);
+        t.add(xa);
+        t.add(xb);
+    }
 }
 
-__device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+__device__ void plan_publish(const State &st, const Scratch &sc, const int (&tot)[PLAN_FIELDS],
+                             int32_t status, int mode, int32_t workers);
 
-// Field totals of this wave's range (same value in every lane).
-__device__ void plan_wave_totals(const int32_t *__restrict__ k, int64_t gb, int64_t ge, int mode,
-                                 int (&tot)[PLAN_FIELDS]) {
-    int64_t c0, c1;
-    wave_range(gb, ge, c0, c1);
-    int f[PLAN_FIELDS] = {0, 0, 0};
-    for (int64_t r0 = c0; r0 < c1; r0 += 64 * PLAN_BATCH) {
-        int32_t kv[PLAN_BATCH];
+// Plans groups [gb, ge).  carry[q]: exclusive field values at gb on entry,
+// at ge on exit (same in every thread).  `write`: emit the per-group plan
+// (else only count).  `fuse`: [gb, ge) is the whole group range and fits
+// one chunk, so the totals are known before the first write; they are
+// published here and the light-bucket count taken from them (single pass).
+// Per-group writes happen only when `status` is 0.  `lds` holds 2 * waves
+// ints.  Barriers inside.
+__device__ void plan_range(const State &st, const Scratch &sc, int64_t gb, int64_t ge,
+                           int (&carry)[PLAN_FIELDS], bool write, bool fuse, int32_t status,
+                           int32_t n_light, int32_t seq, int mode, int32_t workers, int *lds,
+                           Top2 *top) {
+    const bool ok = status == 0;
+    const int lane = lane_id(), wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int64_t cb = gb; cb < ge; cb += (int64_t)nw * PLAN_R * 64) {
+        // this lane's groups are g0 + 64 r; one base pointer per array and
+        // constant offsets keep the address arithmetic out of the registers
+        const int64_t g0 = cb + (int64_t)wv * PLAN_R * 64 + lane;
+        const int32_t *kp = sc.k + g0;
+        int32_t kv[PLAN_R], pv[PLAN_R], cv[PLAN_R];
 #pragma unroll
-        for (int j = 0; j < PLAN_BATCH; ++j) {
-            const int64_t g = r0 + j * 64 + lane_id();
-            kv[j] = g < c1 ? k[g] : 0;
+        for (int r = 0; r < PLAN_R; ++r) {
+            const bool in = g0 + 64 * r < ge;
+            kv[r] = in ? kp[64 * r] : 0;
+            pv[r] = (in && write && ok) ? st.pos[g0 + 64 * r] : 0;
+            cv[r] = (in && write && ok) ? st.cnt[g0 + 64 * r] : 0;
         }
+        int wa = 0, wb = 0;
 #pragma unroll
-        for (int j = 0; j < PLAN_BATCH; ++j) {
+        for (int r = 0; r < PLAN_R; ++r) {
             int x[PLAN_FIELDS];
-            key_fields(kv[j], mode, x);
-#pragma unroll
-            for (int q = 0; q < PLAN_FIELDS; ++q) f[q] += x[q];
+            key_fields(kv[r], mode, x);
+            wa += wave_total(wave_incl_add(x[0]));
+            wb += wave_total(wave_incl_add(x[1] | (x[2] << 16)));
+            if (top && kv[r] > 0)
+                top->add(((unsigned long long)(uint32_t)kv[r] << 32) | (uint32_t)(g0 + 64 * r));
         }
-    }
-#pragma unroll
-    for (int q = 0; q < PLAN_FIELDS; ++q) tot[q] = wave_sum(f[q]);
-}
-
-// Exclusive scan of the waves' totals across the block: each wave gets its
-// offset in `off`, every thread the block totals in `btot`.  Barriers inside.
-__device__ void plan_block_offsets(const int (&wtot)[PLAN_FIELDS], int (&off)[PLAN_FIELDS],
-                                   int (&btot)[PLAN_FIELDS], int *lds) {
-    const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6;
-    if (lane_id() == 0)
-#pragma unroll
-        for (int q = 0; q < PLAN_FIELDS; ++q) lds[wv * PLAN_FIELDS + q] = wtot[q];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < PLAN_FIELDS; ++q) {
-        int before = 0, all = 0;
+        if (lane == 0) {
+            lds[2 * wv] = wa;
+            lds[2 * wv + 1] = wb;
+        }
+        __syncthreads();
+        int before_a = 0, before_b = 0, all_a = 0, all_b = 0;
         for (int w = 0; w < nw; ++w) {
-            const int x = lds[w * PLAN_FIELDS + q];
-            if (w < wv) before += x;
-            all += x;
+            const int xa = lds[2 * w], xb = lds[2 * w + 1];
+            if (w < wv) { before_a += xa; before_b += xb; }
+            all_a += xa;
+            all_b += xb;
         }
-        off[q] = before;
-        btot[q] = all;
+        __syncthreads();
+        if (fuse) {
+            phase_mark(sc, PHASE_HIST_PLAN, 4);
+            const int t3[PLAN_FIELDS] = {all_a, all_b & 0xffff, all_b >> 16};
+            n_light = mode == MODE_STATIC ? 0 : (all_a + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
+            if (threadIdx.x == 0) plan_publish(st, sc, t3, status, mode, workers);
+        }
+        if (write) {
+            // the wave scans again (cheaper than holding every round's
+            // prefixes in registers)
+            int ra = carry[0] + before_a, rb = before_b;
+            int32_t *kw = sc.k + g0, *lw = sc.lpre + g0;
+#pragma unroll
+            for (int r = 0; r < PLAN_R; ++r) {
+                const int32_t kg = kv[r];
+                int x[PLAN_FIELDS];
+                key_fields(kg, mode, x);
+                const int B = x[1] | (x[2] << 16);
+                const int ia = wave_incl_add(x[0]), ib = wave_incl_add(B);
+                const int ea = ra + ia - x[0], eb = rb + ib - B;
+                ra += wave_total(ia);
+                rb += wave_total(ib);
+                if (kg) kw[64 * r] = 0;
+                if (!ok || g0 + 64 * r >= ge) continue;
+                int ex[PLAN_FIELDS] = {ea, carry[1] + (eb & 0xffff), carry[2] + (eb >> 16)};
+                lw[64 * r] = ex[0];
+                if (kg > 0)
+                    plan_group(st, sc, g0 + 64 * r, kg, ex, pv[r], cv[r], n_light, seq, mode,
+                               workers);
+            }
+        }
+        if (fuse) phase_mark(sc, PHASE_HIST_PLAN, 6);
+        carry[0] += all_a;
+        carry[1] += all_b & 0xffff;
+        carry[2] += all_b >> 16;
     }
-    __syncthreads();
 }
 
-// Writes the plan of this wave's range, starting from running values `run`
-// (the exclusive prefix at the range start); clears the histogram.
-__device__ void plan_wave_write(const State &st, const Scratch &sc, int64_t gb, int64_t ge,
-                                int (&run)[PLAN_FIELDS], int32_t n_light, int32_t seq, int mode,
-                                int32_t workers, bool ok) {
-    int64_t c0, c1;
-    wave_range(gb, ge, c0, c1);
-    const int lane = lane_id();
-    for (int64_t r0 = c0; r0 < c1; r0 += 64 * PLAN_BATCH) {
-        int32_t kv[PLAN_BATCH], pv[PLAN_BATCH], cv[PLAN_BATCH];
-#pragma unroll
-        for (int j = 0; j < PLAN_BATCH; ++j) {
-            const int64_t g = r0 + j * 64 + lane;
-            const bool in = g < c1;
-            kv[j] = in ? sc.k[g] : 0;
-            pv[j] = (in && ok) ? st.pos[g] : 0;
-            cv[j] = (in && ok) ? st.cnt[g] : 0;
-        }
-#pragma unroll
-        for (int j = 0; j < PLAN_BATCH; ++j) {
-            const int64_t g = r0 + j * 64 + lane;
-            const int32_t kg = kv[j];
-            if (kg) sc.k[g] = 0;
-            int x[PLAN_FIELDS], ex[PLAN_FIELDS];
-            key_fields(kg, mode, x);
-#pragma unroll
-            for (int q = 0; q < PLAN_FIELDS; ++q) {
-                const int incl = wave_incl_add(x[q]);
-                ex[q] = run[q] + incl - x[q];
-                run[q] += __shfl(incl, 63, 64);
-            }
-            if (ok && g < c1) {
-                sc.lpre[g] = ex[0];
-                if (kg > 0) plan_group(st, sc, g, kg, ex, pv[j], cv[j], n_light, seq, mode, workers);
-            }
-        }
+// Block-wide top two over the threads' Top2 (result in thread 0).
+__device__ void top2_block(Top2 &t, unsigned long long *lds) {
+    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    top2_wave(t);
+    if (lane_id() == 0) {
+        lds[2 * wv] = t.a;
+        lds[2 * wv + 1] = t.b;
     }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int w = 1; w < nw; ++w) {
+            t.add(lds[2 * w]);
+            t.add(lds[2 * w + 1]);
+        }
+    __syncthreads();
 }
 
 // Totals of the plan; thread 0 only.
@@ -318,11 +352,15 @@ __global__ __launch_bounds__(HIST_THREADS) void k_hist_plan_small(
     const int32_t *__restrict__ keys, int64_t n, bool vec, State st, Scratch sc, int32_t seq,
     int mode, int32_t workers) {
     extern __shared__ int32_t cntr[];
-    __shared__ int red[PLAN_FIELDS * (HIST_THREADS / 64)];
+    __shared__ int red[2 * (HIST_THREADS / 64)];
+    __shared__ unsigned long long red_top[2 * (HIST_THREADS / 64)];
     __shared__ int last;
     const int tid = threadIdx.x;
     const int G = (int)st.G;
     phase_mark(sc, PHASE_HIST_PLAN, 0);
+    // the previous sub-batch's two most frequent groups are counted in
+    // registers: a Zipf-hot key would otherwise serialise LDS atomics
+    const int32_t hot0 = sc.hot[0], hot1 = sc.hot[1];
     for (int g = tid; g < G; g += HIST_THREADS) cntr[g] = 0;
     const int64_t base = (int64_t)blockIdx.x * HIST_TILE;
     int32_t v[HIST_KPT];
@@ -338,7 +376,7 @@ __global__ __launch_bounds__(HIST_THREADS) void k_hist_plan_small(
         }
     }
     __syncthreads();
-    int bad = 0;
+    int bad = 0, c0 = 0, c1 = 0;
 #pragma unroll
     for (int j = 0; j < HIST_KPT / 4; ++j) {
         const int64_t i = base + 4 * ((int64_t)j * HIST_THREADS + tid);
@@ -347,8 +385,16 @@ __global__ __launch_bounds__(HIST_THREADS) void k_hist_plan_small(
             if (i + e >= n) continue;
             const int32_t key = v[4 * j + e];
             if (key < 0 || key >= G) bad = 1;
+            else if (key == hot0) ++c0;
+            else if (key == hot1) ++c1;
             else atomicAdd(&cntr[key], 1);
         }
+    }
+    c0 = wave_total(wave_incl_add(c0));
+    c1 = wave_total(wave_incl_add(c1));
+    if (lane_id() == 0) {
+        if (c0) atomicAdd(&cntr[hot0], c0);
+        if (c1) atomicAdd(&cntr[hot1], c1);
     }
     if (__syncthreads_or(bad)) {
         if (tid == 0) atomicExch(sc.bad, seq);
@@ -371,13 +417,25 @@ __global__ __launch_bounds__(HIST_THREADS) void k_hist_plan_small(
 
     // ---- plan (this block only) ----
     const int32_t status = load_coherent(sc.bad) == seq ? CQ_ERR_KEY_RANGE : 0;
-    int wtot[PLAN_FIELDS], off[PLAN_FIELDS], tot[PLAN_FIELDS];
-    plan_wave_totals(sc.k, 0, G, mode, wtot);
-    plan_block_offsets(wtot, off, tot, red);
-    phase_mark(sc, PHASE_HIST_PLAN, 4);
-    const int32_t nl = mode == MODE_STATIC ? 0 : (tot[0] + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
-    if (tid == 0) plan_publish(st, sc, tot, status, mode, workers);
-    plan_wave_write(st, sc, 0, G, off, nl, seq, mode, workers, status == 0);
+    Top2 top;
+    if (G <= PLAN_CHUNK_G) {
+        int carry[PLAN_FIELDS] = {0, 0, 0};
+        plan_range(st, sc, 0, G, carry, true, true, status, 0, seq, mode, workers, red, &top);
+    } else {
+        // counting pass, totals, then the writing pass over the same groups
+        int tot[PLAN_FIELDS] = {0, 0, 0};
+        plan_range(st, sc, 0, G, tot, false, false, status, 0, seq, mode, workers, red, &top);
+        const int32_t nl = mode == MODE_STATIC ? 0 : (tot[0] + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
+        phase_mark(sc, PHASE_HIST_PLAN, 4);
+        if (tid == 0) plan_publish(st, sc, tot, status, mode, workers);
+        int carry[PLAN_FIELDS] = {0, 0, 0};
+        plan_range(st, sc, 0, G, carry, true, false, status, nl, seq, mode, workers, red, nullptr);
+    }
+    top2_block(top, red_top);
+    if (tid == 0) {
+        sc.hot[0] = top.a ? (int32_t)(uint32_t)top.a : -1;
+        sc.hot[1] = top.b ? (int32_t)(uint32_t)top.b : -1;
+    }
     __syncthreads();
     phase_mark(sc, PHASE_HIST_PLAN, 5);
 }
@@ -425,11 +483,11 @@ __global__ __launch_bounds__(HIST_THREADS) void k_hist_hash(const int32_t *__res
 // Plan over large G in three launches: block sums, a scan of the block
 // sums, and the per-group writes.
 __global__ __launch_bounds__(PLAN_THREADS) void k_plan_reduce(int64_t G, int mode, Scratch sc) {
-    __shared__ int red[PLAN_FIELDS * (PLAN_THREADS / 64)];
+    __shared__ int red[2 * (PLAN_THREADS / 64)];
     const int64_t gb = (int64_t)blockIdx.x * PLAN_CHUNK, ge = min(G, gb + PLAN_CHUNK);
-    int wtot[PLAN_FIELDS], off[PLAN_FIELDS], tot[PLAN_FIELDS];
-    plan_wave_totals(sc.k, gb, ge, mode, wtot);
-    plan_block_offsets(wtot, off, tot, red);
+    int tot[PLAN_FIELDS] = {0, 0, 0};
+    State none{};
+    plan_range(none, sc, gb, ge, tot, false, false, 0, 0, 0, mode, 1, red, nullptr);
     if (threadIdx.x == 0)
         for (int q = 0; q < PLAN_FIELDS; ++q) sc.partials[blockIdx.x * PLAN_FIELDS + q] = tot[q];
 }
@@ -458,16 +516,15 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_plan_scan(int32_t nblk, State 
 
 __global__ __launch_bounds__(PLAN_THREADS) void k_plan_down(State st, Scratch sc, int32_t seq,
                                                             int mode, int32_t workers) {
-    __shared__ int red[PLAN_FIELDS * (PLAN_THREADS / 64)];
+    __shared__ int red[2 * (PLAN_THREADS / 64)];
     const int64_t G = st.G;
     const int64_t gb = (int64_t)blockIdx.x * PLAN_CHUNK, ge = min(G, gb + PLAN_CHUNK);
-    int wtot[PLAN_FIELDS], off[PLAN_FIELDS], tot[PLAN_FIELDS];
-    plan_wave_totals(sc.k, gb, ge, mode, wtot);
-    plan_block_offsets(wtot, off, tot, red);
+    int carry[PLAN_FIELDS];
 #pragma unroll
-    for (int q = 0; q < PLAN_FIELDS; ++q) off[q] += sc.partials[blockIdx.x * PLAN_FIELDS + q];
+    for (int q = 0; q < PLAN_FIELDS; ++q) carry[q] = sc.partials[blockIdx.x * PLAN_FIELDS + q];
     const PlanTotals t = *sc.tot;
-    plan_wave_write(st, sc, gb, ge, off, t.n_light_buckets, seq, mode, workers, t.status == 0);
+    plan_range(st, sc, gb, ge, carry, true, false, t.status, t.n_light_buckets, seq, mode,
+               workers, red, nullptr);
 }
 
 // Whole-batch key check (used when a batch spans several sub-batches, so
@@ -597,15 +654,19 @@ __device__ __forceinline__ void trace_record(int64_t *trace, unsigned long long 
 
 // The runs of bucket b (one per tile, in tile order = arrival order): rs[t]
 // = first staged slot, rp[t] = tuples of the bucket in tiles before t,
-// rp[tiles] = bucket size.  Barriers inside.
+// rp[tiles] = bucket size.  The caller's per-group prefetch (`extra`) is
+// issued before the first barrier so its loads overlap the run loads.
+// Barriers inside.
+template <typename F>
 __device__ int bucket_runs(const Scratch &sc, int b, int NB, int tiles, int32_t *rs,
-                           int32_t *rp, int *red) {
+                           int32_t *rp, int *red, F &&extra) {
     for (int t = threadIdx.x; t < tiles; t += blockDim.x) {
         const int32_t *row = sc.rowstart + (int64_t)t * (NB + 1);
         const int32_t s = row[b], e = row[b + 1];
         rs[t] = t * PASS_TILE + s;
         rp[t] = e - s;
     }
+    extra();
     __syncthreads();
     block_excl_scan_array(rp, tiles, red);
     return rp[tiles];
@@ -616,13 +677,19 @@ constexpr int U_RS = 0;                                  // i32[PASS_TILES_MAX]
 constexpr int U_RP = U_RS + 4 * PASS_TILES_MAX;          // i32[PASS_TILES_MAX + 1]
 constexpr int U_EK = U_RP + 4 * (PASS_TILES_MAX + 4);    // i32[LIGHT_CAP] keys
 constexpr int U_EV = U_EK + 4 * LIGHT_CAP;               // i32[LIGHT_CAP] values
-constexpr int U_PZ = U_EV + 4 * LIGHT_CAP;               // i32[LIGHT_CAP] group start in bucket
-constexpr int U_LR = U_PZ + 4 * LIGHT_CAP;               // i32[LIGHT_CAP] rank inside wave chunk
-constexpr int U_HD = U_LR + 4 * LIGHT_CAP;               // i32[LIGHT_CAP] group at its start
-constexpr int U_CW = U_HD + 4 * LIGHT_CAP;               // u16[UPD_WAVES][LIGHT_CAP]
+constexpr int U_PZ = U_EV + 4 * LIGHT_CAP;               // i16[LIGHT_CAP] group start in bucket
+constexpr int U_LR = U_PZ + 2 * LIGHT_CAP;               // u16[LIGHT_CAP] rank inside wave chunk
+constexpr int U_HD = U_LR + 2 * LIGHT_CAP;               // i16[LIGHT_CAP] tuple of rank 0
+constexpr int U_CW = U_HD + 2 * LIGHT_CAP;               // u16[UPD_WAVES][LIGHT_CAP]
 constexpr int UPD_WAVES = UPD_THREADS / 64;
 constexpr int U_ACC = U_CW + 2 * UPD_WAVES * LIGHT_CAP;  // i64[LIGHT_CAP] sum deltas
-constexpr int U_BYTES = U_ACC + 8 * LIGHT_CAP;
+// a light bucket whose groups span at most LIGHT_SPAN ids keeps their
+// staged-range starts and old ring pointers in LDS
+constexpr int LIGHT_SPAN = 2048;
+constexpr int U_KLP = U_ACC + 8 * LIGHT_CAP;             // i32[LIGHT_SPAN + 1]
+constexpr int U_KPO = U_KLP + 4 * (LIGHT_SPAN + 4);      // i32[LIGHT_SPAN]
+constexpr int U_BYTES = U_KPO + 4 * LIGHT_SPAN;
+static_assert(LIGHT_CAP <= 32768, "16-bit positions");
 
 // Light bucket b: groups [bstart[b], bstart[b+1]) packed by the plan, fewer
 // than LIGHT_CAP tuples, read in arrival order.  Each wave takes a
@@ -630,23 +697,27 @@ constexpr int U_BYTES = U_ACC + 8 * LIGHT_CAP;
 // find each other with ballots over the group's start position, so a
 // tuple's rank among its group's earlier tuples is exact and stable.  Every
 // tuple among its group's last W goes to ring slot (pos + rank) mod W.
-__device__ int light_bucket(int b, int size, int tiles, const State &st, const Scratch &sc,
-                            const Out &out, char *smem) {
+__device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const State &st,
+                            const Scratch &sc, const Out &out, char *smem) {
     const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
     const int32_t *rs = reinterpret_cast<const int32_t *>(smem + U_RS);
     const int32_t *rp = reinterpret_cast<const int32_t *>(smem + U_RP);
     int32_t *ek = reinterpret_cast<int32_t *>(smem + U_EK);
     int32_t *ev = reinterpret_cast<int32_t *>(smem + U_EV);
-    int32_t *pz = reinterpret_cast<int32_t *>(smem + U_PZ);
-    int32_t *lr = reinterpret_cast<int32_t *>(smem + U_LR);
-    int32_t *hd = reinterpret_cast<int32_t *>(smem + U_HD);
+    int16_t *pz = reinterpret_cast<int16_t *>(smem + U_PZ);
+    uint16_t *lr = reinterpret_cast<uint16_t *>(smem + U_LR);
+    int16_t *hd = reinterpret_cast<int16_t *>(smem + U_HD);
     uint16_t *cw = reinterpret_cast<uint16_t *>(smem + U_CW);
     long long *acc = reinterpret_cast<long long *>(smem + U_ACC);
-    const int32_t a = sc.bstart[b];
-    const int32_t z = sc.bstart[b + 1];
-    const int32_t s0 = sc.lpre[a];
+    const int32_t *klp = reinterpret_cast<const int32_t *>(smem + U_KLP);
+    const int32_t *kpo = reinterpret_cast<const int32_t *>(smem + U_KPO);
+    const bool in_lds = z - a <= LIGHT_SPAN;
+    // staged-range start (relative to the bucket) and old ring pointer of g
+    auto lp = [&](int32_t g) { return in_lds ? klp[g - a] : sc.lpre[g]; };
+    auto po = [&](int32_t g) { return in_lds ? kpo[g - a] : sc.pold[g]; };
+    const int32_t s0 = lp(a);
     if (size <= 0) return 0;
-    if (size > LIGHT_CAP || sc.lpre[z] - s0 != size) {
+    if (size > LIGHT_CAP || lp(z) - s0 != size) {
         if (tid == 0) atomicOr(sc.fault, FAULT_LIGHT_SIZE);
         return 0;
     }
@@ -656,8 +727,8 @@ __device__ int light_bucket(int b, int size, int tiles, const State &st, const S
         const int32_t g = e.x;
         int32_t p0 = -1;
         if (g >= a && g < z) {
-            const int32_t l0 = sc.lpre[g];
-            if (sc.lpre[g + 1] > l0) p0 = l0 - s0;
+            const int32_t l0 = lp(g);
+            if (lp(g + 1) > l0) p0 = l0 - s0;
         }
         if (p0 < 0 || p0 >= size) {  // impossible for a well-formed plan
             atomicOr(sc.fault, FAULT_LIGHT_SIZE);
@@ -665,7 +736,7 @@ __device__ int light_bucket(int b, int size, int tiles, const State &st, const S
         }
         ek[p] = g;
         ev[p] = e.y;
-        pz[p] = p0;
+        pz[p] = (int16_t)p0;
         hd[p] = -1;
         acc[p] = 0;
     }
@@ -690,7 +761,7 @@ __device__ int light_bucket(int b, int size, int tiles, const State &st, const S
         if (valid) {
             const uint64_t below = m & lanemask_lt();
             const int c = mycw[p0];
-            lr[p] = c + __popcll(below);
+            lr[p] = (uint16_t)(c + __popcll(below));
             if (below == 0) mycw[p0] = (uint16_t)(c + __popcll(m));
         }
     }
@@ -714,11 +785,11 @@ __device__ int light_bucket(int b, int size, int tiles, const State &st, const S
         const int w = p / chunk;
         const int32_t g = ek[p];
         const int32_t rank = cw[w * LIGHT_CAP + p0] + lr[p];
-        const int32_t kg = sc.lpre[g + 1] - sc.lpre[g];
-        if (rank == 0) hd[p0] = g;
+        const int32_t kg = lp(g + 1) - lp(g);
+        if (rank == 0) hd[p0] = (int16_t)p;
         const int32_t need = kg < W ? kg : W;
         if (rank >= kg - need && rank < kg) {
-            const uint32_t slot = ((uint32_t)sc.pold[g] + (uint32_t)rank) % (uint32_t)W;
+            const uint32_t slot = ((uint32_t)po(g) + (uint32_t)rank) % (uint32_t)W;
             int32_t *cell = st.ring + (int64_t)g * W + slot;
             const int32_t old = kg >= W ? 0 : *cell;
             const int32_t v = ev[p];
@@ -730,7 +801,7 @@ __device__ int light_bucket(int b, int size, int tiles, const State &st, const S
     __syncthreads();
     phase_mark(sc, PHASE_UPDATE, 4);
     for (int i = tid; i < size; i += blockDim.x) {
-        const int32_t g = hd[i];
+        const int32_t g = hd[i] >= 0 ? ek[hd[i]] : -1;
         if (g >= 0) {
             const int64_t s = st.sum[g] + acc[i];
             st.sum[g] = s;
@@ -743,16 +814,15 @@ __device__ int light_bucket(int b, int size, int tiles, const State &st, const S
 
 // Heavy bucket (one group, size >= HEAVY_MIN tuples): only its last
 // min(size, W) tuples survive; they are read straight from their runs.
-__device__ int heavy_bucket(int h, int size, int tiles, const State &st, const Scratch &sc,
-                            const Out &out, char *smem, long long *red_ll) {
+__device__ int heavy_bucket(int32_t g, int32_t pold_g, int size, int tiles, const State &st,
+                            const Scratch &sc, const Out &out, char *smem, long long *red_ll) {
     const int tid = threadIdx.x;
     const int32_t *rs = reinterpret_cast<const int32_t *>(smem + U_RS);
     const int32_t *rp = reinterpret_cast<const int32_t *>(smem + U_RP);
-    const int32_t g = sc.hkey[h];
     const int32_t W = st.W;
     const int32_t need = size < W ? size : W;
     const bool full = size >= W;
-    const uint32_t po = (uint32_t)sc.pold[g];
+    const uint32_t po = (uint32_t)pold_g;
     long long acc = 0;
     for (int p = size - need + tid; p < size; p += blockDim.x) {
         const int r = upper_run(rp, tiles, p);
@@ -790,13 +860,39 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_balanced(State st, Scrat
     int32_t *rs = reinterpret_cast<int32_t *>(smem + U_RS);
     int32_t *rp = reinterpret_cast<int32_t *>(smem + U_RP);
     phase_mark(sc, PHASE_UPDATE, 0);
-    for (int b = blockIdx.x; b < NB; b += gridDim.x) {
-        const int size = bucket_runs(sc, b, NB, tiles, rs, rp, red);
-        if (b == (int)blockIdx.x) phase_mark(sc, PHASE_UPDATE, 1);
-        if (b < t.n_light_buckets)
-            tuples += light_bucket(b, size, tiles, st, sc, out, smem);
+    int32_t *klp = reinterpret_cast<int32_t *>(smem + U_KLP);
+    int32_t *kpo = reinterpret_cast<int32_t *>(smem + U_KPO);
+    // Workgroups are dispatched to the XCDs round-robin (workgroup i on XCD
+    // i mod XCDS); each XCD takes one contiguous range of buckets, so the
+    // cache lines that neighbouring buckets share in the staged tiles and
+    // their rows of bucket starts stay in one XCD's L2.
+    const int xcd = blockIdx.x % XCDS, per_xcd = gridDim.x / XCDS;
+    const int span = (NB + XCDS - 1) / XCDS;
+    const int b_lo = xcd * span, b_hi = min(NB, b_lo + span);
+    const int first = (int)blockIdx.x / XCDS < per_xcd ? b_lo + (int)blockIdx.x / XCDS : NB;
+    for (int b = first; b < b_hi; b += per_xcd) {
+        const bool light = b < t.n_light_buckets;
+        int32_t a = 0, z = 0, g = 0, pold_g = 0;
+        if (light) {
+            a = sc.bstart[b];
+            z = sc.bstart[b + 1];
+        } else {
+            g = sc.hkey[b - t.n_light_buckets];
+            pold_g = sc.pold[g];
+        }
+        const int size = bucket_runs(sc, b, NB, tiles, rs, rp, red, [&] {
+            if (light && z - a <= LIGHT_SPAN) {
+                for (int i = threadIdx.x; i <= z - a; i += blockDim.x) {
+                    klp[i] = sc.lpre[a + i];
+                    if (i < z - a) kpo[i] = sc.pold[a + i];
+                }
+            }
+        });
+        if (b == first) phase_mark(sc, PHASE_UPDATE, 1);
+        if (light)
+            tuples += light_bucket(a, z, size, tiles, st, sc, out, smem);
         else
-            tuples += heavy_bucket(b - t.n_light_buckets, size, tiles, st, sc, out, smem, red_ll);
+            tuples += heavy_bucket(g, pold_g, size, tiles, st, sc, out, smem, red_ll);
         ++items;
     }
     phase_mark(sc, PHASE_UPDATE, 5);
@@ -862,7 +958,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_static(State st, Scratch
                 }
                 const int incl = wave_incl_add(len);
                 if (tt < tiles) rp[tt] = carry + incl - len;
-                carry += __shfl(incl, 63, 64);
+                carry += wave_total(incl);
             }
             if (lane == 0) rp[tiles] = carry;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1066,7 +1162,8 @@ hipError_t launch_pass(const int32_t *keys, const int32_t *values, int64_t n, Sc
 int64_t update_grid(int64_t n, int mode, int32_t workers) {
     if (mode == MODE_STATIC) return (workers + STATIC_WORKERS_PER_WG - 1) / STATIC_WORKERS_PER_WG;
     const int64_t nb = (n + LIGHT_BUDGET - 1) / LIGHT_BUDGET + n / HEAVY_MIN + 1;
-    return std::max<int64_t>(1, std::min<int64_t>(nb, NB_MAX));
+    // a whole number of workgroups per XCD
+    return (std::max<int64_t>(1, std::min<int64_t>(nb, NB_MAX)) + XCDS - 1) / XCDS * XCDS;
 }
 
 hipError_t launch_update(State st, Scratch sc, int64_t n, int mode, int32_t workers, Out out,

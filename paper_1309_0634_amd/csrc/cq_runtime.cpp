@@ -101,6 +101,7 @@ void free_all(cq_query *q) {
     dfree(q->sc.bad);
     dfree(q->sc.done);
     dfree(q->sc.fault);
+    dfree(q->sc.hot);
     dfree(q->sc.tot);
     dfree(q->sc.trace);
     dfree(q->sc.phase);
@@ -278,6 +279,7 @@ int cq_create(int64_t groups, int32_t window, uint32_t aggregates, cq_query **ou
     if (rc == CQ_OK) rc = dalloc(&q->sc.bad, 1);
     if (rc == CQ_OK) rc = dalloc(&q->sc.done, 1);
     if (rc == CQ_OK) rc = dalloc(&q->sc.fault, 1);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.hot, 2);
     if (rc == CQ_OK) rc = dalloc(&q->sc.tot, 1);
     hipError_t e = hipSuccess;
     if (rc == CQ_OK) {
@@ -294,6 +296,7 @@ int cq_create(int64_t groups, int32_t window, uint32_t aggregates, cq_query **ou
         if (e == hipSuccess) e = hipMemset(q->sc.bad, 0, sizeof(int32_t));
         if (e == hipSuccess) e = hipMemset(q->sc.done, 0, sizeof(uint32_t));
         if (e == hipSuccess) e = hipMemset(q->sc.fault, 0, sizeof(int32_t));
+        if (e == hipSuccess) e = hipMemset(q->sc.hot, 0xff, 2 * sizeof(int32_t));
         if (e == hipSuccess) e = hipMemset(q->sc.tot, 0, sizeof(PlanTotals));
         if (e == hipSuccess) e = hipDeviceSynchronize();
         rc = from_hip(e);
