@@ -180,12 +180,13 @@ const char *cq_strerror(int code);
                                        tuples) records of the per-group phase */
 
 /* Launch kinds reported by cq_kernel_times, in this order. */
-#define CQ_KERNEL_HIST_PLAN 0 /* histogram + balancer plan           */
-#define CQ_KERNEL_PASS      1 /* tile-local reorder by bucket        */
+#define CQ_KERNEL_HIST      0 /* key histogram                        */
+#define CQ_KERNEL_PASS      1 /* tile-local reorder by bucket         */
 #define CQ_KERNEL_UPDATE    2 /* per-group evict + insert + aggregate */
-#define CQ_KERNEL_EMIT      3 /* separate result emission            */
-#define CQ_KERNEL_OTHER     4 /* whole-batch checks and collection   */
-#define CQ_KERNEL_KINDS     5
+#define CQ_KERNEL_EMIT      3 /* separate result emission             */
+#define CQ_KERNEL_OTHER     4 /* whole-batch checks and collection    */
+#define CQ_KERNEL_PLAN      5 /* scans over groups + balancer plan    */
+#define CQ_KERNEL_KINDS     6
 
 /*
  * cq_set_telemetry -- turn measurement on (flags) or off (0).  Imbalance

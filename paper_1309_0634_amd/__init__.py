@@ -18,7 +18,7 @@ SUM, COUNT, AVG = 1, 2, 4
 OK, ERR_INVALID, ERR_OOM, ERR_KEY_RANGE, ERR_HIP = 0, -1, -2, -3, -4
 PARTITION_BALANCED, PARTITION_STATIC = 0, 1
 TELEMETRY_KERNEL_TIMES, TELEMETRY_WORKERS, TELEMETRY_PHASES = 1, 2, 4
-KERNEL_KINDS = ("hist_plan", "pass", "update", "emit", "other")
+KERNEL_KINDS = ("hist", "pass", "update", "emit", "other", "plan")
 MAX_BATCH = 1 << 30
 MAX_WINDOW = (1 << 22) - 1
 

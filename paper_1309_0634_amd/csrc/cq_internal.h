@@ -26,13 +26,12 @@ constexpr int HIST_HASH_LOG = 14;
 constexpr int HIST_HASH_SLOTS = 1 << HIST_HASH_LOG;
 static_assert(HIST_HASH_SLOTS >= 2 * HIST_HASH_TILE, "hash load factor <= 1/2");
 
-// Plan (scan over groups): PLAN_THREADS x PLAN_KPT groups per block; one
-// block (fused into the histogram's last block) when G <= PLAN_CHUNK.
+// Multi-block plan for G > HIST_DIRECT_MAX_G (scan over groups): PLAN_CHUNK
+// groups per block of PLAN_THREADS.
 constexpr int PLAN_THREADS = 1024;
 constexpr int PLAN_KPT = 32;
 constexpr int PLAN_CHUNK = PLAN_THREADS * PLAN_KPT;
 constexpr int PLAN_FIELDS = 3;   // light tuples, heavy groups, touched groups
-static_assert(PLAN_THREADS == HIST_THREADS, "the last histogram block runs the plan");
 
 // Balanced assignment: a group with >= HEAVY_MIN tuples in a sub-batch is
 // heavy and becomes a bucket of its own; light groups are packed, in id
@@ -107,7 +106,6 @@ struct Scratch {
     // control
     int32_t *partials;  // plan block partials
     int32_t *bad;       // batch sequence number of the last batch with a bad key
-    uint32_t *done;     // histogram blocks finished (last one plans)
     int32_t *fault;     // sticky internal-consistency bits
     int32_t *hot;       // [2] most frequent groups of the last planned sub-batch
     PlanTotals *tot;
@@ -142,8 +140,10 @@ enum Mode { MODE_BALANCED = 0, MODE_STATIC = 1 };
 // Launch sequence pieces (each enqueues on `s`, returns the launch status).
 hipError_t launch_validate(const int32_t *keys, int64_t n, int64_t G, int32_t seq, Scratch sc,
                            hipStream_t s);
-hipError_t launch_hist_plan(const int32_t *keys, int64_t n, State st, Scratch sc, int32_t seq,
-                            int mode, int32_t workers, hipStream_t s);
+hipError_t launch_hist(const int32_t *keys, int64_t n, int64_t G, Scratch sc, int32_t seq,
+                       hipStream_t s);
+hipError_t launch_plan(State st, Scratch sc, int32_t seq, int mode, int32_t workers,
+                       hipStream_t s);
 hipError_t launch_pass(const int32_t *keys, const int32_t *values, int64_t n, Scratch sc,
                        hipStream_t s);
 hipError_t launch_update(State st, Scratch sc, int64_t n, int mode, int32_t workers, Out out,
@@ -153,7 +153,7 @@ hipError_t launch_emit(State st, Scratch sc, int64_t cap, Out out, hipStream_t s
 hipError_t launch_reset_totals(Scratch sc, hipStream_t s);
 // Workgroups of the per-group phase (one trace record each).
 int64_t update_grid(int64_t n, int mode, int32_t workers);
-// Histogram kernels launched by launch_hist_plan for a sub-batch of n.
+// Histogram workgroups launched by launch_hist for a sub-batch of n.
 int64_t hist_blocks(int64_t n, int64_t G);
 
 }  // namespace cq

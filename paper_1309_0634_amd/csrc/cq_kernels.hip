@@ -57,6 +57,18 @@ __device__ __forceinline__ int wave_incl_add(int x) {
 
 __device__ __forceinline__ int wave_total(int incl) { return __builtin_amdgcn_readlane(incl, 63); }
 
+// Inclusive running maximum over the 64 lanes of non-negative values (the
+// same DPP pattern as wave_incl_add; lanes with no source take 0).
+__device__ __forceinline__ int wave_incl_max(int x) {
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false));
+    return x;
+}
+
 __device__ __forceinline__ long long wave_sum_ll(long long v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -140,10 +152,6 @@ __device__ __forceinline__ void phase_mark(const Scratch &sc, int kind, int slot
             (int64_t)wall_clock64();
 }
 
-__device__ __forceinline__ int32_t load_coherent(const int32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // -------------------------------------------------------- plan (per key) --
 // Fields scanned over groups: light tuples, heavy groups, touched groups.
 __device__ __forceinline__ void key_fields(int32_t kg, int mode, int (&f)[PLAN_FIELDS]) {
@@ -191,14 +199,13 @@ __device__ __forceinline__ void plan_group(const State &st, const Scratch &sc, i
     }
 }
 
-// A plan block walks its groups in chunks of PLAN_CHUNK_G consecutive ids;
-// inside a chunk each wave owns PLAN_R rounds of 64 consecutive groups (lane
-// = group), all loaded before use, so every load and store is coalesced.
+// A plan block of the multi-block plan walks its groups in chunks; inside a
+// chunk each wave owns PLAN_R rounds of 64 consecutive groups (lane =
+// group), all loaded before use, so every load and store is coalesced.
 // Prefixes come from DPP wave scans of two packed fields (light tuples;
 // heavy flag | touched flag << 16), wave totals meet in LDS, and a running
 // carry links the chunks.
 constexpr int PLAN_R = 10;
-constexpr int PLAN_CHUNK_G = (PLAN_THREADS / 64) * PLAN_R * 64;
 
 // Top two (count << 32 | group) pairs of this thread's groups.
 struct Top2 {
@@ -222,15 +229,11 @@ __device__ void plan_publish(const State &st, const Scratch &sc, const int (&tot
 
 // Plans groups [gb, ge).  carry[q]: exclusive field values at gb on entry,
 // at ge on exit (same in every thread).  `write`: emit the per-group plan
-// (else only count).  `fuse`: [gb, ge) is the whole group range and fits
-// one chunk, so the totals are known before the first write; they are
-// published here and the light-bucket count taken from them (single pass).
-// Per-group writes happen only when `status` is 0.  `lds` holds 2 * waves
-// ints.  Barriers inside.
+// and clear the histogram (else only count).  Per-group plan writes happen
+// only when `status` is 0.  `lds` holds 2 * waves ints.  Barriers inside.
 __device__ void plan_range(const State &st, const Scratch &sc, int64_t gb, int64_t ge,
-                           int (&carry)[PLAN_FIELDS], bool write, bool fuse, int32_t status,
-                           int32_t n_light, int32_t seq, int mode, int32_t workers, int *lds,
-                           Top2 *top) {
+                           int (&carry)[PLAN_FIELDS], bool write, int32_t status,
+                           int32_t n_light, int32_t seq, int mode, int32_t workers, int *lds) {
     const bool ok = status == 0;
     const int lane = lane_id(), wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int64_t cb = gb; cb < ge; cb += (int64_t)nw * PLAN_R * 64) {
@@ -253,8 +256,6 @@ __device__ void plan_range(const State &st, const Scratch &sc, int64_t gb, int64
             key_fields(kv[r], mode, x);
             wa += wave_total(wave_incl_add(x[0]));
             wb += wave_total(wave_incl_add(x[1] | (x[2] << 16)));
-            if (top && kv[r] > 0)
-                top->add(((unsigned long long)(uint32_t)kv[r] << 32) | (uint32_t)(g0 + 64 * r));
         }
         if (lane == 0) {
             lds[2 * wv] = wa;
@@ -269,12 +270,6 @@ __device__ void plan_range(const State &st, const Scratch &sc, int64_t gb, int64
             all_b += xb;
         }
         __syncthreads();
-        if (fuse) {
-            phase_mark(sc, PHASE_HIST_PLAN, 4);
-            const int t3[PLAN_FIELDS] = {all_a, all_b & 0xffff, all_b >> 16};
-            n_light = mode == MODE_STATIC ? 0 : (all_a + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
-            if (threadIdx.x == 0) plan_publish(st, sc, t3, status, mode, workers);
-        }
         if (write) {
             // the wave scans again (cheaper than holding every round's
             // prefixes in registers)
@@ -299,7 +294,6 @@ __device__ void plan_range(const State &st, const Scratch &sc, int64_t gb, int64
                                workers);
             }
         }
-        if (fuse) phase_mark(sc, PHASE_HIST_PLAN, 6);
         carry[0] += all_a;
         carry[1] += all_b & 0xffff;
         carry[2] += all_b >> 16;
@@ -348,15 +342,11 @@ __device__ void plan_publish(const State &st, const Scratch &sc, const int (&tot
 // Histogram blocks of HIST_THREADS threads over HIST_TILE consecutive tuples
 // each (every thread's keys loaded together), LDS counters indexed by key;
 // the block that finishes last plans the whole sub-batch (G <= PLAN_CHUNK).
-__global__ __launch_bounds__(HIST_THREADS) void k_hist_plan_small(
-    const int32_t *__restrict__ keys, int64_t n, bool vec, State st, Scratch sc, int32_t seq,
-    int mode, int32_t workers) {
+__global__ __launch_bounds__(HIST_THREADS) void k_hist_small(const int32_t *__restrict__ keys,
+                                                             int64_t n, bool vec, int32_t G,
+                                                             Scratch sc, int32_t seq) {
     extern __shared__ int32_t cntr[];
-    __shared__ int red[2 * (HIST_THREADS / 64)];
-    __shared__ unsigned long long red_top[2 * (HIST_THREADS / 64)];
-    __shared__ int last;
     const int tid = threadIdx.x;
-    const int G = (int)st.G;
     phase_mark(sc, PHASE_HIST_PLAN, 0);
     // the previous sub-batch's two most frequent groups are counted in
     // registers: a Zipf-hot key would otherwise serialise LDS atomics
@@ -404,40 +394,118 @@ __global__ __launch_bounds__(HIST_THREADS) void k_hist_plan_small(
         const int32_t c = cntr[g];
         if (c) atomicAdd(&sc.k[g], c);
     }
-    __threadfence();
-    __syncthreads();
     phase_mark(sc, PHASE_HIST_PLAN, 2);
-    if (tid == 0) last = atomicAdd(sc.done, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!last) return;
-    phase_mark(sc, PHASE_HIST_PLAN, 3);
-    // acquire: every block's counts (and bad-key mark) are visible below
-    __threadfence();
-    if (tid == 0) *sc.done = 0;
+}
 
-    // ---- plan (this block only) ----
-    const int32_t status = load_coherent(sc.bad) == seq ? CQ_ERR_KEY_RANGE : 0;
-    Top2 top;
-    if (G <= PLAN_CHUNK_G) {
-        int carry[PLAN_FIELDS] = {0, 0, 0};
-        plan_range(st, sc, 0, G, carry, true, true, status, 0, seq, mode, workers, red, &top);
-    } else {
-        // counting pass, totals, then the writing pass over the same groups
-        int tot[PLAN_FIELDS] = {0, 0, 0};
-        plan_range(st, sc, 0, G, tot, false, false, status, 0, seq, mode, workers, red, &top);
-        const int32_t nl = mode == MODE_STATIC ? 0 : (tot[0] + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
-        phase_mark(sc, PHASE_HIST_PLAN, 4);
-        if (tid == 0) plan_publish(st, sc, tot, status, mode, workers);
-        int carry[PLAN_FIELDS] = {0, 0, 0};
-        plan_range(st, sc, 0, G, carry, true, false, status, nl, seq, mode, workers, red, nullptr);
+// ------------------------------------------------- plan (G <= 32768) --
+// One block per PS_THREADS consecutive groups, one group per thread.  Each
+// block first reduces the fields over the whole histogram itself (at most
+// 128 KB, from L2): that gives the totals and the exclusive field values at
+// its first group with no inter-block communication.  Block 0 publishes the
+// totals and keeps the two most frequent groups for the next histogram.
+// The histogram is cleared by the per-group phase (every touched group
+// belongs to exactly one bucket or worker), since other blocks of this
+// launch still read it; a rejected batch is cleared here.
+constexpr int PS_THREADS = 256;
+constexpr int PS_UNROLL = 8;
+
+__global__ __launch_bounds__(PS_THREADS) void k_plan_small(State st, Scratch sc, int32_t seq,
+                                                          int mode, int32_t workers) {
+    __shared__ int red[4 * (PS_THREADS / 64)];
+    __shared__ unsigned long long red_top[2 * (PS_THREADS / 64)];
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+    const int G = (int)st.G;
+    const int gb = blockIdx.x * PS_THREADS;
+    const int g = gb + tid;
+    phase_mark(sc, PHASE_HIST_PLAN, 3);
+    const int32_t status = *sc.bad == seq ? CQ_ERR_KEY_RANGE : 0;
+    if (status) {
+        if (g < G) sc.k[g] = 0;
+        if (blockIdx.x == 0 && tid == 0) {
+            const int none[PLAN_FIELDS] = {0, 0, 0};
+            plan_publish(st, sc, none, status, mode, workers);
+        }
+        return;
     }
-    top2_block(top, red_top);
-    if (tid == 0) {
-        sc.hot[0] = top.a ? (int32_t)(uint32_t)top.a : -1;
-        sc.hot[1] = top.b ? (int32_t)(uint32_t)top.b : -1;
+    // this thread's own group, loaded first
+    const int32_t kg = g < G ? sc.k[g] : 0;
+    const int32_t po = (g < G && kg > 0) ? st.pos[g] : 0;
+    const int32_t c0 = (g < G && kg > 0) ? st.cnt[g] : 0;
+    // fields: A = light tuples, B = heavy flag | touched flag << 16
+    int bA = 0, bB = 0, tA = 0, tB = 0;
+    const bool track = blockIdx.x == 0;
+    Top2 top;
+    for (int h0 = 0; h0 < G; h0 += PS_THREADS * PS_UNROLL) {
+        int32_t kv[PS_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PS_UNROLL; ++u) {
+            const int h = h0 + u * PS_THREADS + tid;
+            kv[u] = h < G ? sc.k[h] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < PS_UNROLL; ++u) {
+            const int h = h0 + u * PS_THREADS + tid;
+            int x[PLAN_FIELDS];
+            key_fields(kv[u], mode, x);
+            const int A = x[0], B = x[1] | (x[2] << 16);
+            tA += A;
+            tB += B;
+            if (h < gb) {
+                bA += A;
+                bB += B;
+            }
+            if (track && kv[u] > 0)
+                top.add(((unsigned long long)(uint32_t)kv[u] << 32) | (uint32_t)h);
+        }
+    }
+    // own group's exclusive position inside the block
+    int x[PLAN_FIELDS];
+    key_fields(kg, mode, x);
+    const int A = x[0], B = x[1] | (x[2] << 16);
+    const int iA = wave_incl_add(A), iB = wave_incl_add(B);
+    const int sbA = wave_total(wave_incl_add(bA)), sbB = wave_total(wave_incl_add(bB));
+    const int stA = wave_total(wave_incl_add(tA)), stB = wave_total(wave_incl_add(tB));
+    if (lane == 0) {
+        red[4 * wv] = sbA;
+        red[4 * wv + 1] = sbB;
+        red[4 * wv + 2] = stA;
+        red[4 * wv + 3] = stB;
+    }
+    __shared__ int wtot[2 * (PS_THREADS / 64)];
+    if (lane == 63) {
+        wtot[2 * wv] = iA;
+        wtot[2 * wv + 1] = iB;
     }
     __syncthreads();
-    phase_mark(sc, PHASE_HIST_PLAN, 5);
+    int BA = 0, BB = 0, TA = 0, TB = 0, wA = 0, wB = 0;
+#pragma unroll
+    for (int w = 0; w < PS_THREADS / 64; ++w) {
+        BA += red[4 * w];
+        BB += red[4 * w + 1];
+        TA += red[4 * w + 2];
+        TB += red[4 * w + 3];
+        if (w < wv) {
+            wA += wtot[2 * w];
+            wB += wtot[2 * w + 1];
+        }
+    }
+    const int eB = BB + wB + iB - B;
+    const int ex[PLAN_FIELDS] = {BA + wA + iA - A, eB & 0xffff, eB >> 16};
+    const int tot[PLAN_FIELDS] = {TA, TB & 0xffff, TB >> 16};
+    const int32_t nl = mode == MODE_STATIC ? 0 : (TA + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
+    if (blockIdx.x == 0 && tid == 0) plan_publish(st, sc, tot, status, mode, workers);
+    if (g < G) {
+        sc.lpre[g] = ex[0];
+        if (kg > 0) plan_group(st, sc, g, kg, ex, po, c0, nl, seq, mode, workers);
+    }
+    if (track) {
+        top2_block(top, red_top);
+        if (tid == 0) {
+            sc.hot[0] = top.a ? (int32_t)(uint32_t)top.a : -1;
+            sc.hot[1] = top.b ? (int32_t)(uint32_t)top.b : -1;
+        }
+    }
+    phase_mark(sc, PHASE_HIST_PLAN, 4);
 }
 
 // ------------------------------------------------ histogram (large G) --
@@ -487,7 +555,7 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_plan_reduce(int64_t G, int mod
     const int64_t gb = (int64_t)blockIdx.x * PLAN_CHUNK, ge = min(G, gb + PLAN_CHUNK);
     int tot[PLAN_FIELDS] = {0, 0, 0};
     State none{};
-    plan_range(none, sc, gb, ge, tot, false, false, 0, 0, 0, mode, 1, red, nullptr);
+    plan_range(none, sc, gb, ge, tot, false, 0, 0, 0, mode, 1, red);
     if (threadIdx.x == 0)
         for (int q = 0; q < PLAN_FIELDS; ++q) sc.partials[blockIdx.x * PLAN_FIELDS + q] = tot[q];
 }
@@ -523,8 +591,8 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_plan_down(State st, Scratch sc
 #pragma unroll
     for (int q = 0; q < PLAN_FIELDS; ++q) carry[q] = sc.partials[blockIdx.x * PLAN_FIELDS + q];
     const PlanTotals t = *sc.tot;
-    plan_range(st, sc, gb, ge, carry, true, false, t.status, t.n_light_buckets, seq, mode,
-               workers, red, nullptr);
+    plan_range(st, sc, gb, ge, carry, true, t.status, t.n_light_buckets, seq, mode, workers,
+               red);
 }
 
 // Whole-batch key check (used when a batch spans several sub-batches, so
@@ -580,6 +648,8 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(const int32_t *__restrict
     }
     __syncthreads();
     phase_mark(sc, PHASE_PASS, 1);
+    // only the bits that bucket ids < NB can have
+    const int nbits = NB > 1 ? 32 - __clz(NB - 1) : 0;
 #pragma unroll
     for (int r = 0; r < PASS_ROUNDS; ++r) {
         const int b = bk[r];
@@ -587,9 +657,11 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(const int32_t *__restrict
         uint64_t m = ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < NB_BITS; ++bit) {
-            const bool on = (b >> bit) & 1;
-            const uint64_t bb = ballot(on);
-            m &= on ? bb : ~bb;
+            if (bit < nbits) {
+                const bool on = (b >> bit) & 1;
+                const uint64_t bb = ballot(on);
+                m &= on ? bb : ~bb;
+            }
         }
         if (valid) {
             const uint64_t below = m & lanemask_lt();
@@ -679,6 +751,7 @@ constexpr int U_EK = U_RP + 4 * (PASS_TILES_MAX + 4);    // i32[LIGHT_CAP] keys
 constexpr int U_EV = U_EK + 4 * LIGHT_CAP;               // i32[LIGHT_CAP] values
 constexpr int U_PZ = U_EV + 4 * LIGHT_CAP;               // i16[LIGHT_CAP] group start in bucket
 constexpr int U_LR = U_PZ + 2 * LIGHT_CAP;               // u16[LIGHT_CAP] rank inside wave chunk
+                                                         // (first: u8 run of each position)
 constexpr int U_HD = U_LR + 2 * LIGHT_CAP;               // i16[LIGHT_CAP] tuple of rank 0
 constexpr int U_CW = U_HD + 2 * LIGHT_CAP;               // u16[UPD_WAVES][LIGHT_CAP]
 constexpr int UPD_WAVES = UPD_THREADS / 64;
@@ -686,10 +759,13 @@ constexpr int U_ACC = U_CW + 2 * UPD_WAVES * LIGHT_CAP;  // i64[LIGHT_CAP] sum d
 // a light bucket whose groups span at most LIGHT_SPAN ids keeps their
 // staged-range starts and old ring pointers in LDS
 constexpr int LIGHT_SPAN = 2048;
+static_assert(LIGHT_SPAN % UPD_THREADS == 0, "whole groups per thread");
 constexpr int U_KLP = U_ACC + 8 * LIGHT_CAP;             // i32[LIGHT_SPAN + 1]
 constexpr int U_KPO = U_KLP + 4 * (LIGHT_SPAN + 4);      // i32[LIGHT_SPAN]
 constexpr int U_BYTES = U_KPO + 4 * LIGHT_SPAN;
 static_assert(LIGHT_CAP <= 32768, "16-bit positions");
+static_assert(PASS_TILES_MAX <= 256, "8-bit run indices");
+static_assert(LIGHT_CAP % UPD_THREADS == 0, "whole positions per thread");
 
 // Light bucket b: groups [bstart[b], bstart[b+1]) packed by the plan, fewer
 // than LIGHT_CAP tuples, read in arrival order.  Each wave takes a
@@ -721,8 +797,42 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
         if (tid == 0) atomicOr(sc.fault, FAULT_LIGHT_SIZE);
         return 0;
     }
+    // run (tile) of every bucket position, so the gather below needs one
+    // LDS read instead of a binary search over the runs: mark each
+    // non-empty run's tile at its first position, then a running maximum
+    // over the positions (tile ids grow with position).  lr is free until
+    // the ranks.
+    uint8_t *rt = reinterpret_cast<uint8_t *>(lr);
+    {
+        constexpr int PPT = LIGHT_CAP / UPD_THREADS;
+        for (int p = tid; p < size; p += blockDim.x) rt[p] = 0;
+        __syncthreads();
+        for (int r = tid; r < tiles; r += blockDim.x)
+            if (rp[r + 1] > rp[r]) rt[rp[r]] = (uint8_t)r;
+        __syncthreads();
+        int loc[PPT], m = 0;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int p = tid * PPT + j;
+            m = max(m, p < size ? (int)rt[p] : 0);
+            loc[j] = m;
+        }
+        const int incl = wave_incl_max(m);
+        int *wred = reinterpret_cast<int *>(ev);  // ev is filled only below
+        if (lane == 63) wred[wv] = incl;
+        __syncthreads();
+        int before = __shfl_up(incl, 1, 64);
+        if (lane == 0) before = 0;
+        for (int w = 0; w < wv; ++w) before = max(before, wred[w]);
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int p = tid * PPT + j;
+            if (p < size) rt[p] = (uint8_t)max(before, loc[j]);
+        }
+        __syncthreads();
+    }
     for (int p = tid; p < size; p += blockDim.x) {
-        const int r = upper_run(rp, tiles, p);
+        const int r = rt[p];
         const int2 e = sc.sdat[rs[r] + (p - rp[r])];
         const int32_t g = e.x;
         int32_t p0 = -1;
@@ -747,6 +857,7 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
     const int chunk = (size + UPD_WAVES - 1) / UPD_WAVES;
     const int c0 = min(size, wv * chunk), c1 = min(size, c0 + chunk);
     uint16_t *mycw = cw + wv * LIGHT_CAP;
+    const int pbits = size > 1 ? 32 - __clz(size - 1) : 0;  // bits of positions < size
     for (int r0 = c0; r0 < c1; r0 += 64) {
         const int p = r0 + lane;
         const bool valid = p < c1 && pz[p] >= 0;
@@ -754,9 +865,11 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
         uint64_t m = ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < LIGHT_BITS; ++bit) {
-            const bool on = (p0 >> bit) & 1;
-            const uint64_t bb = ballot(on);
-            m &= on ? bb : ~bb;
+            if (bit < pbits) {
+                const bool on = (p0 >> bit) & 1;
+                const uint64_t bb = ballot(on);
+                m &= on ? bb : ~bb;
+            }
         }
         if (valid) {
             const uint64_t below = m & lanemask_lt();
@@ -779,6 +892,21 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
     __syncthreads();
     const int32_t W = st.W;
     phase_mark(sc, PHASE_UPDATE, 3);
+    // the touched groups' sums, counts and output slots are loaded now, so
+    // that their latency overlaps the ring update below
+    constexpr int GPT = LIGHT_SPAN / UPD_THREADS;
+    int64_t gsum[GPT];
+    int32_t gcnt[GPT], gtix[GPT];
+    if (in_lds) {
+#pragma unroll
+        for (int j = 0; j < GPT; ++j) {
+            const int32_t g = a + tid + j * UPD_THREADS;
+            const bool t = g < z && klp[g - a + 1] > klp[g - a];
+            gsum[j] = t ? st.sum[g] : 0;
+            gcnt[j] = t ? st.cnt[g] : 0;
+            gtix[j] = t ? sc.tidx[g] : 0;
+        }
+    }
     for (int p = tid; p < size; p += blockDim.x) {
         const int p0 = pz[p];
         if (p0 < 0) continue;
@@ -800,12 +928,24 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
     }
     __syncthreads();
     phase_mark(sc, PHASE_UPDATE, 4);
-    for (int i = tid; i < size; i += blockDim.x) {
-        const int32_t g = hd[i] >= 0 ? ek[hd[i]] : -1;
-        if (g >= 0) {
-            const int64_t s = st.sum[g] + acc[i];
-            st.sum[g] = s;
-            if (out.n_touched) emit_one(out, sc.tidx[g], g, s, st.cnt[g]);
+    if (in_lds) {
+#pragma unroll
+        for (int j = 0; j < GPT; ++j) {
+            const int32_t g = a + tid + j * UPD_THREADS;
+            if (g < z && klp[g - a + 1] > klp[g - a]) {
+                const int64_t s = gsum[j] + acc[klp[g - a] - s0];
+                st.sum[g] = s;
+                if (out.n_touched) emit_one(out, gtix[j], g, s, gcnt[j]);
+            }
+        }
+    } else {
+        for (int i = tid; i < size; i += blockDim.x) {
+            const int32_t g = hd[i] >= 0 ? ek[hd[i]] : -1;
+            if (g >= 0) {
+                const int64_t s = st.sum[g] + acc[i];
+                st.sum[g] = s;
+                if (out.n_touched) emit_one(out, sc.tidx[g], g, s, st.cnt[g]);
+            }
         }
     }
     __syncthreads();
@@ -823,7 +963,18 @@ __device__ int heavy_bucket(int32_t g, int32_t pold_g, int size, int tiles, cons
     const int32_t need = size < W ? size : W;
     const bool full = size >= W;
     const uint32_t po = (uint32_t)pold_g;
+    // loaded early: their latency overlaps the survivors' loads
+    int64_t gsum = 0;
+    int32_t gcnt = 0, gtix = 0;
+    if (tid == 0) {
+        gsum = st.sum[g];
+        gcnt = st.cnt[g];
+        gtix = sc.tidx[g];
+    }
     long long acc = 0;
+    // (a run table as in light buckets would cost one thread a serial loop
+    // over a hot group's whole run in the last tile; a binary search per
+    // survivor is cheaper here)
     for (int p = size - need + tid; p < size; p += blockDim.x) {
         const int r = upper_run(rp, tiles, p);
         const int32_t v = sc.sdat[rs[r] + (p - rp[r])].y;
@@ -835,9 +986,9 @@ __device__ int heavy_bucket(int32_t g, int32_t pold_g, int size, int tiles, cons
     }
     const long long delta = block_sum_ll(acc, red_ll);
     if (tid == 0) {
-        const int64_t s = st.sum[g] + delta;
+        const int64_t s = gsum + delta;
         st.sum[g] = s;
-        if (out.n_touched) emit_one(out, sc.tidx[g], g, s, st.cnt[g]);
+        if (out.n_touched) emit_one(out, gtix, g, s, gcnt);
     }
     __syncthreads();
     return need;
@@ -893,6 +1044,12 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_balanced(State st, Scrat
             tuples += light_bucket(a, z, size, tiles, st, sc, out, smem);
         else
             tuples += heavy_bucket(g, pold_g, size, tiles, st, sc, out, smem, red_ll);
+        // clear the bucket's histogram entries for the next sub-batch (the
+        // buckets partition the touched groups)
+        if (light)
+            for (int i = threadIdx.x; i < z - a; i += blockDim.x) sc.k[a + i] = 0;
+        else if (threadIdx.x == 0)
+            sc.k[g] = 0;
         ++items;
     }
     phase_mark(sc, PHASE_UPDATE, 5);
@@ -944,6 +1101,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_static(State st, Scratch
             for (int i = lane; i < nk; i += 64) {
                 ctr[i] = 0;
                 acc[i] = 0;
+                sc.k[g0 + i] = 0;  // histogram, for the next sub-batch
             }
             // runs of bucket w, and a wave-wide exclusive scan of their sizes
             int carry = 0;
@@ -1128,19 +1286,28 @@ hipError_t launch_validate(const int32_t *keys, int64_t n, int64_t G, int32_t se
     return hipGetLastError();
 }
 
-hipError_t launch_hist_plan(const int32_t *keys, int64_t n, State st, Scratch sc, int32_t seq,
-                            int mode, int32_t workers, hipStream_t s) {
-    const int64_t G = st.G;
-    if (G <= PLAN_CHUNK && G <= HIST_DIRECT_MAX_G) {
+hipError_t launch_hist(const int32_t *keys, int64_t n, int64_t G, Scratch sc, int32_t seq,
+                       hipStream_t s) {
+    if (G <= HIST_DIRECT_MAX_G) {
         const int64_t grid = hist_blocks(n, G);
-        hipLaunchKernelGGL(k_hist_plan_small, dim3((unsigned)grid), dim3(HIST_THREADS),
-                           (size_t)G * 4, s, keys, n, aligned16(keys), st, sc, seq, mode,
-                           workers);
+        hipLaunchKernelGGL(k_hist_small, dim3((unsigned)grid), dim3(HIST_THREADS),
+                           (size_t)G * 4, s, keys, n, aligned16(keys), (int32_t)G, sc, seq);
+    } else {
+        const int64_t tiles = std::max<int64_t>((n + HIST_HASH_TILE - 1) / HIST_HASH_TILE, 1);
+        hipLaunchKernelGGL(k_hist_hash, dim3((unsigned)tiles), dim3(HIST_THREADS),
+                           (size_t)2 * HIST_HASH_SLOTS * 4, s, keys, n, G, seq, sc);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_plan(State st, Scratch sc, int32_t seq, int mode, int32_t workers,
+                       hipStream_t s) {
+    const int64_t G = st.G;
+    if (G <= HIST_DIRECT_MAX_G) {
+        hipLaunchKernelGGL(k_plan_small, dim3((unsigned)((G + PS_THREADS - 1) / PS_THREADS)),
+                           dim3(PS_THREADS), 0, s, st, sc, seq, mode, workers);
         return hipGetLastError();
     }
-    const int64_t tiles = std::max<int64_t>((n + HIST_HASH_TILE - 1) / HIST_HASH_TILE, 1);
-    hipLaunchKernelGGL(k_hist_hash, dim3((unsigned)tiles), dim3(HIST_THREADS),
-                       (size_t)2 * HIST_HASH_SLOTS * 4, s, keys, n, G, seq, sc);
     const int64_t nblk = (G + PLAN_CHUNK - 1) / PLAN_CHUNK;
     hipLaunchKernelGGL(k_plan_reduce, dim3((unsigned)nblk), dim3(PLAN_THREADS), 0, s, G, mode,
                        sc);

@@ -99,7 +99,6 @@ void free_all(cq_query *q) {
     dfree(q->sc.rowstart);
     dfree(q->sc.partials);
     dfree(q->sc.bad);
-    dfree(q->sc.done);
     dfree(q->sc.fault);
     dfree(q->sc.hot);
     dfree(q->sc.tot);
@@ -133,7 +132,8 @@ hipEvent_t take_event(cq_query *q) {
         return e;
     }
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    // no system-scope fences: these events only time device work
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
@@ -204,9 +204,12 @@ int push(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n, hip
         const int64_t off = b * SUB;
         const int64_t m = std::min<int64_t>(SUB, n - off);
         const Out o = (out && nsub == 1) ? *out : none;
-        rc = timed(q, CQ_KERNEL_HIST_PLAN, s, [&] {
-            return launch_hist_plan(keys + off, m, q->st, sc, seq, q->mode, q->workers, s);
-        });
+        rc = timed(q, CQ_KERNEL_HIST, s,
+                   [&] { return launch_hist(keys + off, m, q->st.G, sc, seq, s); });
+        if (rc == CQ_OK)
+            rc = timed(q, CQ_KERNEL_PLAN, s, [&] {
+                return launch_plan(q->st, sc, seq, q->mode, q->workers, s);
+            });
         if (rc == CQ_OK)
             rc = timed(q, CQ_KERNEL_PASS, s,
                        [&] { return launch_pass(keys + off, values + off, m, sc, s); });
@@ -277,7 +280,6 @@ int cq_create(int64_t groups, int32_t window, uint32_t aggregates, cq_query **ou
     if (rc == CQ_OK) rc = dalloc(&q->sc.rowstart, (int64_t)PASS_TILES_MAX * (NB_MAX + 1));
     if (rc == CQ_OK) rc = dalloc(&q->sc.partials, nblk * PLAN_FIELDS);
     if (rc == CQ_OK) rc = dalloc(&q->sc.bad, 1);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.done, 1);
     if (rc == CQ_OK) rc = dalloc(&q->sc.fault, 1);
     if (rc == CQ_OK) rc = dalloc(&q->sc.hot, 2);
     if (rc == CQ_OK) rc = dalloc(&q->sc.tot, 1);
@@ -294,7 +296,6 @@ int cq_create(int64_t groups, int32_t window, uint32_t aggregates, cq_query **ou
         if (e == hipSuccess) e = hipMemset(q->sc.bucket, 0, sizeof(int32_t) * (size_t)G);
         if (e == hipSuccess) e = hipMemset(q->sc.lpre, 0, sizeof(int32_t) * (size_t)(G + 1));
         if (e == hipSuccess) e = hipMemset(q->sc.bad, 0, sizeof(int32_t));
-        if (e == hipSuccess) e = hipMemset(q->sc.done, 0, sizeof(uint32_t));
         if (e == hipSuccess) e = hipMemset(q->sc.fault, 0, sizeof(int32_t));
         if (e == hipSuccess) e = hipMemset(q->sc.hot, 0xff, 2 * sizeof(int32_t));
         if (e == hipSuccess) e = hipMemset(q->sc.tot, 0, sizeof(PlanTotals));
