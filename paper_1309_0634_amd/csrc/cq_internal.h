@@ -18,7 +18,7 @@ constexpr int SUB = 1 << 20;
 // LDS arrays indexed by key while groups <= HIST_DIRECT_MAX_G, otherwise an
 // open-addressing LDS hash of HIST_HASH_SLOTS slots over HIST_HASH_TILE tuples.
 constexpr int HIST_THREADS = 1024;
-constexpr int HIST_KPT = 32;
+constexpr int HIST_KPT = 8;
 constexpr int HIST_TILE = HIST_THREADS * HIST_KPT;
 constexpr int HIST_DIRECT_MAX_G = 32768;
 constexpr int HIST_HASH_TILE = 8192;

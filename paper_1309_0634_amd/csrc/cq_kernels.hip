@@ -390,7 +390,11 @@ __global__ __launch_bounds__(HIST_THREADS) void k_hist_small(const int32_t *__re
         if (tid == 0) atomicExch(sc.bad, seq);
     }
     phase_mark(sc, PHASE_HIST_PLAN, 1);
-    for (int g = tid; g < G; g += HIST_THREADS) {
+    // blocks start their flush at evenly spread groups, so that they do not
+    // all hit the same counters at the same time
+    const int off = (int)(((int64_t)blockIdx.x * G / gridDim.x) & ~63);
+    for (int i = tid; i < G; i += HIST_THREADS) {
+        const int g = i + off < G ? i + off : i + off - G;
         const int32_t c = cntr[g];
         if (c) atomicAdd(&sc.k[g], c);
     }
@@ -406,8 +410,8 @@ __global__ __launch_bounds__(HIST_THREADS) void k_hist_small(const int32_t *__re
 // The histogram is cleared by the per-group phase (every touched group
 // belongs to exactly one bucket or worker), since other blocks of this
 // launch still read it; a rejected batch is cleared here.
-constexpr int PS_THREADS = 256;
-constexpr int PS_UNROLL = 8;
+constexpr int PS_THREADS = 1024;
+constexpr int PS_UNROLL = 16;
 
 __global__ __launch_bounds__(PS_THREADS) void k_plan_small(State st, Scratch sc, int32_t seq,
                                                           int mode, int32_t workers) {
