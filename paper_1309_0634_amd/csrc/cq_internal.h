@@ -53,6 +53,14 @@ constexpr int PASS_WAVES = 8;
 constexpr int PASS_THREADS = 64 * PASS_WAVES;
 constexpr int PASS_ROUNDS = PASS_TILE / PASS_THREADS;
 constexpr int PASS_TILES_MAX = SUB / PASS_TILE;
+// Up to PASS_LOCAL_G groups the plan is computed inside the pass: every
+// pass block reduces the whole histogram itself and keeps each group's
+// bucket in LDS (16-bit), so no separate plan launch is needed.
+constexpr int PASS_LOCAL_G = 16384;
+constexpr int PL_PER = (PASS_LOCAL_G + PASS_THREADS - 1) / PASS_THREADS;
+static_assert(PL_PER % 4 == 0, "int4 histogram loads");
+static_assert(NB_MAX < 65536, "16-bit bucket ids");
+__host__ __device__ constexpr bool plan_fused(int64_t G) { return G <= PASS_LOCAL_G; }
 static_assert(PASS_TILE / PASS_WAVES < 65536, "per-wave counters are 16-bit");
 
 // Per-group phase.
@@ -144,8 +152,8 @@ hipError_t launch_hist(const int32_t *keys, int64_t n, int64_t G, Scratch sc, in
                        hipStream_t s);
 hipError_t launch_plan(State st, Scratch sc, int32_t seq, int mode, int32_t workers,
                        hipStream_t s);
-hipError_t launch_pass(const int32_t *keys, const int32_t *values, int64_t n, Scratch sc,
-                       hipStream_t s);
+hipError_t launch_pass(const int32_t *keys, const int32_t *values, int64_t n, State st,
+                       Scratch sc, int32_t seq, int mode, int32_t workers, hipStream_t s);
 hipError_t launch_update(State st, Scratch sc, int64_t n, int mode, int32_t workers, Out out,
                          hipStream_t s);
 hipError_t launch_collect_touched(int64_t G, int32_t seq, Scratch sc, hipStream_t s);

@@ -620,22 +620,180 @@ __global__ void k_validate(const int32_t *__restrict__ keys, int64_t n, int64_t 
 // plus a per-wave counter.  Waves then combine into tile-wide bucket
 // offsets, the tile is reordered in LDS and written back contiguously, and
 // the tile's bucket starts are recorded.  Tiles never wait on each other.
+// In-block plan of the fused pass (G <= PASS_LOCAL_G).  Every block reduces
+// the whole histogram itself (thread t scans a contiguous run of groups),
+// so each knows the bucket of every group without waiting on any other
+// block: gbk[g] gets the bucket of each touched group (gcnt holds the
+// counts meanwhile).  The per-group plan
+// of group g is written by block g mod gridDim only; block 0 publishes the
+// totals and keeps the two most frequent groups for the next histogram.
+// Returns the bucket count, or -1 for a rejected batch (whose histogram is
+// cleared here: no block reads it then).  Barriers inside; call uniformly.
+__device__ int pass_local_plan(const State &st, const Scratch &sc, int32_t seq, int mode,
+                               int32_t workers, uint16_t *gbk, int32_t *gcnt, int *red,
+                               unsigned long long *red_top) {
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6, nw = blockDim.x >> 6;
+    const int G = (int)st.G;
+    const int D = gridDim.x, me = blockIdx.x;
+    if (*sc.bad == seq) {
+        for (int g = me * blockDim.x + tid; g < G; g += D * blockDim.x) sc.k[g] = 0;
+        if (me == 0 && tid == 0) {
+            const int none[PLAN_FIELDS] = {0, 0, 0};
+            plan_publish(st, sc, none, CQ_ERR_KEY_RANGE, mode, workers);
+        }
+        return -1;
+    }
+    // this thread's groups [g0, g0 + R), R a multiple of 4 (int4 loads)
+    const int R = ((G + (int)blockDim.x - 1) / (int)blockDim.x + 3) & ~3;
+    const int g0 = tid * R;
+    int32_t kv[PL_PER];
+#pragma unroll
+    for (int q = 0; q < PL_PER / 4; ++q) {
+        const int g = g0 + 4 * q;
+        if (4 * q < R && g + 3 < G) {
+            const int4 x = *reinterpret_cast<const int4 *>(sc.k + g);
+            kv[4 * q] = x.x; kv[4 * q + 1] = x.y; kv[4 * q + 2] = x.z; kv[4 * q + 3] = x.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) kv[4 * q + e] = (4 * q < R && g + e < G) ? sc.k[g + e] : 0;
+        }
+    }
+    // first group of the run owned by this block; its state is loaded now
+    const int own0 = g0 + ((me - g0 % D) % D + D) % D;
+    int32_t po0 = 0, c00 = 0;
+    if (own0 < min(G, g0 + R)) {
+        po0 = st.pos[own0];
+        c00 = st.cnt[own0];
+    }
+    int sA = 0, sB = 0;
+    const bool track = me == 0;
+    Top2 top;
+#pragma unroll
+    for (int j = 0; j < PL_PER; ++j) {
+        int x[PLAN_FIELDS];
+        key_fields(kv[j], mode, x);
+        sA += x[0];
+        sB += x[1] | (x[2] << 16);
+        if (track && kv[j] > 0)
+            top.add(((unsigned long long)(uint32_t)kv[j] << 32) | (uint32_t)(g0 + j));
+        if (j < R && g0 + j < G) gcnt[g0 + j] = kv[j];
+    }
+    phase_mark(sc, PHASE_PASS, 5);
+    const int iA = wave_incl_add(sA), iB = wave_incl_add(sB);
+    if (lane == 63) {
+        red[2 * wv] = iA;
+        red[2 * wv + 1] = iB;
+    }
+    __syncthreads();
+    phase_mark(sc, PHASE_PASS, 6);
+    int bA = 0, bB = 0, TA = 0, TB = 0;
+    for (int w = 0; w < nw; ++w) {
+        const int xa = red[2 * w], xb = red[2 * w + 1];
+        if (w < wv) {
+            bA += xa;
+            bB += xb;
+        }
+        TA += xa;
+        TB += xb;
+    }
+    const int tot[PLAN_FIELDS] = {TA, TB & 0xffff, TB >> 16};
+    const int32_t nl = mode == MODE_STATIC ? 0 : (TA + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
+    const int NB = mode == MODE_STATIC ? workers : nl + tot[1];
+    if (me == 0 && tid == 0) plan_publish(st, sc, tot, 0, mode, workers);
+    // bucket of every group of the run (a lean loop: it runs over all G
+    // groups in every block), then the plan of the first group this block
+    // owns, whose state was loaded early
+    int eA = bA + iA - sA, eB = bB + iB - sB;
+    const int gend = min(G, g0 + R);
+    int oA = 0, oB = 0;
+    if (mode == MODE_STATIC) {
+        for (int g = g0; g < gend; ++g) {
+            const int32_t ks = gcnt[g];
+            if (ks > 0) gbk[g] = (uint16_t)(((uint32_t)g * (uint32_t)workers) / (uint32_t)G);
+            if (g == own0) {
+                oA = eA;
+                oB = eB;
+            }
+            eA += ks;
+            eB += ks > 0 ? 1 << 16 : 0;
+        }
+    } else {
+        for (int g = g0; g < gend; ++g) {
+            const int32_t ks = gcnt[g];
+            const bool heavy = ks >= HEAVY_MIN;
+            if (ks > 0)
+                gbk[g] = (uint16_t)(heavy ? nl + (eB & 0xffff) : (eA + ks - 1) / LIGHT_BUDGET);
+            if (g == own0) {
+                oA = eA;
+                oB = eB;
+            }
+            eA += heavy ? 0 : ks;
+            eB += (heavy ? 1 : 0) + (ks > 0 ? 1 << 16 : 0);
+        }
+    }
+    if (own0 < gend) {
+        const int ex[PLAN_FIELDS] = {oA, oB & 0xffff, oB >> 16};
+        const int32_t ks = gcnt[own0];
+        sc.lpre[own0] = ex[0];
+        if (ks > 0) plan_group(st, sc, own0, ks, ex, po0, c00, nl, seq, mode, workers);
+    }
+    if (D < R) {
+        // a small grid owns several groups of a run: walk it again
+        eA = bA + iA - sA;
+        eB = bB + iB - sB;
+        for (int g = g0; g < gend; ++g) {
+            const int32_t ks = gcnt[g];
+            if (g > own0 && (g - own0) % D == 0) {
+                const int ex[PLAN_FIELDS] = {eA, eB & 0xffff, eB >> 16};
+                sc.lpre[g] = ex[0];
+                if (ks > 0)
+                    plan_group(st, sc, g, ks, ex, st.pos[g], st.cnt[g], nl, seq, mode, workers);
+            }
+            int x[PLAN_FIELDS];
+            key_fields(ks, mode, x);
+            eA += x[0];
+            eB += x[1] | (x[2] << 16);
+        }
+    }
+    phase_mark(sc, PHASE_PASS, 7);
+    if (track) {
+        top2_block(top, red_top);
+        if (tid == 0) {
+            sc.hot[0] = top.a ? (int32_t)(uint32_t)top.a : -1;
+            sc.hot[1] = top.b ? (int32_t)(uint32_t)top.b : -1;
+        }
+    }
+    __syncthreads();
+    return NB;
+}
+
+constexpr int P_WC = 0;                                            // u16[PASS_WAVES][NB_MAX]
+constexpr int P_STAGE = (P_WC + 2 * PASS_WAVES * NB_MAX + 15) & ~15;  // int2[PASS_TILE]
+constexpr int P_BYTES = P_STAGE + 8 * PASS_TILE;
+static_assert(P_BYTES >= 4 * PASS_LOCAL_G, "group counts fit the pool");
+
+// Multisplit pass.  LOCAL: the plan is computed in the block (above) and
+// bucket ids come from LDS; otherwise they are read from the plan's global
+// per-group buckets.
+template <bool LOCAL>
 __global__ __launch_bounds__(PASS_THREADS) void k_pass(const int32_t *__restrict__ keys,
                                                        const int32_t *__restrict__ values,
-                                                       int64_t n, Scratch sc) {
-    __shared__ uint16_t wc[PASS_WAVES][NB_MAX];
+                                                       int64_t n, State st, Scratch sc,
+                                                       int32_t seq, int mode, int32_t workers) {
+    // per-wave bucket counters and the reordered tile; during an in-block
+    // plan the same bytes hold the group counts
+    __shared__ __align__(16) char pool[P_BYTES];
+    uint16_t (*wc)[NB_MAX] = reinterpret_cast<uint16_t (*)[NB_MAX]>(pool + P_WC);
+    int2 *stage = reinterpret_cast<int2 *>(pool + P_STAGE);
     __shared__ int32_t ts[NB_MAX + 1];
-    __shared__ int2 stage[PASS_TILE];
     __shared__ int red[PASS_WAVES];
-    const PlanTotals t = *sc.tot;
-    if (t.status) return;
-    const int NB = t.n_buckets;
-    if (NB > NB_MAX) return;
+    __shared__ uint16_t gbk[LOCAL ? PASS_LOCAL_G : 1];
+    __shared__ int pred[2 * PASS_WAVES];
+    __shared__ unsigned long long ptop[2 * PASS_WAVES];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const int64_t base = (int64_t)blockIdx.x * PASS_TILE;
     const int tile_n = (int)min((int64_t)PASS_TILE, n - base);
     phase_mark(sc, PHASE_PASS, 0);
-    for (int i = tid; i < PASS_WAVES * NB; i += PASS_THREADS) wc[i / NB][i % NB] = 0;
     int32_t key[PASS_ROUNDS], val[PASS_ROUNDS], bk[PASS_ROUNDS], lr[PASS_ROUNDS];
 #pragma unroll
     for (int r = 0; r < PASS_ROUNDS; ++r) {
@@ -644,12 +802,30 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(const int32_t *__restrict
         key[r] = valid ? keys[i] : 0;
         val[r] = valid ? values[i] : 0;
     }
+    int NB;
+    if (LOCAL) {
+        NB = pass_local_plan(st, sc, seq, mode, workers, gbk, reinterpret_cast<int32_t *>(pool),
+                             pred, ptop);
+        if (NB < 0 || NB > NB_MAX) return;
 #pragma unroll
-    for (int r = 0; r < PASS_ROUNDS; ++r) {
-        const int64_t i = base + wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane;
-        bk[r] = (i < n) ? sc.bucket[key[r]] : NB;
-        lr[r] = 0;
+        for (int r = 0; r < PASS_ROUNDS; ++r) {
+            const int64_t i = base + wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane;
+            bk[r] = (i < n && (uint32_t)key[r] < (uint32_t)st.G) ? gbk[key[r]] : NB;
+            lr[r] = 0;
+        }
+    } else {
+        const PlanTotals t = *sc.tot;
+        if (t.status) return;
+        NB = t.n_buckets;
+        if (NB > NB_MAX) return;
+#pragma unroll
+        for (int r = 0; r < PASS_ROUNDS; ++r) {
+            const int64_t i = base + wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane;
+            bk[r] = (i < n) ? sc.bucket[key[r]] : NB;
+            lr[r] = 0;
+        }
     }
+    for (int i = tid; i < PASS_WAVES * NB; i += PASS_THREADS) wc[i / NB][i % NB] = 0;
     __syncthreads();
     phase_mark(sc, PHASE_PASS, 1);
     // only the bits that bucket ids < NB can have
@@ -1307,6 +1483,7 @@ hipError_t launch_hist(const int32_t *keys, int64_t n, int64_t G, Scratch sc, in
 hipError_t launch_plan(State st, Scratch sc, int32_t seq, int mode, int32_t workers,
                        hipStream_t s) {
     const int64_t G = st.G;
+    if (plan_fused(G)) return hipSuccess;  // planned inside the pass
     if (G <= HIST_DIRECT_MAX_G) {
         hipLaunchKernelGGL(k_plan_small, dim3((unsigned)((G + PS_THREADS - 1) / PS_THREADS)),
                            dim3(PS_THREADS), 0, s, st, sc, seq, mode, workers);
@@ -1322,11 +1499,15 @@ hipError_t launch_plan(State st, Scratch sc, int32_t seq, int mode, int32_t work
     return hipGetLastError();
 }
 
-hipError_t launch_pass(const int32_t *keys, const int32_t *values, int64_t n, Scratch sc,
-                       hipStream_t s) {
+hipError_t launch_pass(const int32_t *keys, const int32_t *values, int64_t n, State st,
+                       Scratch sc, int32_t seq, int mode, int32_t workers, hipStream_t s) {
     const int64_t tiles = (n + PASS_TILE - 1) / PASS_TILE;
-    hipLaunchKernelGGL(k_pass, dim3((unsigned)tiles), dim3(PASS_THREADS), 0, s, keys, values, n,
-                       sc);
+    if (plan_fused(st.G))
+        hipLaunchKernelGGL(k_pass<true>, dim3((unsigned)tiles), dim3(PASS_THREADS), 0, s, keys,
+                           values, n, st, sc, seq, mode, workers);
+    else
+        hipLaunchKernelGGL(k_pass<false>, dim3((unsigned)tiles), dim3(PASS_THREADS), 0, s, keys,
+                           values, n, st, sc, seq, mode, workers);
     return hipGetLastError();
 }
 

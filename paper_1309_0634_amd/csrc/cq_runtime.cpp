@@ -206,13 +206,15 @@ int push(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n, hip
         const Out o = (out && nsub == 1) ? *out : none;
         rc = timed(q, CQ_KERNEL_HIST, s,
                    [&] { return launch_hist(keys + off, m, q->st.G, sc, seq, s); });
-        if (rc == CQ_OK)
+        if (rc == CQ_OK && !plan_fused(q->st.G))
             rc = timed(q, CQ_KERNEL_PLAN, s, [&] {
                 return launch_plan(q->st, sc, seq, q->mode, q->workers, s);
             });
         if (rc == CQ_OK)
-            rc = timed(q, CQ_KERNEL_PASS, s,
-                       [&] { return launch_pass(keys + off, values + off, m, sc, s); });
+            rc = timed(q, CQ_KERNEL_PASS, s, [&] {
+                return launch_pass(keys + off, values + off, m, q->st, sc, seq, q->mode,
+                                   q->workers, s);
+            });
         if (rc == CQ_OK)
             rc = timed(q, CQ_KERNEL_UPDATE, s, [&] {
                 return launch_update(q->st, sc, m, q->mode, q->workers, o, s);
