@@ -7,7 +7,8 @@ batches of 1,048,576 int32 (key, value) tuples, keys Zipf(s) over
 All batches are generated on the device and resident in HBM before timing.
 
 Reported: tuples/s and algorithmic HBM GB/s for s in {0, 0.5, 1, 1.5, 2},
-balanced vs static partition, p50/p99 batch latency.  The headline value
+balanced vs static partition, p50/p99 batch latency, and the imbalance of
+the per-group phase (per-CU busy-time spread, per-workgroup tuple loads).  The headline value
 is s=1.5, balanced.  Throughput, batch latency (an event pair per batch)
 and kernel durations (the library's per-launch events) come from three
 separate runs over the same batches, because events are stream markers
@@ -108,6 +109,50 @@ def run_mode(torch, cq, batches, cfg, mode, warmup, steps, kind="clean"):
     res["plan"] = q.batch_plan()
     q.close()
     return res
+
+
+def imbalance(torch, cq, batches, cfg, mode, warmup=3):
+    """Per-CU busy time of the per-group phase on one batch (after `warmup`
+    batches): the union of the device-clock intervals of the workgroups that
+    ran on each compute unit (XCC, shader engine, array, CU from the HW_ID
+    register), over the CUs that did work.  Also the per-workgroup tuple
+    loads (the paper's per-worker tuple counts)."""
+    q = cq.Query(cfg.groups, cfg.window, partition=mode)
+    for b in range(warmup):
+        q.push(*batches[b])
+    q.set_telemetry(cq.TELEMETRY_WORKERS)
+    q.push(*batches[warmup])
+    rec = q.worker_trace()
+    q.set_telemetry(0)
+    q.close()
+    t_first = min(r[2] for r in rec)
+    per_cu = {}
+    for hw, xcc, t0, t1, tuples, items in rec:
+        if tuples <= 0:
+            continue
+        cu = (xcc, (hw >> 13) & 7, (hw >> 12) & 1, (hw >> 8) & 15)
+        per_cu.setdefault(cu, []).append((t0, t1))
+    busy = []
+    for iv in per_cu.values():
+        iv.sort()
+        tot, cs, ce = 0, iv[0][0], iv[0][1]
+        for a, b in iv[1:]:
+            if a > ce:
+                tot += ce - cs
+                cs, ce = a, b
+            else:
+                ce = max(ce, b)
+        busy.append((tot + ce - cs) * 0.01)  # 100 MHz ticks -> us
+    loads = [r[4] for r in rec if r[4] > 0]
+    busy = np.array(busy)
+    span = (max(r[3] for r in rec) - t_first) * 0.01
+    return {"cus_with_work": int(len(busy)),
+            "cu_busy_max_us": round(float(busy.max()), 2),
+            "cu_busy_mean_us": round(float(busy.mean()), 2),
+            "cu_busy_max_over_mean": round(float(busy.max() / busy.mean()), 3),
+            "cu_busy_cv": round(float(busy.std() / busy.mean()), 3),
+            "phase_span_us": round(span, 2),
+            "wg_tuples_max_over_mean": round(float(max(loads) / np.mean(loads)), 3)}
 
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1309_0634_amd", "csrc", "cq_kernels.hip")
@@ -214,6 +259,7 @@ def main():
                 "heavy_groups": int(r["plan"]["heavy_groups"]),
                 "buckets": int(r["plan"]["buckets"]),
                 "touched": int(r["plan"]["touched"]),
+                "imbalance": imbalance(torch, cq, batches, cfg, mode),
             }
             rows.append(row)
             print(json.dumps({"progress": row}), file=sys.stderr, flush=True)
@@ -271,6 +317,7 @@ def main():
         "alg_GBps": row["alg_GBps"],
         "p50_batch_ms": row["p50_batch_ms"],
         "p99_batch_ms": row["p99_batch_ms"],
+        "imbalance_s1.5": {r["partition"]: r["imbalance"] for r in rows if r["s"] == HEADLINE_S},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "cpu_baseline_all_threads": cpu_mt,

@@ -156,6 +156,33 @@ int cq_push_batch_results(cq_query *q, const int32_t *keys, const int32_t *value
                           int64_t *n_touched, void *stream);
 
 /*
+ * cq_push_batches -- `count` consecutive batches of one stream in one call:
+ * the same state and the same per-batch results as cq_push_batch_results
+ * on each batch in order (Section 3.1's iteration over incoming batches).
+ *   keys[i], values[i] : device int32[n[i]] of batch i (host array of
+ *                        device pointers), 0 <= n[i] <= 2^20 (CQ_PIPE_MAX)
+ *   ids[i], sums[i], counts[i], avgs[i], n_touched[i] : batch i's result
+ *                        buffers as for cq_results (the four arrays of
+ *                        pointers may be NULL, n_touched[i] may not)
+ * The batches' launches are overlapped inside the library: batch i+1's
+ * histogram, plan and reorder run while batch i's per-group phase runs, on
+ * two library streams with two sets of batch-local buffers; per-group state
+ * stays in batch order.  Stream-ordered: the work starts after what is
+ * already enqueued on `stream`, and `stream` continues once every batch is
+ * done; returns without waiting for the device.  A batch with a bad key
+ * gets CQ_ERR_KEY_RANGE in *n_touched[i] and leaves the state unchanged;
+ * the other batches proceed.  The input and result buffers must stay valid
+ * until the work on `stream` completes.  Telemetry records describe the
+ * last batch.  Returns CQ_OK, CQ_ERR_INVALID (nothing enqueued), CQ_ERR_OOM
+ * or CQ_ERR_HIP.
+ */
+#define CQ_PIPE_MAX 1048576 /* 2^20 tuples per batch */
+int cq_push_batches(cq_query *q, int32_t count, const int32_t *const *keys,
+                    const int32_t *const *values, const int64_t *n, int32_t *const *ids,
+                    int64_t *const *sums, int32_t *const *counts, double *const *avgs,
+                    int64_t *const *n_touched, void *stream);
+
+/*
  * cq_status -- wait for the query's last stream and return the status of the
  * most recent batch: CQ_OK or CQ_ERR_KEY_RANGE (or CQ_ERR_HIP).
  */

@@ -21,6 +21,7 @@ TELEMETRY_KERNEL_TIMES, TELEMETRY_WORKERS, TELEMETRY_PHASES = 1, 2, 4
 KERNEL_KINDS = ("hist", "pass", "update", "emit", "other", "plan")
 MAX_BATCH = 1 << 30
 MAX_WINDOW = (1 << 22) - 1
+PIPE_MAX = 1 << 20
 
 _lib: Optional[ctypes.CDLL] = None
 
@@ -58,6 +59,7 @@ def lib() -> ctypes.CDLL:
             "cq_worker_trace": ([P, pi64, i64, pi64], ctypes.c_int),
             "cq_batch_plan": ([P, pi64], ctypes.c_int),
             "cq_phase_trace": ([P, i32, pi64, i64, pi64], ctypes.c_int),
+            "cq_push_batches": ([P, i32, P, P, P, P, P, P, P, P, P], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -161,6 +163,34 @@ class Query:
             _dptr(ids), _dptr(sums), _dptr(counts), _dptr(avgs), _dptr(n_touched),
             _stream_handle(stream)), "cq_push_batch_results")
         self.last_n = int(n)
+
+    def push_batches_into(self, batches, outputs, stream=None):
+        """Enqueue several consecutive batches in one call, overlapped inside
+        the library (cq_push_batches).  batches: list of (keys, values)
+        device tensors (at most PIPE_MAX tuples each); outputs: list of
+        (ids, sums, counts, avgs, n_touched) device tensors, one per batch
+        (any of the first four may be None)."""
+        m = len(batches)
+        if len(outputs) != m:
+            raise ValueError("one output tuple per batch")
+        P = ctypes.c_void_p
+        arrs = [(P * max(m, 1))() for _ in range(7)]
+        ns = (ctypes.c_int64 * max(m, 1))()
+        for i, ((k, v), out) in enumerate(zip(batches, outputs)):
+            n = k.numel()
+            if v.numel() != n:
+                raise ValueError("keys and values differ in length")
+            ns[i] = n
+            arrs[0][i] = _dptr(k) if n else None
+            arrs[1][i] = _dptr(v) if n else None
+            for j, t in enumerate(out):
+                arrs[2 + j][i] = _dptr(t) if t is not None else None
+        _check(lib().cq_push_batches(self._h, m, *[ctypes.cast(a, P) for a in arrs[:2]],
+                                     ctypes.cast(ns, P),
+                                     *[ctypes.cast(a, P) for a in arrs[2:]],
+                                     _stream_handle(stream)), "cq_push_batches")
+        if m:
+            self.last_n = int(ns[m - 1])
 
     def results_into(self, ids, sums, counts, avgs, n_touched, stream=None):
         """Enqueue the emission of the last batch's results into caller

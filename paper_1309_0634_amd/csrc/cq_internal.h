@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "cq.h"
+
 namespace cq {
 
 // ---------------------------------------------------------------- sizes --
@@ -12,6 +14,7 @@ namespace cq {
 // B1 then B2 equal windows after B1||B2, so this is exact); results are
 // emitted once, after the last sub-batch.
 constexpr int SUB = 1 << 20;
+static_assert(SUB == CQ_PIPE_MAX, "pipelined batches are single sub-batches");
 
 // Histogram: arrival tiles of HIST_THREADS threads, HIST_KPT keys per thread
 // (loaded together); per-tile counters are
@@ -105,6 +108,7 @@ struct Scratch {
     int32_t *tidx;      // output position of each touched group
     int32_t *stamp;     // batch sequence number that last touched the group
     int32_t *touched;   // touched group ids, ascending
+    int32_t *ncnt;      // window count after this batch (emitted; the state may move on)
     // per bucket / heavy group
     int32_t *bstart;    // light bucket -> first group; [n_light] = G
     int32_t *hkey;      // heavy index -> group
@@ -159,6 +163,7 @@ hipError_t launch_update(State st, Scratch sc, int64_t n, int mode, int32_t work
 hipError_t launch_collect_touched(int64_t G, int32_t seq, Scratch sc, hipStream_t s);
 hipError_t launch_emit(State st, Scratch sc, int64_t cap, Out out, hipStream_t s);
 hipError_t launch_reset_totals(Scratch sc, hipStream_t s);
+hipError_t launch_set_touched(int64_t *n_touched, int64_t v, hipStream_t s);
 // Workgroups of the per-group phase (one trace record each).
 int64_t update_grid(int64_t n, int mode, int32_t workers);
 // Histogram workgroups launched by launch_hist for a sub-batch of n.

@@ -179,10 +179,9 @@ __device__ __forceinline__ void plan_group(const State &st, const Scratch &sc, i
     if ((uint32_t)x_ex[2] < (uint64_t)st.G) sc.touched[x_ex[2]] = (int32_t)g;
     sc.pold[g] = po;
     st.pos[g] = (int32_t)(((uint32_t)po + (uint32_t)kg) % (uint32_t)W);
-    st.cnt[g] = (int32_t)min((int64_t)W, (int64_t)c + kg);
-    // a sub-batch at least as long as the window replaces it whole: the new
-    // sum is the sum of the survivors alone
-    if (kg >= W) st.sum[g] = 0;
+    const int32_t nc = (int32_t)min((int64_t)W, (int64_t)c + kg);
+    st.cnt[g] = nc;
+    sc.ncnt[g] = nc;  // the count emitted for this batch (the state may move on)
     if (mode == MODE_STATIC) {
         sc.bucket[g] = static_worker(g, st.G, workers);
     } else if (kg >= HEAVY_MIN) {
@@ -1082,8 +1081,10 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
         for (int j = 0; j < GPT; ++j) {
             const int32_t g = a + tid + j * UPD_THREADS;
             const bool t = g < z && klp[g - a + 1] > klp[g - a];
-            gsum[j] = t ? st.sum[g] : 0;
-            gcnt[j] = t ? st.cnt[g] : 0;
+            // a group with at least W tuples here has its window replaced
+            // whole: its new sum is the survivors' sum alone
+            gsum[j] = (t && klp[g - a + 1] - klp[g - a] < W) ? st.sum[g] : 0;
+            gcnt[j] = t ? sc.ncnt[g] : 0;
             gtix[j] = t ? sc.tidx[g] : 0;
         }
     }
@@ -1122,9 +1123,9 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
         for (int i = tid; i < size; i += blockDim.x) {
             const int32_t g = hd[i] >= 0 ? ek[hd[i]] : -1;
             if (g >= 0) {
-                const int64_t s = st.sum[g] + acc[i];
+                const int64_t s = (lp(g + 1) - lp(g) >= W ? 0 : st.sum[g]) + acc[i];
                 st.sum[g] = s;
-                if (out.n_touched) emit_one(out, sc.tidx[g], g, s, st.cnt[g]);
+                if (out.n_touched) emit_one(out, sc.tidx[g], g, s, sc.ncnt[g]);
             }
         }
     }
@@ -1147,8 +1148,8 @@ __device__ int heavy_bucket(int32_t g, int32_t pold_g, int size, int tiles, cons
     int64_t gsum = 0;
     int32_t gcnt = 0, gtix = 0;
     if (tid == 0) {
-        gsum = st.sum[g];
-        gcnt = st.cnt[g];
+        gsum = full ? 0 : st.sum[g];  // a window replaced whole restarts at 0
+        gcnt = sc.ncnt[g];
         gtix = sc.tidx[g];
     }
     long long acc = 0;
@@ -1355,10 +1356,11 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_static(State st, Scratch
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             for (int i = lane; i < nk; i += 64) {
                 const int32_t g = g0 + i;
-                if (sc.lpre[g + 1] - sc.lpre[g] > 0) {
-                    const int64_t s = st.sum[g] + acc[i];
+                const int32_t kg = sc.lpre[g + 1] - sc.lpre[g];
+                if (kg > 0) {
+                    const int64_t s = (kg >= W ? 0 : st.sum[g]) + acc[i];
                     st.sum[g] = s;
-                    if (out.n_touched) emit_one(out, sc.tidx[g], g, s, st.cnt[g]);
+                    if (out.n_touched) emit_one(out, sc.tidx[g], g, s, sc.ncnt[g]);
                 }
             }
         }
@@ -1544,6 +1546,13 @@ hipError_t launch_emit(State st, Scratch sc, int64_t cap, Out out, hipStream_t s
     int64_t grid = (cap + EMIT_THREADS - 1) / EMIT_THREADS;
     grid = std::max<int64_t>(1, std::min<int64_t>(grid, 1024));
     hipLaunchKernelGGL(k_emit, dim3((unsigned)grid), dim3(EMIT_THREADS), 0, s, st, sc, out);
+    return hipGetLastError();
+}
+
+__global__ void k_set_touched(int64_t *n_touched, int64_t v) { *n_touched = v; }
+
+hipError_t launch_set_touched(int64_t *n_touched, int64_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_touched, dim3(1), dim3(1), 0, s, n_touched, v);
     return hipGetLastError();
 }
 

@@ -24,7 +24,12 @@ struct cq_query {
     int device = 0;
     uint32_t aggregates = 0;
     State st{};
-    Scratch sc{};
+    Scratch sc{};               // working buffers (batch-local arrays: set 0)
+    Scratch alt{};              // second set of batch-local arrays (pipelined calls)
+    int cur = 0;                // set used by the most recent batch
+    hipStream_t ps[2] = {nullptr, nullptr};  // pipeline: histogram+pass, update
+    hipEvent_t ev_pass[2] = {nullptr, nullptr}, ev_upd[2] = {nullptr, nullptr};
+    hipEvent_t ev_in = nullptr, ev_done = nullptr;
     int mode = MODE_BALANCED;
     int32_t workers = 1024;
     int32_t seq = 0;            // batch sequence number (device-side epochs)
@@ -81,27 +86,68 @@ struct DeviceGuard {
     }
 };
 
+// Batch-local arrays of one buffer set.
+void free_set(Scratch &b) {
+    dfree(b.k);
+    dfree(b.lpre);
+    dfree(b.bucket);
+    dfree(b.pold);
+    dfree(b.tidx);
+    dfree(b.stamp);
+    dfree(b.touched);
+    dfree(b.ncnt);
+    dfree(b.bstart);
+    dfree(b.hkey);
+    dfree(b.sdat);
+    dfree(b.rowstart);
+    dfree(b.partials);
+    dfree(b.tot);
+}
+
+// Allocates and clears the batch-local arrays of a set (histogram zero,
+// plan totals zero); returns a status code.
+int alloc_set(Scratch &b, int64_t G) {
+    const int64_t nblk = (G + PLAN_CHUNK - 1) / PLAN_CHUNK;
+    int rc = dalloc(&b.k, G);
+    if (rc == CQ_OK) rc = dalloc(&b.lpre, G + 1);
+    if (rc == CQ_OK) rc = dalloc(&b.bucket, G);
+    if (rc == CQ_OK) rc = dalloc(&b.pold, G);
+    if (rc == CQ_OK) rc = dalloc(&b.tidx, G);
+    if (rc == CQ_OK) rc = dalloc(&b.stamp, G);
+    if (rc == CQ_OK) rc = dalloc(&b.touched, G);
+    if (rc == CQ_OK) rc = dalloc(&b.ncnt, G);
+    if (rc == CQ_OK) rc = dalloc(&b.bstart, NB_MAX + 1);
+    if (rc == CQ_OK) rc = dalloc(&b.hkey, NB_MAX);
+    if (rc == CQ_OK) rc = dalloc(&b.sdat, SUB);
+    if (rc == CQ_OK) rc = dalloc(&b.rowstart, (int64_t)PASS_TILES_MAX * (NB_MAX + 1));
+    if (rc == CQ_OK) rc = dalloc(&b.partials, nblk * PLAN_FIELDS);
+    if (rc == CQ_OK) rc = dalloc(&b.tot, 1);
+    if (rc != CQ_OK) return rc;
+    hipError_t e = hipMemset(b.k, 0, sizeof(int32_t) * (size_t)G);
+    if (e == hipSuccess) e = hipMemset(b.stamp, 0, sizeof(int32_t) * (size_t)G);
+    if (e == hipSuccess) e = hipMemset(b.bucket, 0, sizeof(int32_t) * (size_t)G);
+    if (e == hipSuccess) e = hipMemset(b.lpre, 0, sizeof(int32_t) * (size_t)(G + 1));
+    if (e == hipSuccess) e = hipMemset(b.tot, 0, sizeof(PlanTotals));
+    return from_hip(e);
+}
+
 void free_all(cq_query *q) {
     dfree(q->st.ring);
     dfree(q->st.pos);
     dfree(q->st.cnt);
     dfree(q->st.sum);
-    dfree(q->sc.k);
-    dfree(q->sc.lpre);
-    dfree(q->sc.bucket);
-    dfree(q->sc.pold);
-    dfree(q->sc.tidx);
-    dfree(q->sc.stamp);
-    dfree(q->sc.touched);
-    dfree(q->sc.bstart);
-    dfree(q->sc.hkey);
-    dfree(q->sc.sdat);
-    dfree(q->sc.rowstart);
-    dfree(q->sc.partials);
+    free_set(q->sc);
+    free_set(q->alt);
+    for (int i = 0; i < 2; ++i) {
+        if (q->ps[i]) (void)hipStreamDestroy(q->ps[i]);
+        if (q->ev_pass[i]) (void)hipEventDestroy(q->ev_pass[i]);
+        if (q->ev_upd[i]) (void)hipEventDestroy(q->ev_upd[i]);
+    }
+    if (q->ev_in) (void)hipEventDestroy(q->ev_in);
+    if (q->ev_done) (void)hipEventDestroy(q->ev_done);
     dfree(q->sc.bad);
     dfree(q->sc.fault);
     dfree(q->sc.hot);
-    dfree(q->sc.tot);
     dfree(q->sc.trace);
     dfree(q->sc.phase);
     for (auto &t : q->live) {
@@ -162,27 +208,59 @@ bool static_ok(int64_t G, int32_t workers) {
     return (G + workers - 1) / workers <= STATIC_KEYS_MAX;
 }
 
+// Buffer set i (batch-local arrays) with the shared ones (key check,
+// fault bits, hot groups, telemetry records; the records only when on).
+Scratch set_of(const cq_query *q, int i) {
+    Scratch b = i ? q->alt : q->sc;
+    b.bad = q->sc.bad;
+    b.fault = q->sc.fault;
+    b.hot = q->sc.hot;
+    b.trace = (q->telemetry & CQ_TELEMETRY_WORKERS) ? q->sc.trace : nullptr;
+    b.phase = (q->telemetry & CQ_TELEMETRY_PHASES) ? q->sc.phase : nullptr;
+    return b;
+}
+
+// Telemetry buffers for sub-batches of up to n tuples.
+int prepare_telemetry(cq_query *q, int64_t n) {
+    if (q->telemetry & CQ_TELEMETRY_WORKERS) {
+        const int64_t grid =
+            update_grid(std::min<int64_t>(std::max<int64_t>(n, 1), SUB), q->mode, q->workers);
+        const int rc = ensure_trace(q, grid);
+        if (rc != CQ_OK) return rc;
+    }
+    if ((q->telemetry & CQ_TELEMETRY_PHASES) && !q->sc.phase) {
+        const int rc = dalloc(&q->sc.phase, (int64_t)PHASE_KINDS * PHASE_BLOCKS * PHASE_SLOTS);
+        if (rc != CQ_OK) return rc;
+        (void)hipMemset(q->sc.phase, 0,
+                        sizeof(int64_t) * (size_t)PHASE_KINDS * PHASE_BLOCKS * PHASE_SLOTS);
+    }
+    return CQ_OK;
+}
+
+// Histogram, plan and reorder of one sub-batch (stream `s`).
+int front(cq_query *q, const int32_t *keys, const int32_t *values, int64_t m, const Scratch &sc,
+          int32_t seq, hipStream_t s) {
+    int rc = timed(q, CQ_KERNEL_HIST, s,
+                   [&] { return launch_hist(keys, m, q->st.G, sc, seq, s); });
+    if (rc == CQ_OK && !plan_fused(q->st.G))
+        rc = timed(q, CQ_KERNEL_PLAN, s,
+                   [&] { return launch_plan(q->st, sc, seq, q->mode, q->workers, s); });
+    if (rc == CQ_OK)
+        rc = timed(q, CQ_KERNEL_PASS, s, [&] {
+            return launch_pass(keys, values, m, q->st, sc, seq, q->mode, q->workers, s);
+        });
+    return rc;
+}
+
 // The whole per-batch sequence; `out` non-null means emit into it.
 int push(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n, hipStream_t s,
          const Out *out) {
     if (q->mode == MODE_STATIC && !static_ok(q->st.G, q->workers)) return CQ_ERR_INVALID;
     const int64_t nsub = (n + SUB - 1) / SUB;
-    const int64_t upd_grid = update_grid(std::min<int64_t>(std::max<int64_t>(n, 1), SUB), q->mode,
-                                         q->workers);
-    int rc = CQ_OK;
-    if (q->telemetry & CQ_TELEMETRY_WORKERS) {
-        rc = ensure_trace(q, upd_grid);
-        if (rc != CQ_OK) return rc;
-    }
-    if ((q->telemetry & CQ_TELEMETRY_PHASES) && !q->sc.phase) {
-        rc = dalloc(&q->sc.phase, (int64_t)PHASE_KINDS * PHASE_BLOCKS * PHASE_SLOTS);
-        if (rc != CQ_OK) return rc;
-        (void)hipMemset(q->sc.phase, 0,
-                        sizeof(int64_t) * (size_t)PHASE_KINDS * PHASE_BLOCKS * PHASE_SLOTS);
-    }
-    Scratch sc = q->sc;
-    if (!(q->telemetry & CQ_TELEMETRY_WORKERS)) sc.trace = nullptr;
-    if (!(q->telemetry & CQ_TELEMETRY_PHASES)) sc.phase = nullptr;
+    int rc = prepare_telemetry(q, n);
+    if (rc != CQ_OK) return rc;
+    q->cur = 0;
+    const Scratch sc = set_of(q, 0);
     q->last_stream = s;
     q->pushed = true;
     q->last_n = n;
@@ -204,17 +282,7 @@ int push(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n, hip
         const int64_t off = b * SUB;
         const int64_t m = std::min<int64_t>(SUB, n - off);
         const Out o = (out && nsub == 1) ? *out : none;
-        rc = timed(q, CQ_KERNEL_HIST, s,
-                   [&] { return launch_hist(keys + off, m, q->st.G, sc, seq, s); });
-        if (rc == CQ_OK && !plan_fused(q->st.G))
-            rc = timed(q, CQ_KERNEL_PLAN, s, [&] {
-                return launch_plan(q->st, sc, seq, q->mode, q->workers, s);
-            });
-        if (rc == CQ_OK)
-            rc = timed(q, CQ_KERNEL_PASS, s, [&] {
-                return launch_pass(keys + off, values + off, m, q->st, sc, seq, q->mode,
-                                   q->workers, s);
-            });
+        rc = front(q, keys + off, values + off, m, sc, seq, s);
         if (rc == CQ_OK)
             rc = timed(q, CQ_KERNEL_UPDATE, s, [&] {
                 return launch_update(q->st, sc, m, q->mode, q->workers, o, s);
@@ -230,6 +298,30 @@ int push(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n, hip
         }
     }
     return rc;
+}
+
+// Ordering-only events between the library's streams and the caller's:
+// no timestamps, no system-scope fences (all the data stays on the device).
+constexpr unsigned kSyncEvent = hipEventDisableTiming | hipEventDisableSystemFence;
+
+// Second buffer set, the two pipeline streams and their events (first use).
+int ensure_pipeline(cq_query *q) {
+    if (q->ps[0]) return CQ_OK;
+    int rc = alloc_set(q->alt, q->st.G);
+    if (rc != CQ_OK) {
+        free_set(q->alt);
+        return rc;
+    }
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&q->ps[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&q->ev_pass[i], kSyncEvent);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&q->ev_upd[i], kSyncEvent);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&q->ev_in, kSyncEvent);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&q->ev_done, kSyncEvent);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    return from_hip(e);
 }
 
 }  // namespace
@@ -264,27 +356,14 @@ int cq_create(int64_t groups, int32_t window, uint32_t aggregates, cq_query **ou
     q->st.G = groups;
     q->st.W = window;
     const int64_t G = groups;
-    const int64_t nblk = (G + PLAN_CHUNK - 1) / PLAN_CHUNK;
     int rc = dalloc(&q->st.ring, G * (int64_t)window);
     if (rc == CQ_OK) rc = dalloc(&q->st.pos, G);
     if (rc == CQ_OK) rc = dalloc(&q->st.cnt, G);
     if (rc == CQ_OK) rc = dalloc(&q->st.sum, G);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.k, G);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.lpre, G + 1);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.bucket, G);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.pold, G);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.tidx, G);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.stamp, G);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.touched, G);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.bstart, NB_MAX + 1);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.hkey, NB_MAX);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.sdat, SUB);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.rowstart, (int64_t)PASS_TILES_MAX * (NB_MAX + 1));
-    if (rc == CQ_OK) rc = dalloc(&q->sc.partials, nblk * PLAN_FIELDS);
+    if (rc == CQ_OK) rc = alloc_set(q->sc, G);
     if (rc == CQ_OK) rc = dalloc(&q->sc.bad, 1);
     if (rc == CQ_OK) rc = dalloc(&q->sc.fault, 1);
     if (rc == CQ_OK) rc = dalloc(&q->sc.hot, 2);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.tot, 1);
     hipError_t e = hipSuccess;
     if (rc == CQ_OK) {
         // zero-filled windows: never-written slots read as 0, so the first
@@ -293,14 +372,9 @@ int cq_create(int64_t groups, int32_t window, uint32_t aggregates, cq_query **ou
         if (e == hipSuccess) e = hipMemset(q->st.pos, 0, sizeof(int32_t) * (size_t)G);
         if (e == hipSuccess) e = hipMemset(q->st.cnt, 0, sizeof(int32_t) * (size_t)G);
         if (e == hipSuccess) e = hipMemset(q->st.sum, 0, sizeof(int64_t) * (size_t)G);
-        if (e == hipSuccess) e = hipMemset(q->sc.k, 0, sizeof(int32_t) * (size_t)G);
-        if (e == hipSuccess) e = hipMemset(q->sc.stamp, 0, sizeof(int32_t) * (size_t)G);
-        if (e == hipSuccess) e = hipMemset(q->sc.bucket, 0, sizeof(int32_t) * (size_t)G);
-        if (e == hipSuccess) e = hipMemset(q->sc.lpre, 0, sizeof(int32_t) * (size_t)(G + 1));
         if (e == hipSuccess) e = hipMemset(q->sc.bad, 0, sizeof(int32_t));
         if (e == hipSuccess) e = hipMemset(q->sc.fault, 0, sizeof(int32_t));
         if (e == hipSuccess) e = hipMemset(q->sc.hot, 0xff, 2 * sizeof(int32_t));
-        if (e == hipSuccess) e = hipMemset(q->sc.tot, 0, sizeof(PlanTotals));
         if (e == hipSuccess) e = hipDeviceSynchronize();
         rc = from_hip(e);
     }
@@ -349,6 +423,72 @@ int cq_push_batch_results(cq_query *q, const int32_t *keys, const int32_t *value
     return push(q, keys, values, n, reinterpret_cast<hipStream_t>(stream), &out);
 }
 
+int cq_push_batches(cq_query *q, int32_t count, const int32_t *const *keys,
+                    const int32_t *const *values, const int64_t *n, int32_t *const *ids,
+                    int64_t *const *sums, int32_t *const *counts, double *const *avgs,
+                    int64_t *const *n_touched, void *stream) {
+    if (!q || count < 0) return CQ_ERR_INVALID;
+    if (count == 0) return CQ_OK;
+    if (!keys || !values || !n || !n_touched) return CQ_ERR_INVALID;
+    for (int32_t i = 0; i < count; ++i) {
+        if (n[i] < 0 || n[i] > SUB || !n_touched[i]) return CQ_ERR_INVALID;
+        if (n[i] > 0 && (!keys[i] || !values[i])) return CQ_ERR_INVALID;
+    }
+    if (q->mode == MODE_STATIC && !static_ok(q->st.G, q->workers)) return CQ_ERR_INVALID;
+    DeviceGuard guard(q->device);
+    int rc = ensure_pipeline(q);
+    if (rc == CQ_OK) rc = prepare_telemetry(q, SUB);
+    if (rc != CQ_OK) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipStream_t sa = q->ps[0], sb = q->ps[1];
+    // everything the caller enqueued before (inputs, earlier batches) first
+    hipError_t e = hipEventRecord(q->ev_in, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(sa, q->ev_in, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(sb, q->ev_in, 0);
+    rc = from_hip(e);
+    // Batch i uses buffer set i mod 2.  Histogram, plan and reorder run on
+    // one stream, the per-group update on the other, so batch i+1's front
+    // half overlaps batch i's update.  Per-group state stays ordered: plans
+    // (pointers, counts) follow one another on the first stream, updates
+    // (windows, sums) on the second.
+    for (int32_t i = 0; i < count && rc == CQ_OK; ++i) {
+        const int b = i & 1;
+        const Scratch sc = set_of(q, b);
+        const int32_t seq = ++q->seq;
+        const Out out = {ids ? ids[i] : nullptr, sums ? sums[i] : nullptr,
+                         counts ? counts[i] : nullptr, avgs ? avgs[i] : nullptr, n_touched[i]};
+        q->cur = b;
+        q->last_n = n[i];
+        if (n[i] == 0) {
+            // nothing touched; the set's totals say so (cq_results after
+            // this call), ordered after the set's previous update
+            rc = from_hip(launch_reset_totals(sc, sb));
+            if (rc == CQ_OK) rc = from_hip(launch_set_touched(n_touched[i], 0, sb));
+            if (rc == CQ_OK) rc = from_hip(hipEventRecord(q->ev_upd[b], sb));
+            continue;
+        }
+        // the update two batches back has finished with this buffer set
+        if (i >= 2) rc = from_hip(hipStreamWaitEvent(sa, q->ev_upd[b], 0));
+        if (rc == CQ_OK) rc = front(q, keys[i], values[i], n[i], sc, seq, sa);
+        if (rc == CQ_OK) rc = from_hip(hipEventRecord(q->ev_pass[b], sa));
+        if (rc == CQ_OK) rc = from_hip(hipStreamWaitEvent(sb, q->ev_pass[b], 0));
+        if (rc == CQ_OK)
+            rc = timed(q, CQ_KERNEL_UPDATE, sb, [&] {
+                return launch_update(q->st, sc, n[i], q->mode, q->workers, out, sb);
+            });
+        if (rc == CQ_OK) rc = from_hip(hipEventRecord(q->ev_upd[b], sb));
+    }
+    // the caller's stream continues once every update is done (updates are
+    // ordered on their stream, and each follows its batch's front half)
+    if (rc == CQ_OK) rc = from_hip(hipEventRecord(q->ev_done, sb));
+    if (rc == CQ_OK) rc = from_hip(hipStreamWaitEvent(s, q->ev_done, 0));
+    q->last_stream = s;
+    q->pushed = true;
+    q->last_mode = q->mode;
+    q->last_workers = q->workers;
+    return rc;
+}
+
 int cq_results(cq_query *q, int32_t *ids, int64_t *sums, int32_t *counts, double *avgs,
                int64_t *n_touched, void *stream) {
     if (!q || !n_touched) return CQ_ERR_INVALID;
@@ -356,7 +496,8 @@ int cq_results(cq_query *q, int32_t *ids, int64_t *sums, int32_t *counts, double
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int64_t cap = std::min<int64_t>(q->st.G, q->last_n);
     const Out out = {ids, sums, counts, avgs, n_touched};
-    int rc = timed(q, CQ_KERNEL_EMIT, s, [&] { return launch_emit(q->st, q->sc, cap, out, s); });
+    const Scratch sc = set_of(q, q->cur);
+    int rc = timed(q, CQ_KERNEL_EMIT, s, [&] { return launch_emit(q->st, sc, cap, out, s); });
     q->last_stream = s;
     q->pushed = true;
     return rc;
@@ -368,7 +509,7 @@ int cq_status(cq_query *q) {
     hipError_t e = hipStreamSynchronize(q->last_stream);
     if (e != hipSuccess) return from_hip(e);
     PlanTotals t;
-    e = hipMemcpy(&t, q->sc.tot, sizeof(t), hipMemcpyDeviceToHost);
+    e = hipMemcpy(&t, set_of(q, q->cur).tot, sizeof(t), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return from_hip(e);
     return t.status;
 }
@@ -378,6 +519,11 @@ int cq_destroy(cq_query *q) {
     DeviceGuard guard(q->device);
     int rc = CQ_OK;
     if (q->pushed) rc = from_hip(hipStreamSynchronize(q->last_stream));
+    for (int i = 0; i < 2; ++i)
+        if (q->ps[i]) {
+            const int r = from_hip(hipStreamSynchronize(q->ps[i]));
+            if (rc == CQ_OK) rc = r;
+        }
     free_all(q);
     delete q;
     return rc;
@@ -463,7 +609,7 @@ int cq_batch_plan(cq_query *q, int64_t *out) {
     hipError_t e = hipStreamSynchronize(q->last_stream);
     if (e != hipSuccess) return from_hip(e);
     PlanTotals t;
-    e = hipMemcpy(&t, q->sc.tot, sizeof(t), hipMemcpyDeviceToHost);
+    e = hipMemcpy(&t, set_of(q, q->cur).tot, sizeof(t), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return from_hip(e);
     int32_t fault = 0;
     e = hipMemcpy(&fault, q->sc.fault, sizeof(fault), hipMemcpyDeviceToHost);

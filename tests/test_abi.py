@@ -59,13 +59,16 @@ def test_null_handles_are_rejected(L):
     assert L.cq_status(None) == cq.ERR_INVALID
     assert L.cq_set_telemetry(None, 1) == cq.ERR_INVALID
     assert L.cq_batch_plan(None, None) == cq.ERR_INVALID
+    assert L.cq_push_batches(None, 1, None, None, None, None, None, None, None, None,
+                             None) == cq.ERR_INVALID
     assert L.cq_destroy(None) == cq.OK
 
 
 def test_binding_names_match_header():
     for name in ("cq_create", "cq_reserve", "cq_set_partition", "cq_push_batch", "cq_results",
                  "cq_status", "cq_destroy", "cq_strerror", "cq_set_telemetry",
-                 "cq_kernel_times", "cq_worker_trace", "cq_batch_plan"):
+                 "cq_kernel_times", "cq_worker_trace", "cq_batch_plan", "cq_phase_trace",
+                 "cq_push_batches", "cq_push_batch_results"):
         assert name in _declared_functions()
 
 
@@ -79,3 +82,5 @@ def test_header_constants_match_binding():
     assert val("CQ_SUM") == cq.SUM and val("CQ_COUNT") == cq.COUNT and val("CQ_AVG") == cq.AVG
     assert val("CQ_ERR_KEY_RANGE") == cq.ERR_KEY_RANGE
     assert val("CQ_PARTITION_STATIC") == cq.PARTITION_STATIC
+    assert val("CQ_PIPE_MAX") == cq.PIPE_MAX
+    assert val("CQ_KERNEL_KINDS") == len(cq.KERNEL_KINDS)

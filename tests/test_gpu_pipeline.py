@@ -1,0 +1,154 @@
+"""GPU parity of the pipelined entry point (cq_push_batches): several
+consecutive batches per call, overlapped inside the library on two streams
+with two sets of batch-local buffers.  Every batch's results must equal the
+CPU oracle's bit for bit, exactly as with one call per batch."""
+import numpy as np
+import pytest
+
+import paper_1309_0634_amd as cq
+from gpu_helpers import assert_same, device, note, to_dev
+from oracle import OracleError, RingOracle
+from workloads import host_batch, skew, tiny
+
+pytestmark = pytest.mark.gpu
+
+MODES = [(cq.PARTITION_BALANCED, 0), (cq.PARTITION_STATIC, 0), (cq.PARTITION_STATIC, 7)]
+MODE_IDS = ["balanced", "static1024", "static7"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    cq.lib()
+    torch.cuda.set_device(0)
+
+
+def push_group(q, groups, batches):
+    """One cq_push_batches call; returns per batch either the status code
+    (rejected) or (ids, sums, counts, avgs) CPU tensors."""
+    import torch
+    dev = device()
+    dbs = [(to_dev(k), to_dev(v)) for k, v in batches]
+    outs = []
+    for k, _ in batches:
+        cap = max(1, min(groups, len(k)))
+        outs.append((torch.empty(cap, dtype=torch.int32, device=dev),
+                     torch.empty(cap, dtype=torch.int64, device=dev),
+                     torch.empty(cap, dtype=torch.int32, device=dev),
+                     torch.empty(cap, dtype=torch.float64, device=dev),
+                     torch.full((1,), 12345, dtype=torch.int64, device=dev)))
+    q.push_batches_into(dbs, outs)
+    torch.cuda.synchronize()
+    res = []
+    for o in outs:
+        nt = int(o[4].item())
+        res.append(nt if nt < 0 else tuple(t[:nt].cpu() for t in o[:4]))
+    return res
+
+
+def check_against_oracle(q, o, groups, batches, ctx):
+    got = push_group(q, groups, batches)
+    for i, ((k, v), g) in enumerate(zip(batches, got)):
+        try:
+            want = o.push(k, v)
+        except OracleError as e:
+            assert g == cq.ERR_KEY_RANGE == e.code, f"{ctx} batch {i}: {g} vs oracle {e.code}"
+            continue
+        assert not isinstance(g, int), f"{ctx} batch {i}: status {g}"
+        assert_same(g, want, f"{ctx} batch {i}")
+
+
+@pytest.mark.parametrize("mode,workers", MODES, ids=MODE_IDS)
+@pytest.mark.parametrize("per_call", [1, 3, 8])
+def test_tiny_stream_pipelined(mode, workers, per_call):
+    note(f"case: tiny stream pipelined, {per_call} batches per call, mode {mode}/{workers}")
+    cfg = tiny()
+    q = cq.Query(cfg.groups, cfg.window, partition=mode, workers=workers)
+    o = RingOracle(cfg.groups, cfg.window)
+    hb = [host_batch(cfg, b) for b in range(40)]
+    for s in range(0, len(hb), per_call):
+        check_against_oracle(q, o, cfg.groups, hb[s:s + per_call], f"tiny from {s}")
+    q.close()
+    o.close()
+
+
+@pytest.mark.parametrize("s", [0.0, 1.5])
+@pytest.mark.parametrize("mode", [cq.PARTITION_BALANCED, cq.PARTITION_STATIC],
+                         ids=["balanced", "static"])
+def test_skew_full_size_pipelined(s, mode):
+    """10,000 groups, W=1000, 2^20-tuple Zipf batches, 3 per call."""
+    note(f"case: skew s={s} pipelined, mode {mode}")
+    cfg = skew(s, batches=6)
+    q = cq.Query(cfg.groups, cfg.window, partition=mode)
+    o = RingOracle(cfg.groups, cfg.window, threads=8)
+    hb = [host_batch(cfg, b) for b in range(6)]
+    check_against_oracle(q, o, cfg.groups, hb[:3], f"skew {s}")
+    check_against_oracle(q, o, cfg.groups, hb[3:], f"skew {s}")
+    q.close()
+    o.close()
+
+
+def test_empty_and_rejected_batches_inside_a_call():
+    note("case: pipelined call with an empty and a rejected batch")
+    rng = np.random.default_rng(11)
+    G, W = 300, 50
+    q = cq.Query(G, W)
+    o = RingOracle(G, W)
+    def rb(n):
+        return (rng.integers(0, G, n).astype(np.int32),
+                rng.integers(0, 10**6, n).astype(np.int32))
+    bad = rb(5000)
+    bad[0][1234] = G  # out of range
+    empty = (np.zeros(0, np.int32), np.zeros(0, np.int32))
+    batches = [rb(4000), empty, bad, rb(7000), rb(1), empty, rb(9000)]
+    check_against_oracle(q, o, G, batches, "mixed")
+    check_against_oracle(q, o, G, [rb(3000), rb(3000)], "after mixed")
+    q.close()
+    o.close()
+
+
+def test_mixed_with_single_batch_calls():
+    """Pipelined calls, then single-batch pushes and cq_results, then a
+    pipelined call again: one consistent stream of state."""
+    note("case: pipelined and single-batch calls interleaved")
+    rng = np.random.default_rng(5)
+    G, W = 2000, 300
+    q = cq.Query(G, W)
+    o = RingOracle(G, W)
+    def rb(n):
+        return (rng.integers(0, G, n).astype(np.int32),
+                rng.integers(-10**6, 10**6, n).astype(np.int32))
+    bs = [rb(int(rng.integers(1, 60000))) for _ in range(5)]
+    check_against_oracle(q, o, G, bs, "first call")
+    # cq_results re-emits the last batch of the call
+    ids = q.results()[0]
+    k, _ = bs[-1]
+    touched = np.unique(k)
+    assert np.array_equal(ids.numpy(), touched)
+    for _ in range(3):
+        k, v = rb(int(rng.integers(1, 60000)))
+        q.push(to_dev(k), to_dev(v))
+        assert_same(q.results(), o.push(k, v), "single push")
+    check_against_oracle(q, o, G, [rb(50000) for _ in range(4)], "second call")
+    q.close()
+    o.close()
+
+
+@pytest.mark.parametrize("G", [20000, 100000], ids=["plan-launch", "hash-histogram"])
+def test_larger_group_counts_pipelined(G):
+    """Group counts that take the separate plan launch (<= 32768) and the
+    hashed histogram with the multi-block plan (> 32768)."""
+    note(f"case: pipelined, G={G}")
+    rng = np.random.default_rng(G)
+    q = cq.Query(G, 100)
+    o = RingOracle(G, 100)
+    for rep in range(2):
+        bs = []
+        for _ in range(4):
+            n = int(rng.integers(1000, 200000))
+            k = (rng.zipf(1.3, n) % G).astype(np.int32)
+            bs.append((k, rng.integers(0, 10**6, n).astype(np.int32)))
+        check_against_oracle(q, o, G, bs, f"G={G} call {rep}")
+    q.close()
+    o.close()
