@@ -1010,9 +1010,22 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
         }
         __syncthreads();
     }
-    for (int p = tid; p < size; p += blockDim.x) {
-        const int r = rt[p];
-        const int2 e = sc.sdat[rs[r] + (p - rp[r])];
+    // all of this thread's gathers are issued before any is used
+    constexpr int SPT = LIGHT_CAP / UPD_THREADS;
+    int2 st_e[SPT];
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int p = tid + j * UPD_THREADS;
+        if (p < size) {
+            const int r = rt[p];
+            st_e[j] = sc.sdat[rs[r] + (p - rp[r])];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int p = tid + j * UPD_THREADS;
+        if (p >= size) continue;
+        const int2 e = st_e[j];
         const int32_t g = e.x;
         int32_t p0 = -1;
         if (g >= a && g < z) {
@@ -1088,7 +1101,15 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
             gtix[j] = t ? sc.tidx[g] : 0;
         }
     }
-    for (int p = tid; p < size; p += blockDim.x) {
+    // ring update: every survivor's old value is loaded before any store
+    int32_t *cells[SPT];
+    int32_t olds[SPT];
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int p = tid + j * UPD_THREADS;
+        cells[j] = nullptr;
+        olds[j] = 0;
+        if (p >= size) continue;
         const int p0 = pz[p];
         if (p0 < 0) continue;
         const int w = p / chunk;
@@ -1099,13 +1120,18 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
         const int32_t need = kg < W ? kg : W;
         if (rank >= kg - need && rank < kg) {
             const uint32_t slot = ((uint32_t)po(g) + (uint32_t)rank) % (uint32_t)W;
-            int32_t *cell = st.ring + (int64_t)g * W + slot;
-            const int32_t old = kg >= W ? 0 : *cell;
-            const int32_t v = ev[p];
-            *cell = v;
-            atomicAdd(reinterpret_cast<unsigned long long *>(&acc[p0]),
-                      (unsigned long long)((long long)v - (long long)old));
+            cells[j] = st.ring + (int64_t)g * W + slot;
+            if (kg < W) olds[j] = *cells[j];
         }
+    }
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        if (!cells[j]) continue;
+        const int p = tid + j * UPD_THREADS;
+        const int32_t v = ev[p];
+        *cells[j] = v;
+        atomicAdd(reinterpret_cast<unsigned long long *>(&acc[pz[p]]),
+                  (unsigned long long)((long long)v - (long long)olds[j]));
     }
     __syncthreads();
     phase_mark(sc, PHASE_UPDATE, 4);
@@ -1156,14 +1182,30 @@ __device__ int heavy_bucket(int32_t g, int32_t pold_g, int size, int tiles, cons
     // (a run table as in light buckets would cost one thread a serial loop
     // over a hot group's whole run in the last tile; a binary search per
     // survivor is cheaper here)
-    for (int p = size - need + tid; p < size; p += blockDim.x) {
-        const int r = upper_run(rp, tiles, p);
-        const int32_t v = sc.sdat[rs[r] + (p - rp[r])].y;
-        const uint32_t slot = (po + (uint32_t)p) % (uint32_t)W;
-        int32_t *cell = st.ring + (int64_t)g * W + slot;
-        const int32_t old = full ? 0 : *cell;
-        *cell = v;
-        acc += (long long)v - (long long)old;
+    // HU survivors per thread at a time, all loaded before any store
+    constexpr int HU = 4;
+    for (int p0 = size - need + tid; p0 < size; p0 += HU * UPD_THREADS) {
+        int32_t vals[HU], olds[HU];
+        int32_t *cells[HU];
+#pragma unroll
+        for (int u = 0; u < HU; ++u) {
+            const int p = p0 + u * UPD_THREADS;
+            cells[u] = nullptr;
+            vals[u] = olds[u] = 0;
+            if (p < size) {
+                const int r = upper_run(rp, tiles, p);
+                vals[u] = sc.sdat[rs[r] + (p - rp[r])].y;
+                const uint32_t slot = (po + (uint32_t)p) % (uint32_t)W;
+                cells[u] = st.ring + (int64_t)g * W + slot;
+                if (!full) olds[u] = *cells[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < HU; ++u)
+            if (cells[u]) {
+                *cells[u] = vals[u];
+                acc += (long long)vals[u] - (long long)olds[u];
+            }
     }
     const long long delta = block_sum_ll(acc, red_ll);
     if (tid == 0) {
