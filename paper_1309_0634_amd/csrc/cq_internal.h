@@ -40,13 +40,13 @@ constexpr int PLAN_FIELDS = 3;   // light tuples, heavy groups, touched groups
 // heavy and becomes a bucket of its own; light groups are packed, in id
 // order, into buckets of about LIGHT_BUDGET tuples (fewer than LIGHT_BUDGET
 // + HEAVY_MIN).
-constexpr int HEAVY_MIN = 1024;
-constexpr int LIGHT_BUDGET = 1024;
+constexpr int HEAVY_MIN = 512;
+constexpr int LIGHT_BUDGET = 512;
 constexpr int LIGHT_CAP = LIGHT_BUDGET + HEAVY_MIN;
-constexpr int LIGHT_BITS = 11;   // positions inside a light bucket
+constexpr int LIGHT_BITS = 10;   // positions inside a light bucket
 static_assert(LIGHT_CAP <= (1 << LIGHT_BITS), "light positions must fit the match bits");
 constexpr int NB_MAX = SUB / LIGHT_BUDGET + SUB / HEAVY_MIN + 2;
-constexpr int NB_BITS = 12;
+constexpr int NB_BITS = 13;
 static_assert(NB_MAX < (1 << NB_BITS), "bucket ids must fit the match bits");
 
 // Multisplit pass: tiles of PASS_TILE tuples, PASS_WAVES waves, each wave a

@@ -937,7 +937,7 @@ constexpr int UPD_WAVES = UPD_THREADS / 64;
 constexpr int U_ACC = U_CW + 2 * UPD_WAVES * LIGHT_CAP;  // i64[LIGHT_CAP] sum deltas
 // a light bucket whose groups span at most LIGHT_SPAN ids keeps their
 // staged-range starts and old ring pointers in LDS
-constexpr int LIGHT_SPAN = 2048;
+constexpr int LIGHT_SPAN = 768;
 static_assert(LIGHT_SPAN % UPD_THREADS == 0, "whole groups per thread");
 constexpr int U_KLP = U_ACC + 8 * LIGHT_CAP;             // i32[LIGHT_SPAN + 1]
 constexpr int U_KPO = U_KLP + 4 * (LIGHT_SPAN + 4);      // i32[LIGHT_SPAN]

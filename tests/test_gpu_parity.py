@@ -69,7 +69,8 @@ def test_single_group_heavy_batches():
     for W in (1, 100, 1000, 1023, 1024, 1025, 5000):
         for mode, workers in MODES[:2]:
             p = Pair(1, W, mode, workers)
-            for n in (0, 1, 5, 1023, 1024, 2047, 2048, 2049, 4096 * 3 + 17, 100_000):
+            for n in (0, 1, 5, 511, 512, 513, 1023, 1024, 2047, 2048, 2049, 4096 * 3 + 17,
+                      100_000):
                 k = np.zeros(n, np.int32)
                 v = rng.integers(-1000, 1000, n).astype(np.int32)
                 p.step(k, v, f"G=1 W={W} n={n} mode {mode}")
@@ -229,11 +230,20 @@ def test_skew_sorted_ids_worst_case_for_static():
     q2.close()
 
 
+def _plan_constant(name):
+    """A balancer constant of the HIP path (its internal header)."""
+    import os
+    import re
+    src = open(os.path.join(os.path.dirname(cq.__file__), "csrc", "cq_internal.h")).read()
+    return int(re.search(r"constexpr int %s = (\d+);" % name, src).group(1))
+
+
 def test_partition_plan_matches_histogram():
     """The balancer's plan equals what numpy derives from the histogram:
-    groups with >= 1024 tuples are heavy buckets, the rest are packed into
-    buckets of 1024 tuples."""
+    groups with >= HEAVY_MIN tuples are heavy buckets, the rest are packed
+    into buckets of LIGHT_BUDGET tuples."""
     note("case: plan totals")
+    hmin, budget = _plan_constant("HEAVY_MIN"), _plan_constant("LIGHT_BUDGET")
     cfg = skew(1.5)
     q = cq.Query(cfg.groups, cfg.window)
     for b in range(3):
@@ -241,9 +251,9 @@ def test_partition_plan_matches_histogram():
         q.push(to_dev(k), to_dev(v))
         plan = q.batch_plan()
         kk = np.bincount(k, minlength=cfg.groups)
-        light = (kk > 0) & (kk < 1024)
-        heavy = kk >= 1024
-        nl = (int(kk[light].sum()) + 1023) // 1024
+        light = (kk > 0) & (kk < hmin)
+        heavy = kk >= hmin
+        nl = (int(kk[light].sum()) + budget - 1) // budget
         assert plan["touched"] == int((kk > 0).sum()) == plan["sub_touched"]
         assert plan["heavy_groups"] == int(heavy.sum())
         assert plan["light_tuples"] == int(kk[light].sum())
