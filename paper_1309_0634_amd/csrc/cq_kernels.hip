@@ -675,7 +675,18 @@ __device__ int pass_local_plan(const State &st, const Scratch &sc, int32_t seq, 
         sB += x[1] | (x[2] << 16);
         if (track && kv[j] > 0)
             top.add(((unsigned long long)(uint32_t)kv[j] << 32) | (uint32_t)(g0 + j));
-        if (j < R && g0 + j < G) gcnt[g0 + j] = kv[j];
+    }
+#pragma unroll
+    for (int q = 0; q < PL_PER / 4; ++q) {
+        const int g = g0 + 4 * q;
+        if (4 * q < R && g + 3 < G) {
+            *reinterpret_cast<int4 *>(gcnt + g) =
+                make_int4(kv[4 * q], kv[4 * q + 1], kv[4 * q + 2], kv[4 * q + 3]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (4 * q < R && g + e < G) gcnt[g + e] = kv[4 * q + e];
+        }
     }
     phase_mark(sc, PHASE_PASS, 5);
     const int iA = wave_incl_add(sA), iB = wave_incl_add(sB);
@@ -717,17 +728,38 @@ __device__ int pass_local_plan(const State &st, const Scratch &sc, int32_t seq, 
             eB += ks > 0 ? 1 << 16 : 0;
         }
     } else {
-        for (int g = g0; g < gend; ++g) {
-            const int32_t ks = gcnt[g];
-            const bool heavy = ks >= HEAVY_MIN;
-            if (ks > 0)
-                gbk[g] = (uint16_t)(heavy ? nl + (eB & 0xffff) : (eA + ks - 1) / LIGHT_BUDGET);
-            if (g == own0) {
-                oA = eA;
-                oB = eB;
+        // four groups per step: one 16-byte LDS read of counts, one 8-byte
+        // write of bucket ids (ids of untouched groups are never read)
+        for (int g4 = g0; g4 < gend; g4 += 4) {
+            int ks[4];
+            if (g4 + 3 < G) {
+                const int4 c = *reinterpret_cast<const int4 *>(gcnt + g4);
+                ks[0] = c.x; ks[1] = c.y; ks[2] = c.z; ks[3] = c.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) ks[e] = g4 + e < G ? gcnt[g4 + e] : 0;
             }
-            eA += heavy ? 0 : ks;
-            eB += (heavy ? 1 : 0) + (ks > 0 ? 1 << 16 : 0);
+            uint32_t bo[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const bool heavy = ks[e] >= HEAVY_MIN;
+                bo[e] = heavy ? (uint32_t)(nl + (eB & 0xffff))
+                              : (uint32_t)max(0, eA + ks[e] - 1) / LIGHT_BUDGET;
+                if (g4 + e == own0) {
+                    oA = eA;
+                    oB = eB;
+                }
+                eA += heavy ? 0 : ks[e];
+                eB += (heavy ? 1 : 0) + (ks[e] > 0 ? 1 << 16 : 0);
+            }
+            if (g4 + 3 < G) {
+                *reinterpret_cast<uint2 *>(gbk + g4) =
+                    make_uint2(bo[0] | (bo[1] << 16), bo[2] | (bo[3] << 16));
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (g4 + e < G) gbk[g4 + e] = (uint16_t)bo[e];
+            }
         }
     }
     if (own0 < gend) {
@@ -786,7 +818,7 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(const int32_t *__restrict
     int2 *stage = reinterpret_cast<int2 *>(pool + P_STAGE);
     __shared__ int32_t ts[NB_MAX + 1];
     __shared__ int red[PASS_WAVES];
-    __shared__ uint16_t gbk[LOCAL ? PASS_LOCAL_G : 1];
+    __shared__ __align__(16) uint16_t gbk[LOCAL ? PASS_LOCAL_G : 4];
     __shared__ int pred[2 * PASS_WAVES];
     __shared__ unsigned long long ptop[2 * PASS_WAVES];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
