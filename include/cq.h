@@ -208,7 +208,8 @@ const char *cq_strerror(int code);
 
 /* Launch kinds reported by cq_kernel_times, in this order. */
 #define CQ_KERNEL_HIST      0 /* key histogram                        */
-#define CQ_KERNEL_PASS      1 /* tile-local reorder by bucket         */
+#define CQ_KERNEL_PASS      1 /* tile-local reorder by bucket (and,
+                                 for up to 16384 groups, the plan)   */
 #define CQ_KERNEL_UPDATE    2 /* per-group evict + insert + aggregate */
 #define CQ_KERNEL_EMIT      3 /* separate result emission             */
 #define CQ_KERNEL_OTHER     4 /* whole-batch checks and collection    */
@@ -244,11 +245,14 @@ int cq_worker_trace(cq_query *q, int64_t *rec, int64_t cap, int64_t *count);
 
 /*
  * cq_phase_trace -- wait for the query's last stream and copy the phase
- * clocks of the most recent sub-batch for one kernel `kind` (0: histogram +
- * plan, 1: reorder pass, 2: per-group update) into the host array `out`
- * (cap records of 8 int64 device-clock ticks, one record per workgroup, 0 =
- * not reached).  *count receives the number of records available (4096).
- * Needs CQ_TELEMETRY_PHASES.  Returns CQ_OK, CQ_ERR_INVALID or CQ_ERR_HIP.
+ * clocks of the most recent sub-batch for one kernel `kind` into the host
+ * array `out` (cap records of 8 int64 device-clock ticks, one record per
+ * workgroup, 0 = not reached).  kind 0: histogram (slots 0-2) and, where
+ * the plan is a launch of its own, the plan (slots 3-4); kind 1: reorder
+ * pass (slots 0-4; with the plan inside the pass, slots 5-7 mark its
+ * steps); kind 2: per-group update (slots 0-5).  *count receives the
+ * number of records available (4096).  Needs CQ_TELEMETRY_PHASES.  Returns
+ * CQ_OK, CQ_ERR_INVALID or CQ_ERR_HIP.
  */
 int cq_phase_trace(cq_query *q, int32_t kind, int64_t *out, int64_t cap, int64_t *count);
 
