@@ -215,6 +215,8 @@ def main():
                     help="seconds of CPU-oracle work for the cpu_baseline sample")
     ap.add_argument("--sweep", default=",".join(str(s) for s in SWEEP))
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--modes", default="balanced,static",
+                    help="partitions to run (the headline needs balanced)")
     ap.add_argument("--calibrate", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -243,7 +245,10 @@ def main():
         bytes_per = algorithmic_bytes(torch, [k for k, _ in batches], cfg.groups, cfg.window,
                                       cfg.batch)
         timed_bytes = sum(bytes_per[args.warmup:])
-        for mode, name in ((cq.PARTITION_BALANCED, "balanced"), (cq.PARTITION_STATIC, "static")):
+        modes = [(m, nm) for m, nm in ((cq.PARTITION_BALANCED, "balanced"),
+                                        (cq.PARTITION_STATIC, "static"))
+                 if nm in args.modes.split(",")]
+        for mode, name in modes:
             is_head = (s == HEADLINE_S and mode == cq.PARTITION_BALANCED)
             r = run_mode(torch, cq, batches, cfg, mode, args.warmup, args.steps)
             lat = run_mode(torch, cq, batches, cfg, mode, args.warmup, args.steps, "latency")

@@ -628,9 +628,13 @@ __global__ void k_validate(const int32_t *__restrict__ keys, int64_t n, int64_t 
 // totals and keeps the two most frequent groups for the next histogram.
 // Returns the bucket count, or -1 for a rejected batch (whose histogram is
 // cleared here: no block reads it then).  Barriers inside; call uniformly.
+// Groups whose plan one pass workgroup writes per step of its in-block plan.
+constexpr int OWN_CAP = 1024;
+
 __device__ int pass_local_plan(const State &st, const Scratch &sc, int32_t seq, int mode,
-                               int32_t workers, uint16_t *gbk, int32_t *gcnt, int *red,
-                               unsigned long long *red_top) {
+                               int32_t workers, uint16_t *gbk, int32_t *gcnt, int4 *oex,
+                               int *red, unsigned long long *red_top, int &own_n,
+                               int32_t &po0, int32_t &c00, int32_t &nl_out) {
     const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6, nw = blockDim.x >> 6;
     const int G = (int)st.G;
     const int D = gridDim.x, me = blockIdx.x;
@@ -657,12 +661,13 @@ __device__ int pass_local_plan(const State &st, const Scratch &sc, int32_t seq, 
             for (int e = 0; e < 4; ++e) kv[4 * q + e] = (4 * q < R && g + e < G) ? sc.k[g + e] : 0;
         }
     }
-    // first group of the run owned by this block; its state is loaded now
-    const int own0 = g0 + ((me - g0 % D) % D + D) % D;
-    int32_t po0 = 0, c00 = 0;
-    if (own0 < min(G, g0 + R)) {
-        po0 = st.pos[own0];
-        c00 = st.cnt[own0];
+    // this block writes the plan of groups [lo, hi), one group per thread
+    // (in passes of OWN_CAP for a small grid); their state is loaded now
+    const int lo = (int)((int64_t)me * G / D), hi = (int)((int64_t)(me + 1) * G / D);
+    po0 = c00 = 0;
+    if (lo + tid < hi) {
+        po0 = st.pos[lo + tid];
+        c00 = st.cnt[lo + tid];
     }
     int sA = 0, sB = 0;
     const bool track = me == 0;
@@ -710,26 +715,22 @@ __device__ int pass_local_plan(const State &st, const Scratch &sc, int32_t seq, 
     const int32_t nl = mode == MODE_STATIC ? 0 : (TA + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
     const int NB = mode == MODE_STATIC ? workers : nl + tot[1];
     if (me == 0 && tid == 0) plan_publish(st, sc, tot, 0, mode, workers);
-    // bucket of every group of the run (a lean loop: it runs over all G
-    // groups in every block), then the plan of the first group this block
-    // owns, whose state was loaded early
-    int eA = bA + iA - sA, eB = bB + iB - sB;
+    // Bucket of every group of the run (a lean loop: it runs over all G
+    // groups in every block), and the exclusive fields and count of the
+    // groups this block owns, handed through LDS to the threads that write
+    // their plan: consecutive groups by consecutive lanes, so the plan's
+    // stores are coalesced.  With at most OWN_CAP owned groups (every batch
+    // of 16 tiles or more) the writes happen later, in the pass, after a
+    // barrier it needs anyway (pass_owned_writes); a smaller grid walks the
+    // run once per OWN_CAP owned groups and writes them here.
     const int gend = min(G, g0 + R);
-    int oA = 0, oB = 0;
-    if (mode == MODE_STATIC) {
-        for (int g = g0; g < gend; ++g) {
-            const int32_t ks = gcnt[g];
-            if (ks > 0) gbk[g] = (uint16_t)(((uint32_t)g * (uint32_t)workers) / (uint32_t)G);
-            if (g == own0) {
-                oA = eA;
-                oB = eB;
-            }
-            eA += ks;
-            eB += ks > 0 ? 1 << 16 : 0;
-        }
-    } else {
-        // four groups per step: one 16-byte LDS read of counts, one 8-byte
-        // write of bucket ids (ids of untouched groups are never read)
+    nl_out = nl;
+    own_n = hi - lo <= OWN_CAP ? hi - lo : 0;
+    int base = lo;
+    do {  // at least once: every block needs the bucket ids, owned groups or not
+        const int top_g = min(hi, base + OWN_CAP);
+        const bool first = base == lo;
+        int eA = bA + iA - sA, eB = bB + iB - sB;
         for (int g4 = g0; g4 < gend; g4 += 4) {
             int ks[4];
             if (g4 + 3 < G) {
@@ -742,50 +743,44 @@ __device__ int pass_local_plan(const State &st, const Scratch &sc, int32_t seq, 
             uint32_t bo[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const bool heavy = ks[e] >= HEAVY_MIN;
-                bo[e] = heavy ? (uint32_t)(nl + (eB & 0xffff))
-                              : (uint32_t)max(0, eA + ks[e] - 1) / LIGHT_BUDGET;
-                if (g4 + e == own0) {
-                    oA = eA;
-                    oB = eB;
-                }
+                const int g = g4 + e;
+                const bool heavy = mode != MODE_STATIC && ks[e] >= HEAVY_MIN;
+                if (mode == MODE_STATIC)
+                    bo[e] = ((uint32_t)g * (uint32_t)workers) / (uint32_t)G;
+                else
+                    bo[e] = heavy ? (uint32_t)(nl + (eB & 0xffff))
+                                  : (uint32_t)max(0, eA + ks[e] - 1) / LIGHT_BUDGET;
+                if (g >= base && g < top_g) oex[g - base] = make_int4(eA, eB, ks[e], 0);
                 eA += heavy ? 0 : ks[e];
                 eB += (heavy ? 1 : 0) + (ks[e] > 0 ? 1 << 16 : 0);
             }
-            if (g4 + 3 < G) {
-                *reinterpret_cast<uint2 *>(gbk + g4) =
-                    make_uint2(bo[0] | (bo[1] << 16), bo[2] | (bo[3] << 16));
-            } else {
+            if (first) {  // bucket ids (those of untouched groups are never read)
+                if (g4 + 3 < G) {
+                    *reinterpret_cast<uint2 *>(gbk + g4) =
+                        make_uint2(bo[0] | (bo[1] << 16), bo[2] | (bo[3] << 16));
+                } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (g4 + e < G) gbk[g4 + e] = (uint16_t)bo[e];
+                    for (int e = 0; e < 4; ++e)
+                        if (g4 + e < G) gbk[g4 + e] = (uint16_t)bo[e];
+                }
             }
         }
-    }
-    if (own0 < gend) {
-        const int ex[PLAN_FIELDS] = {oA, oB & 0xffff, oB >> 16};
-        const int32_t ks = gcnt[own0];
-        sc.lpre[own0] = ex[0];
-        if (ks > 0) plan_group(st, sc, own0, ks, ex, po0, c00, nl, seq, mode, workers);
-    }
-    if (D < R) {
-        // a small grid owns several groups of a run: walk it again
-        eA = bA + iA - sA;
-        eB = bB + iB - sB;
-        for (int g = g0; g < gend; ++g) {
-            const int32_t ks = gcnt[g];
-            if (g > own0 && (g - own0) % D == 0) {
-                const int ex[PLAN_FIELDS] = {eA, eB & 0xffff, eB >> 16};
+        if (own_n == 0 && top_g > base) {
+            __syncthreads();
+            for (int i = tid; i < top_g - base; i += blockDim.x) {
+                const int g = base + i;
+                const int4 e = oex[i];
+                const int ex[PLAN_FIELDS] = {e.x, e.y & 0xffff, e.y >> 16};
                 sc.lpre[g] = ex[0];
-                if (ks > 0)
-                    plan_group(st, sc, g, ks, ex, st.pos[g], st.cnt[g], nl, seq, mode, workers);
+                if (e.z > 0) {
+                    const bool pre = first && i == tid;
+                    plan_group(st, sc, g, e.z, ex, pre ? po0 : st.pos[g], pre ? c00 : st.cnt[g],
+                               nl, seq, mode, workers);
+                }
             }
-            int x[PLAN_FIELDS];
-            key_fields(ks, mode, x);
-            eA += x[0];
-            eB += x[1] | (x[2] << 16);
+            __syncthreads();
         }
-    }
+    } while ((base += OWN_CAP) < hi && own_n == 0);
     phase_mark(sc, PHASE_PASS, 7);
     if (track) {
         top2_block(top, red_top);
@@ -802,6 +797,27 @@ constexpr int P_WC = 0;                                            // u16[PASS_W
 constexpr int P_STAGE = (P_WC + 2 * PASS_WAVES * NB_MAX + 15) & ~15;  // int2[PASS_TILE]
 constexpr int P_BYTES = P_STAGE + 8 * PASS_TILE;
 static_assert(P_BYTES >= 4 * PASS_LOCAL_G, "group counts fit the pool");
+static_assert(P_BYTES - P_STAGE >= 16 * OWN_CAP, "owned fields fit the staging area");
+static_assert(P_STAGE >= 4 * PASS_LOCAL_G, "owned fields do not overlap the group counts");
+
+// The deferred per-group plan writes of a block that owns at most OWN_CAP
+// groups (their fields were left in `oex` by pass_local_plan).
+__device__ void pass_owned_writes(const State &st, const Scratch &sc, const int4 *oex, int own_n,
+                                  int32_t po0, int32_t c00, int32_t nl, int32_t seq, int mode,
+                                  int32_t workers) {
+    const int lo = (int)((int64_t)blockIdx.x * st.G / gridDim.x);
+    for (int i = threadIdx.x; i < own_n; i += blockDim.x) {
+        const int g = lo + i;
+        const int4 e = oex[i];
+        const int ex[PLAN_FIELDS] = {e.x, e.y & 0xffff, e.y >> 16};
+        sc.lpre[g] = ex[0];
+        if (e.z > 0) {
+            const bool pre = i == (int)threadIdx.x;
+            plan_group(st, sc, g, e.z, ex, pre ? po0 : st.pos[g], pre ? c00 : st.cnt[g], nl, seq,
+                       mode, workers);
+        }
+    }
+}
 
 // Multisplit pass.  LOCAL: the plan is computed in the block (above) and
 // bucket ids come from LDS; otherwise they are read from the plan's global
@@ -834,9 +850,12 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(const int32_t *__restrict
         val[r] = valid ? values[i] : 0;
     }
     int NB;
+    int own_n = 0;
+    int32_t po0 = 0, c00 = 0, nl = 0;
     if (LOCAL) {
         NB = pass_local_plan(st, sc, seq, mode, workers, gbk, reinterpret_cast<int32_t *>(pool),
-                             pred, ptop);
+                             reinterpret_cast<int4 *>(pool + P_STAGE), pred, ptop, own_n, po0,
+                             c00, nl);
         if (NB < 0 || NB > NB_MAX) return;
 #pragma unroll
         for (int r = 0; r < PASS_ROUNDS; ++r) {
@@ -858,6 +877,11 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(const int32_t *__restrict
     }
     for (int i = tid; i < PASS_WAVES * NB; i += PASS_THREADS) wc[i / NB][i % NB] = 0;
     __syncthreads();
+    // the plan's per-group writes (fields in the staging area, which is
+    // written only after two more barriers)
+    if (LOCAL && own_n > 0)
+        pass_owned_writes(st, sc, reinterpret_cast<const int4 *>(pool + P_STAGE), own_n, po0,
+                          c00, nl, seq, mode, workers);
     phase_mark(sc, PHASE_PASS, 1);
     // only the bits that bucket ids < NB can have
     const int nbits = NB > 1 ? 32 - __clz(NB - 1) : 0;

@@ -367,3 +367,23 @@ def test_drifting_config_full_size_across_redraws():
     assert plan["fault"] == 0
     p.close()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("G,n", [(16384, 5000), (16384, 300_000), (10, 1 << 20), (3, 20_000),
+                                 (12_345, 4096 * 7 + 5)],
+                         ids=["maxG-2tiles", "maxG-74tiles", "G10-256tiles", "G3", "ragged"])
+def test_in_pass_plan_ownership(G, n):
+    """The plan inside the reorder pass: each workgroup owns a contiguous
+    range of groups (several passes when a small grid owns many, none when
+    the grid outnumbers the groups)."""
+    note(f"case: in-pass plan ownership G={G} n={n}")
+    rng = np.random.default_rng(G + n)
+    for mode, workers in MODES[:2]:
+        if mode == cq.PARTITION_STATIC and G < 1024:
+            workers = G
+        p = Pair(G, 700, mode, workers)
+        for b in range(3):
+            k = (rng.zipf(1.2, n) % G).astype(np.int32)
+            v = rng.integers(-10**6, 10**6, n).astype(np.int32)
+            p.step(k, v, f"G={G} n={n} batch {b} mode {mode}")
+        p.close()
