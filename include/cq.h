@@ -164,12 +164,10 @@ int cq_push_batch_results(cq_query *q, const int32_t *keys, const int32_t *value
  *   ids[i], sums[i], counts[i], avgs[i], n_touched[i] : batch i's result
  *                        buffers as for cq_results (the four arrays of
  *                        pointers may be NULL, n_touched[i] may not)
- * The batches' launches are overlapped inside the library: batch i+1's
- * histogram, plan and reorder run while batch i's per-group phase runs, on
- * two library streams with two sets of batch-local buffers; per-group state
- * stays in batch order.  Stream-ordered: the work starts after what is
- * already enqueued on `stream`, and `stream` continues once every batch is
- * done; returns without waiting for the device.  A batch with a bad key
+ * Consecutive batches use two sets of batch-local buffers, so batch i+1's
+ * key histogram is computed by extra workgroups of batch i's per-group
+ * launch: two launches per batch instead of three.  Stream-ordered on
+ * `stream`; returns without waiting for the device.  A batch with a bad key
  * gets CQ_ERR_KEY_RANGE in *n_touched[i] and leaves the state unchanged;
  * the other batches proceed.  The input and result buffers must stay valid
  * until the work on `stream` completes.  Telemetry records describe the

@@ -158,8 +158,21 @@ hipError_t launch_plan(State st, Scratch sc, int32_t seq, int mode, int32_t work
                        hipStream_t s);
 hipError_t launch_pass(const int32_t *keys, const int32_t *values, int64_t n, State st,
                        Scratch sc, int32_t seq, int mode, int32_t workers, hipStream_t s);
+// The next batch's histogram, computed by extra workgroups of an update
+// launch (pipelined calls); blocks = 0 means none.
+struct NextHist {
+    const int32_t *keys;
+    int64_t n;
+    bool vec;
+    int32_t blocks;
+    int32_t seq;
+    Scratch sc;
+};
+// Whether the next batch's histogram can ride along with an update launch.
+bool can_fuse_hist(int64_t G, int mode);
 hipError_t launch_update(State st, Scratch sc, int64_t n, int mode, int32_t workers, Out out,
-                         hipStream_t s);
+                         hipStream_t s, const int32_t *next_keys = nullptr, int64_t next_n = 0,
+                         Scratch next_sc = Scratch{}, int32_t next_seq = 0);
 hipError_t launch_collect_touched(int64_t G, int32_t seq, Scratch sc, hipStream_t s);
 hipError_t launch_emit(State st, Scratch sc, int64_t cap, Out out, hipStream_t s);
 hipError_t launch_reset_totals(Scratch sc, hipStream_t s);

@@ -944,13 +944,13 @@ __device__ __forceinline__ void emit_one(const Out &out, int32_t j, int32_t g, i
     if (out.avgs) out.avgs[j] = (double)s / (double)c;
 }
 
-__device__ __forceinline__ void trace_record(int64_t *trace, unsigned long long t0,
+__device__ __forceinline__ void trace_record(int64_t *trace, int rec, unsigned long long t0,
                                              int64_t tuples, int64_t items) {
     if (!trace || threadIdx.x != 0) return;
     const unsigned long long t1 = wall_clock64();
     const uint32_t hwid = __builtin_amdgcn_s_getreg((31 << 11) | (0 << 6) | 4);
     const uint32_t xcc = __builtin_amdgcn_s_getreg((15 << 11) | (0 << 6) | 20);
-    int64_t *r = trace + 6 * (int64_t)blockIdx.x;
+    int64_t *r = trace + 6 * (int64_t)rec;
     r[0] = hwid;
     r[1] = xcc;
     r[2] = (int64_t)t0;
@@ -1273,18 +1273,89 @@ __device__ int heavy_bucket(int32_t g, int32_t pold_g, int size, int tiles, cons
     return need;
 }
 
+// Histogram of the next batch of a pipelined call, run by the last
+// nh.blocks workgroups of an update launch (so that it costs no launch of
+// its own): UPD_THREADS threads over FH_TILE consecutive keys.  A tile holds
+// fewer than 2^16 keys, so the LDS counters are 16-bit halves of words
+// (key k in word k/2), and the group counts fit the update's LDS.
+constexpr int FH_KPT = 32;
+constexpr int FH_TILE = UPD_THREADS * FH_KPT;
+static_assert(FH_TILE < 65536, "16-bit counters");
+static_assert(PASS_LOCAL_G / 2 * 4 <= U_BYTES, "packed counters fit the update's LDS");
+
+__device__ void fused_hist(const NextHist &h, int hb, int nhb, int32_t G, uint32_t *cw) {
+    const int tid = threadIdx.x;
+    const int32_t hot0 = h.sc.hot[0], hot1 = h.sc.hot[1];
+    const int words = (G + 1) / 2;
+    for (int w = tid; w < words; w += UPD_THREADS) cw[w] = 0;
+    const int64_t base = (int64_t)hb * FH_TILE;
+    int32_t v[FH_KPT];
+#pragma unroll
+    for (int j = 0; j < FH_KPT / 4; ++j) {
+        const int64_t i = base + 4 * ((int64_t)j * UPD_THREADS + tid);
+        if (h.vec && i + 3 < h.n) {
+            const int4 x = *reinterpret_cast<const int4 *>(h.keys + i);
+            v[4 * j] = x.x; v[4 * j + 1] = x.y; v[4 * j + 2] = x.z; v[4 * j + 3] = x.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[4 * j + e] = (i + e < h.n) ? h.keys[i + e] : 0;
+        }
+    }
+    __syncthreads();
+    int bad = 0, c0 = 0, c1 = 0;
+#pragma unroll
+    for (int j = 0; j < FH_KPT / 4; ++j) {
+        const int64_t i = base + 4 * ((int64_t)j * UPD_THREADS + tid);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (i + e >= h.n) continue;
+            const int32_t key = v[4 * j + e];
+            if (key < 0 || key >= G) bad = 1;
+            else if (key == hot0) ++c0;
+            else if (key == hot1) ++c1;
+            else atomicAdd(&cw[key >> 1], (key & 1) ? 65536u : 1u);
+        }
+    }
+    c0 = wave_total(wave_incl_add(c0));
+    c1 = wave_total(wave_incl_add(c1));
+    if (lane_id() == 0) {
+        if (c0) atomicAdd(&cw[hot0 >> 1], (uint32_t)c0 << (16 * (hot0 & 1)));
+        if (c1) atomicAdd(&cw[hot1 >> 1], (uint32_t)c1 << (16 * (hot1 & 1)));
+    }
+    if (__syncthreads_or(bad)) {
+        if (tid == 0) atomicExch(h.sc.bad, h.seq);
+    }
+    // staggered flush, as in k_hist_small
+    const int off = (int)(((int64_t)hb * words / nhb) & ~31);
+    for (int i = tid; i < words; i += UPD_THREADS) {
+        const int w = i + off < words ? i + off : i + off - words;
+        const uint32_t c = cw[w];
+        if (c & 0xffff) atomicAdd(&h.sc.k[2 * w], (int32_t)(c & 0xffff));
+        if (c >> 16) atomicAdd(&h.sc.k[2 * w + 1], (int32_t)(c >> 16));
+    }
+}
+
 __global__ __launch_bounds__(UPD_THREADS) void k_update_balanced(State st, Scratch sc, int tiles,
-                                                                 Out out) {
+                                                                 Out out, NextHist nh) {
     __shared__ __align__(16) char smem[U_BYTES];
     __shared__ int red[UPD_THREADS / 64];
     __shared__ long long red_ll[UPD_THREADS / 64];
     const unsigned long long t0 = wall_clock64();
-    const PlanTotals t = *sc.tot;
-    if (t.status) {
-        if (blockIdx.x == 0 && threadIdx.x == 0 && out.n_touched) *out.n_touched = t.status;
+    // the next batch's histogram takes the first nh.blocks workgroups (they
+    // are dispatched first and finish early); the update takes the rest
+    const int ug = (int)gridDim.x - nh.blocks;
+    if ((int)blockIdx.x < nh.blocks) {
+        fused_hist(nh, (int)blockIdx.x, nh.blocks, (int32_t)st.G,
+                   reinterpret_cast<uint32_t *>(smem));
         return;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && out.n_touched) *out.n_touched = t.n_touched;
+    const int ub = (int)blockIdx.x - nh.blocks;  // workgroup index within the update
+    const PlanTotals t = *sc.tot;
+    if (t.status) {
+        if (ub == 0 && threadIdx.x == 0 && out.n_touched) *out.n_touched = t.status;
+        return;
+    }
+    if (ub == 0 && threadIdx.x == 0 && out.n_touched) *out.n_touched = t.n_touched;
     int64_t tuples = 0, items = 0;
     const int NB = t.n_buckets;
     int32_t *rs = reinterpret_cast<int32_t *>(smem + U_RS);
@@ -1296,10 +1367,10 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_balanced(State st, Scrat
     // i mod XCDS); each XCD takes one contiguous range of buckets, so the
     // cache lines that neighbouring buckets share in the staged tiles and
     // their rows of bucket starts stay in one XCD's L2.
-    const int xcd = blockIdx.x % XCDS, per_xcd = gridDim.x / XCDS;
+    const int xcd = ub % XCDS, per_xcd = ug / XCDS;
     const int span = (NB + XCDS - 1) / XCDS;
     const int b_lo = xcd * span, b_hi = min(NB, b_lo + span);
-    const int first = (int)blockIdx.x / XCDS < per_xcd ? b_lo + (int)blockIdx.x / XCDS : NB;
+    const int first = ub / XCDS < per_xcd ? b_lo + ub / XCDS : NB;
     for (int b = first; b < b_hi; b += per_xcd) {
         const bool light = b < t.n_light_buckets;
         int32_t a = 0, z = 0, g = 0, pold_g = 0;
@@ -1332,7 +1403,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_balanced(State st, Scrat
         ++items;
     }
     phase_mark(sc, PHASE_UPDATE, 5);
-    trace_record(sc.trace, t0, tuples, items);
+    trace_record(sc.trace, ub, t0, tuples, items);
 }
 
 // Static assignment: worker w (one wave) owns groups [g0(w), g0(w+1)) and
@@ -1618,16 +1689,31 @@ int64_t update_grid(int64_t n, int mode, int32_t workers) {
     return (std::max<int64_t>(1, std::min<int64_t>(nb, NB_MAX)) + XCDS - 1) / XCDS * XCDS;
 }
 
+bool can_fuse_hist(int64_t G, int mode) { return mode != MODE_STATIC && plan_fused(G); }
+
 hipError_t launch_update(State st, Scratch sc, int64_t n, int mode, int32_t workers, Out out,
-                         hipStream_t s) {
+                         hipStream_t s, const int32_t *next_keys, int64_t next_n, Scratch next_sc,
+                         int32_t next_seq) {
     const int tiles = (int)((n + PASS_TILE - 1) / PASS_TILE);
     const int64_t grid = update_grid(n, mode, workers);
-    if (mode == MODE_STATIC)
+    if (mode == MODE_STATIC) {
         hipLaunchKernelGGL(k_update_static, dim3((unsigned)grid), dim3(UPD_THREADS), 0, s, st, sc,
                            tiles, workers, out);
-    else
-        hipLaunchKernelGGL(k_update_balanced, dim3((unsigned)grid), dim3(UPD_THREADS), 0, s, st,
-                           sc, tiles, out);
+    } else {
+        NextHist nh{};
+        if (next_keys && next_n > 0 && can_fuse_hist(st.G, mode)) {
+            nh.keys = next_keys;
+            nh.n = next_n;
+            nh.vec = aligned16(next_keys);
+            // a whole number per XCD, so update workgroup u still runs on
+            // XCD u mod 8 (tiles past the batch count nothing)
+            nh.blocks = (int32_t)(((next_n + FH_TILE - 1) / FH_TILE + XCDS - 1) / XCDS * XCDS);
+            nh.seq = next_seq;
+            nh.sc = next_sc;
+        }
+        hipLaunchKernelGGL(k_update_balanced, dim3((unsigned)(grid + nh.blocks)),
+                           dim3(UPD_THREADS), 0, s, st, sc, tiles, out, nh);
+    }
     return hipGetLastError();
 }
 

@@ -26,10 +26,8 @@ struct cq_query {
     State st{};
     Scratch sc{};               // working buffers (batch-local arrays: set 0)
     Scratch alt{};              // second set of batch-local arrays (pipelined calls)
+    bool have_alt = false;
     int cur = 0;                // set used by the most recent batch
-    hipStream_t ps[2] = {nullptr, nullptr};  // pipeline: histogram+pass, update
-    hipEvent_t ev_pass[2] = {nullptr, nullptr}, ev_upd[2] = {nullptr, nullptr};
-    hipEvent_t ev_in = nullptr, ev_done = nullptr;
     int mode = MODE_BALANCED;
     int32_t workers = 1024;
     int32_t seq = 0;            // batch sequence number (device-side epochs)
@@ -102,6 +100,7 @@ void free_set(Scratch &b) {
     dfree(b.rowstart);
     dfree(b.partials);
     dfree(b.tot);
+    dfree(b.bad);
 }
 
 // Allocates and clears the batch-local arrays of a set (histogram zero,
@@ -122,12 +121,14 @@ int alloc_set(Scratch &b, int64_t G) {
     if (rc == CQ_OK) rc = dalloc(&b.rowstart, (int64_t)PASS_TILES_MAX * (NB_MAX + 1));
     if (rc == CQ_OK) rc = dalloc(&b.partials, nblk * PLAN_FIELDS);
     if (rc == CQ_OK) rc = dalloc(&b.tot, 1);
+    if (rc == CQ_OK) rc = dalloc(&b.bad, 1);
     if (rc != CQ_OK) return rc;
     hipError_t e = hipMemset(b.k, 0, sizeof(int32_t) * (size_t)G);
     if (e == hipSuccess) e = hipMemset(b.stamp, 0, sizeof(int32_t) * (size_t)G);
     if (e == hipSuccess) e = hipMemset(b.bucket, 0, sizeof(int32_t) * (size_t)G);
     if (e == hipSuccess) e = hipMemset(b.lpre, 0, sizeof(int32_t) * (size_t)(G + 1));
     if (e == hipSuccess) e = hipMemset(b.tot, 0, sizeof(PlanTotals));
+    if (e == hipSuccess) e = hipMemset(b.bad, 0, sizeof(int32_t));
     return from_hip(e);
 }
 
@@ -138,14 +139,6 @@ void free_all(cq_query *q) {
     dfree(q->st.sum);
     free_set(q->sc);
     free_set(q->alt);
-    for (int i = 0; i < 2; ++i) {
-        if (q->ps[i]) (void)hipStreamDestroy(q->ps[i]);
-        if (q->ev_pass[i]) (void)hipEventDestroy(q->ev_pass[i]);
-        if (q->ev_upd[i]) (void)hipEventDestroy(q->ev_upd[i]);
-    }
-    if (q->ev_in) (void)hipEventDestroy(q->ev_in);
-    if (q->ev_done) (void)hipEventDestroy(q->ev_done);
-    dfree(q->sc.bad);
     dfree(q->sc.fault);
     dfree(q->sc.hot);
     dfree(q->sc.trace);
@@ -208,11 +201,10 @@ bool static_ok(int64_t G, int32_t workers) {
     return (G + workers - 1) / workers <= STATIC_KEYS_MAX;
 }
 
-// Buffer set i (batch-local arrays) with the shared ones (key check,
-// fault bits, hot groups, telemetry records; the records only when on).
+// Buffer set i (batch-local arrays, key-check flag) with the shared ones
+// (fault bits, hot groups, telemetry records; the records only when on).
 Scratch set_of(const cq_query *q, int i) {
     Scratch b = i ? q->alt : q->sc;
-    b.bad = q->sc.bad;
     b.fault = q->sc.fault;
     b.hot = q->sc.hot;
     b.trace = (q->telemetry & CQ_TELEMETRY_WORKERS) ? q->sc.trace : nullptr;
@@ -237,10 +229,12 @@ int prepare_telemetry(cq_query *q, int64_t n) {
     return CQ_OK;
 }
 
-// Histogram, plan and reorder of one sub-batch (stream `s`).
+// Histogram (unless already enqueued), plan and reorder of one sub-batch.
 int front(cq_query *q, const int32_t *keys, const int32_t *values, int64_t m, const Scratch &sc,
-          int32_t seq, hipStream_t s) {
-    int rc = timed(q, CQ_KERNEL_HIST, s,
+          int32_t seq, hipStream_t s, bool have_hist = false) {
+    int rc = CQ_OK;
+    if (!have_hist)
+        rc = timed(q, CQ_KERNEL_HIST, s,
                    [&] { return launch_hist(keys, m, q->st.G, sc, seq, s); });
     if (rc == CQ_OK && !plan_fused(q->st.G))
         rc = timed(q, CQ_KERNEL_PLAN, s,
@@ -300,28 +294,17 @@ int push(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n, hip
     return rc;
 }
 
-// Ordering-only events between the library's streams and the caller's:
-// no timestamps, no system-scope fences (all the data stays on the device).
-constexpr unsigned kSyncEvent = hipEventDisableTiming | hipEventDisableSystemFence;
-
-// Second buffer set, the two pipeline streams and their events (first use).
-int ensure_pipeline(cq_query *q) {
-    if (q->ps[0]) return CQ_OK;
+// Second buffer set (first pipelined call).
+int ensure_alt(cq_query *q) {
+    if (q->have_alt) return CQ_OK;
     int rc = alloc_set(q->alt, q->st.G);
+    if (rc == CQ_OK) rc = from_hip(hipDeviceSynchronize());
     if (rc != CQ_OK) {
         free_set(q->alt);
         return rc;
     }
-    hipError_t e = hipSuccess;
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
-        e = hipStreamCreateWithFlags(&q->ps[i], hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&q->ev_pass[i], kSyncEvent);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&q->ev_upd[i], kSyncEvent);
-    }
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&q->ev_in, kSyncEvent);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&q->ev_done, kSyncEvent);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
-    return from_hip(e);
+    q->have_alt = true;
+    return CQ_OK;
 }
 
 }  // namespace
@@ -361,7 +344,6 @@ int cq_create(int64_t groups, int32_t window, uint32_t aggregates, cq_query **ou
     if (rc == CQ_OK) rc = dalloc(&q->st.cnt, G);
     if (rc == CQ_OK) rc = dalloc(&q->st.sum, G);
     if (rc == CQ_OK) rc = alloc_set(q->sc, G);
-    if (rc == CQ_OK) rc = dalloc(&q->sc.bad, 1);
     if (rc == CQ_OK) rc = dalloc(&q->sc.fault, 1);
     if (rc == CQ_OK) rc = dalloc(&q->sc.hot, 2);
     hipError_t e = hipSuccess;
@@ -372,7 +354,6 @@ int cq_create(int64_t groups, int32_t window, uint32_t aggregates, cq_query **ou
         if (e == hipSuccess) e = hipMemset(q->st.pos, 0, sizeof(int32_t) * (size_t)G);
         if (e == hipSuccess) e = hipMemset(q->st.cnt, 0, sizeof(int32_t) * (size_t)G);
         if (e == hipSuccess) e = hipMemset(q->st.sum, 0, sizeof(int64_t) * (size_t)G);
-        if (e == hipSuccess) e = hipMemset(q->sc.bad, 0, sizeof(int32_t));
         if (e == hipSuccess) e = hipMemset(q->sc.fault, 0, sizeof(int32_t));
         if (e == hipSuccess) e = hipMemset(q->sc.hot, 0xff, 2 * sizeof(int32_t));
         if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -436,52 +417,42 @@ int cq_push_batches(cq_query *q, int32_t count, const int32_t *const *keys,
     }
     if (q->mode == MODE_STATIC && !static_ok(q->st.G, q->workers)) return CQ_ERR_INVALID;
     DeviceGuard guard(q->device);
-    int rc = ensure_pipeline(q);
+    int rc = ensure_alt(q);
     if (rc == CQ_OK) rc = prepare_telemetry(q, SUB);
     if (rc != CQ_OK) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipStream_t sa = q->ps[0], sb = q->ps[1];
-    // everything the caller enqueued before (inputs, earlier batches) first
-    hipError_t e = hipEventRecord(q->ev_in, s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(sa, q->ev_in, 0);
-    if (e == hipSuccess) e = hipStreamWaitEvent(sb, q->ev_in, 0);
-    rc = from_hip(e);
-    // Batch i uses buffer set i mod 2.  Histogram, plan and reorder run on
-    // one stream, the per-group update on the other, so batch i+1's front
-    // half overlaps batch i's update.  Per-group state stays ordered: plans
-    // (pointers, counts) follow one another on the first stream, updates
-    // (windows, sums) on the second.
+    const int32_t seq0 = q->seq + 1;
+    q->seq += count;
+    // Batch i uses buffer set i mod 2.  Batch i+1's histogram is computed
+    // by extra workgroups of batch i's update launch (it only needs its own
+    // set's histogram, cleared by batch i-1's update), so a batch costs two
+    // launches instead of three; everything stays on the caller's stream.
+    bool have_hist = false;
     for (int32_t i = 0; i < count && rc == CQ_OK; ++i) {
         const int b = i & 1;
         const Scratch sc = set_of(q, b);
-        const int32_t seq = ++q->seq;
+        const int32_t seq = seq0 + i;
         const Out out = {ids ? ids[i] : nullptr, sums ? sums[i] : nullptr,
                          counts ? counts[i] : nullptr, avgs ? avgs[i] : nullptr, n_touched[i]};
         q->cur = b;
         q->last_n = n[i];
         if (n[i] == 0) {
-            // nothing touched; the set's totals say so (cq_results after
-            // this call), ordered after the set's previous update
-            rc = from_hip(launch_reset_totals(sc, sb));
-            if (rc == CQ_OK) rc = from_hip(launch_set_touched(n_touched[i], 0, sb));
-            if (rc == CQ_OK) rc = from_hip(hipEventRecord(q->ev_upd[b], sb));
+            rc = from_hip(launch_reset_totals(sc, s));
+            if (rc == CQ_OK) rc = from_hip(launch_set_touched(n_touched[i], 0, s));
+            have_hist = false;
             continue;
         }
-        // the update two batches back has finished with this buffer set
-        if (i >= 2) rc = from_hip(hipStreamWaitEvent(sa, q->ev_upd[b], 0));
-        if (rc == CQ_OK) rc = front(q, keys[i], values[i], n[i], sc, seq, sa);
-        if (rc == CQ_OK) rc = from_hip(hipEventRecord(q->ev_pass[b], sa));
-        if (rc == CQ_OK) rc = from_hip(hipStreamWaitEvent(sb, q->ev_pass[b], 0));
+        rc = front(q, keys[i], values[i], n[i], sc, seq, s, have_hist);
+        const bool fuse = i + 1 < count && n[i + 1] > 0 && can_fuse_hist(q->st.G, q->mode);
         if (rc == CQ_OK)
-            rc = timed(q, CQ_KERNEL_UPDATE, sb, [&] {
-                return launch_update(q->st, sc, n[i], q->mode, q->workers, out, sb);
+            rc = timed(q, CQ_KERNEL_UPDATE, s, [&] {
+                return fuse ? launch_update(q->st, sc, n[i], q->mode, q->workers, out, s,
+                                            keys[i + 1], n[i + 1], set_of(q, (i + 1) & 1),
+                                            seq + 1)
+                            : launch_update(q->st, sc, n[i], q->mode, q->workers, out, s);
             });
-        if (rc == CQ_OK) rc = from_hip(hipEventRecord(q->ev_upd[b], sb));
+        have_hist = fuse;
     }
-    // the caller's stream continues once every update is done (updates are
-    // ordered on their stream, and each follows its batch's front half)
-    if (rc == CQ_OK) rc = from_hip(hipEventRecord(q->ev_done, sb));
-    if (rc == CQ_OK) rc = from_hip(hipStreamWaitEvent(s, q->ev_done, 0));
     q->last_stream = s;
     q->pushed = true;
     q->last_mode = q->mode;
@@ -519,11 +490,6 @@ int cq_destroy(cq_query *q) {
     DeviceGuard guard(q->device);
     int rc = CQ_OK;
     if (q->pushed) rc = from_hip(hipStreamSynchronize(q->last_stream));
-    for (int i = 0; i < 2; ++i)
-        if (q->ps[i]) {
-            const int r = from_hip(hipStreamSynchronize(q->ps[i]));
-            if (rc == CQ_OK) rc = r;
-        }
     free_all(q);
     delete q;
     return rc;
