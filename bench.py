@@ -169,11 +169,14 @@ def run_pipelined(torch, cq, batches, cfg, warmup, steps, per_call=8):
              torch.empty(cap, dtype=torch.int32, device=dev),
              torch.empty(cap, dtype=torch.float64, device=dev),
              torch.empty(1, dtype=torch.int64, device=dev)) for _ in range(per_call)]
-    w = max(per_call, warmup // per_call * per_call)
-    for b in range(0, w, per_call):
-        q.push_batches_into(batches[b:b + per_call], outs)
+    w = per_call if len(batches) >= 2 * per_call else 0  # one warm-up call
+    if w:
+        q.push_batches_into(batches[:w], outs)
     torch.cuda.synchronize()
-    calls = steps // per_call
+    calls = min(steps, len(batches) - w) // per_call
+    if calls == 0:
+        q.close()
+        return None
     t0 = time.perf_counter()
     for c in range(calls):
         s0 = w + c * per_call
@@ -300,9 +303,11 @@ def main():
             if is_head:
                 kr = run_mode(torch, cq, batches, cfg, mode, args.warmup, args.steps, "kernels")
                 r["kernels"] = kr["kernels"]
-                pw, pn = run_pipelined(torch, cq, batches, cfg, args.warmup, args.steps)
-                row["pipelined_8_per_call"] = {"tuples_per_s": pn * cfg.batch / pw,
-                                               "ms_per_batch": 1e3 * pw / pn, "batches": pn}
+                pr = run_pipelined(torch, cq, batches, cfg, args.warmup, args.steps)
+                if pr:
+                    pw, pn = pr
+                    row["pipelined_8_per_call"] = {"tuples_per_s": pn * cfg.batch / pw,
+                                                   "ms_per_batch": 1e3 * pw / pn, "batches": pn}
                 headline = (row, r, timed_bytes, cfg, batches)
         if not (s == HEADLINE_S):
             del batches

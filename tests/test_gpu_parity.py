@@ -387,3 +387,34 @@ def test_in_pass_plan_ownership(G, n):
             v = rng.integers(-10**6, 10**6, n).astype(np.int32)
             p.step(k, v, f"G={G} n={n} batch {b} mode {mode}")
         p.close()
+
+
+def test_telemetry_records():
+    """Kernel-time, worker and phase telemetry describe the last batch and
+    do not change its results."""
+    note("case: telemetry")
+    cfg = skew(1.5, batches=3)
+    k, v = host_batch(cfg, 0)
+    p = Pair(cfg.groups, cfg.window)
+    p.q.set_telemetry(cq.TELEMETRY_KERNEL_TIMES | cq.TELEMETRY_WORKERS | cq.TELEMETRY_PHASES)
+    p.step(k, v, "telemetry batch")
+    kt = p.q.kernel_times()
+    for kind in ("hist", "pass", "update"):
+        ms, launches = kt[kind]
+        assert launches == 1 and 0 < ms < 100, (kind, ms, launches)
+    rec = p.q.worker_trace()
+    assert len(rec) >= 1
+    plan = p.q.batch_plan()
+    # every tuple is handled by exactly one workgroup: light tuples fully,
+    # heavy groups through at most W survivors
+    worked = [r for r in rec if r[5] > 0]
+    assert len(worked) == plan["buckets"]
+    assert all(r[3] >= r[2] > 0 for r in worked)
+    ph = p.q.phase_trace(1)
+    started = [r for r in ph if r[0] > 0]
+    assert len(started) == (len(k) + 4095) // 4096
+    assert all(r[4] >= r[0] for r in started)
+    p.q.set_telemetry(0)
+    k2, v2 = host_batch(cfg, 1)
+    p.step(k2, v2, "after telemetry")
+    p.close()
