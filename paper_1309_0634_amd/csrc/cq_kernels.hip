@@ -1,27 +1,37 @@
 // HIP kernels for gfx950 (CDNA4, wave64): one sub-batch (<= SUB tuples) of
 // the continuous sliding-window group-by aggregate.
 //
-// Three launches per sub-batch, in stream order:
+// Three launches per sub-batch (up to 16384 groups), in stream order:
 //
-//   k_hist_plan  arrival tiles count keys in LDS; the last tile to finish
-//                plans the sub-batch: the load balancer (Section 4 moves
-//                groups between workers from per-worker tuple counts; here
-//                the exact per-group counts of this very batch decide, with
-//                no one-iteration delay).  Light groups are packed in id
-//                order into buckets of about LIGHT_BUDGET tuples, every
-//                group with >= HEAVY_MIN tuples becomes a bucket of its own,
-//                and each touched group's ring pointer moves on (Section 3.2:
-//                nextPos advances as values enter the window).
-//   k_pass       arrival tiles reorder their tuples by bucket, stably, in
-//                LDS and write them back contiguously: the paper's two-pass
-//                linear reorder (Section 3.1), done per tile so that no tile
-//                waits on another.
-//   k_update_*   the per-group phase: a bucket's tuples are read tile by
-//                tile (arrival order); every tuple among its group's last W
-//                goes to ring slot (pos + rank) mod W, and the group's sum
-//                gains (new value - value overwritten), i.e. the evicted
-//                value is subtracted (Section 3.2: a full window discards its
-//                oldest value).  Results are emitted in ascending group id.
+//   k_hist_small  arrival tiles count keys in LDS (the previous sub-batch's
+//                 two hottest keys in registers) and add their counts to
+//                 the global histogram.
+//   k_pass<true>  per arrival tile: the load balancer, then the reorder.
+//                 Every workgroup reduces the whole histogram itself, so it
+//                 knows each group's bucket without waiting on another
+//                 (Section 4 moves groups between workers from per-worker
+//                 tuple counts; here the exact per-group counts of this very
+//                 batch decide, with no one-iteration delay): light groups
+//                 are packed in id order into buckets of about LIGHT_BUDGET
+//                 tuples, every group with >= HEAVY_MIN tuples becomes a
+//                 bucket of its own, and each touched group's ring pointer
+//                 moves on (Section 3.2: nextPos advances as values enter the
+//                 window).  Then the tile's tuples are reordered by bucket,
+//                 stably, in LDS and written back contiguously: the paper's
+//                 two-pass linear reorder (Section 3.1), done per tile so
+//                 that no tile waits on another.
+//   k_update_*    the per-group phase: a bucket's tuples are read tile by
+//                 tile (arrival order); every tuple among its group's last W
+//                 goes to ring slot (pos + rank) mod W, and the group's sum
+//                 gains (new value - value overwritten), i.e. the evicted
+//                 value is subtracted (Section 3.2: a full window discards
+//                 its oldest value).  Results are emitted in ascending group
+//                 id.  In a pipelined call its first workgroups compute the
+//                 next batch's histogram.
+//
+// More groups: a separate plan launch (k_plan_small, then k_pass<false>
+// reads buckets from global memory), and beyond 32768 groups a hashed
+// histogram (k_hist_hash) with a three-launch plan.
 //
 // Integer work bounded by memory traffic and latency: no MFMA.
 #include <algorithm>
@@ -613,21 +623,22 @@ __global__ void k_validate(const int32_t *__restrict__ keys, int64_t n, int64_t 
 
 // --------------------------------------------------------------- k_pass --
 // One arrival tile of PASS_TILE tuples per workgroup.  Wave w owns tuples
-// [w*1024, (w+1)*1024) of the tile, visited in 64-lane rounds; every tuple
+// [w*512, (w+1)*512) of the tile, visited in 64-lane rounds; every tuple
 // learns its rank among the wave's earlier tuples of the same bucket from
 // ballots over the bucket id bits (lanes of one bucket find each other)
 // plus a per-wave counter.  Waves then combine into tile-wide bucket
 // offsets, the tile is reordered in LDS and written back contiguously, and
 // the tile's bucket starts are recorded.  Tiles never wait on each other.
+
 // In-block plan of the fused pass (G <= PASS_LOCAL_G).  Every block reduces
 // the whole histogram itself (thread t scans a contiguous run of groups),
 // so each knows the bucket of every group without waiting on any other
 // block: gbk[g] gets the bucket of each touched group (gcnt holds the
-// counts meanwhile).  The per-group plan
-// of group g is written by block g mod gridDim only; block 0 publishes the
-// totals and keeps the two most frequent groups for the next histogram.
-// Returns the bucket count, or -1 for a rejected batch (whose histogram is
-// cleared here: no block reads it then).  Barriers inside; call uniformly.
+// counts meanwhile).  Block b writes the per-group plan of the contiguous
+// groups [b*G/grid, (b+1)*G/grid); block 0 publishes the totals and keeps
+// the two most frequent groups for the next histogram.  Returns the bucket
+// count, or -1 for a rejected batch (whose histogram is cleared here: no
+// block reads it then).  Barriers inside; call uniformly.
 // Groups whose plan one pass workgroup writes per step of its in-block plan.
 constexpr int OWN_CAP = 1024;
 
