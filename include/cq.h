@@ -57,8 +57,16 @@ extern "C" {
 #define CQ_ERR_HIP       -4   /* a HIP runtime call failed                */
 
 /* Work assignment of the per-group phase (see cq_set_partition). */
-#define CQ_PARTITION_BALANCED 0
-#define CQ_PARTITION_STATIC   1
+#define CQ_PARTITION_BALANCED    0
+#define CQ_PARTITION_STATIC      1
+/* The paper's load-balancing techniques (Section 4), on the static
+ * workers: see cq_set_partition. */
+#define CQ_PARTITION_GETFIRST    2
+#define CQ_PARTITION_CHECKALL    3
+#define CQ_PARTITION_PROBCHECK   4
+#define CQ_PARTITION_BESTBALANCE 5
+#define CQ_PARTITION_SHIFT       6
+#define CQ_PARTITION_SHIFTLOCAL  7
 
 /* Largest batch accepted by cq_push_batch. */
 #define CQ_MAX_BATCH (1ll << 30)
@@ -101,12 +109,51 @@ int cq_reserve(cq_query *q, int64_t max_batch);
  *     equal, consecutive group range [ceil(w*groups/workers),
  *     ceil((w+1)*groups/workers)) and processes every tuple of its groups
  *     -- the paper's initial assignment with balancing turned off
- *     (Section 5.1).  Needs workers <= 1536 and at most 2048 groups per
- *     worker.
- * Results are identical in every mode.  Takes effect at the next push.
- * Returns CQ_OK or CQ_ERR_INVALID.
+ *     (Section 5.1).  Needs workers <= 4096 and at most 2048 groups per
+ *     worker;
+ *   CQ_PARTITION_GETFIRST .. CQ_PARTITION_SHIFTLOCAL: the static workers,
+ *     starting from the same ranges, with the group-to-worker mapping
+ *     revised on the host after every batch by that technique of Section 4
+ *     from the batch's tuples per worker, taking effect from the next batch
+ *     (Section 3.1: one iteration of delay).  Groups move whole; no worker
+ *     is given more than 2048 groups.  Each push then waits for its
+ *     batch's histogram on the host (the GPU keeps working meanwhile), as
+ *     the paper's CPU coordinator does.  Only for up to 16384 groups.
+ * Results are identical in every mode.  Takes effect at the next push and
+ * restarts a technique's mapping from the initial ranges.  Returns CQ_OK
+ * or CQ_ERR_INVALID.
  */
 int cq_set_partition(cq_query *q, int32_t mode, int32_t workers);
+
+/*
+ * cq_set_policy_params -- parameters of the Section 4 techniques: the
+ * imbalance threshold in tuples (the paper's threadThreshold, default
+ * 1000) and probCheck's pot (0 < pot <= 1, default 0.5; Section 5.1).
+ * Returns CQ_OK or CQ_ERR_INVALID.
+ */
+int cq_set_policy_params(cq_query *q, int64_t threshold, double pot);
+
+/*
+ * cq_policy_stats -- after a push under a Section 4 technique: out[0] =
+ * groups moved after the last batch, out[1] / out[2] = the largest /
+ * smallest tuples per worker of that batch under the mapping it ran with,
+ * out[3] = groups moved since the technique was selected.  Zeros in the
+ * other modes.  Returns CQ_OK or CQ_ERR_INVALID.
+ */
+int cq_policy_stats(cq_query *q, int64_t *out);
+
+/*
+ * cq_policy_apply -- one balancing step of technique `policy` on the host,
+ * without a query or a device (the step cq_push_batch runs after a batch
+ * under that technique).  The mapping is given and returned as ordered
+ * lists: worker w's groups are wlist[wstart[w] .. wstart[w+1]) (wstart has
+ * workers+1 entries, wlist `groups`; every group exactly once).  counts[g]
+ * are the batch's tuples of group g.  *moves receives the number of groups
+ * moved.  Returns CQ_OK or CQ_ERR_INVALID (bad arguments or mapping).
+ */
+int cq_policy_apply(int32_t policy, int32_t workers, int64_t groups, const int32_t *counts,
+                    int32_t *wstart, int32_t *wlist, int64_t threshold, double pot,
+                    int32_t max_keys, int64_t *moves);
 
 /*
  * cq_push_batch -- apply one batch of n tuples (Section 3.1: one iteration

@@ -17,6 +17,13 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "cq.h")
 SUM, COUNT, AVG = 1, 2, 4
 OK, ERR_INVALID, ERR_OOM, ERR_KEY_RANGE, ERR_HIP = 0, -1, -2, -3, -4
 PARTITION_BALANCED, PARTITION_STATIC = 0, 1
+# the Section 4 techniques, on the static workers
+(PARTITION_GETFIRST, PARTITION_CHECKALL, PARTITION_PROBCHECK, PARTITION_BESTBALANCE,
+ PARTITION_SHIFT, PARTITION_SHIFTLOCAL) = range(2, 8)
+POLICIES = {"getFirst": PARTITION_GETFIRST, "checkAll": PARTITION_CHECKALL,
+            "probCheck": PARTITION_PROBCHECK, "bestBalance": PARTITION_BESTBALANCE,
+            "shift": PARTITION_SHIFT, "shiftLocal": PARTITION_SHIFTLOCAL}
+STATIC_KEYS_MAX = 2048
 TELEMETRY_KERNEL_TIMES, TELEMETRY_WORKERS, TELEMETRY_PHASES = 1, 2, 4
 KERNEL_KINDS = ("hist", "pass", "update", "emit", "other", "plan")
 MAX_BATCH = 1 << 30
@@ -60,6 +67,10 @@ def lib() -> ctypes.CDLL:
             "cq_batch_plan": ([P, pi64], ctypes.c_int),
             "cq_phase_trace": ([P, i32, pi64, i64, pi64], ctypes.c_int),
             "cq_push_batches": ([P, i32, P, P, P, P, P, P, P, P, P], ctypes.c_int),
+            "cq_set_policy_params": ([P, i64, ctypes.c_double], ctypes.c_int),
+            "cq_policy_stats": ([P, pi64], ctypes.c_int),
+            "cq_policy_apply": ([i32, i32, i64, P, P, P, i64, ctypes.c_double, i32, pi64],
+                                ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -87,6 +98,25 @@ def _stream_handle(stream) -> Optional[int]:
 
 def _dptr(t) -> Optional[int]:
     return None if t is None else t.data_ptr()
+
+
+def policy_apply(policy: int, counts, wstart, wlist, threshold: int = 1000, pot: float = 0.5,
+                 max_keys: int = STATIC_KEYS_MAX):
+    """One host-side balancing step (cq_policy_apply) on numpy arrays: the
+    mapping ``wstart``/``wlist`` (int32, CSR, modified in place) and the
+    batch's per-group ``counts`` (int32).  Returns the number of moves."""
+    import numpy as np
+    for a in (counts, wstart, wlist):
+        if not (isinstance(a, np.ndarray) and a.dtype == np.int32 and a.flags.c_contiguous):
+            raise TypeError("policy_apply takes C-contiguous int32 numpy arrays")
+    if counts.shape[0] != wlist.shape[0]:
+        raise ValueError("counts and wlist must both have one entry per group")
+    moves = ctypes.c_int64(0)
+    _check(lib().cq_policy_apply(int(policy), int(wstart.shape[0] - 1), int(wlist.shape[0]),
+                                 counts.ctypes.data, wstart.ctypes.data, wlist.ctypes.data,
+                                 int(threshold), float(pot), int(max_keys), ctypes.byref(moves)),
+           "cq_policy_apply")
+    return moves.value
 
 
 class Query:
@@ -131,6 +161,17 @@ class Query:
     # -- configuration -----------------------------------------------------
     def set_partition(self, mode: int, workers: int = 0):
         _check(lib().cq_set_partition(self._h, int(mode), int(workers)), "cq_set_partition")
+
+    def set_policy_params(self, threshold: int = 1000, pot: float = 0.5):
+        _check(lib().cq_set_policy_params(self._h, int(threshold), float(pot)),
+               "cq_set_policy_params")
+
+    def policy_stats(self):
+        """(moves after the last batch, max and min tuples per worker of that
+        batch, moves since the technique was selected)."""
+        out = (ctypes.c_int64 * 4)()
+        _check(lib().cq_policy_stats(self._h, out), "cq_policy_stats")
+        return tuple(int(v) for v in out)
 
     def reserve(self, max_batch: int):
         _check(lib().cq_reserve(self._h, int(max_batch)), "cq_reserve")

@@ -121,6 +121,12 @@ struct Scratch {
     int32_t *fault;     // sticky internal-consistency bits
     int32_t *hot;       // [2] most frequent groups of the last planned sub-batch
     PlanTotals *tot;
+    // group-to-worker mapping of a Section 4 technique on the static
+    // workers (null: the contiguous initial ranges)
+    const int32_t *owner;   // G: worker of each group
+    const int32_t *wstart;  // workers + 1: each worker's first list entry
+    const int32_t *wlist;   // G: groups in worker-list order
+    const int32_t *lidx;    // G: position of each group in its worker's list
     int64_t *trace;     // optional per-workgroup records (6 int64 each)
     int64_t *phase;     // optional phase clocks [kind][block][PHASE_SLOTS]
 };

@@ -193,7 +193,7 @@ __device__ __forceinline__ void plan_group(const State &st, const Scratch &sc, i
     st.cnt[g] = nc;
     sc.ncnt[g] = nc;  // the count emitted for this batch (the state may move on)
     if (mode == MODE_STATIC) {
-        sc.bucket[g] = static_worker(g, st.G, workers);
+        sc.bucket[g] = sc.owner ? sc.owner[g] : static_worker(g, st.G, workers);
     } else if (kg >= HEAVY_MIN) {
         sc.bucket[g] = n_light + x_ex[1];
         if ((uint32_t)x_ex[1] < (uint32_t)NB_MAX) sc.hkey[x_ex[1]] = (int32_t)g;
@@ -736,6 +736,8 @@ __device__ int pass_local_plan(const State &st, const Scratch &sc, int32_t seq, 
     // run once per OWN_CAP owned groups and writes them here.
     const int gend = min(G, g0 + R);
     nl_out = nl;
+    if (mode == MODE_STATIC && sc.owner)  // a Section 4 mapping: buckets are workers
+        for (int g = tid; g < G; g += blockDim.x) gbk[g] = (uint16_t)sc.owner[g];
     own_n = hi - lo <= OWN_CAP ? hi - lo : 0;
     int base = lo;
     do {  // at least once: every block needs the bucket ids, owned groups or not
@@ -765,7 +767,7 @@ __device__ int pass_local_plan(const State &st, const Scratch &sc, int32_t seq, 
                 eA += heavy ? 0 : ks[e];
                 eB += (heavy ? 1 : 0) + (ks[e] > 0 ? 1 << 16 : 0);
             }
-            if (first) {  // bucket ids (those of untouched groups are never read)
+            if (first && !sc.owner) {  // bucket ids (untouched groups' are never read)
                 if (g4 + 3 < G) {
                     *reinterpret_cast<uint2 *>(gbk + g4) =
                         make_uint2(bo[0] | (bo[1] << 16), bo[2] | (bo[3] << 16));
@@ -1454,15 +1456,24 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_static(State st, Scratch
     long long *acc = reinterpret_cast<long long *>(smem + S_ACC) + wv * STATIC_KEYS_MAX;
     int64_t tuples = 0;
     if (w < workers && w < NB) {
-        const int32_t g0 = static_first(w, G, workers), g1 = static_first(w + 1, G, workers);
-        const int nk = g1 - g0;
+        // worker w's groups: a range, or its list under a Section 4 mapping
+        int32_t g0 = 0, nk;
+        const int32_t *list = nullptr;
+        if (sc.wstart) {
+            const int32_t a = sc.wstart[w];
+            nk = sc.wstart[w + 1] - a;
+            list = sc.wlist + a;
+        } else {
+            g0 = static_first(w, G, workers);
+            nk = static_first(w + 1, G, workers) - g0;
+        }
         if (nk > STATIC_KEYS_MAX) {
             if (lane == 0) atomicOr(sc.fault, FAULT_STATIC_KEYS);
         } else {
             for (int i = lane; i < nk; i += 64) {
                 ctr[i] = 0;
                 acc[i] = 0;
-                sc.k[g0 + i] = 0;  // histogram, for the next sub-batch
+                sc.k[list ? list[i] : g0 + i] = 0;  // histogram, for the next sub-batch
             }
             // runs of bucket w, and a wave-wide exclusive scan of their sizes
             int carry = 0;
@@ -1488,14 +1499,14 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_static(State st, Scratch
             for (int c0 = 0; c0 < size; c0 += 64) {
                 const int p = c0 + lane;
                 bool valid = p < size;
-                int32_t g = g0, v = 0;
+                int32_t g = list ? (nk ? list[0] : 0) : g0, v = 0;
                 if (valid) {
                     const int r = upper_run(rp, tiles, p);
                     const int2 e = sc.sdat[rs[r] + (p - rp[r])];
                     g = e.x;
                     v = e.y;
                 }
-                int loc = g - g0;
+                int loc = list ? (valid ? sc.lidx[g] : 0) : g - g0;
                 if (valid && (loc < 0 || loc >= nk)) {  // impossible for a well-formed plan
                     atomicOr(sc.fault, FAULT_STATIC_KEYS);
                     loc = 0;
@@ -1535,7 +1546,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_static(State st, Scratch
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             for (int i = lane; i < nk; i += 64) {
-                const int32_t g = g0 + i;
+                const int32_t g = list ? list[i] : g0 + i;
                 const int32_t kg = sc.lpre[g + 1] - sc.lpre[g];
                 if (kg > 0) {
                     const int64_t s = (kg >= W ? 0 : st.sum[g]) + acc[i];

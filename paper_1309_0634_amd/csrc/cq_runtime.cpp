@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "cq.h"
+#include "cq_balance.h"
 #include "cq_internal.h"
 
 using namespace cq;
@@ -42,6 +43,15 @@ struct cq_query {
     std::vector<hipEvent_t> spare;
     double ms[CQ_KERNEL_KINDS] = {0};
     int64_t launches[CQ_KERNEL_KINDS] = {0};
+    // Section 4 technique on the static workers (0: none)
+    int policy = 0;
+    Balancer bal;
+    int32_t *m_owner = nullptr, *m_wstart = nullptr, *m_wlist = nullptr, *m_lidx = nullptr;
+    int32_t *h_counts = nullptr;  // pinned: a batch's histogram, then its rejection flag
+    int32_t *h_map = nullptr;     // pinned: owner, wstart, wlist, lidx on their way up
+    hipEvent_t ev_counts = nullptr, ev_map = nullptr;
+    bool map_pending = false;     // an upload from h_map may still be running
+    int64_t policy_total = 0;     // groups moved since the technique was selected
 };
 
 namespace {
@@ -150,6 +160,16 @@ void free_all(cq_query *q) {
     for (auto e : q->spare) (void)hipEventDestroy(e);
     q->live.clear();
     q->spare.clear();
+    dfree(q->m_owner);
+    dfree(q->m_wstart);
+    dfree(q->m_wlist);
+    dfree(q->m_lidx);
+    if (q->h_counts) (void)hipHostFree(q->h_counts);
+    if (q->h_map) (void)hipHostFree(q->h_map);
+    q->h_counts = q->h_map = nullptr;
+    if (q->ev_counts) (void)hipEventDestroy(q->ev_counts);
+    if (q->ev_map) (void)hipEventDestroy(q->ev_map);
+    q->ev_counts = q->ev_map = nullptr;
 }
 
 int ensure_trace(cq_query *q, int64_t records) {
@@ -209,7 +229,92 @@ Scratch set_of(const cq_query *q, int i) {
     b.hot = q->sc.hot;
     b.trace = (q->telemetry & CQ_TELEMETRY_WORKERS) ? q->sc.trace : nullptr;
     b.phase = (q->telemetry & CQ_TELEMETRY_PHASES) ? q->sc.phase : nullptr;
+    const bool mapped = q->mode == MODE_STATIC && q->policy;
+    b.owner = mapped ? q->m_owner : nullptr;
+    b.wstart = mapped ? q->m_wstart : nullptr;
+    b.wlist = mapped ? q->m_wlist : nullptr;
+    b.lidx = mapped ? q->m_lidx : nullptr;
     return b;
+}
+
+// ---- Section 4 techniques: host-side mapping, one batch behind ----
+
+// Device and pinned buffers of the mapping (once per query).
+int policy_buffers(cq_query *q) {
+    if (q->m_owner) return CQ_OK;
+    const int64_t G = q->st.G;
+    int rc = dalloc(&q->m_owner, G);
+    if (rc == CQ_OK) rc = dalloc(&q->m_wstart, NB_MAX + 1);
+    if (rc == CQ_OK) rc = dalloc(&q->m_wlist, G);
+    if (rc == CQ_OK) rc = dalloc(&q->m_lidx, G);
+    hipError_t e = hipSuccess;
+    if (rc == CQ_OK)
+        e = hipHostMalloc(reinterpret_cast<void **>(&q->h_counts), sizeof(int32_t) * (size_t)(G + 1),
+                          hipHostMallocDefault);
+    if (e == hipSuccess && rc == CQ_OK)
+        e = hipHostMalloc(reinterpret_cast<void **>(&q->h_map),
+                          sizeof(int32_t) * (size_t)(3 * G + NB_MAX + 1), hipHostMallocDefault);
+    if (e == hipSuccess && rc == CQ_OK)
+        e = hipEventCreateWithFlags(&q->ev_counts, hipEventDisableTiming);
+    if (e == hipSuccess && rc == CQ_OK) e = hipEventCreateWithFlags(&q->ev_map, hipEventDisableTiming);
+    if (rc == CQ_OK) rc = from_hip(e);
+    if (rc != CQ_OK) {
+        dfree(q->m_owner);
+        dfree(q->m_wstart);
+        dfree(q->m_wlist);
+        dfree(q->m_lidx);
+        if (q->h_counts) (void)hipHostFree(q->h_counts);
+        if (q->h_map) (void)hipHostFree(q->h_map);
+        q->h_counts = q->h_map = nullptr;
+        if (q->ev_counts) (void)hipEventDestroy(q->ev_counts);
+        if (q->ev_map) (void)hipEventDestroy(q->ev_map);
+        q->ev_counts = q->ev_map = nullptr;
+    }
+    return rc;
+}
+
+// Enqueues the upload of the balancer's mapping on s (after the work
+// already on s, before whatever is enqueued next).
+int policy_upload(cq_query *q, hipStream_t s) {
+    const int64_t G = q->st.G;
+    const int32_t T = q->bal.T;
+    if (q->map_pending && hipEventSynchronize(q->ev_map) != hipSuccess) return CQ_ERR_HIP;
+    int32_t *owner = q->h_map, *wstart = owner + G, *wlist = wstart + T + 1, *lidx = wlist + G;
+    std::copy(q->bal.owner.begin(), q->bal.owner.end(), owner);
+    q->bal.export_csr(wstart, wlist, lidx);
+    const size_t gb = sizeof(int32_t) * (size_t)G;
+    hipError_t e = hipMemcpyAsync(q->m_owner, owner, gb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(q->m_wstart, wstart, sizeof(int32_t) * (size_t)(T + 1),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(q->m_wlist, wlist, gb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(q->m_lidx, lidx, gb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(q->ev_map, s);
+    q->map_pending = e == hipSuccess;
+    return from_hip(e);
+}
+
+// After the histogram of a batch: its counts and rejection flag on their
+// way to the host.
+int policy_fetch(cq_query *q, const Scratch &sc, hipStream_t s) {
+    const int64_t G = q->st.G;
+    hipError_t e = hipMemcpyAsync(q->h_counts, sc.k, sizeof(int32_t) * (size_t)G,
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(q->h_counts + G, sc.bad, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(q->ev_counts, s);
+    return from_hip(e);
+}
+
+// After the rest of the batch is enqueued: wait for its counts, run one
+// step of the technique, and send a changed mapping up for the next batch.
+int policy_step(cq_query *q, int32_t seq, hipStream_t s) {
+    if (hipEventSynchronize(q->ev_counts) != hipSuccess) return CQ_ERR_HIP;
+    q->bal.last_moves = 0;
+    if (q->h_counts[q->st.G] == seq) return CQ_OK;  // rejected batch: nothing happened
+    const int64_t moved = q->bal.step(q->policy, q->h_counts);
+    q->policy_total += moved;
+    return moved ? policy_upload(q, s) : CQ_OK;
 }
 
 // Telemetry buffers for sub-batches of up to n tuples.
@@ -236,6 +341,7 @@ int front(cq_query *q, const int32_t *keys, const int32_t *values, int64_t m, co
     if (!have_hist)
         rc = timed(q, CQ_KERNEL_HIST, s,
                    [&] { return launch_hist(keys, m, q->st.G, sc, seq, s); });
+    if (rc == CQ_OK && sc.owner) rc = policy_fetch(q, sc, s);
     if (rc == CQ_OK && !plan_fused(q->st.G))
         rc = timed(q, CQ_KERNEL_PLAN, s,
                    [&] { return launch_plan(q->st, sc, seq, q->mode, q->workers, s); });
@@ -255,6 +361,8 @@ int push(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n, hip
     if (rc != CQ_OK) return rc;
     q->cur = 0;
     const Scratch sc = set_of(q, 0);
+    if (sc.owner && q->map_pending && hipStreamWaitEvent(s, q->ev_map, 0) != hipSuccess)
+        return CQ_ERR_HIP;
     q->last_stream = s;
     q->pushed = true;
     q->last_n = n;
@@ -281,6 +389,7 @@ int push(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n, hip
             rc = timed(q, CQ_KERNEL_UPDATE, s, [&] {
                 return launch_update(q->st, sc, m, q->mode, q->workers, o, s);
             });
+        if (rc == CQ_OK && sc.owner) rc = policy_step(q, seq, s);
     }
     if (rc == CQ_OK && nsub > 1) {
         rc = timed(q, CQ_KERNEL_OTHER, s,
@@ -377,12 +486,47 @@ int cq_reserve(cq_query *q, int64_t max_batch) {
 
 int cq_set_partition(cq_query *q, int32_t mode, int32_t workers) {
     if (!q) return CQ_ERR_INVALID;
-    if (mode != CQ_PARTITION_BALANCED && mode != CQ_PARTITION_STATIC) return CQ_ERR_INVALID;
+    if (mode < CQ_PARTITION_BALANCED || mode > CQ_PARTITION_SHIFTLOCAL) return CQ_ERR_INVALID;
     if (workers < 0) return CQ_ERR_INVALID;
     const int32_t w = workers ? workers : 1024;
-    if (mode == CQ_PARTITION_STATIC && !static_ok(q->st.G, w)) return CQ_ERR_INVALID;
-    q->mode = mode == CQ_PARTITION_STATIC ? MODE_STATIC : MODE_BALANCED;
+    if (mode != CQ_PARTITION_BALANCED && !static_ok(q->st.G, w)) return CQ_ERR_INVALID;
+    const bool technique = mode >= CQ_PARTITION_GETFIRST;
+    if (technique) {
+        if (q->st.G > PASS_LOCAL_G) return CQ_ERR_INVALID;
+        DeviceGuard guard(q->device);
+        int rc = policy_buffers(q);
+        if (rc != CQ_OK) return rc;
+        // the device mapping may still be read by pushes in flight
+        if (hipDeviceSynchronize() != hipSuccess) return CQ_ERR_HIP;
+        q->bal.reset(w, q->st.G);
+        q->bal.max_keys = STATIC_KEYS_MAX;
+        q->bal.last_moves = q->bal.last_max = q->bal.last_min = 0;
+        q->policy_total = 0;
+        rc = policy_upload(q, nullptr);
+        if (rc == CQ_OK && hipEventSynchronize(q->ev_map) != hipSuccess) rc = CQ_ERR_HIP;
+        q->map_pending = false;
+        if (rc != CQ_OK) return rc;
+    }
+    q->policy = technique ? mode : 0;
+    q->mode = mode == CQ_PARTITION_BALANCED ? MODE_BALANCED : MODE_STATIC;
     q->workers = w;
+    return CQ_OK;
+}
+
+int cq_set_policy_params(cq_query *q, int64_t threshold, double pot) {
+    if (!q || threshold < 0 || !(pot > 0.0 && pot <= 1.0)) return CQ_ERR_INVALID;
+    q->bal.threshold = threshold;
+    q->bal.pot = pot;
+    return CQ_OK;
+}
+
+int cq_policy_stats(cq_query *q, int64_t *out) {
+    if (!q || !out) return CQ_ERR_INVALID;
+    const bool on = q->policy != 0;
+    out[0] = on ? q->bal.last_moves : 0;
+    out[1] = on ? q->bal.last_max : 0;
+    out[2] = on ? q->bal.last_min : 0;
+    out[3] = on ? q->policy_total : 0;
     return CQ_OK;
 }
 
@@ -421,6 +565,9 @@ int cq_push_batches(cq_query *q, int32_t count, const int32_t *const *keys,
     if (rc == CQ_OK) rc = prepare_telemetry(q, SUB);
     if (rc != CQ_OK) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const bool mapped = q->mode == MODE_STATIC && q->policy;
+    if (mapped && q->map_pending && hipStreamWaitEvent(s, q->ev_map, 0) != hipSuccess)
+        return CQ_ERR_HIP;
     const int32_t seq0 = q->seq + 1;
     q->seq += count;
     // Batch i uses buffer set i mod 2.  Batch i+1's histogram is computed
@@ -443,7 +590,8 @@ int cq_push_batches(cq_query *q, int32_t count, const int32_t *const *keys,
             continue;
         }
         rc = front(q, keys[i], values[i], n[i], sc, seq, s, have_hist);
-        const bool fuse = i + 1 < count && n[i + 1] > 0 && can_fuse_hist(q->st.G, q->mode);
+        const bool fuse =
+            i + 1 < count && n[i + 1] > 0 && !mapped && can_fuse_hist(q->st.G, q->mode);
         if (rc == CQ_OK)
             rc = timed(q, CQ_KERNEL_UPDATE, s, [&] {
                 return fuse ? launch_update(q->st, sc, n[i], q->mode, q->workers, out, s,
@@ -451,6 +599,7 @@ int cq_push_batches(cq_query *q, int32_t count, const int32_t *const *keys,
                                             seq + 1)
                             : launch_update(q->st, sc, n[i], q->mode, q->workers, out, s);
             });
+        if (rc == CQ_OK && mapped) rc = policy_step(q, seq, s);
         have_hist = fuse;
     }
     q->last_stream = s;

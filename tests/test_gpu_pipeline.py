@@ -1,6 +1,7 @@
 """GPU parity of the pipelined entry point (cq_push_batches): several
-consecutive batches per call, overlapped inside the library on two streams
-with two sets of batch-local buffers.  Every batch's results must equal the
+consecutive batches per call, on the caller's stream, alternating between two
+sets of batch-local buffers so that each batch's histogram rides in the
+previous batch's update launch.  Every batch's results must equal the
 CPU oracle's bit for bit, exactly as with one call per batch."""
 import numpy as np
 import pytest
