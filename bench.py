@@ -113,6 +113,55 @@ def run_mode(torch, cq, batches, cfg, mode, warmup, steps, kind="clean"):
     return res
 
 
+def techniques(torch, cq, s_list, warmup, steps):
+    """The Section 5 comparison: no balancing (the static ranges), the six
+    Section 4 techniques on the same 1024 static workers (host step after
+    every batch, one batch of delay, threshold 1000, pot 0.5), and the
+    device-side balanced partition, on DS2-like (hot keys are the smallest
+    ids) and DS3-like (permuted) Zipf streams of 10,000 groups, W=1000,
+    1,048,576-tuple batches."""
+    from workloads import DeviceStream, skew
+    dev = torch.device("cuda", 0)
+    modes = [(cq.PARTITION_STATIC, "no balance (static)")]
+    modes += [(m, nm) for nm, m in cq.POLICIES.items()]
+    modes += [(cq.PARTITION_BALANCED, "balanced (device)")]
+    rows = []
+    for s in s_list:
+        for permuted, ds in ((False, "DS2-like"), (True, "DS3-like")):
+            cfg = skew(s, permuted=permuted, batches=warmup + steps)
+            stream = DeviceStream(cfg, dev)
+            batches = [stream.batch(b) for b in range(warmup + steps)]
+            torch.cuda.synchronize()
+            base = None
+            for mode, name in modes:
+                q = cq.Query(cfg.groups, cfg.window, partition=mode)
+                for b in range(warmup):
+                    q.push(*batches[b])
+                torch.cuda.synchronize()
+                moves0 = q.policy_stats()[3]
+                t0 = time.perf_counter()
+                for b in range(warmup, warmup + steps):
+                    q.push(*batches[b])
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                st = q.policy_stats()
+                q.close()
+                ms = 1e3 * wall / steps
+                base = ms if base is None else base
+                row = {"dataset": f"{ds} s={s:g}", "partition": name,
+                       "ms_per_batch": round(ms, 4),
+                       "tuples_per_s": steps * cfg.batch / wall,
+                       "time_vs_no_balance": round(ms / base, 4)}
+                if mode >= cq.PARTITION_GETFIRST:
+                    row["moves_timed"] = st[3] - moves0
+                    row["last_batch_tpt_max_min"] = [st[1], st[2]]
+                rows.append(row)
+                print(json.dumps({"progress": row}), file=sys.stderr, flush=True)
+            del batches, stream
+            torch.cuda.empty_cache()
+    return rows
+
+
 def imbalance(torch, cq, batches, cfg, mode, warmup=3):
     """Per-CU busy time of the per-group phase on one batch (after `warmup`
     batches): the union of the device-clock intervals of the workgroups that
@@ -249,6 +298,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--modes", default="balanced,static",
                     help="partitions to run (the headline needs balanced)")
+    ap.add_argument("--techniques", default="1.0,1.5",
+                    help="Zipf s values of the Section 4 technique comparison ('' skips it)")
+    ap.add_argument("--tech-steps", type=int, default=40)
     ap.add_argument("--calibrate", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -317,6 +369,7 @@ def main():
         print("bench.py: the sweep must include s=1.5", file=sys.stderr)
         sys.exit(2)
     row, r, timed_bytes, cfg, batches = headline
+    headline = None
     kern = r["kernels"]
     dom = max(kern, key=lambda k: kern[k][0])
     dom_ms, dom_launches = kern[dom]
@@ -327,9 +380,15 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom, "kernel_avg_us": round(1e3 * dom_ms / dom_launches, 2),
                 "kernel_times_ms": {k: round(v[0], 3) for k, v in kern.items()}}
+    host = None if args.no_cpu else [(k.cpu().numpy(), v.cpu().numpy()) for k, v in batches]
+    del batches
+    torch.cuda.empty_cache()
+    tech = None
+    if args.techniques:
+        tech = techniques(torch, cq, [float(x) for x in args.techniques.split(",")],
+                          min(args.warmup, 5), args.tech_steps)
     cpu = cpu_mt = None
     if not args.no_cpu:
-        host = [(k.cpu().numpy(), v.cpu().numpy()) for k, v in batches]
         done, t = cpu_baseline(host, cfg, args.cpu_budget)
         cpu = {"value": done * cfg.batch / t, "unit": "tuples/s", "cores": 1, "kind": "oracle",
                "sample": f"{done} batches of the s=1.5 stream (the {len(host)} headline batches "
@@ -365,6 +424,7 @@ def main():
         "cpu_baseline": cpu,
         "cpu_baseline_all_threads": cpu_mt,
         "sweep": rows,
+        "techniques": tech,
     }
     print(json.dumps(out), flush=True)
 
