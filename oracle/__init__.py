@@ -48,6 +48,8 @@ def _load(path: str) -> ctypes.CDLL:
     lib.oracle_push.restype = ctypes.c_int
     lib.oracle_push_mt.argtypes = [P, P, P, i64, P, P, P, P, P, ctypes.c_int]
     lib.oracle_push_mt.restype = ctypes.c_int
+    lib.oracle_push_tuples.argtypes = [P, P, P, i64, P, P, P]
+    lib.oracle_push_tuples.restype = ctypes.c_int
     lib.oracle_window.argtypes = [P, i64, P]
     lib.oracle_window.restype = ctypes.c_int32
     return lib
@@ -123,6 +125,23 @@ class RingOracle:
             raise OracleError(rc)
         m = nt.value
         return ids[:m], sums[:m], counts[:m], avgs[:m]
+
+    def push_tuples(self, keys: np.ndarray, values: np.ndarray):
+        """Apply a batch tuple by tuple; returns (sums, counts, avgs), one
+        entry per tuple: its group's window right after that tuple entered
+        (Section 5.1's per-tuple, from-scratch aggregate)."""
+        keys = np.ascontiguousarray(keys, dtype=np.int32)
+        values = np.ascontiguousarray(values, dtype=np.int32)
+        n = len(keys)
+        assert len(values) == n
+        sums = np.empty(max(n, 1), np.int64)
+        counts = np.empty(max(n, 1), np.int32)
+        avgs = np.empty(max(n, 1), np.float64)
+        rc = self.lib.oracle_push_tuples(self._h, _ptr(keys), _ptr(values), n, _ptr(sums),
+                                         _ptr(counts), _ptr(avgs))
+        if rc != 0:
+            raise OracleError(rc)
+        return sums[:n], counts[:n], avgs[:n]
 
     def window_of(self, group: int) -> np.ndarray:
         out = np.empty(self.window, np.int32)

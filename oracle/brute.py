@@ -33,3 +33,18 @@ class BruteForce:
             c = len(win)
             out.append((g, s, c, s / c))
         return out
+
+    def push_tuples(self, keys, values):
+        """Per tuple: its group's last W values right after it arrived,
+        summed afresh (Section 5.1 rescans the window after every insert)."""
+        keys = [int(k) for k in keys]
+        values = [int(v) for v in values]
+        if any(k < 0 or k >= self.groups for k in keys):
+            raise ValueError("key out of range")
+        out = []
+        for k, v in zip(keys, values):
+            self.history[k].append(v)
+            win = self.history[k][-self.window:]
+            s = sum(win)
+            out.append((s, len(win), s / len(win)))
+        return out

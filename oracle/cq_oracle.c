@@ -133,6 +133,32 @@ int oracle_push(oracle_query *q, const int32_t *keys, const int32_t *values,
     return 0;
 }
 
+int oracle_push_tuples(oracle_query *q, const int32_t *keys, const int32_t *values,
+                       int64_t n, int64_t *sums, int32_t *counts, double *avgs)
+{
+    if (!q || n < 0 || (n > 0 && (!keys || !values)))
+        return -1;
+    if (!keys_valid(q, keys, n))
+        return -3;
+    /* Section 5.1: after every tuple enters its group's window, the whole
+     * window is scanned and its sum computed from scratch */
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t g = keys[i];
+        window_insert(q, g, values[i]);
+        int64_t ws = window_sum(q, g);
+        int32_t wc = q->filled[g];
+        if (sums)
+            sums[i] = ws;
+        if (counts)
+            counts[i] = wc;
+        if (avgs)
+            avgs[i] = (double)ws / (double)wc;
+    }
+    /* the batch is over: clear the touched marks */
+    emit_range(q, 0, q->groups, NULL, NULL, NULL, NULL);
+    return 0;
+}
+
 typedef struct {
     oracle_query *q;
     const int32_t *keys, *values;

@@ -55,6 +55,14 @@ int oracle_push_mt(oracle_query *q, const int32_t *keys, const int32_t *values,
                    int64_t n, int32_t *ids, int64_t *sums, int32_t *counts,
                    double *avgs, int64_t *n_touched, int threads);
 
+/* The per-tuple form of Section 5.1: apply the batch tuple by tuple and,
+ * after each insertion, write that group's window SUM (scanned from
+ * scratch), COUNT and AVG at the tuple's own index (arrays of n entries,
+ * any may be NULL).  The state afterwards is the same as oracle_push's.
+ * Returns 0, or -3 if a key is out of range (nothing changed). */
+int oracle_push_tuples(oracle_query *q, const int32_t *keys, const int32_t *values,
+                       int64_t n, int64_t *sums, int32_t *counts, double *avgs);
+
 /* Copy of one group's window in age order (oldest first); returns its
  * length (<= W).  For white-box tests of the ring. */
 int32_t oracle_window(const oracle_query *q, int64_t group, int32_t *out);

@@ -270,7 +270,142 @@ def pin_empty_batch(make):
     _assert_equal_results(_as_tuples(a.push(k, v)), _as_tuples(b.push(k, v)), "after empty")
 
 
+# ---- per-tuple results (the Section 5.1 aggregate after every insertion) --
+
+def _tuples(res):
+    s, c, a = res
+    return [(int(x), int(y), float(z)) for x, y, z in zip(s, c, a)]
+
+
+def pin_tuples_bruteforce(make, cases=30):
+    """Per-tuple SUM/COUNT/AVG == the brute-force history slice after each
+    tuple, over windows that wrap within and across batches."""
+    for case in range(cases):
+        rng = _rng(300 + case)
+        G = int(rng.integers(1, 9))
+        W = int(rng.choice([1, 2, 3, 5, 8, 13]))
+        ora, bf = make(G, W), BruteForce(G, W)
+        for b in range(int(rng.integers(1, 6))):
+            n = int(rng.integers(0, 60))
+            keys = rng.integers(0, G, n).astype(np.int32)
+            vals = rng.integers(-50, 50, n).astype(np.int32)
+            got = _tuples(ora.push_tuples(keys, vals))
+            want = bf.push_tuples(keys, vals)
+            assert len(got) == len(want)
+            for x, y in zip(got, want):
+                assert x[:2] == y[:2] and _same_float(x[2], y[2]), (case, b, x, y)
+
+
+def pin_tuples_last_is_batch_result(make):
+    """A group's per-tuple result at its last tuple of the batch is the
+    batch's result for that group (per-batch and per-tuple forms agree)."""
+    rng = _rng(320)
+    for G, W in [(7, 4), (50, 30), (3, 200)]:
+        a, b = make(G, W), make(G, W)
+        for _ in range(5):
+            n = int(rng.integers(1, 400))
+            keys = rng.integers(0, G, n).astype(np.int32)
+            vals = rng.integers(I32_MIN, I32_MAX, n, endpoint=True).astype(np.int32)
+            per = _tuples(a.push_tuples(keys, vals))
+            batch = _as_tuples(b.push(keys, vals))
+            last = {}
+            for i, k in enumerate(keys.tolist()):
+                last[k] = i
+            assert sorted(last) == [t[0] for t in batch]
+            for g, s, c, avg in batch:
+                x = per[last[g]]
+                assert x[:2] == (s, c) and _same_float(x[2], avg), (G, W, g, x)
+
+
+def pin_tuples_w1(make):
+    """W = 1: every tuple's window is the tuple itself."""
+    rng = _rng(321)
+    ora = make(9, 1)
+    for _ in range(4):
+        keys = rng.integers(0, 9, 300).astype(np.int32)
+        vals = rng.integers(I32_MIN, I32_MAX, 300, endpoint=True).astype(np.int32)
+        s, c, a = ora.push_tuples(keys, vals)
+        assert np.array_equal(s, vals.astype(np.int64)) and np.all(c == 1)
+        assert np.array_equal(a, vals.astype(np.float64))
+
+
+def pin_tuples_running_sum(make):
+    """With W above every group's tuple count, a tuple's SUM is its group's
+    running sum so far and COUNT its running count (numpy cumsum per key)."""
+    rng = _rng(322)
+    G, W = 6, 1000
+    ora = make(G, W)
+    hist_s = np.zeros(G, np.int64)
+    hist_c = np.zeros(G, np.int64)
+    for _ in range(3):
+        n = 250
+        keys = rng.integers(0, G, n).astype(np.int32)
+        vals = rng.integers(I32_MIN, I32_MAX, n, endpoint=True).astype(np.int32)
+        s, c, _ = ora.push_tuples(keys, vals)
+        for g in range(G):
+            m = keys == g
+            want = hist_s[g] + np.cumsum(vals[m].astype(np.int64))
+            assert np.array_equal(s[m], want)
+            assert np.array_equal(c[m], hist_c[g] + np.arange(1, m.sum() + 1))
+            if m.any():
+                hist_s[g] = want[-1]
+                hist_c[g] += m.sum()
+
+
+def pin_tuples_round_robin(make):
+    """Round-robin keys (DS1), value = arrival number t: the tuple t of group
+    g = t mod G ends a window of m = min(W, t // G + 1) values t, t-G, ...,
+    whose SUM is m*t - G*m*(m-1)/2."""
+    for G, W, n, nb in [(5, 3, 97, 4), (16, 40, 1000, 3)]:
+        ora = make(G, W)
+        T = 0
+        for _ in range(nb):
+            t = np.arange(T, T + n, dtype=np.int64)
+            s, c, _ = ora.push_tuples((t % G).astype(np.int32), t.astype(np.int32))
+            m = np.minimum(W, t // G + 1)
+            assert np.array_equal(c, m)
+            assert np.array_equal(s, m * t - G * m * (m - 1) // 2)
+            T += n
+
+
+def pin_tuples_batch_split(make):
+    """Per-tuple results do not depend on where the stream is cut into
+    batches: B1||B2 gives the concatenation of B1's and then B2's."""
+    rng = _rng(323)
+    G, W = 11, 6
+    a, b = make(G, W), make(G, W)
+    keys = rng.integers(0, G, 500).astype(np.int32)
+    vals = rng.integers(-1000, 1000, 500).astype(np.int32)
+    whole = _tuples(a.push_tuples(keys, vals))
+    cut = int(rng.integers(1, 499))
+    parts = _tuples(b.push_tuples(keys[:cut], vals[:cut])) + \
+        _tuples(b.push_tuples(keys[cut:], vals[cut:]))
+    assert whole == parts
+
+
+def pin_tuples_bad_key(make):
+    """A bad key rejects the batch: no state change (later results equal
+    those of a twin that never saw it)."""
+    rng = _rng(324)
+    a, b = make(5, 4), make(5, 4)
+    keys = rng.integers(0, 5, 40).astype(np.int32)
+    vals = rng.integers(0, 9, 40).astype(np.int32)
+    a.push_tuples(keys, vals)
+    b.push_tuples(keys, vals)
+    bad = keys.copy()
+    bad[7] = 5
+    try:
+        a.push_tuples(bad, vals)
+    except Exception as e:  # noqa: BLE001 - the oracle's own error type
+        assert getattr(e, "code", None) == -3
+    else:
+        raise AssertionError("bad key accepted")
+    assert _tuples(a.push_tuples(keys, vals)) == _tuples(b.push_tuples(keys, vals))
+
+
 ALL_PINS = [pin_bruteforce, pin_count_closed_form, pin_sum_before_eviction,
             pin_w1_last_writer, pin_round_robin, pin_reinterleave, pin_order_matters,
             pin_batch_split, pin_avg_is_rounded_quotient, pin_bad_key_rejects,
-            pin_empty_batch]
+            pin_empty_batch, pin_tuples_bruteforce, pin_tuples_last_is_batch_result,
+            pin_tuples_w1, pin_tuples_running_sum, pin_tuples_round_robin,
+            pin_tuples_batch_split, pin_tuples_bad_key]

@@ -35,6 +35,13 @@ MUTANTS = {
     "sum_int32": ("int64_t s = 0;\n    for (int32_t j", "int32_t s = 0;\n    for (int32_t j"),
     # every group emitted, touched or not
     "emit_untouched": ("if (!q->touched[g])\n            continue;\n", ""),
+    # per-tuple form: the window read before the tuple enters it
+    "tuple_sum_before_insert": ("window_insert(q, g, values[i]);\n        int64_t ws = window_sum(q, g);",
+                                "int64_t ws = window_sum(q, g);\n        window_insert(q, g, values[i]);"),
+    # per-tuple form: COUNT reported as the window size
+    "tuple_count_is_w": ("int32_t wc = q->filled[g];", "int32_t wc = q->W;"),
+    # per-tuple form: AVG by integer division
+    "tuple_avg_integer_div": ("avgs[i] = (double)ws / (double)wc;", "avgs[i] = (double)(ws / wc);"),
 }
 
 
