@@ -202,6 +202,35 @@ int cq_push_batch_results(cq_query *q, const int32_t *keys, const int32_t *value
                           int32_t *ids, int64_t *sums, int32_t *counts, double *avgs,
                           int64_t *n_touched, void *stream);
 
+/* Limits of cq_push_batch_tuples. */
+#define CQ_TUPLE_MAX_WINDOW 1024
+#define CQ_TUPLE_MAX_PASSES 64
+
+/*
+ * cq_push_batch_tuples -- apply one batch exactly as cq_push_batch does and,
+ * for every tuple, report its group's aggregate right after that tuple
+ * entered the window: the paper recomputes the aggregate after each
+ * insertion by scanning the whole window (Section 5.1), and its last
+ * experiment scans it ten times (Section 5.2, further experiments).
+ *   sums[i], counts[i], avgs[i] : device arrays of n entries (any may be
+ *       NULL), in arrival order: SUM (int64) of the window of keys[i]'s
+ *       group after tuple i, COUNT = min(W, values seen), AVG =
+ *       (double)SUM / (double)COUNT;
+ *   passes : 0 = the sums follow incrementally (new value minus evicted
+ *       value); 1 .. CQ_TUPLE_MAX_PASSES = every tuple's window is summed
+ *       from scratch that many times (the paper's 1 and 10).  The results
+ *       are the same integers either way.
+ * Needs the balanced partition, at most 16384 groups and a window of at
+ * most CQ_TUPLE_MAX_WINDOW.  The first call allocates 4 MiB + 4 bytes per
+ * group of device memory for the query.  Stream-ordered like cq_push_batch;
+ * a rejected batch (bad key) writes no per-tuple entry and cq_status
+ * reports it.  cq_results afterwards gives the batch's per-group results.
+ * Returns CQ_OK, CQ_ERR_INVALID, CQ_ERR_OOM or CQ_ERR_HIP.
+ */
+int cq_push_batch_tuples(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n,
+                         int32_t passes, int64_t *sums, int32_t *counts, double *avgs,
+                         void *stream);
+
 /*
  * cq_push_batches -- `count` consecutive batches of one stream in one call:
  * the same state and the same per-batch results as cq_push_batch_results
@@ -259,7 +288,8 @@ const char *cq_strerror(int code);
 #define CQ_KERNEL_EMIT      3 /* separate result emission             */
 #define CQ_KERNEL_OTHER     4 /* whole-batch checks and collection    */
 #define CQ_KERNEL_PLAN      5 /* scans over groups + balancer plan    */
-#define CQ_KERNEL_KINDS     6
+#define CQ_KERNEL_TUPLES    6 /* per-tuple results (cq_push_batch_tuples) */
+#define CQ_KERNEL_KINDS     7
 
 /*
  * cq_set_telemetry -- turn measurement on (flags) or off (0).  Imbalance

@@ -25,7 +25,9 @@ POLICIES = {"getFirst": PARTITION_GETFIRST, "checkAll": PARTITION_CHECKALL,
             "shift": PARTITION_SHIFT, "shiftLocal": PARTITION_SHIFTLOCAL}
 STATIC_KEYS_MAX = 2048
 TELEMETRY_KERNEL_TIMES, TELEMETRY_WORKERS, TELEMETRY_PHASES = 1, 2, 4
-KERNEL_KINDS = ("hist", "pass", "update", "emit", "other", "plan")
+KERNEL_KINDS = ("hist", "pass", "update", "emit", "other", "plan", "tuples")
+TUPLE_MAX_WINDOW = 1024
+TUPLE_MAX_PASSES = 64
 MAX_BATCH = 1 << 30
 MAX_WINDOW = (1 << 22) - 1
 PIPE_MAX = 1 << 20
@@ -67,6 +69,7 @@ def lib() -> ctypes.CDLL:
             "cq_batch_plan": ([P, pi64], ctypes.c_int),
             "cq_phase_trace": ([P, i32, pi64, i64, pi64], ctypes.c_int),
             "cq_push_batches": ([P, i32, P, P, P, P, P, P, P, P, P], ctypes.c_int),
+            "cq_push_batch_tuples": ([P, P, P, i64, i32, P, P, P, P], ctypes.c_int),
             "cq_set_policy_params": ([P, i64, ctypes.c_double], ctypes.c_int),
             "cq_policy_stats": ([P, pi64], ctypes.c_int),
             "cq_policy_apply": ([i32, i32, i64, P, P, P, i64, ctypes.c_double, i32, pi64],
@@ -204,6 +207,35 @@ class Query:
             _dptr(ids), _dptr(sums), _dptr(counts), _dptr(avgs), _dptr(n_touched),
             _stream_handle(stream)), "cq_push_batch_results")
         self.last_n = int(n)
+
+    def push_tuples_into(self, keys, values, sums, counts, avgs, passes=0, stream=None):
+        """Enqueue one batch and, per tuple, its group's window aggregate
+        right after it entered (cq_push_batch_tuples): SUM / COUNT / AVG
+        into caller device tensors of len(keys) entries (any may be None).
+        passes = 0: incremental sums; >= 1: every window summed from
+        scratch that many times."""
+        n = keys.numel()
+        if values.numel() != n:
+            raise ValueError("keys and values differ in length")
+        for t in (sums, counts, avgs):
+            if t is not None and t.numel() < n:
+                raise ValueError("per-tuple outputs need one entry per tuple")
+        _check(lib().cq_push_batch_tuples(
+            self._h, _dptr(keys) if n else None, _dptr(values) if n else None, int(n),
+            int(passes), _dptr(sums), _dptr(counts), _dptr(avgs), _stream_handle(stream)),
+            "cq_push_batch_tuples")
+        self.last_n = int(n)
+
+    def push_tuples(self, keys, values, passes=0, stream=None):
+        """push_tuples_into with fresh device tensors; returns them."""
+        import torch
+        n = keys.numel()
+        dev = keys.device
+        sums = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+        counts = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        avgs = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+        self.push_tuples_into(keys, values, sums, counts, avgs, passes, stream)
+        return sums[:n], counts[:n], avgs[:n]
 
     def push_batches_into(self, batches, outputs, stream=None):
         """Enqueue several consecutive batches in one call, overlapped inside

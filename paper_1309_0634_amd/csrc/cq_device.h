@@ -1,0 +1,152 @@
+// Device helpers shared by the HIP sources: wave and block scans, run
+// tables of the reordered tiles, phase clocks.  Internal; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cq_internal.h"
+
+namespace cq {
+
+// ------------------------------------------------------------ utilities --
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    return (lane_id() == 0) ? 0ull : (~0ull >> (64 - lane_id()));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Inclusive prefix sum over the 64 lanes of a wave with DPP row shifts and
+// row broadcasts (GFX9 cross-lane data movement), without LDS traffic: four
+// shifted adds give prefixes inside each row of 16 lanes, two broadcasts
+// carry row totals forward.  Lanes with no source add 0.
+__device__ __forceinline__ int wave_incl_add(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
+
+__device__ __forceinline__ int wave_total(int incl) { return __builtin_amdgcn_readlane(incl, 63); }
+
+// Inclusive running maximum over the 64 lanes of non-negative values (the
+// same DPP pattern as wave_incl_add; lanes with no source take 0).
+__device__ __forceinline__ int wave_incl_max(int x) {
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false));
+    return x;
+}
+
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Exclusive block scan of F ints per thread; `lds` holds F * waves ints.
+// Returns the block totals in `total`.  Barriers inside: call uniformly.
+template <int F>
+__device__ void block_excl_scan(int (&v)[F], int (&total)[F], int *lds) {
+    const int lane = lane_id(), wid = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    int incl[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) incl[f] = wave_incl_add(v[f]);
+    if (lane == 63) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) lds[wid * F + f] = incl[f];
+    }
+    __syncthreads();
+    if (wid == 0) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            int x = lane < nw ? lds[lane * F + f] : 0;
+            int s = wave_incl_add(x);
+            if (lane < nw) lds[lane * F + f] = s;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+        int before = wid > 0 ? lds[(wid - 1) * F + f] : 0;
+        total[f] = lds[(nw - 1) * F + f];
+        v[f] = before + incl[f] - v[f];
+    }
+    __syncthreads();
+}
+
+// Exclusive scan of a[0, m) in LDS (in place), a[m] = total.  Each thread
+// scans a contiguous piece.  Barriers inside.
+__device__ void block_excl_scan_array(int32_t *a, int m, int *lds) {
+    const int per = (m + blockDim.x - 1) / blockDim.x;
+    const int b0 = min(m, (int)threadIdx.x * per), b1 = min(m, b0 + per);
+    int f[1] = {0}, t[1];
+    for (int i = b0; i < b1; ++i) f[0] += a[i];
+    block_excl_scan<1>(f, t, lds);
+    for (int i = b0; i < b1; ++i) {
+        const int x = a[i];
+        a[i] = f[0];
+        f[0] += x;
+    }
+    if (threadIdx.x == 0) a[m] = t[0];
+    __syncthreads();
+}
+
+__device__ long long block_sum_ll(long long v, long long *lds) {
+    const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_sum_ll(v);
+    if (lane_id() == 0) lds[wid] = v;
+    __syncthreads();
+    long long t = 0;
+    for (int w = 0; w < nw; ++w) t += lds[w];
+    __syncthreads();
+    return t;
+}
+
+// Largest r in [0, m) with pre[r] <= p (pre ascending, pre[0] = 0 <= p).
+__device__ __forceinline__ int upper_run(const int32_t *pre, int m, int p) {
+    int lo = 0, hi = m - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Records the device clock for phase `slot` of this workgroup (thread 0).
+__device__ __forceinline__ void phase_mark(const Scratch &sc, int kind, int slot) {
+    if (sc.phase && threadIdx.x == 0 && blockIdx.x < PHASE_BLOCKS)
+        sc.phase[((int64_t)kind * PHASE_BLOCKS + blockIdx.x) * PHASE_SLOTS + slot] =
+            (int64_t)wall_clock64();
+}
+
+// The runs of bucket b (one per tile, in tile order = arrival order): rs[t]
+// = first staged slot, rp[t] = tuples of the bucket in tiles before t,
+// rp[tiles] = bucket size.  The caller's per-group prefetch (`extra`) is
+// issued before the first barrier so its loads overlap the run loads.
+// Barriers inside.
+template <typename F>
+__device__ int bucket_runs(const Scratch &sc, int b, int NB, int tiles, int32_t *rs,
+                           int32_t *rp, int *red, F &&extra) {
+    for (int t = threadIdx.x; t < tiles; t += blockDim.x) {
+        const int32_t *row = sc.rowstart + (int64_t)t * (NB + 1);
+        const int32_t s = row[b], e = row[b + 1];
+        rs[t] = t * PASS_TILE + s;
+        rp[t] = e - s;
+    }
+    extra();
+    __syncthreads();
+    block_excl_scan_array(rp, tiles, red);
+    return rp[tiles];
+}
+
+}  // namespace cq

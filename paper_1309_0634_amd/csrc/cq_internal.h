@@ -127,6 +127,9 @@ struct Scratch {
     const int32_t *wstart;  // workers + 1: each worker's first list entry
     const int32_t *wlist;   // G: groups in worker-list order
     const int32_t *lidx;    // G: position of each group in its worker's list
+    // per-tuple results only (null otherwise)
+    int32_t *sidx;      // SUB: arrival index of each staged tuple
+    int32_t *pcnt;      // G: window count of each touched group before the sub-batch
     int64_t *trace;     // optional per-workgroup records (6 int64 each)
     int64_t *phase;     // optional phase clocks [kind][block][PHASE_SLOTS]
 };
@@ -152,6 +155,22 @@ struct Out {
 constexpr int32_t FAULT_LIGHT_SIZE = 1;
 constexpr int32_t FAULT_BUCKETS = 2;
 constexpr int32_t FAULT_STATIC_KEYS = 4;
+constexpr int32_t FAULT_TUPLE_RUNS = 8;   // a bucket's runs disagree with its plan
+constexpr int32_t FAULT_PASSES = 16;      // repeated window scans disagreed
+
+// Per-tuple results (the paper's aggregate after every insertion): one
+// entry per tuple, in arrival order; any pointer may be null.  passes = 0:
+// the window sum follows incrementally; passes >= 1: every tuple's window
+// is summed from scratch that many times.
+struct PtOut {
+    int64_t *sums;
+    int32_t *counts;
+    double *avgs;
+    int32_t passes;
+};
+constexpr int PT_WMAX = CQ_TUPLE_MAX_WINDOW;  // largest window of the per-tuple variant
+constexpr int PT_CH = 1024;                   // ranks of a heavy group per work item
+static_assert(PT_CH >= PT_WMAX, "only a heavy group's first item reaches back before rank W");
 
 enum Mode { MODE_BALANCED = 0, MODE_STATIC = 1 };
 
@@ -179,6 +198,9 @@ bool can_fuse_hist(int64_t G, int mode);
 hipError_t launch_update(State st, Scratch sc, int64_t n, int mode, int32_t workers, Out out,
                          hipStream_t s, const int32_t *next_keys = nullptr, int64_t next_n = 0,
                          Scratch next_sc = Scratch{}, int32_t next_seq = 0);
+// Per-tuple results of the planned and reordered sub-batch (n tuples);
+// reads the window store before the update launch changes it.
+hipError_t launch_tuples(State st, Scratch sc, int64_t n, PtOut out, hipStream_t s);
 hipError_t launch_collect_touched(int64_t G, int32_t seq, Scratch sc, hipStream_t s);
 hipError_t launch_emit(State st, Scratch sc, int64_t cap, Out out, hipStream_t s);
 hipError_t launch_reset_totals(Scratch sc, hipStream_t s);

@@ -52,6 +52,9 @@ struct cq_query {
     hipEvent_t ev_counts = nullptr, ev_map = nullptr;
     bool map_pending = false;     // an upload from h_map may still be running
     int64_t policy_total = 0;     // groups moved since the technique was selected
+    // per-tuple results: arrival index of each staged tuple, count before
+    // the sub-batch (allocated by the first per-tuple push)
+    int32_t *pt_sidx = nullptr, *pt_pcnt = nullptr;
 };
 
 namespace {
@@ -170,6 +173,8 @@ void free_all(cq_query *q) {
     if (q->ev_counts) (void)hipEventDestroy(q->ev_counts);
     if (q->ev_map) (void)hipEventDestroy(q->ev_map);
     q->ev_counts = q->ev_map = nullptr;
+    dfree(q->pt_sidx);
+    dfree(q->pt_pcnt);
 }
 
 int ensure_trace(cq_query *q, int64_t records) {
@@ -354,13 +359,17 @@ int front(cq_query *q, const int32_t *keys, const int32_t *values, int64_t m, co
 
 // The whole per-batch sequence; `out` non-null means emit into it.
 int push(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n, hipStream_t s,
-         const Out *out) {
+         const Out *out, const PtOut *pt = nullptr) {
     if (q->mode == MODE_STATIC && !static_ok(q->st.G, q->workers)) return CQ_ERR_INVALID;
     const int64_t nsub = (n + SUB - 1) / SUB;
     int rc = prepare_telemetry(q, n);
     if (rc != CQ_OK) return rc;
     q->cur = 0;
-    const Scratch sc = set_of(q, 0);
+    Scratch sc = set_of(q, 0);
+    if (pt) {
+        sc.sidx = q->pt_sidx;
+        sc.pcnt = q->pt_pcnt;
+    }
     if (sc.owner && q->map_pending && hipStreamWaitEvent(s, q->ev_map, 0) != hipSuccess)
         return CQ_ERR_HIP;
     q->last_stream = s;
@@ -385,6 +394,13 @@ int push(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n, hip
         const int64_t m = std::min<int64_t>(SUB, n - off);
         const Out o = (out && nsub == 1) ? *out : none;
         rc = front(q, keys + off, values + off, m, sc, seq, s);
+        if (rc == CQ_OK && pt) {
+            PtOut po = *pt;  // this sub-batch's tuples
+            if (po.sums) po.sums += off;
+            if (po.counts) po.counts += off;
+            if (po.avgs) po.avgs += off;
+            rc = timed(q, CQ_KERNEL_TUPLES, s, [&] { return launch_tuples(q->st, sc, m, po, s); });
+        }
         if (rc == CQ_OK)
             rc = timed(q, CQ_KERNEL_UPDATE, s, [&] {
                 return launch_update(q->st, sc, m, q->mode, q->workers, o, s);
@@ -546,6 +562,28 @@ int cq_push_batch_results(cq_query *q, const int32_t *keys, const int32_t *value
     DeviceGuard guard(q->device);
     const Out out = {ids, sums, counts, avgs, n_touched};
     return push(q, keys, values, n, reinterpret_cast<hipStream_t>(stream), &out);
+}
+
+int cq_push_batch_tuples(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n,
+                         int32_t passes, int64_t *sums, int32_t *counts, double *avgs,
+                         void *stream) {
+    if (!q || n < 0 || n > CQ_MAX_BATCH || passes < 0 || passes > CQ_TUPLE_MAX_PASSES)
+        return CQ_ERR_INVALID;
+    if (n > 0 && (!keys || !values)) return CQ_ERR_INVALID;
+    if (q->mode != MODE_BALANCED || q->st.G > PASS_LOCAL_G || q->st.W > CQ_TUPLE_MAX_WINDOW)
+        return CQ_ERR_INVALID;
+    DeviceGuard guard(q->device);
+    if (!q->pt_sidx) {
+        int rc = dalloc(&q->pt_sidx, SUB);
+        if (rc == CQ_OK) rc = dalloc(&q->pt_pcnt, q->st.G);
+        if (rc != CQ_OK) {
+            dfree(q->pt_sidx);
+            dfree(q->pt_pcnt);
+            return rc;
+        }
+    }
+    const PtOut pt = {sums, counts, avgs, passes};
+    return push(q, keys, values, n, reinterpret_cast<hipStream_t>(stream), nullptr, &pt);
 }
 
 int cq_push_batches(cq_query *q, int32_t count, const int32_t *const *keys,

@@ -1,0 +1,346 @@
+// HIP kernel for gfx950: per-tuple results of one planned and reordered
+// sub-batch -- the aggregate the paper recomputes after every insertion
+// (Section 5.1: the whole window is scanned after each new tuple; the last
+// experiment of Section 5.2 scans it ten times).
+//
+// The launch sits between the reorder pass and the update, so the window
+// store still holds the state from before the sub-batch.  For a group g
+// with ring pointer p (the slot of its next write) and its tuples of this
+// sub-batch v_0 .. v_{k-1} in arrival order, let
+//   seq[x]     = ring[g][(p + x) mod W] for 0 <= x < W: the slot that
+//                insertion x overwrites (slots never written hold 0), and
+//   seq[W + j] = v_j.
+// The window right after v_r entered is seq[r+1 .. W+r]: W entries, zeros
+// standing for values never written.  Its SUM is the sum of that range and
+// its COUNT min(W, count before the sub-batch + r + 1).
+//   passes = 0 : SUM = (sum before) + sum over j <= r of (v_j - seq[j]),
+//                the incremental form, exact in integers;
+//   passes >= 1: the range is summed from scratch, `passes` times, each
+//                pass reading the window again.
+// Either way the results are identical integers.
+//
+// Work items: every light bucket of the plan (consecutive groups, at most
+// LIGHT_CAP tuples) and every PT_CH ranks of every heavy group, so a hot
+// group is spread over many workgroups.  A light bucket's tuples arrive
+// bucket-sorted per tile; an LDS sort on (group, arrival position) puts
+// every group's tuples together in rank order.  A heavy group's tuples are
+// its runs in tile order, already in rank order.
+#include <climits>
+
+#include "cq.h"
+#include "cq_device.h"
+#include "cq_internal.h"
+
+namespace cq {
+
+namespace {
+
+constexpr int PT_THREADS = 256;
+constexpr int PT_GRID_MAX = 2048;
+
+// LDS layout (bytes)
+constexpr int T_RS = 0;                                  // i32[PASS_TILES_MAX]
+constexpr int T_RP = T_RS + 4 * PASS_TILES_MAX;          // i32[PASS_TILES_MAX + 4]
+constexpr int T_HC = T_RP + 4 * (PASS_TILES_MAX + 4);    // i32[NB_MAX + 4] heavy item prefix
+constexpr int T_RED = T_HC + 4 * (NB_MAX + 4);           // scan scratch
+constexpr int T_W = T_RED + 8 * 64;                      // work area
+// light bucket: sort keys, values, arrival indices (i32[LIGHT_CAP] each),
+// prefix sums (i64[LIGHT_CAP])
+constexpr int L_CK = T_W;
+constexpr int L_V = L_CK + 4 * LIGHT_CAP;
+constexpr int L_I = L_V + 4 * LIGHT_CAP;
+constexpr int L_PS = L_I + 4 * LIGHT_CAP;
+constexpr int L_END = L_PS + 8 * LIGHT_CAP;
+// heavy item: values of ranks [lo, r1) (i32), arrival indices of [r0, r1)
+// (i32), prefix sums (i64)
+constexpr int H_SPAN = PT_CH + PT_WMAX;
+constexpr int H_V = T_W;
+constexpr int H_I = H_V + 4 * H_SPAN;
+constexpr int H_PS = H_I + 4 * PT_CH;
+constexpr int H_END = H_PS + 8 * H_SPAN;
+constexpr int T_BYTES = L_END > H_END ? L_END : H_END;
+static_assert(LIGHT_CAP <= 1024, "10-bit arrival positions in the light sort key");
+static_assert(LIGHT_CAP % PT_THREADS == 0, "whole positions per thread");
+static_assert(PASS_LOCAL_G <= (1 << 21), "group offsets fit the light sort key");
+
+// Inclusive scan of a[0, m) (int64, in LDS, in place); each thread scans a
+// contiguous piece.  `red` holds one int64 per wave.  Barriers inside.
+__device__ void block_incl_scan_ll(long long *a, int m, long long *red) {
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+    const int per = (m + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int b0 = min(m, tid * per), b1 = min(m, b0 + per);
+    long long s = 0;
+    for (int i = b0; i < b1; ++i) {
+        s += a[i];
+        a[i] = s;
+    }
+    long long x = s;  // inclusive over the wave's threads
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const long long y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) red[wv] = x;
+    __syncthreads();
+    long long off = x - s;
+    for (int w = 0; w < wv; ++w) off += red[w];
+    for (int i = b0; i < b1; ++i) a[i] += off;
+    __syncthreads();
+}
+
+// Ascending bitonic sort of a[0, m) in LDS, m a power of two.  Barriers
+// inside.
+__device__ void bitonic_sort(int32_t *a, int m) {
+    for (int k = 2; k <= m; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < m; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const int32_t x = a[i], y = a[l];
+                    if ((x > y) == ((i & k) == 0)) {
+                        a[i] = y;
+                        a[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Slot x of group g's eviction order (the slot insertion x overwrites).
+__device__ __forceinline__ int32_t old_slot(const int32_t *row, int32_t po, int x, int32_t W) {
+    return row[((uint32_t)po + (uint32_t)x) % (uint32_t)W];
+}
+
+// SUM of the window right after rank r entered, from scratch, `passes`
+// times: old slots x in (r, W) from the ring row, then ranks
+// [max(0, r+1-W), r] from `vals` (vals[j - vbase] holds rank j).
+__device__ long long rescan(const int32_t *row, int32_t po, int32_t W, int r, const int32_t *vals,
+                            int vbase, int passes, const Scratch &sc) {
+    long long first = 0;
+    bool same = true;
+    for (int pass = 0; pass < passes; ++pass) {
+        long long s = 0;
+        if (r + 1 < W) {
+            uint32_t slot = ((uint32_t)po + (uint32_t)(r + 1)) % (uint32_t)W;
+            for (int x = r + 1; x < W; ++x) {
+                s += row[slot];
+                if (++slot == (uint32_t)W) slot = 0;
+            }
+        }
+        for (int j = max(0, r + 1 - W); j <= r; ++j) s += vals[j - vbase];
+        if (pass == 0) first = s;
+        else same = same && s == first;
+        __asm__ volatile("" ::: "memory");  // the next pass reads the window again
+    }
+    if (!same) atomicOr(sc.fault, FAULT_PASSES);
+    return first;
+}
+
+__device__ __forceinline__ void put(const PtOut &out, int32_t i, long long s, int32_t c) {
+    if (out.sums) out.sums[i] = s;
+    if (out.counts) out.counts[i] = c;
+    if (out.avgs) out.avgs[i] = (double)s / (double)c;
+}
+
+// Light bucket b: groups [bstart[b], bstart[b+1]), tuples in light-prefix
+// space [lpre[a], lpre[z]).
+__device__ void light_item(int b, int NB, int tiles, const State &st, const Scratch &sc,
+                           const PtOut &out, char *smem) {
+    const int tid = threadIdx.x;
+    int32_t *rs = reinterpret_cast<int32_t *>(smem + T_RS);
+    int32_t *rp = reinterpret_cast<int32_t *>(smem + T_RP);
+    int *red = reinterpret_cast<int *>(smem + T_RED);
+    int32_t *ck = reinterpret_cast<int32_t *>(smem + L_CK);
+    int32_t *lv = reinterpret_cast<int32_t *>(smem + L_V);
+    int32_t *li = reinterpret_cast<int32_t *>(smem + L_I);
+    long long *ps = reinterpret_cast<long long *>(smem + L_PS);
+    const int32_t W = st.W;
+    const int32_t a = sc.bstart[b], z = sc.bstart[b + 1];
+    const int32_t s0 = sc.lpre[a];
+    const int size = sc.lpre[z] - s0;
+    const int total = bucket_runs(sc, b, NB, tiles, rs, rp, red, [] {});
+    if (size <= 0) return;
+    if (size > LIGHT_CAP || total != size) {
+        if (tid == 0) atomicOr(sc.fault, FAULT_TUPLE_RUNS);
+        return;
+    }
+    int m = 1;
+    while (m < size) m <<= 1;
+    for (int p = tid; p < m; p += blockDim.x) {
+        if (p < size) {
+            const int r = upper_run(rp, tiles, p);
+            const int64_t pos = rs[r] + (p - rp[r]);
+            const int2 e = sc.sdat[pos];
+            lv[p] = e.y;
+            li[p] = sc.sidx[pos];
+            ck[p] = ((e.x - a) << 10) | p;
+        } else {
+            ck[p] = INT_MAX;
+        }
+    }
+    __syncthreads();
+    bitonic_sort(ck, m);
+    // every staged tuple of the bucket belongs to one of its groups
+    // (a consistency check: the plan and the reorder agree)
+    for (int q = tid; q < size; q += blockDim.x) {
+        const int32_t off = ck[q] >> 10;
+        if (off < 0 || off >= z - a) {
+            atomicOr(sc.fault, FAULT_TUPLE_RUNS);
+            ck[q] = 0 | (ck[q] & 1023);  // keep the reads below inside the bucket
+        }
+    }
+    __syncthreads();
+    // values and arrival indices into sorted (group, rank) order
+    constexpr int PPT = LIGHT_CAP / PT_THREADS;
+    int32_t tv[PPT], ti[PPT];
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+        const int q = tid + u * PT_THREADS;
+        if (q < size) {
+            const int p = ck[q] & 1023;
+            tv[u] = lv[p];
+            ti[u] = li[p];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+        const int q = tid + u * PT_THREADS;
+        if (q < size) {
+            lv[q] = tv[u];
+            li[q] = ti[u];
+        }
+    }
+    __syncthreads();
+    if (out.passes == 0) {
+        for (int q = tid; q < size; q += blockDim.x) {
+            const int32_t g = a + (ck[q] >> 10);
+            const int gs = sc.lpre[g] - s0;
+            const int r = q - gs;
+            const int32_t ev = r < W ? old_slot(st.ring + (int64_t)g * W, sc.pold[g], r, W)
+                                     : lv[q - W];
+            ps[q] = (long long)lv[q] - (long long)ev;
+        }
+        __syncthreads();
+        block_incl_scan_ll(ps, size, reinterpret_cast<long long *>(red));
+    }
+    for (int q = tid; q < size; q += blockDim.x) {
+        const int32_t g = a + (ck[q] >> 10);
+        const int gs = sc.lpre[g] - s0;
+        const int r = q - gs;
+        long long s;
+        if (out.passes == 0)
+            s = st.sum[g] + ps[q] - (gs > 0 ? ps[gs - 1] : 0);
+        else
+            s = rescan(st.ring + (int64_t)g * W, sc.pold[g], W, r, lv + gs, 0, out.passes, sc);
+        const int32_t c = (int32_t)min((int64_t)W, (int64_t)sc.pcnt[g] + r + 1);
+        put(out, li[q], s, c);
+    }
+}
+
+// Ranks [r0, r1) of heavy group x (bucket nl + x).
+__device__ void heavy_item(int x, int c, int nl, int NB, int tiles, const State &st,
+                           const Scratch &sc, const PtOut &out, char *smem) {
+    const int tid = threadIdx.x;
+    int32_t *rs = reinterpret_cast<int32_t *>(smem + T_RS);
+    int32_t *rp = reinterpret_cast<int32_t *>(smem + T_RP);
+    int *red = reinterpret_cast<int *>(smem + T_RED);
+    int32_t *hv = reinterpret_cast<int32_t *>(smem + H_V);
+    int32_t *hi = reinterpret_cast<int32_t *>(smem + H_I);
+    long long *ps = reinterpret_cast<long long *>(smem + H_PS);
+    const int32_t W = st.W;
+    const int32_t g = sc.hkey[x];
+    const int32_t kg = sc.k[g];
+    const int total = bucket_runs(sc, nl + x, NB, tiles, rs, rp, red, [] {});
+    if (total != kg) {
+        if (tid == 0) atomicOr(sc.fault, FAULT_TUPLE_RUNS);
+        return;
+    }
+    const int r0 = c * PT_CH, r1 = min(kg, r0 + PT_CH);
+    const int lo = max(0, r0 - W + 1);  // r0 is 0 or at least PT_CH >= W
+    const int L = r1 - lo;
+    for (int j = tid; j < L; j += blockDim.x) {
+        const int rank = lo + j;
+        const int r = upper_run(rp, tiles, rank);
+        const int64_t pos = rs[r] + (rank - rp[r]);
+        hv[j] = sc.sdat[pos].y;
+        if (rank >= r0) hi[rank - r0] = sc.sidx[pos];
+    }
+    __syncthreads();
+    const int32_t *row = st.ring + (int64_t)g * W;
+    const int32_t po = sc.pold[g];
+    if (out.passes == 0) {
+        for (int j = tid; j < L; j += blockDim.x) {
+            if (r0 == 0) {  // ranks from 0: v_j - seq[j]
+                const int32_t ev = j < W ? old_slot(row, po, j, W) : hv[j - W];
+                ps[j] = (long long)hv[j] - (long long)ev;
+            } else {  // window entirely inside this sub-batch: plain prefix
+                ps[j] = hv[j];
+            }
+        }
+        __syncthreads();
+        block_incl_scan_ll(ps, L, reinterpret_cast<long long *>(red));
+    }
+    const long long s_before = r0 == 0 ? st.sum[g] : 0;
+    const int32_t cnt0 = sc.pcnt[g];
+    for (int r = r0 + tid; r < r1; r += blockDim.x) {
+        long long s;
+        if (out.passes == 0) {
+            if (r0 == 0) {
+                s = s_before + ps[r];
+            } else {
+                const int back = r - W - lo;  // >= -1
+                s = ps[r - lo] - (back >= 0 ? ps[back] : 0);
+            }
+        } else {
+            s = rescan(row, po, W, r, hv, lo, out.passes, sc);
+        }
+        const int32_t cn = (int32_t)min((int64_t)W, (int64_t)cnt0 + r + 1);
+        put(out, hi[r - r0], s, cn);
+    }
+}
+
+__global__ __launch_bounds__(PT_THREADS) void k_tuples(State st, Scratch sc, int tiles,
+                                                       PtOut out) {
+    __shared__ __align__(16) char smem[T_BYTES];
+    const PlanTotals t = *sc.tot;
+    if (t.status) return;  // rejected batch: nothing to report
+    const int nl = t.n_light_buckets, nh = t.n_heavy, NB = t.n_buckets;
+    if (NB > NB_MAX || nh > NB_MAX || nl + nh != NB) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(sc.fault, FAULT_TUPLE_RUNS);
+        return;
+    }
+    // heavy work items: ceil(k / PT_CH) per heavy group, prefix in hc
+    int32_t *hc = reinterpret_cast<int32_t *>(smem + T_HC);
+    int *red = reinterpret_cast<int *>(smem + T_RED);
+    for (int x = threadIdx.x; x < nh; x += blockDim.x)
+        hc[x] = (sc.k[sc.hkey[x]] + PT_CH - 1) / PT_CH;
+    __syncthreads();
+    block_excl_scan_array(hc, nh, red);
+    const int items = nl + hc[nh];
+    for (int it = blockIdx.x; it < items; it += gridDim.x) {
+        if (it < nl) {
+            light_item(it, NB, tiles, st, sc, out, smem);
+        } else {
+            const int h = it - nl;
+            const int x = upper_run(hc, nh, h);  // hc strictly increasing
+            heavy_item(x, h - hc[x], nl, NB, tiles, st, sc, out, smem);
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_tuples(State st, Scratch sc, int64_t n, PtOut out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int tiles = (int)((n + PASS_TILE - 1) / PASS_TILE);
+    const int64_t want = (n + LIGHT_BUDGET - 1) / LIGHT_BUDGET + (n + PT_CH - 1) / PT_CH + 8;
+    const int grid = (int)std::min<int64_t>(PT_GRID_MAX, want);
+    hipLaunchKernelGGL(k_tuples, dim3(grid), dim3(PT_THREADS), 0, s, st, sc, tiles, out);
+    return hipGetLastError();
+}
+
+}  // namespace cq

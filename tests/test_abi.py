@@ -61,6 +61,10 @@ def test_null_handles_are_rejected(L):
     assert L.cq_batch_plan(None, None) == cq.ERR_INVALID
     assert L.cq_push_batches(None, 1, None, None, None, None, None, None, None, None,
                              None) == cq.ERR_INVALID
+    assert L.cq_push_batch_tuples(None, None, None, 0, 0, None, None, None,
+                                  None) == cq.ERR_INVALID
+    assert L.cq_set_policy_params(None, 1000, 0.5) == cq.ERR_INVALID
+    assert L.cq_policy_stats(None, None) == cq.ERR_INVALID
     assert L.cq_destroy(None) == cq.OK
 
 
@@ -68,7 +72,8 @@ def test_binding_names_match_header():
     for name in ("cq_create", "cq_reserve", "cq_set_partition", "cq_push_batch", "cq_results",
                  "cq_status", "cq_destroy", "cq_strerror", "cq_set_telemetry",
                  "cq_kernel_times", "cq_worker_trace", "cq_batch_plan", "cq_phase_trace",
-                 "cq_push_batches", "cq_push_batch_results"):
+                 "cq_push_batches", "cq_push_batch_results", "cq_push_batch_tuples",
+                 "cq_set_policy_params", "cq_policy_stats", "cq_policy_apply"):
         assert name in _declared_functions()
 
 
@@ -84,3 +89,8 @@ def test_header_constants_match_binding():
     assert val("CQ_PARTITION_STATIC") == cq.PARTITION_STATIC
     assert val("CQ_PIPE_MAX") == cq.PIPE_MAX
     assert val("CQ_KERNEL_KINDS") == len(cq.KERNEL_KINDS)
+    assert val("CQ_KERNEL_TUPLES") == cq.KERNEL_KINDS.index("tuples")
+    assert val("CQ_TUPLE_MAX_WINDOW") == cq.TUPLE_MAX_WINDOW
+    assert val("CQ_TUPLE_MAX_PASSES") == cq.TUPLE_MAX_PASSES
+    for name, v in cq.POLICIES.items():
+        assert val("CQ_PARTITION_" + name.upper()) == v
