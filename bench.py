@@ -44,6 +44,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Window-element additions per second the vector ALUs can issue: the
+# from-scratch rescans add one binary64 value per window element (exact for
+# these integer sums), and MI355X issues 256 CUs x 64 lanes x 2.4 GHz fp64
+# adds (its 78.6 TFLOP/s fp64 vector peak counts an FMA as two).
+FP64_ADD_PEAK = 256 * 64 * 2.4e9
 SWEEP = (0.0, 0.5, 1.0, 1.5, 2.0)
 HEADLINE_S = 1.5
 METRIC = "tuples/sec and HBM GB/s at Zipf s=0..2, balanced vs static; p99 batch latency"
@@ -159,6 +164,50 @@ def techniques(torch, cq, s_list, warmup, steps):
                 print(json.dumps({"progress": row}), file=sys.stderr, flush=True)
             del batches, stream
             torch.cuda.empty_cache()
+    return rows
+
+
+def per_tuple(torch, cq, batches, cfg, warmup, steps, passes_list):
+    """The paper-literal variant (cq_push_batch_tuples): per-tuple window
+    SUM/COUNT/AVG after every insertion, incrementally (passes 0) or with
+    every window summed from scratch (passes 1 and 10, Section 5.1 and the
+    ten-fold scan of Section 5.2).  Whole pushes timed on the device stream,
+    then the k_tuples launches alone with the library's events."""
+    dev = batches[0][0].device
+    n = cfg.batch
+    sums = torch.empty(n, dtype=torch.int64, device=dev)
+    counts = torch.empty(n, dtype=torch.int32, device=dev)
+    avgs = torch.empty(n, dtype=torch.float64, device=dev)
+    rows = []
+    for passes in passes_list:
+        st = steps if passes <= 1 else max(4, steps // 4)
+        q = cq.Query(cfg.groups, cfg.window)
+        for b in range(warmup):
+            q.push_tuples_into(*batches[b], sums, counts, avgs, passes)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b in range(warmup, warmup + st):
+            q.push_tuples_into(*batches[b], sums, counts, avgs, passes)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        q.set_telemetry(cq.TELEMETRY_KERNEL_TIMES)
+        q.kernel_times()
+        for b in range(warmup, warmup + st):
+            q.push_tuples_into(*batches[b], sums, counts, avgs, passes)
+        kt = q.kernel_times()
+        q.close()
+        ms_t, launches = kt["tuples"]
+        k_us = 1e3 * ms_t / max(1, launches)
+        row = {"passes": passes, "ms_per_batch": round(1e3 * wall / st, 4),
+               "tuples_per_s": st * n / wall, "k_tuples_avg_us": round(k_us, 2),
+               "output_bytes_per_batch": 20 * n}
+        if passes:
+            # window elements summed per launch: every tuple's W entries, each pass
+            adds = float(n) * cfg.window * passes
+            row["window_elems_per_s"] = adds / (k_us * 1e-6)
+            row["alu_frac"] = round(row["window_elems_per_s"] / FP64_ADD_PEAK, 4)
+        rows.append(row)
+        print(json.dumps({"progress": {"per_tuple": row}}), file=sys.stderr, flush=True)
     return rows
 
 
@@ -301,6 +350,8 @@ def main():
     ap.add_argument("--techniques", default="1.0,1.5",
                     help="Zipf s values of the Section 4 technique comparison ('' skips it)")
     ap.add_argument("--tech-steps", type=int, default=40)
+    ap.add_argument("--tuple-passes", default="0,1,10",
+                    help="passes of the per-tuple variant to time ('' skips it)")
     ap.add_argument("--calibrate", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -380,6 +431,10 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom, "kernel_avg_us": round(1e3 * dom_ms / dom_launches, 2),
                 "kernel_times_ms": {k: round(v[0], 3) for k, v in kern.items()}}
+    pt = None
+    if args.tuple_passes:
+        pt = per_tuple(torch, cq, batches, cfg, min(args.warmup, 5), min(args.steps, 40),
+                       [int(x) for x in args.tuple_passes.split(",")])
     host = None if args.no_cpu else [(k.cpu().numpy(), v.cpu().numpy()) for k, v in batches]
     del batches
     torch.cuda.empty_cache()
@@ -425,6 +480,7 @@ def main():
         "cpu_baseline_all_threads": cpu_mt,
         "sweep": rows,
         "techniques": tech,
+        "per_tuple": pt,
     }
     print(json.dumps(out), flush=True)
 

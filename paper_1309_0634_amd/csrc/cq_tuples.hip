@@ -51,7 +51,7 @@ constexpr int L_V = L_CK + 4 * LIGHT_CAP;
 constexpr int L_I = L_V + 4 * LIGHT_CAP;
 constexpr int L_PS = L_I + 4 * LIGHT_CAP;
 constexpr int L_END = L_PS + 8 * LIGHT_CAP;
-// heavy item: values of ranks [lo, r1) (i32), arrival indices of [r0, r1)
+// heavy item: a piece of seq (i32), arrival indices of ranks [r0, r1)
 // (i32), prefix sums (i64)
 constexpr int H_SPAN = PT_CH + PT_WMAX;
 constexpr int H_V = T_W;
@@ -113,29 +113,21 @@ __device__ __forceinline__ int32_t old_slot(const int32_t *row, int32_t po, int 
     return row[((uint32_t)po + (uint32_t)x) % (uint32_t)W];
 }
 
-// SUM of the window right after rank r entered, from scratch, `passes`
-// times: old slots x in (r, W) from the ring row, then ranks
-// [max(0, r+1-W), r] from `vals` (vals[j - vbase] holds rank j).
-__device__ long long rescan(const int32_t *row, int32_t po, int32_t W, int r, const int32_t *vals,
-                            int vbase, int passes, const Scratch &sc) {
-    long long first = 0;
-    bool same = true;
-    for (int pass = 0; pass < passes; ++pass) {
-        long long s = 0;
-        if (r + 1 < W) {
-            uint32_t slot = ((uint32_t)po + (uint32_t)(r + 1)) % (uint32_t)W;
-            for (int x = r + 1; x < W; ++x) {
-                s += row[slot];
-                if (++slot == (uint32_t)W) slot = 0;
-            }
-        }
-        for (int j = max(0, r + 1 - W); j <= r; ++j) s += vals[j - vbase];
-        if (pass == 0) first = s;
-        else same = same && s == first;
-        __asm__ volatile("" ::: "memory");  // the next pass reads the window again
+// Sum of n int32 values at p, in four independent fp64 accumulators.
+// Every partial sum is an integer of magnitude below W * 2^31 <= 2^41, so
+// each addition is exact in binary64 whatever the order: the total is the
+// exact integer.  (The int64 form needs three dependent integer operations
+// per value; this needs a conversion and an add, in four chains.)
+__device__ __forceinline__ void sum_run(const int32_t *p, int n, double (&acc)[4]) {
+    int i = 0;
+    for (; i + 32 <= n; i += 32) {  // 32 loads in flight before the adds
+        int32_t t[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) t[u] = p[i + u];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) acc[u & 3] += (double)t[u];
     }
-    if (!same) atomicOr(sc.fault, FAULT_PASSES);
-    return first;
+    for (; i < n; ++i) acc[i & 3] += (double)p[i];
 }
 
 __device__ __forceinline__ void put(const PtOut &out, int32_t i, long long s, int32_t c) {
@@ -225,29 +217,60 @@ __device__ void light_item(int b, int NB, int tiles, const State &st, const Scra
         }
         __syncthreads();
         block_incl_scan_ll(ps, size, reinterpret_cast<long long *>(red));
+        for (int q = tid; q < size; q += blockDim.x) {
+            const int32_t g = a + (ck[q] >> 10);
+            const int gs = sc.lpre[g] - s0;
+            const int r = q - gs;
+            const long long s = st.sum[g] + ps[q] - (gs > 0 ? ps[gs - 1] : 0);
+            const int32_t c = (int32_t)min((int64_t)W, (int64_t)sc.pcnt[g] + r + 1);
+            put(out, li[q], s, c);
+        }
+        return;
     }
+    // From scratch: one tuple per thread.  The old slots come from the
+    // ring row (the lanes of a wave mostly hold consecutive ranks of one
+    // group, so their reads are consecutive), the values from LDS.  (Copying
+    // each group's old window to LDS and rescanning with a wave per group
+    // measured slower: a light group can hold up to HEAVY_MIN - 1 tuples,
+    // and one wave then carries them all.)
     for (int q = tid; q < size; q += blockDim.x) {
         const int32_t g = a + (ck[q] >> 10);
         const int gs = sc.lpre[g] - s0;
         const int r = q - gs;
-        long long s;
-        if (out.passes == 0)
-            s = st.sum[g] + ps[q] - (gs > 0 ? ps[gs - 1] : 0);
-        else
-            s = rescan(st.ring + (int64_t)g * W, sc.pold[g], W, r, lv + gs, 0, out.passes, sc);
-        const int32_t c = (int32_t)min((int64_t)W, (int64_t)sc.pcnt[g] + r + 1);
-        put(out, li[q], s, c);
+        const int32_t *row = st.ring + (int64_t)g * W;
+        const int len = r + 1 < W ? W - (r + 1) : 0;  // old slots still in the window
+        const int s1 = (int)(((uint32_t)sc.pold[g] + (uint32_t)(r + 1)) % (uint32_t)W);
+        const int n1 = min(len, W - s1);
+        const int j0 = max(0, r + 1 - W);
+        long long first = 0;
+        bool same = true;
+        for (int pass = 0; pass < out.passes; ++pass) {
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            sum_run(row + s1, n1, acc);
+            sum_run(row, len - n1, acc);
+            sum_run(lv + gs + j0, r - j0 + 1, acc);
+            const long long v = (long long)((acc[0] + acc[1]) + (acc[2] + acc[3]));
+            if (pass == 0) first = v;
+            else same = same && v == first;
+            __asm__ volatile("" ::: "memory");  // the next pass reads the window again
+        }
+        if (!same) atomicOr(sc.fault, FAULT_PASSES);
+        const int32_t cn = (int32_t)min((int64_t)W, (int64_t)sc.pcnt[g] + r + 1);
+        put(out, li[q], first, cn);
     }
 }
 
-// Ranks [r0, r1) of heavy group x (bucket nl + x).
+// Ranks [r0, r1) of heavy group x (bucket nl + x).  The item stages the
+// piece of seq it needs in LDS: positions [xb, W + r1), the old slots
+// (first item only) followed by the values, so every window is one
+// contiguous LDS range: window(r) = seq[r+1 .. W+r].
 __device__ void heavy_item(int x, int c, int nl, int NB, int tiles, const State &st,
                            const Scratch &sc, const PtOut &out, char *smem) {
     const int tid = threadIdx.x;
     int32_t *rs = reinterpret_cast<int32_t *>(smem + T_RS);
     int32_t *rp = reinterpret_cast<int32_t *>(smem + T_RP);
     int *red = reinterpret_cast<int *>(smem + T_RED);
-    int32_t *hv = reinterpret_cast<int32_t *>(smem + H_V);
+    int32_t *sq = reinterpret_cast<int32_t *>(smem + H_V);
     int32_t *hi = reinterpret_cast<int32_t *>(smem + H_I);
     long long *ps = reinterpret_cast<long long *>(smem + H_PS);
     const int32_t W = st.W;
@@ -259,46 +282,52 @@ __device__ void heavy_item(int x, int c, int nl, int NB, int tiles, const State 
         return;
     }
     const int r0 = c * PT_CH, r1 = min(kg, r0 + PT_CH);
-    const int lo = max(0, r0 - W + 1);  // r0 is 0 or at least PT_CH >= W
-    const int L = r1 - lo;
-    for (int j = tid; j < L; j += blockDim.x) {
-        const int rank = lo + j;
-        const int r = upper_run(rp, tiles, rank);
-        const int64_t pos = rs[r] + (rank - rp[r]);
-        hv[j] = sc.sdat[pos].y;
-        if (rank >= r0) hi[rank - r0] = sc.sidx[pos];
-    }
-    __syncthreads();
+    // LDS index j holds seq position xb + j: the first item from seq[0],
+    // later ones (r0 >= PT_CH >= W) from the oldest value of rank r0's
+    // window.  window(r) = seq[r+1 .. W+r] is then one contiguous LDS range.
+    const int xb = r0 == 0 ? 0 : r0 + 1;
+    const int Lq = W + r1 - xb;  // <= PT_CH + PT_WMAX
     const int32_t *row = st.ring + (int64_t)g * W;
     const int32_t po = sc.pold[g];
-    if (out.passes == 0) {
-        for (int j = tid; j < L; j += blockDim.x) {
-            if (r0 == 0) {  // ranks from 0: v_j - seq[j]
-                const int32_t ev = j < W ? old_slot(row, po, j, W) : hv[j - W];
-                ps[j] = (long long)hv[j] - (long long)ev;
-            } else {  // window entirely inside this sub-batch: plain prefix
-                ps[j] = hv[j];
-            }
+    for (int j = tid; j < Lq; j += blockDim.x) {
+        const int xs = xb + j;
+        if (xs < W) {
+            sq[j] = old_slot(row, po, xs, W);
+        } else {
+            const int rank = xs - W;
+            const int r = upper_run(rp, tiles, rank);
+            const int64_t pos = rs[r] + (rank - rp[r]);
+            sq[j] = sc.sdat[pos].y;
+            if (rank >= r0) hi[rank - r0] = sc.sidx[pos];
         }
-        __syncthreads();
-        block_incl_scan_ll(ps, L, reinterpret_cast<long long *>(red));
     }
-    const long long s_before = r0 == 0 ? st.sum[g] : 0;
+    __syncthreads();
+    if (out.passes == 0) {
+        for (int j = tid; j < Lq; j += blockDim.x) ps[j] = sq[j];
+        __syncthreads();
+        block_incl_scan_ll(ps, Lq, reinterpret_cast<long long *>(red));
+    }
     const int32_t cnt0 = sc.pcnt[g];
     for (int r = r0 + tid; r < r1; r += blockDim.x) {
+        const int e = W + r - xb;  // window(r) = sq[e - W + 1 .. e]
         long long s;
         if (out.passes == 0) {
-            if (r0 == 0) {
-                s = s_before + ps[r];
-            } else {
-                const int back = r - W - lo;  // >= -1
-                s = ps[r - lo] - (back >= 0 ? ps[back] : 0);
-            }
+            s = ps[e] - (e - W >= 0 ? ps[e - W] : 0);
         } else {
-            s = rescan(row, po, W, r, hv, lo, out.passes, sc);
+            long long first = 0;
+            bool same = true;
+            for (int pass = 0; pass < out.passes; ++pass) {
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+                sum_run(sq + (e - W + 1), W, acc);
+                const long long v = (long long)((acc[0] + acc[1]) + (acc[2] + acc[3]));
+                if (pass == 0) first = v;
+                else same = same && v == first;
+                __asm__ volatile("" ::: "memory");  // the next pass reads the window again
+            }
+            if (!same) atomicOr(sc.fault, FAULT_PASSES);
+            s = first;
         }
-        const int32_t cn = (int32_t)min((int64_t)W, (int64_t)cnt0 + r + 1);
-        put(out, hi[r - r0], s, cn);
+        put(out, hi[r - r0], s, (int32_t)min((int64_t)W, (int64_t)cnt0 + r + 1));
     }
 }
 
