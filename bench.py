@@ -285,7 +285,8 @@ def run_pipelined(torch, cq, batches, cfg, warmup, steps, per_call=8):
     return wall, calls * per_call
 
 
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1309_0634_amd", "csrc", "cq_kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1309_0634_amd", "csrc", f)
+                  for f in ("cq_kernels.hip", "cq_device.h", "cq_internal.h")]
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -301,7 +302,10 @@ def measured_traffic(kernel: str):
     m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not (m_sha and m_b):
         return None
-    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:  # the kernels' source and the headers they build on
+        h.update(open(f, "rb").read())
+    sha = h.hexdigest()
     return float(m_b.group(1)) if sha == m_sha.group(1) else None
 
 
