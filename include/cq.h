@@ -271,6 +271,83 @@ int cq_destroy(cq_query *q);
 /* Static description of a status code. */
 const char *cq_strerror(int code);
 
+/* ------------------------------ serving ------------------------------- */
+
+/*
+ * cq_query_footprint -- device bytes a query of `groups` groups and window
+ * `window` allocates (window store, per-group state and its working
+ * buffers; each allocation rounded up to 4 KiB), or -1 for invalid sizes.
+ */
+int64_t cq_query_footprint(int64_t groups, int32_t window);
+
+typedef struct cq_server cq_server;
+
+#define CQ_SERVER_MAX_LANES 16
+#define CQ_SERVER_MAX_SLOTS 64
+
+/*
+ * cq_server_create -- a serving loop on the current device: many resident
+ * queries whose batches arrive over time (Section 3.1 takes one batch per
+ * iteration as the stream delivers it; Section 3.2 keeps every window in
+ * GPU memory).
+ *   memory_budget : device bytes the resident queries may hold (0 = 80% of
+ *                   the free device memory now);
+ *   lanes         : HIP streams, default priority (0 = 4, at most
+ *                   CQ_SERVER_MAX_LANES).  Each query is pinned to one lane,
+ *                   so its batches run in submission order, while batches
+ *                   of queries on other lanes overlap with them on the GPU;
+ *   slots         : requests in flight per lane (0 = 2, at most
+ *                   CQ_SERVER_MAX_SLOTS).
+ * A dispatcher thread starts waiting requests in arrival order as slots
+ * free up (a request never passes an earlier one of its own query).
+ * Returns CQ_OK, CQ_ERR_INVALID, CQ_ERR_OOM or CQ_ERR_HIP.
+ */
+int cq_server_create(int64_t memory_budget, int32_t lanes, int32_t slots, cq_server **out);
+
+/*
+ * cq_server_add_query -- admit a query (as cq_create) if its footprint fits
+ * the budget still free; *qid receives its id.  Returns CQ_OK,
+ * CQ_ERR_INVALID, CQ_ERR_OOM (does not fit, nothing allocated) or
+ * CQ_ERR_HIP.  cq_server_remove_query waits for the query's requests, frees
+ * it and returns its bytes to the budget.
+ */
+int cq_server_add_query(cq_server *srv, int64_t groups, int32_t window, uint32_t aggregates,
+                        int32_t *qid);
+int cq_server_remove_query(cq_server *srv, int32_t qid);
+
+/*
+ * cq_server_submit -- queue one batch of query qid: device arrays keys,
+ * values (n tuples), and result arrays exactly as cq_push_batch_results
+ * (ids/sums/counts/avgs of min(groups, n) entries, any may be NULL;
+ * n_touched required; a rejected batch gets its status there).  Every
+ * array must stay valid until the request completes.  *ticket receives the
+ * request's number.  Returns at once: CQ_OK or CQ_ERR_INVALID.
+ */
+int cq_server_submit(cq_server *srv, int32_t qid, const int32_t *keys, const int32_t *values,
+                     int64_t n, int32_t *ids, int64_t *sums, int32_t *counts, double *avgs,
+                     int64_t *n_touched, int64_t *ticket);
+
+/*
+ * cq_server_wait -- block until request `ticket` has completed on the GPU
+ * (its results are then in place) and return its launch status; a ticket
+ * can be waited for once.  ticket = -1 waits for every request submitted so
+ * far and forgets their tickets.
+ */
+int cq_server_wait(cq_server *srv, int64_t ticket);
+
+/*
+ * cq_server_stats -- over the requests completed since the previous call:
+ * out[0] requests, out[1] p50 and out[2] p99 and out[3] max latency in
+ * microseconds (host clock, submission to observed completion), out[4]
+ * tuples, out[5] tuples per second over the span from the earliest
+ * submission to the last completion; out[6] / out[7] device bytes held /
+ * budget.  Then starts counting afresh.
+ */
+int cq_server_stats(cq_server *srv, double *out);
+
+/* Waits for every request, frees every query, the lanes and the server. */
+int cq_server_destroy(cq_server *srv);
+
 /* ---------------- measurement (not needed for results) ---------------- */
 
 /* Telemetry flags for cq_set_telemetry. */

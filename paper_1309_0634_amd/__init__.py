@@ -71,6 +71,14 @@ def lib() -> ctypes.CDLL:
             "cq_push_batches": ([P, i32, P, P, P, P, P, P, P, P, P], ctypes.c_int),
             "cq_push_batch_tuples": ([P, P, P, i64, i32, P, P, P, P], ctypes.c_int),
             "cq_set_policy_params": ([P, i64, ctypes.c_double], ctypes.c_int),
+            "cq_query_footprint": ([i64, i32], i64),
+            "cq_server_create": ([i64, i32, i32, ctypes.POINTER(P)], ctypes.c_int),
+            "cq_server_add_query": ([P, i64, i32, u32, ctypes.POINTER(i32)], ctypes.c_int),
+            "cq_server_remove_query": ([P, i32], ctypes.c_int),
+            "cq_server_submit": ([P, i32, P, P, i64, P, P, P, P, P, pi64], ctypes.c_int),
+            "cq_server_wait": ([P, i64], ctypes.c_int),
+            "cq_server_stats": ([P, pdbl], ctypes.c_int),
+            "cq_server_destroy": ([P], ctypes.c_int),
             "cq_policy_stats": ([P, pi64], ctypes.c_int),
             "cq_policy_apply": ([i32, i32, i64, P, P, P, i64, ctypes.c_double, i32, pi64],
                                 ctypes.c_int),
@@ -327,3 +335,83 @@ class Query:
         keys = ("light_buckets", "heavy_groups", "light_tuples", "touched", "buckets",
                 "sub_touched", "status", "tiles", "fault")
         return dict(zip(keys, list(out)))
+
+
+def query_footprint(groups: int, window: int) -> int:
+    """Device bytes a query allocates (cq_query_footprint); -1 if invalid."""
+    return int(lib().cq_query_footprint(int(groups), int(window)))
+
+
+class Server:
+    """A serving loop (cq_server_*): resident queries admitted by device
+    footprint, batches submitted as they arrive and run on a few streams
+    while the caller keeps submitting."""
+
+    def __init__(self, memory_budget: int = 0, lanes: int = 0, slots: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().cq_server_create(int(memory_budget), int(lanes), int(slots),
+                                      ctypes.byref(h)), "cq_server_create")
+        self._h = h
+        self._keep = {}  # ticket -> tensors the request reads or writes
+
+    def add_query(self, groups: int, window: int, aggregates: int = SUM | COUNT | AVG) -> int:
+        qid = ctypes.c_int32(0)
+        _check(lib().cq_server_add_query(self._h, int(groups), int(window), int(aggregates),
+                                         ctypes.byref(qid)), "cq_server_add_query")
+        return qid.value
+
+    def remove_query(self, qid: int):
+        _check(lib().cq_server_remove_query(self._h, int(qid)), "cq_server_remove_query")
+
+    def submit(self, qid: int, keys, values, ids=None, sums=None, counts=None, avgs=None,
+               n_touched=None) -> int:
+        """Queue one batch (int32 device tensors); results go to the given
+        device tensors (n_touched: int64, one entry, allocated if None).
+        Returns the ticket; the tensors are kept alive until it is waited."""
+        import torch
+        n = keys.numel()
+        if values.numel() != n:
+            raise ValueError("keys and values differ in length")
+        if n_touched is None:
+            n_touched = torch.empty(1, dtype=torch.int64, device=keys.device)
+        t = ctypes.c_int64(0)
+        _check(lib().cq_server_submit(
+            self._h, int(qid), _dptr(keys) if n else None, _dptr(values) if n else None, int(n),
+            _dptr(ids), _dptr(sums), _dptr(counts), _dptr(avgs), _dptr(n_touched),
+            ctypes.byref(t)), "cq_server_submit")
+        self._keep[t.value] = (keys, values, ids, sums, counts, avgs, n_touched)
+        return t.value
+
+    def wait(self, ticket: int = -1):
+        rc = lib().cq_server_wait(self._h, int(ticket))
+        if ticket < 0:
+            self._keep.clear()
+        else:
+            self._keep.pop(ticket, None)
+        _check(rc, "cq_server_wait")
+
+    def stats(self):
+        out = (ctypes.c_double * 8)()
+        _check(lib().cq_server_stats(self._h, out), "cq_server_stats")
+        keys = ("requests", "p50_us", "p99_us", "max_us", "tuples", "tuples_per_s",
+                "bytes_held", "budget")
+        return dict(zip(keys, list(out)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            rc = lib().cq_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+            _check(rc, "cq_server_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

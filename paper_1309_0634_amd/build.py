@@ -9,7 +9,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIBRARY = os.path.join(PKG, "libcq.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("cq_kernels.hip", "cq_tuples.hip", "cq_runtime.cpp", "cq_balance.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("cq_kernels.hip", "cq_tuples.hip", "cq_runtime.cpp", "cq_balance.cpp", "cq_server.cpp")]
 ARCH = os.environ.get("CQ_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -35,7 +35,7 @@ def build(output: str = LIBRARY, verbose: bool = False) -> str:
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = output + ".tmp"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

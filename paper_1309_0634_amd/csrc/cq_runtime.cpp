@@ -493,6 +493,19 @@ int cq_create(int64_t groups, int32_t window, uint32_t aggregates, cq_query **ou
     return CQ_OK;
 }
 
+int64_t cq_query_footprint(int64_t groups, int32_t window) {
+    if (groups < 1 || groups > INT32_MAX - 1 || window < 1 || window > CQ_MAX_WINDOW) return -1;
+    const int64_t G = groups;
+    auto pg = [](int64_t bytes) { return (std::max<int64_t>(bytes, 1) + 4095) / 4096 * 4096; };
+    const int64_t nblk = (G + PLAN_CHUNK - 1) / PLAN_CHUNK;
+    int64_t b = pg(4 * G * (int64_t)window) + 2 * pg(4 * G) + pg(8 * G);  // ring, pos, cnt, sum
+    b += 7 * pg(4 * G) + pg(4 * (G + 1));                                 // per-group plan arrays
+    b += pg(4 * (NB_MAX + 1)) + pg(4 * NB_MAX);                          // bucket starts, heavy keys
+    b += pg(8 * (int64_t)SUB) + pg(4 * (int64_t)PASS_TILES_MAX * (NB_MAX + 1));  // staging, runs
+    b += pg(4 * nblk * PLAN_FIELDS) + pg(sizeof(PlanTotals)) + pg(4) + pg(4) + pg(8);
+    return b;
+}
+
 int cq_reserve(cq_query *q, int64_t max_batch) {
     // every working buffer is sized at cq_create (batches are processed in
     // fixed-size sub-batches), so there is nothing left to reserve

@@ -65,6 +65,14 @@ def test_null_handles_are_rejected(L):
                                   None) == cq.ERR_INVALID
     assert L.cq_set_policy_params(None, 1000, 0.5) == cq.ERR_INVALID
     assert L.cq_policy_stats(None, None) == cq.ERR_INVALID
+    assert L.cq_server_add_query(None, 10, 10, 7, None) == cq.ERR_INVALID
+    assert L.cq_server_remove_query(None, 0) == cq.ERR_INVALID
+    assert L.cq_server_submit(None, 0, None, None, 0, None, None, None, None, None,
+                              None) == cq.ERR_INVALID
+    assert L.cq_server_wait(None, -1) == cq.ERR_INVALID
+    assert L.cq_server_stats(None, None) == cq.ERR_INVALID
+    assert L.cq_server_create(-1, 0, 0, None) == cq.ERR_INVALID
+    assert L.cq_server_destroy(None) == cq.OK
     assert L.cq_destroy(None) == cq.OK
 
 
@@ -94,3 +102,15 @@ def test_header_constants_match_binding():
     assert val("CQ_TUPLE_MAX_PASSES") == cq.TUPLE_MAX_PASSES
     for name, v in cq.POLICIES.items():
         assert val("CQ_PARTITION_" + name.upper()) == v
+
+
+def test_query_footprint(L):
+    """The admission size: the window store dominates and grows with G*W;
+    invalid sizes give -1 (host arithmetic only)."""
+    f = cq.query_footprint
+    assert f(0, 10) == -1 and f(10, 0) == -1 and f(10, cq.MAX_WINDOW + 1) == -1
+    base = f(10_000, 1)
+    assert f(10_000, 1000) - base >= 4 * 10_000 * 999
+    assert f(10_000, 1000) - base <= 4 * 10_000 * 999 + 2 * 4096
+    assert f(1_000_000, 100) > f(100_000, 100) > f(10_000, 100)
+    assert all(f(g, w) % 4096 == 0 for g, w in [(1, 1), (777, 13), (123_457, 99)])
