@@ -211,6 +211,100 @@ def per_tuple(torch, cq, batches, cfg, warmup, steps, passes_list):
     return rows
 
 
+def serving(torch, cq, lambdas, seconds, lanes=8, slots=2, nq=256):
+    """The serving loop (cq_server_*): `nq` resident queries (groups
+    log-uniform in [100, 1e6], windows in [10, 1e4]) admitted by device
+    footprint against 80% of the free HBM; batches (lognormal sizes, median
+    65,536, Zipf s=1.5 keys whose hot set is redrawn every 10 s of arrival
+    time) arrive as a Poisson process at each rate in `lambdas` for
+    `seconds`, each for a query drawn uniformly; latency is submission to
+    completion."""
+    from workloads import ServingBatches, serving_queries, serving_sizes
+    dev = torch.device("cuda", 0)
+    torch.cuda.empty_cache()
+    qs = serving_queries(nq)
+    epochs = int(len(lambdas) * seconds // 10) + 1
+    per = 2  # batches per query and epoch
+    sizes = serving_sizes(nq * epochs * per, 0).reshape(nq, epochs, per)
+    gen = ServingBatches(dev)
+    t0 = time.perf_counter()
+    batches = [[[gen.batch(q, G, e, i, int(sizes[q, e, i])) for i in range(per)]
+                for e in range(epochs)] for q, (G, _) in enumerate(qs)]
+    outs = []
+    for q, (G, _) in enumerate(qs):
+        cap = int(max(1, min(G, sizes[q].max())))
+        outs.append((torch.empty(cap, dtype=torch.int32, device=dev),
+                     torch.empty(cap, dtype=torch.int64, device=dev),
+                     torch.empty(cap, dtype=torch.int32, device=dev),
+                     torch.empty(cap, dtype=torch.float64, device=dev),
+                     torch.empty(1, dtype=torch.int64, device=dev)))
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    srv = cq.Server(0, lanes, slots)
+    admitted, rejected = [], 0
+    t0 = time.perf_counter()
+    for q, (G, W) in enumerate(qs):
+        try:
+            admitted.append((q, srv.add_query(G, W)))
+        except cq.CQError as e:
+            if e.code != cq.ERR_OOM:
+                raise
+            rejected += 1
+    setup_s = time.perf_counter() - t0
+    held = srv.stats()
+    rows = []
+    arrival0 = 0.0
+    for lam in lambdas:
+        rng = np.random.default_rng([20130909, 81, int(lam)])
+        srv.stats()
+        t, start, count, tuples = 0.0, time.perf_counter(), 0, 0
+        while True:
+            t += rng.exponential(1.0 / lam)
+            if t >= seconds:
+                break
+            wait_s = t - (time.perf_counter() - start)
+            if wait_s > 0:
+                time.sleep(wait_s)
+            q, qid = admitted[int(rng.integers(len(admitted)))]
+            e = min(epochs - 1, int((arrival0 + t) // 10))
+            k, v = batches[q][e][int(rng.integers(per))]
+            srv.submit(qid, k, v, *outs[q])
+            count += 1
+            tuples += k.numel()
+        srv.wait()
+        st = srv.stats()
+        arrival0 += seconds
+        row = {"arrivals_per_s": lam, "requests": int(st["requests"]),
+               "p50_ms": round(st["p50_us"] / 1e3, 4), "p99_ms": round(st["p99_us"] / 1e3, 4),
+               "max_ms": round(st["max_us"] / 1e3, 4), "tuples_per_s": st["tuples_per_s"],
+               "mean_batch": round(tuples / max(1, count))}
+        rows.append(row)
+        print(json.dumps({"progress": {"serving": row}}), file=sys.stderr, flush=True)
+    # capacity: the same mix submitted as fast as the client can, for as
+    # many requests as the highest rate delivered
+    rng = np.random.default_rng([20130909, 82])
+    burst = max(1, rows[-1]["requests"]) if rows else 1000
+    srv.stats()
+    tuples = 0
+    for _ in range(burst):
+        q, qid = admitted[int(rng.integers(len(admitted)))]
+        k, v = batches[q][epochs - 1][int(rng.integers(per))]
+        srv.submit(qid, k, v, *outs[q])
+        tuples += k.numel()
+    srv.wait()
+    st = srv.stats()
+    sat = {"requests": int(st["requests"]), "p50_ms": round(st["p50_us"] / 1e3, 4),
+           "p99_ms": round(st["p99_us"] / 1e3, 4), "tuples_per_s": st["tuples_per_s"],
+           "mean_batch": round(tuples / burst)}
+    print(json.dumps({"progress": {"serving_saturated": sat}}), file=sys.stderr, flush=True)
+    srv.close()
+    return {"queries": nq, "admitted": len(admitted), "rejected_by_footprint": rejected,
+            "bytes_held": int(held["bytes_held"]), "budget": int(held["budget"]),
+            "lanes": lanes, "slots_per_lane": slots, "seconds_per_rate": seconds,
+            "setup_s": round(setup_s, 2), "generation_s": round(gen_s, 2), "rates": rows,
+            "saturated": sat}
+
+
 def imbalance(torch, cq, batches, cfg, mode, warmup=3):
     """Per-CU busy time of the per-group phase on one batch (after `warmup`
     batches): the union of the device-clock intervals of the workgroups that
@@ -356,6 +450,9 @@ def main():
     ap.add_argument("--tech-steps", type=int, default=40)
     ap.add_argument("--tuple-passes", default="0,1,10",
                     help="passes of the per-tuple variant to time ('' skips it)")
+    ap.add_argument("--serving", default="10,50,100,250,500",
+                    help="arrival rates (batches/s) of the serving loop ('' skips it)")
+    ap.add_argument("--serving-seconds", type=float, default=3.0)
     ap.add_argument("--calibrate", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -446,6 +543,10 @@ def main():
     if args.techniques:
         tech = techniques(torch, cq, [float(x) for x in args.techniques.split(",")],
                           min(args.warmup, 5), args.tech_steps)
+    serve = None
+    if args.serving:
+        serve = serving(torch, cq, [float(x) for x in args.serving.split(",")],
+                        args.serving_seconds)
     cpu = cpu_mt = None
     if not args.no_cpu:
         done, t = cpu_baseline(host, cfg, args.cpu_budget)
@@ -485,6 +586,7 @@ def main():
         "sweep": rows,
         "techniques": tech,
         "per_tuple": pt,
+        "serving": serve,
     }
     print(json.dumps(out), flush=True)
 

@@ -292,7 +292,7 @@ typedef struct cq_server cq_server;
  * GPU memory).
  *   memory_budget : device bytes the resident queries may hold (0 = 80% of
  *                   the free device memory now);
- *   lanes         : HIP streams, default priority (0 = 4, at most
+ *   lanes         : HIP streams, default priority (0 = 8, at most
  *                   CQ_SERVER_MAX_LANES).  Each query is pinned to one lane,
  *                   so its batches run in submission order, while batches
  *                   of queries on other lanes overlap with them on the GPU;

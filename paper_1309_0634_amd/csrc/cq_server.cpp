@@ -9,16 +9,16 @@
 //   - lanes: a few HIP streams at the default priority.  Every query is
 //     pinned to one lane, so its batches run in submission order; batches
 //     of queries on different lanes overlap on the device;
-//   - continuous batching: a dispatcher thread starts waiting requests in
-//     arrival order as soon as their lane has a free slot (at most `slots`
-//     requests in flight per lane), while the caller keeps submitting; a
-//     request whose query already has an earlier request waiting keeps its
-//     place behind it;
-//   - completion: the dispatcher polls one event per request and records
-//     its latency (host clock from submission to the moment its event is
-//     seen complete).
-// Each query object is only ever driven by the dispatcher thread; the
-// caller's threads touch the shared tables under one mutex.
+//   - continuous batching: one launcher thread per lane starts the lane's
+//     waiting requests in arrival order as soon as the lane has a free slot
+//     (at most `slots` requests in flight per lane), while the caller keeps
+//     submitting; lanes launch in parallel (the kernel launches happen
+//     outside the lock) and sleep when they have nothing to start;
+//   - completion: one reaper thread polls one event per request in flight
+//     and records its latency (host clock from submission to the moment
+//     its event is seen complete).
+// A query object is only ever driven by its lane's launcher; the caller's
+// threads touch the shared tables under one mutex.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -88,9 +88,12 @@ struct cq_server {
     Clock::time_point stat_first{}, stat_last{};
     bool stat_open = false;
     std::mutex mu;
-    std::condition_variable work, progress;
+    std::condition_variable work;      // lane threads: a request or a free slot
+    std::condition_variable launched;  // reaper: something is on the device
+    std::condition_variable progress;  // callers: a request finished
     bool stop = false;
-    std::thread dispatcher;
+    std::vector<std::thread> dispatchers;  // one launcher per lane
+    std::thread reaper;
 };
 
 namespace {
@@ -113,33 +116,47 @@ struct DeviceGuard {
     }
 };
 
-// Starts request r on its lane (called by the dispatcher, lock held).
-void launch(cq_server *s, Request &r) {
+// Starts request r on its lane.  Called by the lane's dispatcher with the
+// lock held; releases it around the launches, so lanes launch in parallel
+// and submissions are not held up.  The query cannot go away meanwhile
+// (removal waits for its pending requests).
+void launch(cq_server *s, std::unique_lock<std::mutex> &lk, Request r) {
     Entry &e = s->queries[r.qid];
     r.lane = e.lane;
+    cq_query *q = e.q;
     hipStream_t st = s->lanes[e.lane];
-    int rc = cq_push_batch_results(e.q, r.keys, r.values, r.n, r.ids, r.sums, r.counts, r.avgs,
-                                   r.n_touched, st);
-    if (rc == CQ_OK) {
-        if (!s->spare_events.empty()) {
-            r.done = s->spare_events.back();
-            s->spare_events.pop_back();
-        } else if (hipEventCreateWithFlags(&r.done, hipEventDisableTiming) != hipSuccess) {
-            r.done = nullptr;
-            rc = CQ_ERR_HIP;
-        }
-        if (rc == CQ_OK && hipEventRecord(r.done, st) != hipSuccess) rc = CQ_ERR_HIP;
+    hipEvent_t ev = nullptr;
+    if (!s->spare_events.empty()) {
+        ev = s->spare_events.back();
+        s->spare_events.pop_back();
     }
+    s->inflight_per_lane[r.lane] += 1;
+    s->inflight.push_back(r);  // listed (without an event yet) while it launches
+    lk.unlock();
+    int rc = CQ_OK;
+    if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        ev = nullptr;
+        rc = CQ_ERR_HIP;
+    }
+    if (rc == CQ_OK)
+        rc = cq_push_batch_results(q, r.keys, r.values, r.n, r.ids, r.sums, r.counts, r.avgs,
+                                   r.n_touched, st);
+    if (rc == CQ_OK && hipEventRecord(ev, st) != hipSuccess) rc = CQ_ERR_HIP;
+    lk.lock();
+    size_t i = 0;
+    while (s->inflight[i].ticket != r.ticket) ++i;
     if (rc != CQ_OK) {  // finished at once, with the error
-        if (r.done) s->spare_events.push_back(r.done);
-        r.done = nullptr;
+        if (ev) s->spare_events.push_back(ev);
         s->finished[r.ticket] = {rc, 0.0};
-        e.pending -= 1;
+        s->inflight_per_lane[r.lane] -= 1;
+        s->queries[r.qid].pending -= 1;
+        s->inflight[i] = s->inflight.back();
+        s->inflight.pop_back();
         s->progress.notify_all();
         return;
     }
-    s->inflight_per_lane[e.lane] += 1;
-    s->inflight.push_back(r);
+    s->inflight[i].done = ev;
+    s->launched.notify_one();
 }
 
 // Retires every in-flight request whose event has completed (lock held).
@@ -147,6 +164,10 @@ bool reap(cq_server *s) {
     bool any = false;
     for (size_t i = 0; i < s->inflight.size();) {
         Request &r = s->inflight[i];
+        if (!r.done) {  // still launching
+            ++i;
+            continue;
+        }
         const hipError_t q = hipEventQuery(r.done);
         if (q == hipErrorNotReady) {
             ++i;
@@ -168,44 +189,60 @@ bool reap(cq_server *s) {
         s->inflight.pop_back();
         any = true;
     }
-    if (any) s->progress.notify_all();
-    return any;
-}
-
-// Starts waiting requests in arrival order while their lanes have room; a
-// query's later request never passes its earlier one (lock held).
-bool admit(cq_server *s) {
-    bool any = false;
-    std::vector<int32_t> blocked;  // queries with an earlier request still waiting
-    for (auto it = s->waiting.begin(); it != s->waiting.end();) {
-        const int32_t qid = it->qid;
-        const int lane = s->queries[qid].lane;
-        if (std::find(blocked.begin(), blocked.end(), qid) != blocked.end() ||
-            s->inflight_per_lane[lane] >= s->slots) {
-            blocked.push_back(qid);
-            ++it;
-            continue;
-        }
-        Request r = *it;
-        it = s->waiting.erase(it);
-        launch(s, r);
-        any = true;
+    if (any) {
+        s->progress.notify_all();
+        s->work.notify_all();  // slots are free again
     }
     return any;
 }
 
-void dispatch_loop(cq_server *s) {
+// Starts the oldest waiting request of `lane` if the lane has a free slot
+// and no earlier request of the same query is still waiting (lock held;
+// released around the launch).  Returns whether one was started.
+bool admit_one(cq_server *s, std::unique_lock<std::mutex> &lk, int lane) {
+    if (s->inflight_per_lane[lane] >= s->slots) return false;
+    for (auto it = s->waiting.begin(); it != s->waiting.end(); ++it) {
+        if (s->queries[it->qid].lane != lane) continue;
+        // requests of one query sit on one lane in arrival order, so the
+        // first one of this lane is never behind another of its query
+        Request r = *it;
+        s->waiting.erase(it);
+        launch(s, lk, r);
+        return true;
+    }
+    return false;
+}
+
+bool lane_idle(const cq_server *s, int lane) {
+    if (s->inflight_per_lane[lane] > 0) return false;
+    for (const Request &r : s->waiting)
+        if (s->queries.at(r.qid).lane == lane) return false;
+    return true;
+}
+
+// A lane's launcher: starts its lane's requests, sleeps when there is
+// nothing to start.
+void lane_loop(cq_server *s, int lane) {
     (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
     while (true) {
-        const bool reaped = reap(s);
-        const bool started = admit(s);
+        if (admit_one(s, lk, lane)) continue;
+        if (s->stop && lane_idle(s, lane)) break;
+        s->work.wait(lk);
+    }
+}
+
+// The reaper: polls the events of everything on the device (one thread
+// spins, and only while something is in flight).
+void reap_loop(cq_server *s) {
+    (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        if (reap(s)) continue;
         if (s->stop && s->waiting.empty() && s->inflight.empty()) break;
-        if (reaped || started) continue;
         if (s->inflight.empty()) {
-            s->work.wait(lk);  // nothing on the device: sleep until a submission
+            s->launched.wait(lk);
         } else {
-            // requests on the device: poll their events again shortly
             lk.unlock();
             std::this_thread::yield();
             lk.lock();
@@ -238,7 +275,7 @@ int cq_server_create(int64_t memory_budget, int32_t lanes, int32_t slots, cq_ser
         memory_budget = (int64_t)(0.8 * (double)free_b);
     }
     s->budget = memory_budget;
-    s->nlanes = lanes ? lanes : 4;
+    s->nlanes = lanes ? lanes : 8;
     s->slots = slots ? slots : 2;
     s->inflight_per_lane.assign(s->nlanes, 0);
     for (int i = 0; i < s->nlanes; ++i) {
@@ -251,7 +288,8 @@ int cq_server_create(int64_t memory_budget, int32_t lanes, int32_t slots, cq_ser
         }
         s->lanes.push_back(st);
     }
-    s->dispatcher = std::thread(dispatch_loop, s);
+    for (int i = 0; i < s->nlanes; ++i) s->dispatchers.emplace_back(lane_loop, s, i);
+    s->reaper = std::thread(reap_loop, s);
     *out = s;
     return CQ_OK;
 }
@@ -327,7 +365,7 @@ int cq_server_submit(cq_server *s, int32_t qid, const int32_t *keys, const int32
     it->second.pending += 1;
     s->waiting.push_back(r);
     *ticket = r.ticket;
-    s->work.notify_one();
+    s->work.notify_all();
     return CQ_OK;
 }
 
@@ -384,9 +422,12 @@ int cq_server_destroy(cq_server *s) {
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->stop = true;
-        s->work.notify_one();
+        s->work.notify_all();
+        s->launched.notify_all();
     }
-    if (s->dispatcher.joinable()) s->dispatcher.join();  // drains every request first
+    for (std::thread &t : s->dispatchers)
+        if (t.joinable()) t.join();  // each drains its lane first
+    if (s->reaper.joinable()) s->reaper.join();
     DeviceGuard guard(s->device);
     int rc = CQ_OK;
     for (auto &kv : s->queries) {

@@ -209,6 +209,60 @@ class DeviceStream:
         return keys.contiguous(), values.contiguous()
 
 
+# --------------------------------------------------------------------------
+# serving mix: many resident queries, batches of varying size
+# --------------------------------------------------------------------------
+
+SERVING_ID = 5
+
+
+def serving_queries(count: int = 256) -> list:
+    """(groups, window) of `count` resident queries: both log-uniform,
+    groups in [100, 1e6] and windows in [10, 1e4] (rint(exp(U)))."""
+    rng = _rng(ROOT_SEED, SERVING_ID, 1)
+    g = np.rint(np.exp(rng.uniform(np.log(100), np.log(1e6), count))).astype(np.int64)
+    w = np.rint(np.exp(rng.uniform(np.log(10), np.log(1e4), count))).astype(np.int64)
+    return [(int(a), int(b)) for a, b in zip(g, w)]
+
+
+def serving_sizes(count: int, seed: int) -> np.ndarray:
+    """Batch sizes: lognormal with median 65,536 and sigma 1, clipped to
+    [1,024, 4,194,304]."""
+    rng = _rng(ROOT_SEED, SERVING_ID, 2, seed)
+    n = np.rint(np.exp(rng.normal(np.log(65536), 1.0, count)))
+    return np.clip(n, 1024, 1 << 22).astype(np.int64)
+
+
+class ServingBatches:
+    """Device batches of query q (groups G): Zipf s=1.5 keys over G ranks
+    whose hot set (the rank -> id permutation) is redrawn per epoch, values
+    uniform in [0, 1e6)."""
+
+    def __init__(self, device, zipf_s: float = 1.5):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.s = zipf_s
+        self.gen = torch.Generator(device=self.device)
+
+    def batch(self, q: int, groups: int, epoch: int, i: int, n: int):
+        torch = self.torch
+        ss = np.random.SeedSequence([ROOT_SEED, SERVING_ID, 3, q, epoch, i])
+        self.gen.manual_seed(int(ss.generate_state(1, dtype=np.uint64)[0] & ((1 << 63) - 1)))
+        r = torch.arange(1, groups + 1, device=self.device, dtype=torch.float64)
+        cdf = torch.cumsum(r.pow(-self.s), 0)
+        cdf /= cdf[-1].clone()
+        u = torch.rand(n, generator=self.gen, device=self.device, dtype=torch.float64)
+        rank = torch.searchsorted(cdf, u, right=True).clamp_(max=groups - 1)
+        pss = np.random.SeedSequence([ROOT_SEED, SERVING_ID, 4, q, epoch])
+        self.gen.manual_seed(int(pss.generate_state(1, dtype=np.uint64)[0] & ((1 << 63) - 1)))
+        perm = torch.randperm(groups, generator=self.gen, device=self.device).to(torch.int32)
+        keys = perm[rank].contiguous()
+        values = torch.randint(0, VALUE_HI, (n,), generator=self.gen, device=self.device,
+                               dtype=torch.int32)
+        return keys, values
+
+
 def probe_batch(groups: int) -> Tuple[np.ndarray, np.ndarray]:
     """One (g, 0) tuple for every group g, in ascending g."""
     return np.arange(groups, dtype=np.int32), np.zeros(groups, dtype=np.int32)
