@@ -126,6 +126,15 @@ int cq_reserve(cq_query *q, int64_t max_batch);
 int cq_set_partition(cq_query *q, int32_t mode, int32_t workers);
 
 /*
+ * cq_set_key_mod -- on = 1: the query takes each key as (uint32_t)key mod
+ * groups, so one input stream can feed queries with different group
+ * counts (a key never falls outside the range); on = 0 (the default): keys
+ * are used as given and a key outside [0, groups) rejects its batch.
+ * Takes effect at the next push.  Returns CQ_OK or CQ_ERR_INVALID.
+ */
+int cq_set_key_mod(cq_query *q, int32_t on);
+
+/*
  * cq_set_policy_params -- parameters of the Section 4 techniques: the
  * imbalance threshold in tuples (the paper's threadThreshold, default
  * 1000) and probCheck's pot (0 < pot <= 1, default 0.5; Section 5.1).
@@ -270,6 +279,61 @@ int cq_destroy(cq_query *q);
 
 /* Static description of a status code. */
 const char *cq_strerror(int code);
+
+/* ------------------- many queries over one stream --------------------- */
+
+/* Number of groups of a query (CQ_OK or CQ_ERR_INVALID). */
+int cq_query_groups(const cq_query *q, int64_t *groups);
+
+typedef struct cq_multi cq_multi;
+
+#define CQ_MULTI_MAX_LANES 16
+
+/*
+ * cq_multi_create -- a set of `count` queries that all take the same input
+ * batches (give them cq_set_key_mod when their group counts differ).  The
+ * queries are spread over `lanes` HIP streams of their own (0 = 8, at most
+ * CQ_MULTI_MAX_LANES, default priority), forked from and joined back into
+ * the caller's stream by events: queries on different lanes overlap on the
+ * device, each query's batches stay in order.  The set does not own the
+ * queries (destroy them after the set).  Returns CQ_OK, CQ_ERR_INVALID,
+ * CQ_ERR_OOM or CQ_ERR_HIP.
+ */
+int cq_multi_create(cq_query *const *queries, int32_t count, int32_t lanes, cq_multi **out);
+
+/*
+ * cq_multi_push -- apply one batch (device keys, values; n tuples) to every
+ * query of the set, stream-ordered on `stream` (NULL = default stream): work
+ * enqueued on `stream` afterwards, e.g. cq_results of any query, sees every
+ * query updated.  During a tuning window the call also waits for the batch
+ * on the host.  Returns CQ_OK, CQ_ERR_INVALID or CQ_ERR_HIP (a bad key
+ * rejects that query's batch as in cq_push_batch).
+ */
+int cq_multi_push(cq_multi *m, const int32_t *keys, const int32_t *values, int64_t n,
+                  void *stream);
+
+/*
+ * cq_multi_tune -- open a tuning window over the next pushes: every query
+ * runs each of its candidate partitions (balanced; static with 1024 and with
+ * 4096 workers where a worker would own at most 2048 groups) for `reps`
+ * consecutive batches (1..64), timed on its lane; at the end of the window
+ * each query keeps its fastest candidate (median) and the queries are
+ * re-spread over the lanes longest first onto the least loaded lane.
+ * Results are identical under every candidate.  Returns CQ_OK,
+ * CQ_ERR_INVALID or CQ_ERR_HIP.
+ */
+int cq_multi_tune(cq_multi *m, int32_t reps);
+
+/*
+ * cq_multi_plan -- per query (host arrays of count entries, any may be
+ * NULL): chosen partition mode and workers (-1 before a tuning window has
+ * ended), lane, and the chosen candidate's median time in milliseconds
+ * (-1 before tuning).  Returns CQ_OK or CQ_ERR_INVALID.
+ */
+int cq_multi_plan(cq_multi *m, int32_t *modes, int32_t *workers, int32_t *lanes, float *ms);
+
+/* Waits for the set's lanes and frees them (not the queries). */
+int cq_multi_destroy(cq_multi *m);
 
 /* ------------------------------ serving ------------------------------- */
 

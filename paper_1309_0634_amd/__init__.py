@@ -72,6 +72,13 @@ def lib() -> ctypes.CDLL:
             "cq_push_batch_tuples": ([P, P, P, i64, i32, P, P, P, P], ctypes.c_int),
             "cq_set_policy_params": ([P, i64, ctypes.c_double], ctypes.c_int),
             "cq_query_footprint": ([i64, i32], i64),
+            "cq_query_groups": ([P, pi64], ctypes.c_int),
+            "cq_set_key_mod": ([P, i32], ctypes.c_int),
+            "cq_multi_create": ([P, i32, i32, ctypes.POINTER(P)], ctypes.c_int),
+            "cq_multi_push": ([P, P, P, i64, P], ctypes.c_int),
+            "cq_multi_tune": ([P, i32], ctypes.c_int),
+            "cq_multi_plan": ([P, P, P, P, P], ctypes.c_int),
+            "cq_multi_destroy": ([P], ctypes.c_int),
             "cq_server_create": ([i64, i32, i32, ctypes.POINTER(P)], ctypes.c_int),
             "cq_server_add_query": ([P, i64, i32, u32, ctypes.POINTER(i32)], ctypes.c_int),
             "cq_server_remove_query": ([P, i32], ctypes.c_int),
@@ -172,6 +179,10 @@ class Query:
     # -- configuration -----------------------------------------------------
     def set_partition(self, mode: int, workers: int = 0):
         _check(lib().cq_set_partition(self._h, int(mode), int(workers)), "cq_set_partition")
+
+    def set_key_mod(self, on: bool = True):
+        """Take every key as (uint32)key mod groups (cq_set_key_mod)."""
+        _check(lib().cq_set_key_mod(self._h, int(bool(on))), "cq_set_key_mod")
 
     def set_policy_params(self, threshold: int = 1000, pot: float = 0.5):
         _check(lib().cq_set_policy_params(self._h, int(threshold), float(pot)),
@@ -415,3 +426,49 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Multi:
+    """Queries that share one input stream (cq_multi_*), spread over lanes,
+    with an online autotuner.  Keeps the Query objects alive."""
+
+    def __init__(self, queries, lanes: int = 0):
+        self.queries = list(queries)
+        arr = (ctypes.c_void_p * len(self.queries))(*[q._h.value for q in self.queries])
+        h = ctypes.c_void_p()
+        _check(lib().cq_multi_create(arr, len(self.queries), int(lanes), ctypes.byref(h)),
+               "cq_multi_create")
+        self._h = h
+
+    def push(self, keys, values, stream=None):
+        n = keys.numel()
+        if values.numel() != n:
+            raise ValueError("keys and values differ in length")
+        _check(lib().cq_multi_push(self._h, _dptr(keys) if n else None,
+                                   _dptr(values) if n else None, int(n),
+                                   _stream_handle(stream)), "cq_multi_push")
+        for q in self.queries:
+            q.last_n = int(n)
+
+    def tune(self, reps: int = 2):
+        _check(lib().cq_multi_tune(self._h, int(reps)), "cq_multi_tune")
+
+    def plan(self):
+        k = len(self.queries)
+        modes, workers, lanes = ((ctypes.c_int32 * k)() for _ in range(3))
+        ms = (ctypes.c_float * k)()
+        _check(lib().cq_multi_plan(self._h, modes, workers, lanes, ms), "cq_multi_plan")
+        return [{"mode": modes[i], "workers": workers[i], "lane": lanes[i], "ms": ms[i]}
+                for i in range(k)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            rc = lib().cq_multi_destroy(self._h)
+            self._h = None
+            _check(rc, "cq_multi_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass

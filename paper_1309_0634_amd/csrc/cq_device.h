@@ -112,6 +112,17 @@ __device__ long long block_sum_ll(long long v, long long *lds) {
     return t;
 }
 
+// A key as the query sees it: the raw key, or, when the query reduces keys
+// (m != 0), the unsigned value of the raw key mod G, without a division:
+// for M = floor((2^64 - 1) / G) + 1, a mod G is the high 64 bits of
+// (M * a mod 2^64) * G for every 32-bit a (Lemire, Kaser and Kurz, "Faster
+// remainder by direct computation", 2019).  G = 1 uses M = 1.
+__device__ __forceinline__ int32_t view_key(int32_t raw, uint64_t m, int64_t G) {
+    if (!m) return raw;
+    const uint64_t low = m * (uint64_t)(uint32_t)raw;
+    return (int32_t)__umul64hi(low, (uint64_t)G);
+}
+
 // Largest r in [0, m) with pre[r] <= p (pre ascending, pre[0] = 0 <= p).
 __device__ __forceinline__ int upper_run(const int32_t *pre, int m, int p) {
     int lo = 0, hi = m - 1;

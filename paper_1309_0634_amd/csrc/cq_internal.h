@@ -127,6 +127,9 @@ struct Scratch {
     const int32_t *wstart;  // workers + 1: each worker's first list entry
     const int32_t *wlist;   // G: groups in worker-list order
     const int32_t *lidx;    // G: position of each group in its worker's list
+    // keys reduced mod G (0: keys used as given): the multiplier of the
+    // division-free remainder, floor((2^64 - 1) / G) + 1 (1 for G = 1)
+    uint64_t kmod;
     // per-tuple results only (null otherwise)
     int32_t *sidx;      // SUB: arrival index of each staged tuple
     int32_t *pcnt;      // G: window count of each touched group before the sub-batch

@@ -255,6 +255,10 @@ __global__ __launch_bounds__(HIST_THREADS) void k_hist_small(const int32_t *__re
             for (int e = 0; e < 4; ++e) v[4 * j + e] = (i + e < n) ? keys[i + e] : 0;
         }
     }
+    if (sc.kmod) {
+#pragma unroll
+        for (int j = 0; j < HIST_KPT; ++j) v[j] = view_key(v[j], sc.kmod, G);
+    }
     __syncthreads();
     int bad = 0, c0 = 0, c1 = 0;
 #pragma unroll
@@ -429,7 +433,7 @@ __global__ __launch_bounds__(HIST_THREADS) void k_hist_hash(const int32_t *__res
     const int64_t b1 = min(n, b0 + HIST_HASH_TILE);
     int bad = 0;
     for (int64_t i = b0 + tid; i < b1; i += HIST_THREADS) {
-        const int32_t key = keys[i];
+        const int32_t key = view_key(keys[i], sc.kmod, G);
         if (key < 0 || (int64_t)key >= G) bad = 1;
         else atomicAdd(&hc[hash_slot(hk, key)], 1);
     }
@@ -496,7 +500,7 @@ __global__ void k_validate(const int32_t *__restrict__ keys, int64_t n, int64_t 
     int bad = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t key = keys[i];
+        const int32_t key = view_key(keys[i], sc.kmod, G);
         if (key < 0 || (int64_t)key >= G) bad = 1;
     }
     if (__syncthreads_or(bad) && threadIdx.x == 0) atomicExch(sc.bad, seq);
@@ -740,7 +744,7 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(const int32_t *__restrict
     for (int r = 0; r < PASS_ROUNDS; ++r) {
         const int64_t i = base + wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane;
         const bool valid = i < n;
-        key[r] = valid ? keys[i] : 0;
+        key[r] = valid ? view_key(keys[i], sc.kmod, st.G) : 0;
         val[r] = valid ? values[i] : 0;
     }
     int NB;
@@ -1179,6 +1183,10 @@ __device__ void fused_hist(const NextHist &h, int hb, int nhb, int32_t G, uint32
 #pragma unroll
             for (int e = 0; e < 4; ++e) v[4 * j + e] = (i + e < h.n) ? h.keys[i + e] : 0;
         }
+    }
+    if (h.sc.kmod) {
+#pragma unroll
+        for (int j = 0; j < FH_KPT; ++j) v[j] = view_key(v[j], h.sc.kmod, G);
     }
     __syncthreads();
     int bad = 0, c0 = 0, c1 = 0;

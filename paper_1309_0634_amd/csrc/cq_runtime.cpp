@@ -52,6 +52,7 @@ struct cq_query {
     hipEvent_t ev_counts = nullptr, ev_map = nullptr;
     bool map_pending = false;     // an upload from h_map may still be running
     int64_t policy_total = 0;     // groups moved since the technique was selected
+    uint64_t kmod = 0;            // keys reduced mod groups (multiplier; 0 = off)
     // per-tuple results: arrival index of each staged tuple, count before
     // the sub-batch (allocated by the first per-tuple push)
     int32_t *pt_sidx = nullptr, *pt_pcnt = nullptr;
@@ -234,6 +235,7 @@ Scratch set_of(const cq_query *q, int i) {
     b.hot = q->sc.hot;
     b.trace = (q->telemetry & CQ_TELEMETRY_WORKERS) ? q->sc.trace : nullptr;
     b.phase = (q->telemetry & CQ_TELEMETRY_PHASES) ? q->sc.phase : nullptr;
+    b.kmod = q->kmod;
     const bool mapped = q->mode == MODE_STATIC && q->policy;
     b.owner = mapped ? q->m_owner : nullptr;
     b.wstart = mapped ? q->m_wstart : nullptr;
@@ -539,6 +541,19 @@ int cq_set_partition(cq_query *q, int32_t mode, int32_t workers) {
     q->policy = technique ? mode : 0;
     q->mode = mode == CQ_PARTITION_BALANCED ? MODE_BALANCED : MODE_STATIC;
     q->workers = w;
+    return CQ_OK;
+}
+
+int cq_query_groups(const cq_query *q, int64_t *groups) {
+    if (!q || !groups) return CQ_ERR_INVALID;
+    *groups = q->st.G;
+    return CQ_OK;
+}
+
+int cq_set_key_mod(cq_query *q, int32_t on) {
+    if (!q || (on != 0 && on != 1)) return CQ_ERR_INVALID;
+    const uint64_t G = (uint64_t)q->st.G;
+    q->kmod = on ? (G == 1 ? 1 : UINT64_MAX / G + 1) : 0;
     return CQ_OK;
 }
 

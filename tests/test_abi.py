@@ -73,6 +73,13 @@ def test_null_handles_are_rejected(L):
     assert L.cq_server_stats(None, None) == cq.ERR_INVALID
     assert L.cq_server_create(-1, 0, 0, None) == cq.ERR_INVALID
     assert L.cq_server_destroy(None) == cq.OK
+    assert L.cq_set_key_mod(None, 1) == cq.ERR_INVALID
+    assert L.cq_query_groups(None, None) == cq.ERR_INVALID
+    assert L.cq_multi_create(None, 1, 0, None) == cq.ERR_INVALID
+    assert L.cq_multi_push(None, None, None, 0, None) == cq.ERR_INVALID
+    assert L.cq_multi_tune(None, 2) == cq.ERR_INVALID
+    assert L.cq_multi_plan(None, None, None, None, None) == cq.ERR_INVALID
+    assert L.cq_multi_destroy(None) == cq.OK
     assert L.cq_destroy(None) == cq.OK
 
 
@@ -114,3 +121,20 @@ def test_query_footprint(L):
     assert f(10_000, 1000) - base <= 4 * 10_000 * 999 + 2 * 4096
     assert f(1_000_000, 100) > f(100_000, 100) > f(10_000, 100)
     assert all(f(g, w) % 4096 == 0 for g, w in [(1, 1), (777, 13), (123_457, 99)])
+
+
+def test_division_free_remainder():
+    """The kernels reduce a key mod G without dividing: with
+    M = floor((2^64-1)/G) + 1 (M = 1 for G = 1), (uint32)a mod G is the high
+    64 bits of (M*a mod 2^64)*G.  Checked here against % (the identity the
+    device code relies on), at the edges and on random 32-bit values."""
+    import random
+    m64 = (1 << 64) - 1
+    rnd = random.Random(5)
+    for G in [1, 2, 3, 7, 100, 9999, 10000, 16384, 65537, 1 << 20, 1_000_000,
+              (1 << 31) - 2, (1 << 31) - 1]:
+        M = 1 if G == 1 else m64 // G + 1
+        for a in [0, 1, G - 1, G, 2 * G - 1, (1 << 31) - 1, 1 << 31, (1 << 32) - 1] + \
+                [rnd.getrandbits(32) for _ in range(3000)]:
+            a &= (1 << 32) - 1
+            assert ((((M * a) & m64) * G) >> 64) == a % G, (a, G)
