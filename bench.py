@@ -305,6 +305,65 @@ def serving(torch, cq, lambdas, seconds, lanes=8, slots=2, nq=256):
             "saturated": sat}
 
 
+def multi(torch, cq, nq=64, warmup=2, steps=6, lanes=8, reps=2):
+    """The multi-query set (cq_multi_*): `nq` queries (groups and windows
+    log-uniform) share 4,194,304-tuple Zipf s=1.0 batches, each taking key
+    mod its group count.  Timed: every query on one lane, the queries spread
+    over `lanes` lanes, and the same after the autotuner's window."""
+    from workloads import DeviceStream, multi_queries, multi_stream
+    dev = torch.device("cuda", 0)
+    torch.cuda.empty_cache()
+    spec = multi_queries(nq)
+    ncand = 3
+    total = warmup + 3 * steps + ncand * reps
+    cfg = multi_stream(batches=total)
+    ds = DeviceStream(cfg, dev)
+    batches = [ds.batch(b) for b in range(total)]
+    qs = []
+    for G, W in spec:
+        q = cq.Query(G, W)
+        q.set_key_mod(True)
+        qs.append(q)
+    ring_bytes = sum(4 * G * W for G, W in spec)
+    it = iter(batches)
+
+    def timed(m, k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            m.push(*next(it))
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    rows = {}
+    m1 = cq.Multi(qs, 1)
+    for _ in range(warmup):
+        m1.push(*next(it))
+    rows["one_lane"] = timed(m1, steps)
+    m1.close()
+    m = cq.Multi(qs, lanes)
+    rows[f"{lanes}_lanes"] = timed(m, steps)
+    m.tune(reps)
+    for _ in range(ncand * reps):
+        m.push(*next(it))
+    rows[f"{lanes}_lanes_tuned"] = timed(m, steps)
+    plan = m.plan()
+    m.close()
+    for q in qs:
+        q.close()
+    out = {"queries": nq, "batch": cfg.batch, "ring_bytes": ring_bytes, "lanes": lanes,
+           "timed_batches": steps}
+    for k, sec in rows.items():
+        out[k] = {"ms_per_batch": round(1e3 * sec, 3), "input_tuples_per_s": cfg.batch / sec,
+                  "query_tuples_per_s": nq * cfg.batch / sec}
+    out["tuned_modes"] = {
+        "balanced": sum(p["mode"] == cq.PARTITION_BALANCED for p in plan),
+        "static_1024": sum(p["mode"] == cq.PARTITION_STATIC and p["workers"] == 1024 for p in plan),
+        "static_4096": sum(p["mode"] == cq.PARTITION_STATIC and p["workers"] == 4096 for p in plan)}
+    print(json.dumps({"progress": {"multi": out}}), file=sys.stderr, flush=True)
+    return out
+
+
 def imbalance(torch, cq, batches, cfg, mode, warmup=3):
     """Per-CU busy time of the per-group phase on one batch (after `warmup`
     batches): the union of the device-clock intervals of the workgroups that
@@ -450,6 +509,8 @@ def main():
     ap.add_argument("--tech-steps", type=int, default=40)
     ap.add_argument("--tuple-passes", default="0,1,10",
                     help="passes of the per-tuple variant to time ('' skips it)")
+    ap.add_argument("--multi", type=int, default=64,
+                    help="queries of the multi-query set (0 skips it)")
     ap.add_argument("--serving", default="10,50,100,250,500",
                     help="arrival rates (batches/s) of the serving loop ('' skips it)")
     ap.add_argument("--serving-seconds", type=float, default=3.0)
@@ -543,6 +604,7 @@ def main():
     if args.techniques:
         tech = techniques(torch, cq, [float(x) for x in args.techniques.split(",")],
                           min(args.warmup, 5), args.tech_steps)
+    mq = multi(torch, cq, args.multi) if args.multi else None
     serve = None
     if args.serving:
         serve = serving(torch, cq, [float(x) for x in args.serving.split(",")],
@@ -586,6 +648,7 @@ def main():
         "sweep": rows,
         "techniques": tech,
         "per_tuple": pt,
+        "multi_query": mq,
         "serving": serve,
     }
     print(json.dumps(out), flush=True)

@@ -209,6 +209,23 @@ class DeviceStream:
         return keys.contiguous(), values.contiguous()
 
 
+def multi_stream(batches: int = 100) -> StreamConfig:
+    """The shared input of the multi-query set: 4,194,304-tuple batches of
+    Zipf s=1.0 keys over [0, 2^20) with permuted hot ranks, values uniform
+    in [0, 1e6).  Each query takes key mod its own group count."""
+    return StreamConfig("multi_k1m_n4m_s1.0", 4, 1 << 20, 1, 1 << 22, batches, "zipf",
+                        zipf_s=1.0, permuted=True, s_index=0)
+
+
+def multi_queries(count: int = 64) -> list:
+    """(groups, window) of the multi-query set: groups log-uniform in
+    [100, 1e6], windows log-uniform in [10, 1e4] (rint(exp(U)))."""
+    rng = _rng(ROOT_SEED, 4, 1)
+    g = np.rint(np.exp(rng.uniform(np.log(100), np.log(1e6), count))).astype(np.int64)
+    w = np.rint(np.exp(rng.uniform(np.log(10), np.log(1e4), count))).astype(np.int64)
+    return [(int(a), int(b)) for a, b in zip(g, w)]
+
+
 # --------------------------------------------------------------------------
 # serving mix: many resident queries, batches of varying size
 # --------------------------------------------------------------------------
