@@ -305,6 +305,52 @@ def serving(torch, cq, lambdas, seconds, lanes=8, slots=2, nq=256):
             "saturated": sat}
 
 
+def drifting_run(torch, cq, warmup, steps):
+    """The large stream: 1,048,576 groups, W=100, 16,777,216-tuple Zipf
+    s=1.2 batches, hot permutation redrawn every 50 batches (the timed
+    batches straddle a redraw).  Balanced partition, push + emit, timed on
+    the device stream; algorithmic bytes per batch as for the headline."""
+    from workloads import DeviceStream, drifting
+    dev = torch.device("cuda", 0)
+    torch.cuda.empty_cache()
+    cfg = drifting(batches=60)
+    first = 50 - warmup - steps // 2  # so that the redraw at batch 50 is inside
+    ds = DeviceStream(cfg, dev)
+    idx = list(range(first, first + warmup + steps))
+    batches = [ds.batch(b) for b in idx]
+    torch.cuda.synchronize()
+    bytes_per = algorithmic_bytes(torch, [k for k, _ in batches], cfg.groups, cfg.window,
+                                  cfg.batch)
+    q = cq.Query(cfg.groups, cfg.window)
+    cap = min(cfg.groups, cfg.batch)
+    outs = (torch.empty(cap, dtype=torch.int32, device=dev),
+            torch.empty(cap, dtype=torch.int64, device=dev),
+            torch.empty(cap, dtype=torch.int32, device=dev),
+            torch.empty(cap, dtype=torch.float64, device=dev),
+            torch.empty(1, dtype=torch.int64, device=dev))
+    for b in range(warmup):
+        q.push_results_into(*batches[b], *outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in range(warmup, warmup + steps):
+        q.push_results_into(*batches[b], *outs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan = q.batch_plan()
+    q.close()
+    alg = sum(bytes_per[warmup:])
+    out = {"workload": cfg.name, "batches_timed": steps, "first_batch": idx[warmup],
+           "ms_per_batch": round(1e3 * wall / steps, 3),
+           "tuples_per_s": steps * cfg.batch / wall,
+           "alg_MB_per_batch": round(alg / steps / 1e6, 2),
+           "alg_GBps": alg / wall / 1e9, "alg_frac_of_hbm": round(alg / wall / 1e9 / HBM_PEAK_GBS, 4),
+           "heavy_groups_last": int(plan["heavy_groups"]), "touched_last": int(plan["touched"])}
+    print(json.dumps({"progress": {"drifting": out}}), file=sys.stderr, flush=True)
+    del batches
+    torch.cuda.empty_cache()
+    return out
+
+
 def multi(torch, cq, nq=64, warmup=2, steps=6, lanes=8, reps=2):
     """The multi-query set (cq_multi_*): `nq` queries (groups and windows
     log-uniform) share 4,194,304-tuple Zipf s=1.0 batches, each taking key
@@ -509,6 +555,8 @@ def main():
     ap.add_argument("--tech-steps", type=int, default=40)
     ap.add_argument("--tuple-passes", default="0,1,10",
                     help="passes of the per-tuple variant to time ('' skips it)")
+    ap.add_argument("--drift", type=int, default=6,
+                    help="timed batches of the large drifting stream (0 skips it)")
     ap.add_argument("--multi", type=int, default=64,
                     help="queries of the multi-query set (0 skips it)")
     ap.add_argument("--serving", default="10,50,100,250,500",
@@ -604,6 +652,7 @@ def main():
     if args.techniques:
         tech = techniques(torch, cq, [float(x) for x in args.techniques.split(",")],
                           min(args.warmup, 5), args.tech_steps)
+    drift = drifting_run(torch, cq, 2, args.drift) if args.drift else None
     mq = multi(torch, cq, args.multi) if args.multi else None
     serve = None
     if args.serving:
@@ -648,6 +697,7 @@ def main():
         "sweep": rows,
         "techniques": tech,
         "per_tuple": pt,
+        "drifting": drift,
         "multi_query": mq,
         "serving": serve,
     }

@@ -24,15 +24,15 @@ constexpr int HIST_THREADS = 1024;
 constexpr int HIST_KPT = 8;
 constexpr int HIST_TILE = HIST_THREADS * HIST_KPT;
 constexpr int HIST_DIRECT_MAX_G = 32768;
-constexpr int HIST_HASH_TILE = 8192;
-constexpr int HIST_HASH_LOG = 14;
+constexpr int HIST_HASH_TILE = 4096;   // 256 workgroups for a 2^20 sub-batch
+constexpr int HIST_HASH_LOG = 13;
 constexpr int HIST_HASH_SLOTS = 1 << HIST_HASH_LOG;
 static_assert(HIST_HASH_SLOTS >= 2 * HIST_HASH_TILE, "hash load factor <= 1/2");
 
 // Multi-block plan for G > HIST_DIRECT_MAX_G (scan over groups): PLAN_CHUNK
 // groups per block of PLAN_THREADS.
-constexpr int PLAN_THREADS = 1024;
-constexpr int PLAN_KPT = 32;
+constexpr int PLAN_THREADS = 256;
+constexpr int PLAN_KPT = 10;   // 2560 groups a block: 410 blocks for 2^20 groups
 constexpr int PLAN_CHUNK = PLAN_THREADS * PLAN_KPT;
 constexpr int PLAN_FIELDS = 3;   // light tuples, heavy groups, touched groups
 
