@@ -152,3 +152,53 @@ def test_rejected_batch_in_the_mix():
         else:
             assert_same(got, o.push(k, v), "mixed request")
     srv.close()
+
+
+def test_concurrent_submitters_and_churn():
+    """Four caller threads submit to their own queries at once while a fifth
+    adds and removes queries; every request equals the oracle."""
+    note("case: serving, concurrent submitters")
+    import threading
+    srv = cq.Server(0, 4, 2)
+    shapes = [(500, 20), (7000, 300), (30000, 64), (120000, 5)]
+    qids = [srv.add_query(G, W) for G, W in shapes]
+    rng = np.random.default_rng([20130909, 73])
+    work = [make_batches(np.random.default_rng([20130909, 74, i]), G, 10)
+            for i, (G, _) in enumerate(shapes)]
+    dev_w = [[(to_dev(k), to_dev(v)) for k, v in bs] for bs in work]
+    outs = [[outputs(G, len(k)) for k, _ in bs] for (G, _), bs in zip(shapes, work)]
+    errors = []
+
+    def submitter(i):
+        try:
+            for b, (k, v) in enumerate(dev_w[i]):
+                srv.submit(qids[i], k, v, *outs[i][b])
+        except Exception as e:  # noqa: BLE001 - reported below
+            errors.append(e)
+
+    def churn():
+        try:
+            for j in range(6):
+                q = srv.add_query(int(rng.integers(100, 5000)), int(rng.integers(1, 50)))
+                k = to_dev(np.zeros(10, np.int32))
+                srv.wait(srv.submit(q, k, k))
+                srv.remove_query(q)
+        except Exception as e:  # noqa: BLE001 - reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=submitter, args=(i,)) for i in range(len(shapes))]
+    threads.append(threading.Thread(target=churn))
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not errors, errors
+    srv.wait()
+    for i, (G, W) in enumerate(shapes):
+        o = RingOracle(G, W)
+        for b, (k, v) in enumerate(work[i]):
+            got = got_of(outs[i][b])
+            assert not isinstance(got, int), f"query {i} batch {b}: status {got}"
+            assert_same(got, o.push(k, v), f"concurrent query {i} batch {b}")
+        o.close()
+    srv.close()
