@@ -416,6 +416,7 @@ def imbalance(torch, cq, batches, cfg, mode, warmup=3):
     ran on each compute unit (XCC, shader engine, array, CU from the HW_ID
     register), over the CUs that did work.  Also the per-workgroup tuple
     loads (the paper's per-worker tuple counts)."""
+    warmup = max(0, min(warmup, len(batches) - 1))
     q = cq.Query(cfg.groups, cfg.window, partition=mode)
     for b in range(warmup):
         q.push(*batches[b])
