@@ -567,9 +567,9 @@ def main():
                     help="first run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not "
-              "supported (the path would shard groups by owner across GPUs, see the "
-              "design notes)", file=sys.stderr)
+        print(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported "
+              "(on several GPUs the path would shard groups by owner and exchange each "
+              "group's last W tuples of a batch in one all-to-all)", file=sys.stderr)
         sys.exit(2)
 
     import torch

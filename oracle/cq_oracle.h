@@ -16,8 +16,7 @@
  *     pointer (nextPos in the paper) marks the slot of the oldest value;
  *   - the aggregate of a group is recomputed from scratch over its window.
  *
- * Readings where the paper is silent (each one is listed with its reason in
- * the design notes of the repository):
+ * Readings where the paper is silent:
  *   - tuples of a batch are applied in array order (arrival order);
  *   - results are emitted once per batch, for every group the batch touched,
  *     in ascending group id, with the value after the group's last tuple
