@@ -138,3 +138,14 @@ def test_division_free_remainder():
                 [rnd.getrandbits(32) for _ in range(3000)]:
             a &= (1 << 32) - 1
             assert ((((M * a) & m64) * G) >> 64) == a % G, (a, G)
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU; asking for more exits with a message
+    before anything touches a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
