@@ -355,13 +355,14 @@ def multi(torch, cq, nq=64, warmup=2, steps=6, lanes=8, reps=2):
     """The multi-query set (cq_multi_*): `nq` queries (groups and windows
     log-uniform) share 4,194,304-tuple Zipf s=1.0 batches, each taking key
     mod its group count.  Timed: every query on one lane, the queries spread
-    over `lanes` lanes, and the same after the autotuner's window."""
+    over `lanes` lanes, the same after the autotuner's window, and that set
+    replayed as one captured HIP graph per batch."""
     from workloads import DeviceStream, multi_queries, multi_stream
     dev = torch.device("cuda", 0)
     torch.cuda.empty_cache()
     spec = multi_queries(nq)
     ncand = 3
-    total = warmup + 3 * steps + ncand * reps
+    total = warmup + 4 * steps + ncand * reps + 1
     cfg = multi_stream(batches=total)
     ds = DeviceStream(cfg, dev)
     batches = [ds.batch(b) for b in range(total)]
@@ -393,6 +394,9 @@ def multi(torch, cq, nq=64, warmup=2, steps=6, lanes=8, reps=2):
     for _ in range(ncand * reps):
         m.push(*next(it))
     rows[f"{lanes}_lanes_tuned"] = timed(m, steps)
+    m.set_graph(True)
+    m.push(*next(it))  # captures this batch size's graph
+    rows[f"{lanes}_lanes_tuned_graph"] = timed(m, steps)
     plan = m.plan()
     m.close()
     for q in qs:

@@ -332,6 +332,19 @@ int cq_multi_tune(cq_multi *m, int32_t reps);
  */
 int cq_multi_plan(cq_multi *m, int32_t *modes, int32_t *workers, int32_t *lanes, float *ms);
 
+/*
+ * cq_multi_set_graph -- on = 1: outside tuning windows, each push copies the
+ * batch into staging buffers of the set and replays the set's whole
+ * per-batch launch sequence (every query, every lane, fork and join) as one
+ * HIP graph, captured on the first push of each batch size; on = 0: eager
+ * pushes again.  The queries must have telemetry off and no Section 4
+ * technique; their results and state are the same either way, and
+ * cq_push_batch on a query of the set keeps working in between.  A new
+ * tuning window or a larger batch drops the captured graphs.  Returns
+ * CQ_OK, CQ_ERR_INVALID or CQ_ERR_HIP.
+ */
+int cq_multi_set_graph(cq_multi *m, int32_t on);
+
 /* Waits for the set's lanes and frees them (not the queries). */
 int cq_multi_destroy(cq_multi *m);
 

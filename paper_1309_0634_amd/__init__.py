@@ -79,6 +79,7 @@ def lib() -> ctypes.CDLL:
             "cq_multi_tune": ([P, i32], ctypes.c_int),
             "cq_multi_plan": ([P, P, P, P, P], ctypes.c_int),
             "cq_multi_destroy": ([P], ctypes.c_int),
+            "cq_multi_set_graph": ([P, i32], ctypes.c_int),
             "cq_server_create": ([i64, i32, i32, ctypes.POINTER(P)], ctypes.c_int),
             "cq_server_add_query": ([P, i64, i32, u32, ctypes.POINTER(i32)], ctypes.c_int),
             "cq_server_remove_query": ([P, i32], ctypes.c_int),
@@ -449,6 +450,10 @@ class Multi:
                                    _stream_handle(stream)), "cq_multi_push")
         for q in self.queries:
             q.last_n = int(n)
+
+    def set_graph(self, on: bool = True):
+        """Replay each push as one captured HIP graph (cq_multi_set_graph)."""
+        _check(lib().cq_multi_set_graph(self._h, int(bool(on))), "cq_multi_set_graph")
 
     def tune(self, reps: int = 2):
         _check(lib().cq_multi_tune(self._h, int(reps)), "cq_multi_tune")

@@ -118,6 +118,8 @@ struct Scratch {
     // control
     int32_t *partials;  // plan block partials
     int32_t *bad;       // batch sequence number of the last batch with a bad key
+    int32_t *seqp;      // null, or (pushes captured into a graph) the device copy of
+                        // the batch sequence number, advanced by the push itself
     int32_t *fault;     // sticky internal-consistency bits
     int32_t *hot;       // [2] most frequent groups of the last planned sub-batch
     PlanTotals *tot;
@@ -207,7 +209,16 @@ hipError_t launch_tuples(State st, Scratch sc, int64_t n, PtOut out, hipStream_t
 hipError_t launch_collect_touched(int64_t G, int32_t seq, Scratch sc, hipStream_t s);
 hipError_t launch_emit(State st, Scratch sc, int64_t cap, Out out, hipStream_t s);
 hipError_t launch_reset_totals(Scratch sc, hipStream_t s);
+// Advances the device copy of the batch sequence number by one.
+hipError_t launch_bump_seq(Scratch sc, hipStream_t s);
+// Sets the device copy of the batch sequence number.
+hipError_t launch_set_seq(Scratch sc, int32_t v, hipStream_t s);
 hipError_t launch_set_touched(int64_t *n_touched, int64_t v, hipStream_t s);
+// Graph capture of pushes (multi-query sets): see cq_runtime.cpp.
+bool query_capturable(const cq_query *q);
+int query_set_graph(cq_query *q, bool on, hipStream_t s);
+void query_replayed(cq_query *q, int64_t n, hipStream_t s);
+void query_ran_on(cq_query *q, hipStream_t s);
 // Workgroups of the per-group phase (one trace record each).
 int64_t update_grid(int64_t n, int mode, int32_t workers);
 // Histogram workgroups launched by launch_hist for a sub-batch of n.

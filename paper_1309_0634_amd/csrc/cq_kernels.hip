@@ -235,6 +235,7 @@ __device__ void plan_publish(const State &st, const Scratch &sc, const int (&tot
 __global__ __launch_bounds__(HIST_THREADS) void k_hist_small(const int32_t *__restrict__ keys,
                                                              int64_t n, bool vec, int32_t G,
                                                              Scratch sc, int32_t seq) {
+    if (sc.seqp) seq = *sc.seqp;  // captured for replay: the argument would be stale
     extern __shared__ int32_t cntr[];
     const int tid = threadIdx.x;
     phase_mark(sc, PHASE_HIST_PLAN, 0);
@@ -309,6 +310,7 @@ constexpr int PS_UNROLL = 16;
 
 __global__ __launch_bounds__(PS_THREADS) void k_plan_small(State st, Scratch sc, int32_t seq,
                                                           int mode, int32_t workers) {
+    if (sc.seqp) seq = *sc.seqp;  // captured for replay: the argument would be stale
     __shared__ int red[4 * (PS_THREADS / 64)];
     __shared__ unsigned long long red_top[2 * (PS_THREADS / 64)];
     const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
@@ -421,6 +423,7 @@ __device__ __forceinline__ int hash_slot(int32_t *hk, int32_t key) {
 __global__ __launch_bounds__(HIST_THREADS) void k_hist_hash(const int32_t *__restrict__ keys,
                                                             int64_t n, int64_t G, int32_t seq,
                                                             Scratch sc) {
+    if (sc.seqp) seq = *sc.seqp;  // captured for replay: the argument would be stale
     extern __shared__ int32_t lds[];
     int32_t *hk = lds, *hc = lds + HIST_HASH_SLOTS;
     const int tid = threadIdx.x;
@@ -461,6 +464,7 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_plan_reduce(int64_t G, int mod
 __global__ __launch_bounds__(PLAN_THREADS) void k_plan_scan(int32_t nblk, State st, Scratch sc,
                                                             int32_t seq, int mode,
                                                             int32_t workers) {
+    if (sc.seqp) seq = *sc.seqp;  // captured for replay: the argument would be stale
     __shared__ int red[PLAN_FIELDS * (PLAN_THREADS / 64)];
     const int per = (nblk + PLAN_THREADS - 1) / PLAN_THREADS;
     const int b0 = min(nblk, (int)threadIdx.x * per), b1 = min(nblk, b0 + per);
@@ -482,6 +486,7 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_plan_scan(int32_t nblk, State 
 
 __global__ __launch_bounds__(PLAN_THREADS) void k_plan_down(State st, Scratch sc, int32_t seq,
                                                             int mode, int32_t workers) {
+    if (sc.seqp) seq = *sc.seqp;  // captured for replay: the argument would be stale
     __shared__ int red[2 * (PLAN_THREADS / 64)];
     const int64_t G = st.G;
     const int64_t gb = (int64_t)blockIdx.x * PLAN_CHUNK, ge = min(G, gb + PLAN_CHUNK);
@@ -497,6 +502,7 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_plan_down(State st, Scratch sc
 // that a bad key anywhere rejects the batch before any state changes).
 __global__ void k_validate(const int32_t *__restrict__ keys, int64_t n, int64_t G, int32_t seq,
                            Scratch sc) {
+    if (sc.seqp) seq = *sc.seqp;  // captured for replay: the argument would be stale
     int bad = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -725,6 +731,7 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(const int32_t *__restrict
                                                        const int32_t *__restrict__ values,
                                                        int64_t n, State st, Scratch sc,
                                                        int32_t seq, int mode, int32_t workers) {
+    if (sc.seqp) seq = *sc.seqp;  // captured for replay: the argument would be stale
     // per-wave bucket counters and the reordered tile; during an in-block
     // plan the same bytes hold the group counts
     __shared__ __align__(16) char pool[P_BYTES];
@@ -1210,7 +1217,7 @@ __device__ void fused_hist(const NextHist &h, int hb, int nhb, int32_t G, uint32
         if (c1) atomicAdd(&cw[hot1 >> 1], (uint32_t)c1 << (16 * (hot1 & 1)));
     }
     if (__syncthreads_or(bad)) {
-        if (tid == 0) atomicExch(h.sc.bad, h.seq);
+        if (tid == 0) atomicExch(h.sc.bad, h.sc.seqp ? *h.sc.seqp + 1 : h.seq);
     }
     // staggered flush, as in k_hist_small
     const int off = (int)(((int64_t)hb * words / nhb) & ~31);
@@ -1457,6 +1464,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_static(State st, Scratch
 // ---------------------------------------------- touched list (multi-sub) --
 __global__ __launch_bounds__(PLAN_THREADS) void k_touch_reduce(int64_t G, int32_t seq,
                                                                Scratch sc) {
+    if (sc.seqp) seq = *sc.seqp;  // captured for replay: the argument would be stale
     __shared__ int red[PLAN_THREADS / 64];
     const int64_t g0 = (int64_t)blockIdx.x * PLAN_CHUNK + (int64_t)threadIdx.x * PLAN_KPT;
     int f[1] = {0}, t[1];
@@ -1483,6 +1491,7 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_touch_scan(int32_t nblk, Scrat
 
 __global__ __launch_bounds__(PLAN_THREADS) void k_touch_write(int64_t G, int32_t seq,
                                                               Scratch sc) {
+    if (sc.seqp) seq = *sc.seqp;  // captured for replay: the argument would be stale
     __shared__ int red[PLAN_THREADS / 64];
     const int64_t g0 = (int64_t)blockIdx.x * PLAN_CHUNK + (int64_t)threadIdx.x * PLAN_KPT;
     int f[1] = {0}, t[1];
@@ -1631,8 +1640,26 @@ hipError_t launch_emit(State st, Scratch sc, int64_t cap, Out out, hipStream_t s
 
 __global__ void k_set_touched(int64_t *n_touched, int64_t v) { *n_touched = v; }
 
+__global__ void k_bump_seq(int32_t *seqp) {
+    if (threadIdx.x == 0) atomicAdd(seqp, 1);
+}
+
+__global__ void k_set_seq(int32_t *seqp, int32_t v) {
+    if (threadIdx.x == 0) atomicExch(seqp, v);
+}
+
 hipError_t launch_set_touched(int64_t *n_touched, int64_t v, hipStream_t s) {
     hipLaunchKernelGGL(k_set_touched, dim3(1), dim3(1), 0, s, n_touched, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_bump_seq(Scratch sc, hipStream_t s) {
+    hipLaunchKernelGGL(k_bump_seq, dim3(1), dim3(64), 0, s, sc.seqp);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_seq(Scratch sc, int32_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_seq, dim3(1), dim3(64), 0, s, sc.seqp, v);
     return hipGetLastError();
 }
 

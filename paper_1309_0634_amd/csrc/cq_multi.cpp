@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "cq.h"
+#include "cq_internal.h"
 
 namespace {
 
@@ -64,6 +65,13 @@ struct cq_multi {
     std::vector<hipEvent_t> t0, t1;                     // per query
     std::vector<int> chosen;
     std::vector<float> chosen_ms;
+    // graph replay: the set's whole per-batch launch sequence, captured
+    // once per batch size, reads the batch from staging buffers
+    bool graph = false;
+    hipStream_t origin = nullptr;
+    int32_t *keys_st = nullptr, *vals_st = nullptr;
+    int64_t st_cap = 0;
+    std::vector<std::pair<int64_t, hipGraphExec_t>> execs;
 };
 
 namespace {
@@ -75,6 +83,97 @@ int from_hip(hipError_t e) { return e == hipSuccess ? CQ_OK : CQ_ERR_HIP; }
 // The candidate query i runs at tuning push `step`.
 int cand_at(const cq_multi *m, int i, int step) {
     return (step / m->reps) % (int)m->cands[i].size();
+}
+
+void drop_graphs(cq_multi *m) {
+    for (auto &e : m->execs) (void)hipGraphExecDestroy(e.second);
+    m->execs.clear();
+}
+
+// Enqueues one batch on every query, lane by lane (eager, or while the
+// origin stream is being captured).
+int enqueue_all(cq_multi *m, const int32_t *keys, const int32_t *values, int64_t n,
+                hipStream_t s, bool tuning) {
+    const int nq = (int)m->qs.size();
+    hipError_t e = hipEventRecord(m->fork, s);
+    for (hipStream_t l : m->lanes)
+        if (e == hipSuccess) e = hipStreamWaitEvent(l, m->fork, 0);
+    int rc = from_hip(e);
+    // lane by lane, so each lane's launches are issued back to back
+    for (int l = 0; l < (int)m->lanes.size() && rc == CQ_OK; ++l) {
+        for (int i = 0; i < nq && rc == CQ_OK; ++i) {
+            if (m->lane_of[i] != l) continue;
+            if (tuning) {
+                const Cand c = m->cands[i][cand_at(m, i, m->tune_step)];
+                rc = cq_set_partition(m->qs[i], c.mode, c.workers);
+                if (rc == CQ_OK) rc = from_hip(hipEventRecord(m->t0[i], m->lanes[l]));
+            }
+            if (rc == CQ_OK) rc = cq_push_batch(m->qs[i], keys, values, n, m->lanes[l]);
+            if (rc == CQ_OK && tuning) rc = from_hip(hipEventRecord(m->t1[i], m->lanes[l]));
+        }
+        if (rc == CQ_OK) rc = from_hip(hipEventRecord(m->joins[l], m->lanes[l]));
+        if (rc == CQ_OK) rc = from_hip(hipStreamWaitEvent(s, m->joins[l], 0));
+    }
+    return rc;
+}
+
+// Graph push: copy the batch to staging, then replay the captured sequence
+// for this size (capturing it the first time).
+int graph_push(cq_multi *m, const int32_t *keys, const int32_t *values, int64_t n,
+               hipStream_t s) {
+    if (n > m->st_cap) {  // larger staging: every captured graph read the old one
+        drop_graphs(m);
+        if (hipStreamSynchronize(s) != hipSuccess) return CQ_ERR_HIP;
+        if (m->keys_st) (void)hipFree(m->keys_st);
+        if (m->vals_st) (void)hipFree(m->vals_st);
+        m->keys_st = m->vals_st = nullptr;
+        m->st_cap = 0;
+        if (hipMalloc(&m->keys_st, sizeof(int32_t) * (size_t)n) != hipSuccess ||
+            hipMalloc(&m->vals_st, sizeof(int32_t) * (size_t)n) != hipSuccess)
+            return CQ_ERR_OOM;
+        m->st_cap = n;
+    }
+    const size_t bytes = sizeof(int32_t) * (size_t)n;
+    if (n > 0 &&
+        (hipMemcpyAsync(m->keys_st, keys, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+         hipMemcpyAsync(m->vals_st, values, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess))
+        return CQ_ERR_HIP;
+    for (auto &e : m->execs)
+        if (e.first == n) {
+            for (cq_query *q : m->qs) cq::query_replayed(q, n, s);
+            return from_hip(hipGraphLaunch(e.second, s));
+        }
+    // capture: the pushes run their host logic now (each query's sequence
+    // number moves on), their launches go into the graph, and the launch
+    // below performs them
+    for (cq_query *q : m->qs) {
+        const int rc = cq::query_set_graph(q, true, s);
+        if (rc != CQ_OK) return rc;
+    }
+    hipEvent_t ready = nullptr;
+    if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess) return CQ_ERR_HIP;
+    hipError_t e = hipEventRecord(ready, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(m->origin, ready, 0);
+    if (e == hipSuccess) e = hipStreamBeginCapture(m->origin, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(ready);
+        return CQ_ERR_HIP;
+    }
+    const int rc = enqueue_all(m, m->keys_st, m->vals_st, n, m->origin, false);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(m->origin, &g);
+    (void)hipEventDestroy(ready);
+    if (rc != CQ_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc != CQ_OK ? rc : CQ_ERR_HIP;
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return CQ_ERR_HIP;
+    m->execs.push_back({n, x});
+    for (cq_query *q : m->qs) cq::query_ran_on(q, s);  // the work runs on s, not on a lane
+    return from_hip(hipGraphLaunch(x, s));
 }
 
 // After the tuning window: fastest candidate per query, lanes by LPT.
@@ -177,6 +276,23 @@ int cq_multi_tune(cq_multi *m, int32_t reps) {
     }
     m->tune_step = 0;
     m->tune_len = most * reps;
+    drop_graphs(m);  // partitions will change
+    return CQ_OK;
+}
+
+int cq_multi_set_graph(cq_multi *m, int32_t on) {
+    if (!m || (on != 0 && on != 1)) return CQ_ERR_INVALID;
+    DeviceGuard guard(m->device);
+    if (on) {
+        for (cq_query *q : m->qs)
+            if (!cq::query_capturable(q)) return CQ_ERR_INVALID;
+        if (!m->origin && hipStreamCreateWithFlags(&m->origin, hipStreamNonBlocking) != hipSuccess)
+            return CQ_ERR_HIP;
+    } else {
+        drop_graphs(m);
+        for (cq_query *q : m->qs) (void)cq::query_set_graph(q, false, nullptr);
+    }
+    m->graph = on != 0;
     return CQ_OK;
 }
 
@@ -186,28 +302,11 @@ int cq_multi_push(cq_multi *m, const int32_t *keys, const int32_t *values, int64
     DeviceGuard guard(m->device);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const bool tuning = m->tune_step < m->tune_len;
-    const int nq = (int)m->qs.size();
-    hipError_t e = hipEventRecord(m->fork, s);
-    for (hipStream_t l : m->lanes)
-        if (e == hipSuccess) e = hipStreamWaitEvent(l, m->fork, 0);
-    int rc = from_hip(e);
-    // lane by lane, so each lane's launches are issued back to back
-    for (int l = 0; l < (int)m->lanes.size() && rc == CQ_OK; ++l) {
-        for (int i = 0; i < nq && rc == CQ_OK; ++i) {
-            if (m->lane_of[i] != l) continue;
-            if (tuning) {
-                const Cand c = m->cands[i][cand_at(m, i, m->tune_step)];
-                rc = cq_set_partition(m->qs[i], c.mode, c.workers);
-                if (rc == CQ_OK) rc = from_hip(hipEventRecord(m->t0[i], m->lanes[l]));
-            }
-            if (rc == CQ_OK) rc = cq_push_batch(m->qs[i], keys, values, n, m->lanes[l]);
-            if (rc == CQ_OK && tuning) rc = from_hip(hipEventRecord(m->t1[i], m->lanes[l]));
-        }
-        if (rc == CQ_OK) rc = from_hip(hipEventRecord(m->joins[l], m->lanes[l]));
-        if (rc == CQ_OK) rc = from_hip(hipStreamWaitEvent(s, m->joins[l], 0));
-    }
+    if (m->graph && !tuning) return graph_push(m, keys, values, n, s);
+    int rc = enqueue_all(m, keys, values, n, s, tuning);
     if (rc != CQ_OK || !tuning) return rc;
     // tuning: collect this push's times (waits for it), advance the window
+    const int nq = (int)m->qs.size();
     for (int i = 0; i < nq && rc == CQ_OK; ++i) {
         float ms = 0.f;
         rc = from_hip(hipEventSynchronize(m->t1[i]));
@@ -236,6 +335,13 @@ int cq_multi_destroy(cq_multi *m) {
     if (!m) return CQ_OK;
     DeviceGuard guard(m->device);
     for (hipStream_t l : m->lanes) (void)hipStreamSynchronize(l);
+    if (m->origin) (void)hipStreamSynchronize(m->origin);
+    (void)hipDeviceSynchronize();  // replays run on the callers' streams
+    drop_graphs(m);
+    for (cq_query *q : m->qs) (void)cq::query_set_graph(q, false, nullptr);
+    if (m->keys_st) (void)hipFree(m->keys_st);
+    if (m->vals_st) (void)hipFree(m->vals_st);
+    if (m->origin) (void)hipStreamDestroy(m->origin);
     for (hipStream_t l : m->lanes) (void)hipStreamDestroy(l);
     for (hipEvent_t j : m->joins) (void)hipEventDestroy(j);
     for (hipEvent_t t : m->t0) (void)hipEventDestroy(t);

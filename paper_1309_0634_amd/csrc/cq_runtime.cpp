@@ -53,6 +53,7 @@ struct cq_query {
     bool map_pending = false;     // an upload from h_map may still be running
     int64_t policy_total = 0;     // groups moved since the technique was selected
     uint64_t kmod = 0;            // keys reduced mod groups (multiplier; 0 = off)
+    bool graph = false;           // pushes are being captured for replay
     // per-tuple results: arrival index of each staged tuple, count before
     // the sub-batch (allocated by the first per-tuple push)
     int32_t *pt_sidx = nullptr, *pt_pcnt = nullptr;
@@ -155,6 +156,7 @@ void free_all(cq_query *q) {
     free_set(q->alt);
     dfree(q->sc.fault);
     dfree(q->sc.hot);
+    dfree(q->sc.seqp);
     dfree(q->sc.trace);
     dfree(q->sc.phase);
     for (auto &t : q->live) {
@@ -233,6 +235,7 @@ Scratch set_of(const cq_query *q, int i) {
     Scratch b = i ? q->alt : q->sc;
     b.fault = q->sc.fault;
     b.hot = q->sc.hot;
+    b.seqp = q->graph ? q->sc.seqp : nullptr;
     b.trace = (q->telemetry & CQ_TELEMETRY_WORKERS) ? q->sc.trace : nullptr;
     b.phase = (q->telemetry & CQ_TELEMETRY_PHASES) ? q->sc.phase : nullptr;
     b.kmod = q->kmod;
@@ -380,6 +383,13 @@ int push(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n, hip
     q->last_mode = q->mode;
     q->last_workers = q->workers;
     const int32_t seq = ++q->seq;
+    if (sc.seqp) {  // captured: the replayed push advances its own number
+        rc = from_hip(launch_bump_seq(sc, s));
+        if (rc != CQ_OK) {
+            --q->seq;
+            return rc;
+        }
+    }
     if (n == 0) {
         rc = from_hip(launch_reset_totals(sc, s));
         if (rc == CQ_OK && out)
@@ -436,6 +446,44 @@ int ensure_alt(cq_query *q) {
 
 }  // namespace
 
+namespace cq {
+
+// Whether a query's pushes can be captured into a graph: no host step
+// (techniques), no telemetry events, no per-tuple outputs.
+bool query_capturable(const cq_query *q) { return !q->policy && !q->telemetry; }
+
+// Enters or leaves capture mode.  Entering sets the device copy of the
+// sequence number to the host's (on stream s, before the capture starts).
+int query_set_graph(cq_query *q, bool on, hipStream_t s) {
+    DeviceGuard guard(q->device);
+    if (on && !q->graph) {
+        q->graph = true;
+        const int rc = from_hip(launch_set_seq(set_of(q, 0), q->seq, s));
+        if (rc != CQ_OK) q->graph = false;
+        return rc;
+    }
+    q->graph = on;
+    return CQ_OK;
+}
+
+// The stream a query's last work was enqueued on (captured pushes run
+// where their graph is launched).
+void query_ran_on(cq_query *q, hipStream_t s) { q->last_stream = s; }
+
+// After a replay of a captured push of n tuples on stream s: the host's
+// record of the query follows what the replay did on the device.
+void query_replayed(cq_query *q, int64_t n, hipStream_t s) {
+    q->seq += 1;
+    q->cur = 0;
+    q->last_n = n;
+    q->last_stream = s;
+    q->pushed = true;
+    q->last_mode = q->mode;
+    q->last_workers = q->workers;
+}
+
+}  // namespace cq
+
 extern "C" {
 
 const char *cq_strerror(int code) {
@@ -473,6 +521,7 @@ int cq_create(int64_t groups, int32_t window, uint32_t aggregates, cq_query **ou
     if (rc == CQ_OK) rc = alloc_set(q->sc, G);
     if (rc == CQ_OK) rc = dalloc(&q->sc.fault, 1);
     if (rc == CQ_OK) rc = dalloc(&q->sc.hot, 2);
+    if (rc == CQ_OK) rc = dalloc(&q->sc.seqp, 1);
     hipError_t e = hipSuccess;
     if (rc == CQ_OK) {
         // zero-filled windows: never-written slots read as 0, so the first
@@ -483,6 +532,7 @@ int cq_create(int64_t groups, int32_t window, uint32_t aggregates, cq_query **ou
         if (e == hipSuccess) e = hipMemset(q->st.sum, 0, sizeof(int64_t) * (size_t)G);
         if (e == hipSuccess) e = hipMemset(q->sc.fault, 0, sizeof(int32_t));
         if (e == hipSuccess) e = hipMemset(q->sc.hot, 0xff, 2 * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMemset(q->sc.seqp, 0, sizeof(int32_t));
         if (e == hipSuccess) e = hipDeviceSynchronize();
         rc = from_hip(e);
     }
@@ -649,6 +699,13 @@ int cq_push_batches(cq_query *q, int32_t count, const int32_t *const *keys,
                          counts ? counts[i] : nullptr, avgs ? avgs[i] : nullptr, n_touched[i]};
         q->cur = b;
         q->last_n = n[i];
+        if (sc.seqp) {  // captured: the replayed push advances its own number
+            rc = from_hip(launch_bump_seq(sc, s));
+            if (rc != CQ_OK) {
+                q->seq = seq - 1;  // the batches from here on never reached the device
+                break;
+            }
+        }
         if (n[i] == 0) {
             rc = from_hip(launch_reset_totals(sc, s));
             if (rc == CQ_OK) rc = from_hip(launch_set_touched(n_touched[i], 0, s));

@@ -79,6 +79,7 @@ def test_null_handles_are_rejected(L):
     assert L.cq_multi_push(None, None, None, 0, None) == cq.ERR_INVALID
     assert L.cq_multi_tune(None, 2) == cq.ERR_INVALID
     assert L.cq_multi_plan(None, None, None, None, None) == cq.ERR_INVALID
+    assert L.cq_multi_set_graph(None, 1) == cq.ERR_INVALID
     assert L.cq_multi_destroy(None) == cq.OK
     assert L.cq_destroy(None) == cq.OK
 

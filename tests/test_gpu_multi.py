@@ -106,3 +106,63 @@ def test_multi_set_with_tuning(lanes):
     for q, o in zip(qs, oras):
         q.close()
         o.close()
+
+
+def test_multi_graph_replay():
+    """A set replayed as one captured HIP graph per batch size: after every
+    replay every query equals the oracle, with eager work and
+    synchronisations in between, an eager push on one query of the set
+    between replays, a larger batch (new staging, new graphs), an empty
+    batch, and a switch back to eager pushes."""
+    import torch
+    note("case: multi-query graph replay")
+    rng = np.random.default_rng([20130909, 93])
+    shape = [QUERIES[i] for i in (0, 2, 3, 5, 6, 8, 9, 11)]
+    qs = []
+    for G, W in shape:
+        q = cq.Query(G, W)
+        q.set_key_mod(True)
+        qs.append(q)
+    oras = [RingOracle(G, W, threads=2) for G, W in shape]
+    m = cq.Multi(qs, 4)
+    other = cq.Query(5000, 50)
+    other_o = RingOracle(5000, 50)
+
+    def check(k, v, ctx):
+        for i, ((G, W), q, o) in enumerate(zip(shape, qs, oras)):
+            assert_same(q.results(), o.push(reduced(k, G).astype(np.int32), v),
+                        f"{ctx} query {i} (G={G}, W={W})")
+
+    sizes = [120000, 120000, 60000, 120000, 60000, 0, 60000, (1 << 20) + 999, 120000, 60000]
+    batches = shared_batches(rng, [70000, 70000, 70000] + [n for n in sizes] + [40000])
+    m.tune(1)
+    for b in range(3):
+        k, v = batches[b]
+        m.push(to_dev(k), to_dev(v))
+        check(k, v, f"tuning batch {b}")
+    m.set_graph(True)
+    for j, (k, v) in enumerate(batches[3:3 + len(sizes)]):
+        m.push(to_dev(k), to_dev(v))
+        check(k, v, f"replay {j} (n={len(k)})")
+        # the program's own eager work between replays
+        ok_ = rng.integers(0, 5000, 30000).astype(np.int32)
+        ov = rng.integers(0, 100, 30000).astype(np.int32)
+        other.push(to_dev(ok_), to_dev(ov))
+        assert_same(other.results(), other_o.push(ok_, ov), f"eager work after replay {j}")
+        torch.cuda.synchronize()
+        if j == 4:  # an eager push on one query of the set, between replays
+            G, _ = shape[2]
+            ek = rng.integers(0, G, 10000).astype(np.int32)
+            ev = rng.integers(0, 100, 10000).astype(np.int32)
+            qs[2].push(to_dev(ek), to_dev(ev))
+            assert_same(qs[2].results(), oras[2].push(ek, ev), "eager push inside the set")
+    m.set_graph(False)
+    k, v = batches[-1]
+    m.push(to_dev(k), to_dev(v))
+    check(k, v, "eager again")
+    m.close()
+    for q, o in zip(qs, oras):
+        q.close()
+        o.close()
+    other.close()
+    other_o.close()
