@@ -46,8 +46,6 @@ constexpr int LIGHT_CAP = LIGHT_BUDGET + HEAVY_MIN;
 constexpr int LIGHT_BITS = 10;   // positions inside a light bucket
 static_assert(LIGHT_CAP <= (1 << LIGHT_BITS), "light positions must fit the match bits");
 constexpr int NB_MAX = SUB / LIGHT_BUDGET + SUB / HEAVY_MIN + 2;
-constexpr int NB_BITS = 13;
-static_assert(NB_MAX < (1 << NB_BITS), "bucket ids must fit the match bits");
 
 // Multisplit pass: tiles of PASS_TILE tuples, PASS_WAVES waves, each wave a
 // contiguous chunk of PASS_TILE / PASS_WAVES tuples in 64-lane rounds.
@@ -62,6 +60,10 @@ constexpr int PASS_TILES_MAX = SUB / PASS_TILE;
 constexpr int PASS_LOCAL_G = 16384;
 constexpr int PL_PER = (PASS_LOCAL_G + PASS_THREADS - 1) / PASS_THREADS;
 static_assert(PL_PER % 4 == 0, "int4 histogram loads");
+static_assert(PASS_THREADS * PL_PER <= PASS_LOCAL_G, "in-block plan loads stay in the histogram");
+// Counters the histogram array holds: at least PASS_LOCAL_G, so that the
+// in-block plan's loads need no bounds test.
+inline int64_t hist_entries(int64_t G) { return G > PASS_LOCAL_G ? G : PASS_LOCAL_G; }
 static_assert(NB_MAX < 65536, "16-bit bucket ids");
 __host__ __device__ constexpr bool plan_fused(int64_t G) { return G <= PASS_LOCAL_G; }
 static_assert(PASS_TILE / PASS_WAVES < 65536, "per-wave counters are 16-bit");

@@ -190,9 +190,10 @@ __device__ void plan_range(const State &st, const Scratch &sc, int64_t gb, int64
     }
 }
 
-// Block-wide top two over the threads' Top2 (result in thread 0).
-__device__ void top2_block(Top2 &t, unsigned long long *lds) {
-    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+// Block-wide top two over the threads' Top2 (result in thread 0); `nw`
+// waves in the block.
+__device__ void top2_block(Top2 &t, unsigned long long *lds, int nw) {
+    const int wv = threadIdx.x >> 6;
     top2_wave(t);
     if (lane_id() == 0) {
         lds[2 * wv] = t.a;
@@ -399,7 +400,7 @@ __global__ __launch_bounds__(PS_THREADS) void k_plan_small(State st, Scratch sc,
         if (kg > 0) plan_group(st, sc, g, kg, ex, po, c0, nl, seq, mode, workers);
     }
     if (track) {
-        top2_block(top, red_top);
+        top2_block(top, red_top, PS_THREADS / 64);
         if (tid == 0) {
             sc.hot[0] = top.a ? (int32_t)(uint32_t)top.a : -1;
             sc.hot[1] = top.b ? (int32_t)(uint32_t)top.b : -1;
@@ -533,43 +534,57 @@ __global__ void k_validate(const int32_t *__restrict__ keys, int64_t n, int64_t 
 // Groups whose plan one pass workgroup writes per step of its in-block plan.
 constexpr int OWN_CAP = 1024;
 
+// `load_tile` issues the tile's own loads.  It runs after the loads the plan
+// waits on (the bad-key flag, the histogram, the owned groups' state), so the
+// tile's tuples arrive while the plan is computed: loads complete in order.
+template <typename F>
 __device__ int pass_local_plan(const State &st, const Scratch &sc, int32_t seq, int mode,
                                int32_t workers, uint16_t *gbk, int32_t *gcnt, int4 *oex,
                                int *red, unsigned long long *red_top, int &own_n,
-                               int32_t &po0, int32_t &c00, int32_t &nl_out) {
-    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6, nw = blockDim.x >> 6;
+                               int32_t &po0, int32_t &c00, int32_t &nl_out, F &&load_tile) {
+    // launched with PASS_THREADS threads (a constant: the block size would
+    // otherwise be read from memory first)
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6, nw = PASS_WAVES;
     const int G = (int)st.G;
     const int D = gridDim.x, me = blockIdx.x;
-    if (*sc.bad == seq) {
-        for (int g = me * blockDim.x + tid; g < G; g += D * blockDim.x) sc.k[g] = 0;
+    const bool bad = *sc.bad == seq;
+    // this thread's groups [g0, g0 + R), R a multiple of 4 (int4 loads)
+    const int R = ((G + PASS_THREADS - 1) / PASS_THREADS + 3) & ~3;
+    const int g0 = tid * R;
+    // exclusive fields at each run's start, beside the owned groups' fields
+    int2 *runpre = reinterpret_cast<int2 *>(oex + OWN_CAP);
+    // The histogram holds at least PASS_LOCAL_G >= PASS_THREADS * PL_PER
+    // counters, so every load below is in bounds and is issued
+    // unconditionally: a load under a divergent branch would be waited on
+    // where the branch joins, one round trip after another.  Counts outside
+    // the thread's run or past G are masked to zero.
+    int32_t kv[PL_PER];
+#pragma unroll
+    for (int q = 0; q < PL_PER / 4; ++q) {
+        const int g = g0 + 4 * q;
+        const int4 x = *reinterpret_cast<const int4 *>(sc.k + g);
+        const bool in = 4 * q < R;
+        kv[4 * q] = in && g < G ? x.x : 0;
+        kv[4 * q + 1] = in && g + 1 < G ? x.y : 0;
+        kv[4 * q + 2] = in && g + 2 < G ? x.z : 0;
+        kv[4 * q + 3] = in && g + 3 < G ? x.w : 0;
+    }
+    // this block writes the plan of groups [lo, hi), one group per thread
+    // (in passes of OWN_CAP for a small grid); their state is loaded now
+    const int lo = (int)((int64_t)me * G / D), hi = (int)((int64_t)(me + 1) * G / D);
+    // (clamped into [0, G) and loaded unconditionally; read only by the
+    // thread that owns group lo + tid < hi)
+    const int gs = min(lo + tid, G - 1);
+    po0 = st.pos[gs];
+    c00 = st.cnt[gs];
+    load_tile();
+    if (bad) {
+        for (int g = me * PASS_THREADS + tid; g < G; g += D * PASS_THREADS) sc.k[g] = 0;
         if (me == 0 && tid == 0) {
             const int none[PLAN_FIELDS] = {0, 0, 0};
             plan_publish(st, sc, none, CQ_ERR_KEY_RANGE, mode, workers);
         }
         return -1;
-    }
-    // this thread's groups [g0, g0 + R), R a multiple of 4 (int4 loads)
-    const int R = ((G + (int)blockDim.x - 1) / (int)blockDim.x + 3) & ~3;
-    const int g0 = tid * R;
-    int32_t kv[PL_PER];
-#pragma unroll
-    for (int q = 0; q < PL_PER / 4; ++q) {
-        const int g = g0 + 4 * q;
-        if (4 * q < R && g + 3 < G) {
-            const int4 x = *reinterpret_cast<const int4 *>(sc.k + g);
-            kv[4 * q] = x.x; kv[4 * q + 1] = x.y; kv[4 * q + 2] = x.z; kv[4 * q + 3] = x.w;
-        } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) kv[4 * q + e] = (4 * q < R && g + e < G) ? sc.k[g + e] : 0;
-        }
-    }
-    // this block writes the plan of groups [lo, hi), one group per thread
-    // (in passes of OWN_CAP for a small grid); their state is loaded now
-    const int lo = (int)((int64_t)me * G / D), hi = (int)((int64_t)(me + 1) * G / D);
-    po0 = c00 = 0;
-    if (lo + tid < hi) {
-        po0 = st.pos[lo + tid];
-        c00 = st.cnt[lo + tid];
     }
     int sA = 0, sB = 0;
     const bool track = me == 0;
@@ -583,18 +598,13 @@ __device__ int pass_local_plan(const State &st, const Scratch &sc, int32_t seq, 
         if (track && kv[j] > 0)
             top.add(((unsigned long long)(uint32_t)kv[j] << 32) | (uint32_t)(g0 + j));
     }
+    // the run's counts into LDS (zeros past G included): the bucket loop
+    // below reads them back there rather than keeping every count live
 #pragma unroll
-    for (int q = 0; q < PL_PER / 4; ++q) {
-        const int g = g0 + 4 * q;
-        if (4 * q < R && g + 3 < G) {
-            *reinterpret_cast<int4 *>(gcnt + g) =
+    for (int q = 0; q < PL_PER / 4; ++q)
+        if (4 * q < R)
+            *reinterpret_cast<int4 *>(gcnt + g0 + 4 * q) =
                 make_int4(kv[4 * q], kv[4 * q + 1], kv[4 * q + 2], kv[4 * q + 3]);
-        } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (4 * q < R && g + e < G) gcnt[g + e] = kv[4 * q + e];
-        }
-    }
     phase_mark(sc, PHASE_PASS, 5);
     const int iA = wave_incl_add(sA), iB = wave_incl_add(sB);
     if (lane == 63) {
@@ -617,61 +627,83 @@ __device__ int pass_local_plan(const State &st, const Scratch &sc, int32_t seq, 
     const int32_t nl = mode == MODE_STATIC ? 0 : (TA + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
     const int NB = mode == MODE_STATIC ? workers : nl + tot[1];
     if (me == 0 && tid == 0) plan_publish(st, sc, tot, 0, mode, workers);
-    // Bucket of every group of the run (a lean loop: it runs over all G
-    // groups in every block), and the exclusive fields and count of the
-    // groups this block owns, handed through LDS to the threads that write
-    // their plan: consecutive groups by consecutive lanes, so the plan's
-    // stores are coalesced.  With at most OWN_CAP owned groups (every batch
-    // of 16 tiles or more) the writes happen later, in the pass, after a
-    // barrier it needs anyway (pass_owned_writes); a smaller grid walks the
-    // run once per OWN_CAP owned groups and writes them here.
+    // Bucket of every group of the run.  This loop runs over all G groups in
+    // every block, so it is kept free of branches: the mode is tested once,
+    // heavy or light is a select, and the owned groups' fields are left to
+    // the loop after it.  Untouched groups get an id too; it is never read.
     const int gend = min(G, g0 + R);
     nl_out = nl;
-    if (mode == MODE_STATIC && sc.owner)  // a Section 4 mapping: buckets are workers
-        for (int g = tid; g < G; g += blockDim.x) gbk[g] = (uint16_t)sc.owner[g];
-    own_n = hi - lo <= OWN_CAP ? hi - lo : 0;
-    int base = lo;
-    do {  // at least once: every block needs the bucket ids, owned groups or not
-        const int top_g = min(hi, base + OWN_CAP);
-        const bool first = base == lo;
-        int eA = bA + iA - sA, eB = bB + iB - sB;
+    const int eA0 = bA + iA - sA, eB0 = bB + iB - sB;  // exclusive fields at g0
+    if (mode == MODE_STATIC && sc.owner) {  // a Section 4 mapping: buckets are workers
+        for (int g = tid; g < G; g += PASS_THREADS) gbk[g] = (uint16_t)sc.owner[g];
+    } else {
+        int a = eA0, h = eB0 & 0xffff;  // light tuples and heavy groups before g
+        // (gbk holds PASS_LOCAL_G ids, so the last int4 of a run past G is
+        // stored whole)
         for (int g4 = g0; g4 < gend; g4 += 4) {
-            int ks[4];
-            if (g4 + 3 < G) {
-                const int4 c = *reinterpret_cast<const int4 *>(gcnt + g4);
-                ks[0] = c.x; ks[1] = c.y; ks[2] = c.z; ks[3] = c.w;
+            const int4 c = *reinterpret_cast<const int4 *>(gcnt + g4);
+            const int ks[4] = {c.x, c.y, c.z, c.w};
+            uint32_t bo[4];
+            if (mode == MODE_STATIC) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    bo[e] = ((uint32_t)(g4 + e) * (uint32_t)workers) / (uint32_t)G;
             } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) ks[e] = g4 + e < G ? gcnt[g4 + e] : 0;
-            }
-            uint32_t bo[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int g = g4 + e;
-                const bool heavy = mode != MODE_STATIC && ks[e] >= HEAVY_MIN;
-                if (mode == MODE_STATIC)
-                    bo[e] = ((uint32_t)g * (uint32_t)workers) / (uint32_t)G;
-                else
-                    bo[e] = heavy ? (uint32_t)(nl + (eB & 0xffff))
-                                  : (uint32_t)max(0, eA + ks[e] - 1) / LIGHT_BUDGET;
-                if (g >= base && g < top_g) oex[g - base] = make_int4(eA, eB, ks[e], 0);
-                eA += heavy ? 0 : ks[e];
-                eB += (heavy ? 1 : 0) + (ks[e] > 0 ? 1 << 16 : 0);
-            }
-            if (first && !sc.owner) {  // bucket ids (untouched groups' are never read)
-                if (g4 + 3 < G) {
-                    *reinterpret_cast<uint2 *>(gbk + g4) =
-                        make_uint2(bo[0] | (bo[1] << 16), bo[2] | (bo[3] << 16));
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if (g4 + e < G) gbk[g4 + e] = (uint16_t)bo[e];
+                for (int e = 0; e < 4; ++e) {
+                    const bool heavy = ks[e] >= HEAVY_MIN;
+                    const uint32_t light = (uint32_t)max(0, a + ks[e] - 1) / LIGHT_BUDGET;
+                    bo[e] = heavy ? (uint32_t)(nl + h) : light;
+                    a += heavy ? 0 : ks[e];
+                    h += heavy ? 1 : 0;
                 }
             }
+            *reinterpret_cast<uint2 *>(gbk + g4) =
+                make_uint2(bo[0] | (bo[1] << 16), bo[2] | (bo[3] << 16));
+        }
+    }
+    // The exclusive fields and count of the groups this block owns, handed
+    // through LDS to the threads that write their plan: consecutive groups
+    // by consecutive lanes, so the plan's stores are coalesced.  Each owned
+    // group's fields are rebuilt by one thread from the fields at the start
+    // of the run that holds it (left in LDS by that run's thread) and the
+    // counts before it in the run; the groups go round the waves, so that no
+    // wave holds the block back at the next barrier.  With at most OWN_CAP
+    // owned groups (every batch of 16 tiles or more) the writes happen
+    // later, in the pass, after a barrier it needs anyway
+    // (pass_owned_writes); a smaller grid takes OWN_CAP owned groups at a
+    // time and writes them here.
+    runpre[tid] = make_int2(eA0, eB0);
+    __syncthreads();
+    own_n = hi - lo <= OWN_CAP ? hi - lo : 0;
+    const int spread = (tid & 63) * PASS_WAVES + (tid >> 6);  // lane-major over the waves
+    int base = lo;
+    do {
+        const int top_g = min(hi, base + OWN_CAP);
+        const bool first = base == lo;
+        for (int i = spread; i < top_g - base; i += PASS_THREADS) {
+            const int g = base + i;
+            const int t = g / R, r0 = t * R;  // g's run and its first group
+            const int2 p = runpre[t];
+            int eA = p.x, eB = p.y;
+#pragma unroll
+            for (int q = 0; q < PL_PER / 4; ++q) {
+                if (r0 + 4 * q >= g) break;
+                const int4 c = *reinterpret_cast<const int4 *>(gcnt + r0 + 4 * q);
+                const int ks[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = r0 + 4 * q + e < g ? ks[e] : 0;
+                    const bool heavy = mode != MODE_STATIC && k >= HEAVY_MIN;
+                    eA += heavy ? 0 : k;
+                    eB += (heavy ? 1 : 0) + (k > 0 ? 1 << 16 : 0);
+                }
+            }
+            oex[i] = make_int4(eA, eB, gcnt[g], 0);
         }
         if (own_n == 0 && top_g > base) {
             __syncthreads();
-            for (int i = tid; i < top_g - base; i += blockDim.x) {
+            for (int i = tid; i < top_g - base; i += PASS_THREADS) {
                 const int g = base + i;
                 const int4 e = oex[i];
                 const int ex[PLAN_FIELDS] = {e.x, e.y & 0xffff, e.y >> 16};
@@ -687,7 +719,7 @@ __device__ int pass_local_plan(const State &st, const Scratch &sc, int32_t seq, 
     } while ((base += OWN_CAP) < hi && own_n == 0);
     phase_mark(sc, PHASE_PASS, 7);
     if (track) {
-        top2_block(top, red_top);
+        top2_block(top, red_top, PASS_WAVES);
         if (tid == 0) {
             sc.hot[0] = top.a ? (int32_t)(uint32_t)top.a : -1;
             sc.hot[1] = top.b ? (int32_t)(uint32_t)top.b : -1;
@@ -697,11 +729,18 @@ __device__ int pass_local_plan(const State &st, const Scratch &sc, int32_t seq, 
     return NB;
 }
 
+// bytes of one wave's leader table in the multisplit: every bucket id has an
+// entry (at most NB_MAX - 2 buckets: a static partition's workers, or about
+// SUB / LIGHT_BUDGET + 1 balanced ones)
+constexpr int LEAD = 2 * PASS_LOCAL_G / PASS_WAVES;
+static_assert(LEAD >= NB_MAX - 2, "a leader entry for every bucket");
 constexpr int P_WC = 0;                                            // u16[PASS_WAVES][NB_MAX]
+static_assert(NB_MAX % 2 == 0, "per-wave counter rows are cleared as 32-bit pairs");
 constexpr int P_STAGE = (P_WC + 2 * PASS_WAVES * NB_MAX + 15) & ~15;  // int2[PASS_TILE]
 constexpr int P_BYTES = P_STAGE + 8 * PASS_TILE;
 static_assert(P_BYTES >= 4 * PASS_LOCAL_G, "group counts fit the pool");
-static_assert(P_BYTES - P_STAGE >= 16 * OWN_CAP, "owned fields fit the staging area");
+static_assert(P_BYTES - P_STAGE >= 16 * OWN_CAP + 8 * PASS_THREADS,
+              "owned fields and run-start fields fit the staging area");
 static_assert(P_STAGE >= 4 * PASS_LOCAL_G, "owned fields do not overlap the group counts");
 
 // The deferred per-group plan writes of a block that owns at most OWN_CAP
@@ -710,7 +749,7 @@ __device__ void pass_owned_writes(const State &st, const Scratch &sc, const int4
                                   int32_t po0, int32_t c00, int32_t nl, int32_t seq, int mode,
                                   int32_t workers) {
     const int lo = (int)((int64_t)blockIdx.x * st.G / gridDim.x);
-    for (int i = threadIdx.x; i < own_n; i += blockDim.x) {
+    for (int i = threadIdx.x; i < own_n; i += PASS_THREADS) {
         const int g = lo + i;
         const int4 e = oex[i];
         const int ex[PLAN_FIELDS] = {e.x, e.y & 0xffff, e.y >> 16};
@@ -739,7 +778,9 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(const int32_t *__restrict
     int2 *stage = reinterpret_cast<int2 *>(pool + P_STAGE);
     __shared__ int32_t ts[NB_MAX + 1];
     __shared__ int red[PASS_WAVES];
-    __shared__ __align__(16) uint16_t gbk[LOCAL ? PASS_LOCAL_G : 4];
+    // group -> bucket ids during an in-block plan; then, in both variants,
+    // one LEAD-byte leader table per wave for the multisplit
+    __shared__ __align__(16) uint16_t gbk[PASS_LOCAL_G];
     __shared__ int pred[2 * PASS_WAVES];
     __shared__ unsigned long long ptop[2 * PASS_WAVES];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
@@ -747,40 +788,58 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(const int32_t *__restrict
     const int tile_n = (int)min((int64_t)PASS_TILE, n - base);
     phase_mark(sc, PHASE_PASS, 0);
     int32_t key[PASS_ROUNDS], val[PASS_ROUNDS], bk[PASS_ROUNDS], lr[PASS_ROUNDS];
+    // Raw keys, loaded unconditionally from an index clamped into the batch
+    // (n >= 1), so that no load waits on another; lanes past n are masked
+    // where the keys are first used, and the group view is applied there.
+    auto load_tile = [&]() {
 #pragma unroll
-    for (int r = 0; r < PASS_ROUNDS; ++r) {
-        const int64_t i = base + wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane;
-        const bool valid = i < n;
-        key[r] = valid ? view_key(keys[i], sc.kmod, st.G) : 0;
-        val[r] = valid ? values[i] : 0;
-    }
+        for (int r = 0; r < PASS_ROUNDS; ++r) {
+            const int64_t i = min(base + wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane, n - 1);
+            key[r] = keys[i];
+            val[r] = values[i];
+        }
+    };
     int NB;
     int own_n = 0;
     int32_t po0 = 0, c00 = 0, nl = 0;
     if (LOCAL) {
         NB = pass_local_plan(st, sc, seq, mode, workers, gbk, reinterpret_cast<int32_t *>(pool),
                              reinterpret_cast<int4 *>(pool + P_STAGE), pred, ptop, own_n, po0,
-                             c00, nl);
-        if (NB < 0 || NB > NB_MAX) return;
+                             c00, nl, load_tile);
+        if (NB < 0) return;
+        if (NB > LEAD) {  // no plan makes this many buckets
+            if (tid == 0) atomicOr(sc.fault, FAULT_BUCKETS);
+            return;
+        }
 #pragma unroll
         for (int r = 0; r < PASS_ROUNDS; ++r) {
             const int64_t i = base + wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane;
+            key[r] = view_key(key[r], sc.kmod, st.G);
             bk[r] = (i < n && (uint32_t)key[r] < (uint32_t)st.G) ? gbk[key[r]] : NB;
             lr[r] = 0;
         }
     } else {
+        load_tile();
         const PlanTotals t = *sc.tot;
         if (t.status) return;
         NB = t.n_buckets;
-        if (NB > NB_MAX) return;
+        if (NB > LEAD) {  // no plan makes this many buckets
+            if (tid == 0) atomicOr(sc.fault, FAULT_BUCKETS);
+            return;
+        }
 #pragma unroll
         for (int r = 0; r < PASS_ROUNDS; ++r) {
             const int64_t i = base + wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane;
+            key[r] = view_key(key[r], sc.kmod, st.G);
             bk[r] = (i < n) ? sc.bucket[key[r]] : NB;
             lr[r] = 0;
         }
     }
-    for (int i = tid; i < PASS_WAVES * NB; i += PASS_THREADS) wc[i / NB][i % NB] = 0;
+    // clear the per-wave counters two at a time, row by row (no division by
+    // NB; a row may be cleared one entry past NB, which NB_MAX leaves room for)
+    for (int p = tid; 2 * p < NB; p += PASS_THREADS)
+#pragma unroll
+        for (int w = 0; w < PASS_WAVES; ++w) reinterpret_cast<uint32_t *>(wc[w])[p] = 0;
     __syncthreads();
     // the plan's per-group writes (fields in the staging area, which is
     // written only after two more barriers)
@@ -788,20 +847,33 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(const int32_t *__restrict
         pass_owned_writes(st, sc, reinterpret_cast<const int4 *>(pool + P_STAGE), own_n, po0,
                           c00, nl, seq, mode, workers);
     phase_mark(sc, PHASE_PASS, 1);
-    // only the bits that bucket ids < NB can have
-    const int nbits = NB > 1 ? 32 - __clz(NB - 1) : 0;
+    // The lanes of a round that share a bucket elect one of them: each
+    // writes its lane id into the wave's table at its bucket and, after a
+    // wave-scope release/acquire, reads the entry back, so all of them read
+    // the same surviving id (the accesses are wave-scope atomics: lanes race
+    // on the entry by design, and a plain read could be folded into the
+    // lane's own write).  Matching that 6-bit id takes 6 ballots instead of
+    // one per bit of the bucket id.
+    uint8_t *lead = reinterpret_cast<uint8_t *>(gbk) + wave * LEAD;
 #pragma unroll
     for (int r = 0; r < PASS_ROUNDS; ++r) {
         const int b = bk[r];
         const bool valid = (unsigned)b < (unsigned)NB;
+        if (valid)
+            __hip_atomic_store(lead + b, (uint8_t)lane, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WAVEFRONT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int L = valid ? (int)__hip_atomic_load(lead + b, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WAVEFRONT)
+                            : 0;
         uint64_t m = ballot(valid);
 #pragma unroll
-        for (int bit = 0; bit < NB_BITS; ++bit) {
-            if (bit < nbits) {
-                const bool on = (b >> bit) & 1;
-                const uint64_t bb = ballot(on);
-                m &= on ? bb : ~bb;
-            }
+        for (int bit = 0; bit < 6; ++bit) {
+            const bool on = (L >> bit) & 1;
+            const uint64_t bb = ballot(on);
+            m &= on ? bb : ~bb;
         }
         if (valid) {
             const uint64_t below = m & lanemask_lt();

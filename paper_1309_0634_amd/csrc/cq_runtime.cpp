@@ -122,7 +122,7 @@ void free_set(Scratch &b) {
 // plan totals zero); returns a status code.
 int alloc_set(Scratch &b, int64_t G) {
     const int64_t nblk = (G + PLAN_CHUNK - 1) / PLAN_CHUNK;
-    int rc = dalloc(&b.k, G);
+    int rc = dalloc(&b.k, hist_entries(G));
     if (rc == CQ_OK) rc = dalloc(&b.lpre, G + 1);
     if (rc == CQ_OK) rc = dalloc(&b.bucket, G);
     if (rc == CQ_OK) rc = dalloc(&b.pold, G);
@@ -138,7 +138,7 @@ int alloc_set(Scratch &b, int64_t G) {
     if (rc == CQ_OK) rc = dalloc(&b.tot, 1);
     if (rc == CQ_OK) rc = dalloc(&b.bad, 1);
     if (rc != CQ_OK) return rc;
-    hipError_t e = hipMemset(b.k, 0, sizeof(int32_t) * (size_t)G);
+    hipError_t e = hipMemset(b.k, 0, sizeof(int32_t) * (size_t)hist_entries(G));
     if (e == hipSuccess) e = hipMemset(b.stamp, 0, sizeof(int32_t) * (size_t)G);
     if (e == hipSuccess) e = hipMemset(b.bucket, 0, sizeof(int32_t) * (size_t)G);
     if (e == hipSuccess) e = hipMemset(b.lpre, 0, sizeof(int32_t) * (size_t)(G + 1));
@@ -551,7 +551,7 @@ int64_t cq_query_footprint(int64_t groups, int32_t window) {
     auto pg = [](int64_t bytes) { return (std::max<int64_t>(bytes, 1) + 4095) / 4096 * 4096; };
     const int64_t nblk = (G + PLAN_CHUNK - 1) / PLAN_CHUNK;
     int64_t b = pg(4 * G * (int64_t)window) + 2 * pg(4 * G) + pg(8 * G);  // ring, pos, cnt, sum
-    b += 7 * pg(4 * G) + pg(4 * (G + 1));                                 // per-group plan arrays
+    b += pg(4 * hist_entries(G)) + 6 * pg(4 * G) + pg(4 * (G + 1));       // histogram, per-group plan
     b += pg(4 * (NB_MAX + 1)) + pg(4 * NB_MAX);                          // bucket starts, heavy keys
     b += pg(8 * (int64_t)SUB) + pg(4 * (int64_t)PASS_TILES_MAX * (NB_MAX + 1));  // staging, runs
     b += pg(4 * nblk * PLAN_FIELDS) + pg(sizeof(PlanTotals)) + pg(4) + pg(4) + pg(8);
