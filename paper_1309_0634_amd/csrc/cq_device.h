@@ -142,22 +142,50 @@ __device__ __forceinline__ void phase_mark(const Scratch &sc, int kind, int slot
 
 // The runs of bucket b (one per tile, in tile order = arrival order): rs[t]
 // = first staged slot, rp[t] = tuples of the bucket in tiles before t,
-// rp[tiles] = bucket size.  The caller's per-group prefetch (`extra`) is
-// issued before the first barrier so its loads overlap the run loads.
-// Barriers inside.
-template <typename F>
-__device__ int bucket_runs(const Scratch &sc, int b, int NB, int tiles, int32_t *rs,
-                           int32_t *rp, int *red, F &&extra) {
-    for (int t = threadIdx.x; t < tiles; t += blockDim.x) {
+// rp[tiles] = bucket size.  runs_load issues this thread's row loads (tiles
+// tid + j * NT, clamped into [0, tiles), so that every load is issued
+// unconditionally and all are in flight together; the caller may issue its
+// own loads beside them), runs_store writes the runs to LDS and scans them
+// (barriers inside).
+template <int NT>
+struct RunRows {
+    static constexpr int R = (PASS_TILES_MAX + NT - 1) / NT;
+    int32_t s[R], e[R];
+};
+
+template <int NT>
+__device__ void runs_load(const Scratch &sc, int b, int NB, int tiles, RunRows<NT> &rr) {
+#pragma unroll
+    for (int j = 0; j < RunRows<NT>::R; ++j) {
+        const int t = min((int)threadIdx.x + j * NT, tiles - 1);
         const int32_t *row = sc.rowstart + (int64_t)t * (NB + 1);
-        const int32_t s = row[b], e = row[b + 1];
-        rs[t] = t * PASS_TILE + s;
-        rp[t] = e - s;
+        rr.s[j] = row[b];
+        rr.e[j] = row[b + 1];
     }
-    extra();
+}
+
+template <int NT>
+__device__ int runs_store(int tiles, const RunRows<NT> &rr, int32_t *rs, int32_t *rp, int *red) {
+#pragma unroll
+    for (int j = 0; j < RunRows<NT>::R; ++j) {
+        const int t = (int)threadIdx.x + j * NT;
+        if (t < tiles) {
+            rs[t] = t * PASS_TILE + rr.s[j];
+            rp[t] = rr.e[j] - rr.s[j];
+        }
+    }
     __syncthreads();
     block_excl_scan_array(rp, tiles, red);
     return rp[tiles];
+}
+
+// Both steps with nothing between them (NT threads per block).
+template <int NT>
+__device__ int bucket_runs(const Scratch &sc, int b, int NB, int tiles, int32_t *rs,
+                           int32_t *rp, int *red) {
+    RunRows<NT> rr;
+    runs_load<NT>(sc, b, NB, tiles, rr);
+    return runs_store<NT>(tiles, rr, rs, rp, red);
 }
 
 }  // namespace cq

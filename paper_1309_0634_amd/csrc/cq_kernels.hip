@@ -970,6 +970,11 @@ static_assert(LIGHT_CAP % UPD_THREADS == 0, "whole positions per thread");
 // find each other with ballots over the group's start position, so a
 // tuple's rank among its group's earlier tuples is exact and stable.  Every
 // tuple among its group's last W goes to ring slot (pos + rank) mod W.
+// IN_LDS: the bucket's groups span at most LIGHT_SPAN ids and their
+// staged-range starts and old ring pointers were prefetched into LDS (a
+// template parameter, so that each read is a plain LDS or global load, never
+// a generic one that the compiler must wait on as both).
+template <bool IN_LDS>
 __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const State &st,
                             const Scratch &sc, const Out &out, char *smem) {
     const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
@@ -984,7 +989,7 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
     long long *acc = reinterpret_cast<long long *>(smem + U_ACC);
     const int32_t *klp = reinterpret_cast<const int32_t *>(smem + U_KLP);
     const int32_t *kpo = reinterpret_cast<const int32_t *>(smem + U_KPO);
-    const bool in_lds = z - a <= LIGHT_SPAN;
+    constexpr bool in_lds = IN_LDS;
     // staged-range start (relative to the bucket) and old ring pointer of g
     auto lp = [&](int32_t g) { return in_lds ? klp[g - a] : sc.lpre[g]; };
     auto po = [&](int32_t g) { return in_lds ? kpo[g - a] : sc.pold[g]; };
@@ -1060,7 +1065,9 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
         hd[p] = -1;
         acc[p] = 0;
     }
-    for (int i = tid; i < UPD_WAVES * size; i += blockDim.x) cw[(i / size) * LIGHT_CAP + i % size] = 0;
+    for (int i = tid; i < size; i += UPD_THREADS)
+#pragma unroll
+        for (int w = 0; w < UPD_WAVES; ++w) cw[w * LIGHT_CAP + i] = 0;
     __syncthreads();
     phase_mark(sc, PHASE_UPDATE, 2);
     // ranks inside each wave's chunk of the arrival order
@@ -1107,30 +1114,37 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
     constexpr int GPT = LIGHT_SPAN / UPD_THREADS;
     int64_t gsum[GPT];
     int32_t gcnt[GPT], gtix[GPT];
+    // (every load is issued, from group a where the thread has no touched
+    // group, and the values are selected afterwards: a load under a
+    // divergent branch would be waited on before the next one is issued)
     if (in_lds) {
 #pragma unroll
         for (int j = 0; j < GPT; ++j) {
             const int32_t g = a + tid + j * UPD_THREADS;
             const bool t = g < z && klp[g - a + 1] > klp[g - a];
-            // a group with at least W tuples here has its window replaced
-            // whole: its new sum is the survivors' sum alone
-            gsum[j] = (t && klp[g - a + 1] - klp[g - a] < W) ? st.sum[g] : 0;
-            gcnt[j] = t ? sc.ncnt[g] : 0;
-            gtix[j] = t ? sc.tidx[g] : 0;
+            const int32_t gl = t ? g : a;
+            gsum[j] = st.sum[gl];  // (raw: read only for a touched group, below)
+            gcnt[j] = sc.ncnt[gl];
+            gtix[j] = sc.tidx[gl];
         }
     }
     // ring update: every survivor's old value is loaded before any store
+    // (unconditionally, from the ring's first cell where there is none to
+    // read, so that the loads are in flight together)
     int32_t *cells[SPT];
     int32_t olds[SPT];
+    bool keep[SPT];  // the old value counts: a survivor whose window is not replaced
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
         const int p = tid + j * UPD_THREADS;
         cells[j] = nullptr;
-        olds[j] = 0;
+        keep[j] = false;
         if (p >= size) continue;
         const int p0 = pz[p];
         if (p0 < 0) continue;
-        const int w = p / chunk;
+        int w = 0;  // the wave whose chunk holds p
+#pragma unroll
+        for (int k = 1; k < UPD_WAVES; ++k) w += p >= k * chunk ? 1 : 0;
         const int32_t g = ek[p];
         const int32_t rank = cw[w * LIGHT_CAP + p0] + lr[p];
         const int32_t kg = lp(g + 1) - lp(g);
@@ -1139,8 +1153,13 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
         if (rank >= kg - need && rank < kg) {
             const uint32_t slot = ((uint32_t)po(g) + (uint32_t)rank) % (uint32_t)W;
             cells[j] = st.ring + (int64_t)g * W + slot;
-            if (kg < W) olds[j] = *cells[j];
+            keep[j] = kg < W;
         }
+    }
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {  // (an index, so that the load stays a global one)
+        const int32_t o = st.ring[cells[j] ? cells[j] - st.ring : 0];
+        olds[j] = keep[j] ? o : 0;
     }
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
@@ -1158,7 +1177,10 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
         for (int j = 0; j < GPT; ++j) {
             const int32_t g = a + tid + j * UPD_THREADS;
             if (g < z && klp[g - a + 1] > klp[g - a]) {
-                const int64_t s = gsum[j] + acc[klp[g - a] - s0];
+                // a group with at least W tuples here has its window
+                // replaced whole: its new sum is the survivors' sum alone
+                const int64_t s = (klp[g - a + 1] - klp[g - a] < W ? gsum[j] : 0) +
+                                  acc[klp[g - a] - s0];
                 st.sum[g] = s;
                 if (out.n_touched) emit_one(out, gtix[j], g, s, gcnt[j]);
             }
@@ -1188,14 +1210,10 @@ __device__ int heavy_bucket(int32_t g, int32_t pold_g, int size, int tiles, cons
     const int32_t need = size < W ? size : W;
     const bool full = size >= W;
     const uint32_t po = (uint32_t)pold_g;
-    // loaded early: their latency overlaps the survivors' loads
-    int64_t gsum = 0;
-    int32_t gcnt = 0, gtix = 0;
-    if (tid == 0) {
-        gsum = full ? 0 : st.sum[g];  // a window replaced whole restarts at 0
-        gcnt = sc.ncnt[g];
-        gtix = sc.tidx[g];
-    }
+    // loaded early, by every thread (one address), so that no wait on them
+    // comes before the survivors' loads are issued
+    const int64_t gsum_old = st.sum[g];
+    const int32_t gcnt = sc.ncnt[g], gtix = sc.tidx[g];
     long long acc = 0;
     // (a run table as in light buckets would cost one thread a serial loop
     // over a hot group's whole run in the last tile; a binary search per
@@ -1205,29 +1223,29 @@ __device__ int heavy_bucket(int32_t g, int32_t pold_g, int size, int tiles, cons
     for (int p0 = size - need + tid; p0 < size; p0 += HU * UPD_THREADS) {
         int32_t vals[HU], olds[HU];
         int32_t *cells[HU];
+        // positions past the bucket are clamped onto its last one, so every
+        // load is issued unconditionally; only real positions store
 #pragma unroll
         for (int u = 0; u < HU; ++u) {
             const int p = p0 + u * UPD_THREADS;
-            cells[u] = nullptr;
-            vals[u] = olds[u] = 0;
-            if (p < size) {
-                const int r = upper_run(rp, tiles, p);
-                vals[u] = sc.sdat[rs[r] + (p - rp[r])].y;
-                const uint32_t slot = (po + (uint32_t)p) % (uint32_t)W;
-                cells[u] = st.ring + (int64_t)g * W + slot;
-                if (!full) olds[u] = *cells[u];
-            }
+            const int pc = p < size ? p : size - 1;
+            const int r = upper_run(rp, tiles, pc);
+            vals[u] = sc.sdat[rs[r] + (pc - rp[r])].y;
+            const uint32_t slot = (po + (uint32_t)pc) % (uint32_t)W;
+            int32_t *cell = st.ring + (int64_t)g * W + slot;
+            cells[u] = p < size ? cell : nullptr;
+            olds[u] = *cell;  // (dropped below for a window replaced whole)
         }
 #pragma unroll
         for (int u = 0; u < HU; ++u)
             if (cells[u]) {
                 *cells[u] = vals[u];
-                acc += (long long)vals[u] - (long long)olds[u];
+                acc += (long long)vals[u] - (full ? 0LL : (long long)olds[u]);
             }
     }
     const long long delta = block_sum_ll(acc, red_ll);
     if (tid == 0) {
-        const int64_t s = gsum + delta;
+        const int64_t s = (full ? 0 : gsum_old) + delta;  // a window replaced whole restarts at 0
         st.sum[g] = s;
         if (out.n_touched) emit_one(out, gtix, g, s, gcnt);
     }
@@ -1339,25 +1357,46 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_balanced(State st, Scrat
     const int first = ub / XCDS < per_xcd ? b_lo + ub / XCDS : NB;
     for (int b = first; b < b_hi; b += per_xcd) {
         const bool light = b < t.n_light_buckets;
-        int32_t a = 0, z = 0, g = 0, pold_g = 0;
+        int32_t a = 0, z = 0, g = 0;
         if (light) {
             a = sc.bstart[b];
             z = sc.bstart[b + 1];
         } else {
             g = sc.hkey[b - t.n_light_buckets];
-            pold_g = sc.pold[g];
         }
-        const int size = bucket_runs(sc, b, NB, tiles, rs, rp, red, [&] {
-            if (light && z - a <= LIGHT_SPAN) {
-                for (int i = threadIdx.x; i <= z - a; i += blockDim.x) {
-                    klp[i] = sc.lpre[a + i];
-                    if (i < z - a) kpo[i] = sc.pold[a + i];
-                }
+        // The bucket's runs, and (a light bucket of at most LIGHT_SPAN
+        // groups) its groups' staged-range starts and old ring pointers for
+        // LDS: every load is issued before any is waited on (indexes
+        // clamped into the bucket's groups, values kept only where in range).
+        RunRows<UPD_THREADS> rr;
+        runs_load<UPD_THREADS>(sc, b, NB, tiles, rr);
+        const int32_t pold_g = sc.pold[light ? a : g];  // read by a heavy bucket only
+        constexpr int KPT = LIGHT_SPAN / UPD_THREADS;
+        int32_t pl[KPT + 1], pp[KPT];
+        const int m = z - a;  // groups of a light bucket (at least 1)
+        const bool pre = light && m <= LIGHT_SPAN;
+        if (pre) {
+#pragma unroll
+            for (int j = 0; j <= KPT; ++j)
+                pl[j] = sc.lpre[a + min((int)threadIdx.x + j * UPD_THREADS, m)];
+#pragma unroll
+            for (int j = 0; j < KPT; ++j)
+                pp[j] = sc.pold[a + max(0, min((int)threadIdx.x + j * UPD_THREADS, m - 1))];
+        }
+        if (pre) {
+#pragma unroll
+            for (int j = 0; j <= KPT; ++j) {
+                const int i = (int)threadIdx.x + j * UPD_THREADS;
+                if (i <= m) klp[i] = pl[j];
+                if (j < KPT && i < m) kpo[i] = pp[j];
             }
-        });
+        }
+        const int size = runs_store<UPD_THREADS>(tiles, rr, rs, rp, red);
         if (b == first) phase_mark(sc, PHASE_UPDATE, 1);
         if (light)
-            tuples += light_bucket(a, z, size, tiles, st, sc, out, smem);
+            tuples += z - a <= LIGHT_SPAN
+                          ? light_bucket<true>(a, z, size, tiles, st, sc, out, smem)
+                          : light_bucket<false>(a, z, size, tiles, st, sc, out, smem);
         else
             tuples += heavy_bucket(g, pold_g, size, tiles, st, sc, out, smem, red_ll);
         // clear the bucket's histogram entries for the next sub-batch (the

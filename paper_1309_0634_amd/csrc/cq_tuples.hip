@@ -152,7 +152,7 @@ __device__ void light_item(int b, int NB, int tiles, const State &st, const Scra
     const int32_t a = sc.bstart[b], z = sc.bstart[b + 1];
     const int32_t s0 = sc.lpre[a];
     const int size = sc.lpre[z] - s0;
-    const int total = bucket_runs(sc, b, NB, tiles, rs, rp, red, [] {});
+    const int total = bucket_runs<PT_THREADS>(sc, b, NB, tiles, rs, rp, red);
     if (size <= 0) return;
     if (size > LIGHT_CAP || total != size) {
         if (tid == 0) atomicOr(sc.fault, FAULT_TUPLE_RUNS);
@@ -276,7 +276,7 @@ __device__ void heavy_item(int x, int c, int nl, int NB, int tiles, const State 
     const int32_t W = st.W;
     const int32_t g = sc.hkey[x];
     const int32_t kg = sc.k[g];
-    const int total = bucket_runs(sc, nl + x, NB, tiles, rs, rp, red, [] {});
+    const int total = bucket_runs<PT_THREADS>(sc, nl + x, NB, tiles, rs, rp, red);
     if (total != kg) {
         if (tid == 0) atomicOr(sc.fault, FAULT_TUPLE_RUNS);
         return;
