@@ -25,6 +25,7 @@ constexpr int HIST_KPT = 8;
 constexpr int HIST_TILE = HIST_THREADS * HIST_KPT;
 constexpr int HIST_DIRECT_MAX_G = 32768;
 constexpr int HIST_HASH_TILE = 4096;   // 256 workgroups for a 2^20 sub-batch
+static_assert(HIST_HASH_TILE % HIST_THREADS == 0, "whole keys per thread in a hashed tile");
 constexpr int HIST_HASH_LOG = 13;
 constexpr int HIST_HASH_SLOTS = 1 << HIST_HASH_LOG;
 static_assert(HIST_HASH_SLOTS >= 2 * HIST_HASH_TILE, "hash load factor <= 1/2");

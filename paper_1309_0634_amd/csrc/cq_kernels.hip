@@ -435,9 +435,17 @@ __global__ __launch_bounds__(HIST_THREADS) void k_hist_hash(const int32_t *__res
     __syncthreads();
     const int64_t b0 = (int64_t)blockIdx.x * HIST_HASH_TILE;
     const int64_t b1 = min(n, b0 + HIST_HASH_TILE);
+    // all of the thread's keys are loaded before any is hashed (indexes
+    // clamped into the batch, n >= 1; positions past the tile are skipped)
+    constexpr int KPT = HIST_HASH_TILE / HIST_THREADS;
+    int32_t kv[KPT];
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) kv[j] = keys[min(b0 + tid + j * HIST_THREADS, n - 1)];
     int bad = 0;
-    for (int64_t i = b0 + tid; i < b1; i += HIST_THREADS) {
-        const int32_t key = view_key(keys[i], sc.kmod, G);
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+        if (b0 + tid + j * HIST_THREADS >= b1) continue;
+        const int32_t key = view_key(kv[j], sc.kmod, G);
         if (key < 0 || (int64_t)key >= G) bad = 1;
         else atomicAdd(&hc[hash_slot(hk, key)], 1);
     }

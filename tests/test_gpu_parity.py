@@ -301,6 +301,30 @@ def test_fused_push_results_matches_split_calls():
     q.close()
 
 
+@pytest.mark.parametrize("mode,G,s", [(cq.PARTITION_STATIC, 10_000, 0.0),
+                                       (cq.PARTITION_STATIC, 16_384, 1.5),
+                                       (cq.PARTITION_STATIC, 40_000, 1.0),
+                                       (cq.PARTITION_BALANCED, 16_384, 0.0),
+                                       (cq.PARTITION_BALANCED, 40_000, 0.5)],
+                         ids=["static4096-g10000-s0", "static4096-g16384-s1.5",
+                              "static4096-g40000-s1", "balanced-g16384-s0",
+                              "balanced-g40000-s0.5"])
+def test_most_buckets_per_pass(mode, G, s):
+    """The most buckets a reorder pass sees: a static partition of 4096
+    workers (bucket ids up to 4095, every entry of the multisplit's per-wave
+    leader table) and uniform keys under the balanced partition (about 2048
+    light buckets), on the in-block plan (G <= 16384) and the separate one;
+    batches ragged across tiles and sub-batches."""
+    note(f"case: most buckets mode {mode} G={G} s={s}")
+    cfg = StreamConfig(f"most_buckets_g{G}_s{s:g}", 9, G, 300, 1 << 20, 3,
+                       "zipf" if s > 0 else "uniform", zipf_s=s, s_index=int(s * 10))
+    p = Pair(G, cfg.window, mode, 4096 if mode == cq.PARTITION_STATIC else 0, oracle_threads=4)
+    for b, n in enumerate([(1 << 20) + 13, 300_001, 4096 * 5 + 1]):
+        k, v = host_batch(cfg, b, n)
+        p.step(k, v, f"most buckets batch {b} (n={n})")
+    p.close()
+
+
 def test_static_partition_limits():
     note("case: static limits")
     q = cq.Query(1 << 20, 4)
