@@ -108,6 +108,11 @@ __device__ void bitonic_sort(int32_t *a, int m) {
     }
 }
 
+// Marks a loaded value as used here, so that the compiler keeps its load
+// where it was issued (beside the others) rather than sinking it into the
+// branch that uses it, where it would wait alone.
+__device__ __forceinline__ void keep(int32_t &x) { __asm__ volatile("" : "+v"(x)); }
+
 // Slot x of group g's eviction order (the slot insertion x overwrites).
 __device__ __forceinline__ int32_t old_slot(const int32_t *row, int32_t po, int x, int32_t W) {
     return row[((uint32_t)po + (uint32_t)x) % (uint32_t)W];
@@ -149,10 +154,15 @@ __device__ void light_item(int b, int NB, int tiles, const State &st, const Scra
     int32_t *li = reinterpret_cast<int32_t *>(smem + L_I);
     long long *ps = reinterpret_cast<long long *>(smem + L_PS);
     const int32_t W = st.W;
+    // the run rows depend on b alone: they are in flight while the bucket's
+    // light prefix is read (the bounds are issued first: loads complete in
+    // order, so waiting on them does not wait on the rows)
     const int32_t a = sc.bstart[b], z = sc.bstart[b + 1];
+    RunRows<PT_THREADS> rr;
+    runs_load<PT_THREADS>(sc, b, NB, tiles, rr);
     const int32_t s0 = sc.lpre[a];
     const int size = sc.lpre[z] - s0;
-    const int total = bucket_runs<PT_THREADS>(sc, b, NB, tiles, rs, rp, red);
+    const int total = runs_store<PT_THREADS>(tiles, rr, rs, rp, red);
     if (size <= 0) return;
     if (size > LIGHT_CAP || total != size) {
         if (tid == 0) atomicOr(sc.fault, FAULT_TUPLE_RUNS);
@@ -160,16 +170,41 @@ __device__ void light_item(int b, int NB, int tiles, const State &st, const Scra
     }
     int m = 1;
     while (m < size) m <<= 1;
-    for (int p = tid; p < m; p += blockDim.x) {
-        if (p < size) {
-            const int r = upper_run(rp, tiles, p);
-            const int64_t pos = rs[r] + (p - rp[r]);
-            const int2 e = sc.sdat[pos];
-            lv[p] = e.y;
-            li[p] = sc.sidx[pos];
-            ck[p] = ((e.x - a) << 10) | p;
-        } else {
-            ck[p] = INT_MAX;
+    constexpr int PPT = LIGHT_CAP / PT_THREADS;
+    {
+        // all of a thread's gathers are issued before any is used
+        // (positions past the bucket are clamped onto its last one)
+        // (the run searches first: a search is a loop, and loads issued
+        // before one would be waited on where it starts)
+        int2 ge[PPT];
+        int32_t gi[PPT], gp[PPT];
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            const int pc = min(tid + u * PT_THREADS, size - 1);
+            const int r = upper_run(rp, tiles, pc);
+            gp[u] = rs[r] + (pc - rp[r]);
+        }
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            ge[u] = sc.sdat[gp[u]];
+            gi[u] = sc.sidx[gp[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            keep(ge[u].x);
+            keep(ge[u].y);
+            keep(gi[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            const int p = tid + u * PT_THREADS;
+            if (p < size) {
+                lv[p] = ge[u].y;
+                li[p] = gi[u];
+                ck[p] = ((ge[u].x - a) << 10) | p;
+            } else if (p < m) {
+                ck[p] = INT_MAX;
+            }
         }
     }
     __syncthreads();
@@ -185,7 +220,6 @@ __device__ void light_item(int b, int NB, int tiles, const State &st, const Scra
     }
     __syncthreads();
     // values and arrival indices into sorted (group, rank) order
-    constexpr int PPT = LIGHT_CAP / PT_THREADS;
     int32_t tv[PPT], ti[PPT];
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
@@ -206,23 +240,47 @@ __device__ void light_item(int b, int NB, int tiles, const State &st, const Scra
         }
     }
     __syncthreads();
+    // Per sorted position q: its group, the group's staged start, old ring
+    // pointer, sum and count before the batch.  Every load of a kind is
+    // issued for all of a thread's positions before any is used (positions
+    // past the bucket are clamped onto its last one and not written).
+    int32_t gq[PPT], lq[PPT], pq[PPT], cq[PPT];
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) gq[u] = a + (ck[min(tid + u * PT_THREADS, size - 1)] >> 10);
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+        lq[u] = sc.lpre[gq[u]];
+        pq[u] = sc.pold[gq[u]];
+        cq[u] = sc.pcnt[gq[u]];
+    }
     if (out.passes == 0) {
-        for (int q = tid; q < size; q += blockDim.x) {
-            const int32_t g = a + (ck[q] >> 10);
-            const int gs = sc.lpre[g] - s0;
-            const int r = q - gs;
-            const int32_t ev = r < W ? old_slot(st.ring + (int64_t)g * W, sc.pold[g], r, W)
-                                     : lv[q - W];
+        long long sq0[PPT];
+        int32_t oq[PPT];
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) sq0[u] = st.sum[gq[u]];
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {  // the slot rank r overwrites (read whatever r is)
+            const int r = min(tid + u * PT_THREADS, size - 1) - (lq[u] - s0);
+            oq[u] = old_slot(st.ring + (int64_t)gq[u] * W, pq[u], r, W);
+        }
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            const int q = tid + u * PT_THREADS;
+            if (q >= size) continue;
+            const int r = q - (lq[u] - s0);
+            const int32_t ev = r < W ? oq[u] : lv[q - W];
             ps[q] = (long long)lv[q] - (long long)ev;
         }
         __syncthreads();
         block_incl_scan_ll(ps, size, reinterpret_cast<long long *>(red));
-        for (int q = tid; q < size; q += blockDim.x) {
-            const int32_t g = a + (ck[q] >> 10);
-            const int gs = sc.lpre[g] - s0;
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            const int q = tid + u * PT_THREADS;
+            if (q >= size) continue;
+            const int gs = lq[u] - s0;
             const int r = q - gs;
-            const long long s = st.sum[g] + ps[q] - (gs > 0 ? ps[gs - 1] : 0);
-            const int32_t c = (int32_t)min((int64_t)W, (int64_t)sc.pcnt[g] + r + 1);
+            const long long s = sq0[u] + ps[q] - (gs > 0 ? ps[gs - 1] : 0);
+            const int32_t c = (int32_t)min((int64_t)W, (int64_t)cq[u] + r + 1);
             put(out, li[q], s, c);
         }
         return;
@@ -233,13 +291,16 @@ __device__ void light_item(int b, int NB, int tiles, const State &st, const Scra
     // each group's old window to LDS and rescanning with a wave per group
     // measured slower: a light group can hold up to HEAVY_MIN - 1 tuples,
     // and one wave then carries them all.)
-    for (int q = tid; q < size; q += blockDim.x) {
-        const int32_t g = a + (ck[q] >> 10);
-        const int gs = sc.lpre[g] - s0;
+#pragma unroll 1
+    for (int u = 0; u < PPT; ++u) {
+        const int q = tid + u * PT_THREADS;
+        if (q >= size) break;
+        const int32_t g = gq[u];
+        const int gs = lq[u] - s0;
         const int r = q - gs;
         const int32_t *row = st.ring + (int64_t)g * W;
         const int len = r + 1 < W ? W - (r + 1) : 0;  // old slots still in the window
-        const int s1 = (int)(((uint32_t)sc.pold[g] + (uint32_t)(r + 1)) % (uint32_t)W);
+        const int s1 = (int)(((uint32_t)pq[u] + (uint32_t)(r + 1)) % (uint32_t)W);
         const int n1 = min(len, W - s1);
         const int j0 = max(0, r + 1 - W);
         long long first = 0;
@@ -255,7 +316,7 @@ __device__ void light_item(int b, int NB, int tiles, const State &st, const Scra
             __asm__ volatile("" ::: "memory");  // the next pass reads the window again
         }
         if (!same) atomicOr(sc.fault, FAULT_PASSES);
-        const int32_t cn = (int32_t)min((int64_t)W, (int64_t)sc.pcnt[g] + r + 1);
+        const int32_t cn = (int32_t)min((int64_t)W, (int64_t)cq[u] + r + 1);
         put(out, li[q], first, cn);
     }
 }
@@ -274,9 +335,11 @@ __device__ void heavy_item(int x, int c, int nl, int NB, int tiles, const State 
     int32_t *hi = reinterpret_cast<int32_t *>(smem + H_I);
     long long *ps = reinterpret_cast<long long *>(smem + H_PS);
     const int32_t W = st.W;
-    const int32_t g = sc.hkey[x];
-    const int32_t kg = sc.k[g];
-    const int total = bucket_runs<PT_THREADS>(sc, nl + x, NB, tiles, rs, rp, red);
+    const int32_t g = sc.hkey[x];  // (issued before the rows, which it does not wait on)
+    RunRows<PT_THREADS> rr;        // in flight while the group's state is read
+    runs_load<PT_THREADS>(sc, nl + x, NB, tiles, rr);
+    const int32_t kg = sc.k[g], po = sc.pold[g], cnt0 = sc.pcnt[g];
+    const int total = runs_store<PT_THREADS>(tiles, rr, rs, rp, red);
     if (total != kg) {
         if (tid == 0) atomicOr(sc.fault, FAULT_TUPLE_RUNS);
         return;
@@ -288,17 +351,46 @@ __device__ void heavy_item(int x, int c, int nl, int NB, int tiles, const State 
     const int xb = r0 == 0 ? 0 : r0 + 1;
     const int Lq = W + r1 - xb;  // <= PT_CH + PT_WMAX
     const int32_t *row = st.ring + (int64_t)g * W;
-    const int32_t po = sc.pold[g];
-    for (int j = tid; j < Lq; j += blockDim.x) {
-        const int xs = xb + j;
-        if (xs < W) {
-            sq[j] = old_slot(row, po, xs, W);
-        } else {
-            const int rank = xs - W;
+    {
+        // Both candidate loads of every staged position (an old slot and a
+        // staged tuple, indexes clamped into range) are issued before any
+        // is used; the position's own kind is kept.
+        constexpr int SPT = (H_SPAN + PT_THREADS - 1) / PT_THREADS;
+        // (the run searches first: a search is a loop, and loads issued
+        // before one would be waited on where it starts)
+        int32_t so[SPT], si[SPT], sp[SPT];
+        int2 se[SPT];
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int xs = xb + min(tid + u * PT_THREADS, Lq - 1);
+            const int rank = max(0, min(xs - W, kg - 1));
             const int r = upper_run(rp, tiles, rank);
-            const int64_t pos = rs[r] + (rank - rp[r]);
-            sq[j] = sc.sdat[pos].y;
-            if (rank >= r0) hi[rank - r0] = sc.sidx[pos];
+            sp[u] = rs[r] + (rank - rp[r]);
+        }
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int xs = xb + min(tid + u * PT_THREADS, Lq - 1);
+            so[u] = old_slot(row, po, xs, W);
+            se[u] = sc.sdat[sp[u]];
+            si[u] = sc.sidx[sp[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            keep(so[u]);
+            keep(se[u].y);
+            keep(si[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int j = tid + u * PT_THREADS;
+            if (j >= Lq) continue;
+            const int xs = xb + j;
+            if (xs < W) {
+                sq[j] = so[u];
+            } else {
+                sq[j] = se[u].y;
+                if (xs - W >= r0) hi[xs - W - r0] = si[u];
+            }
         }
     }
     __syncthreads();
@@ -307,7 +399,6 @@ __device__ void heavy_item(int x, int c, int nl, int NB, int tiles, const State 
         __syncthreads();
         block_incl_scan_ll(ps, Lq, reinterpret_cast<long long *>(red));
     }
-    const int32_t cnt0 = sc.pcnt[g];
     for (int r = r0 + tid; r < r1; r += blockDim.x) {
         const int e = W + r - xb;  // window(r) = sq[e - W + 1 .. e]
         long long s;
