@@ -211,6 +211,22 @@ def test_skew_config_prefix_all_modes(s):
         q.close()
 
 
+@pytest.mark.parametrize("s", [0.0, 0.5, 1.0, 1.5, 2.0])
+def test_skew_config_full_run_balanced(s):
+    """The whole timed configuration: all 200 batches of the 10,000-group,
+    W=1000, 1,048,576-tuple Zipf stream under the balanced partition, every
+    batch's results against the oracle's."""
+    note(f"case: skew stream s={s}, all 200 batches, balanced")
+    cfg = skew(s)
+    p = Pair(cfg.groups, cfg.window, oracle_threads=4)
+    for b in range(cfg.batches):
+        k, v = host_batch(cfg, b)
+        p.step(k, v, f"s={s} batch {b}")
+    plan = p.q.batch_plan()
+    assert plan["fault"] == 0 and plan["status"] == 0
+    p.close()
+
+
 def test_skew_sorted_ids_worst_case_for_static():
     """DS2-like order (hot keys are the smallest ids): the static worker that
     owns the first range gets nearly all the load; results stay identical."""
