@@ -493,18 +493,64 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_plan_scan(int32_t nblk, State 
     }
 }
 
+// Per-group writes of the multi-block plan.  IN_BLOCK: every block sums the
+// blocks' partials itself (those before it give its carry, all of them the
+// totals, which block 0 publishes), so no scan launch runs between the two;
+// the partials are read by every block, so this is kept to grids of at most
+// PLAN_SCAN_IN_BLOCK_MAX blocks.  Otherwise k_plan_scan left each block's
+// carry in its partials and the totals in `tot`.
+constexpr int PLAN_SCAN_IN_BLOCK_MAX = 4 * PLAN_THREADS;  // blocks (2,621,440 groups)
+
+template <bool IN_BLOCK>
 __global__ __launch_bounds__(PLAN_THREADS) void k_plan_down(State st, Scratch sc, int32_t seq,
-                                                            int mode, int32_t workers) {
+                                                            int mode, int32_t workers,
+                                                            int32_t nblk) {
     if (sc.seqp) seq = *sc.seqp;  // captured for replay: the argument would be stale
-    __shared__ int red[2 * (PLAN_THREADS / 64)];
+    __shared__ int red[2 * PLAN_FIELDS * (PLAN_THREADS / 64)];
     const int64_t G = st.G;
-    const int64_t gb = (int64_t)blockIdx.x * PLAN_CHUNK, ge = min(G, gb + PLAN_CHUNK);
+    const int me = blockIdx.x, tid = threadIdx.x;
+    const int64_t gb = (int64_t)me * PLAN_CHUNK, ge = min(G, gb + PLAN_CHUNK);
     int carry[PLAN_FIELDS];
+    int32_t status, nl;
+    if (IN_BLOCK) {
+        // every partial this thread sums is loaded before any is added
+        // (block indexes clamped into [0, nblk); the extra ones are skipped)
+        constexpr int BPT = PLAN_SCAN_IN_BLOCK_MAX / PLAN_THREADS;
+        int x[BPT][PLAN_FIELDS];
 #pragma unroll
-    for (int q = 0; q < PLAN_FIELDS; ++q) carry[q] = sc.partials[blockIdx.x * PLAN_FIELDS + q];
-    const PlanTotals t = *sc.tot;
-    plan_range(st, sc, gb, ge, carry, true, t.status, t.n_light_buckets, seq, mode, workers,
-               red);
+        for (int j = 0; j < BPT; ++j) {
+            const int b = min(tid + j * PLAN_THREADS, nblk - 1);
+#pragma unroll
+            for (int q = 0; q < PLAN_FIELDS; ++q) x[j][q] = sc.partials[b * PLAN_FIELDS + q];
+        }
+        const int32_t bad = *sc.bad;
+        int v[2 * PLAN_FIELDS] = {0, 0, 0, 0, 0, 0}, tot[2 * PLAN_FIELDS];
+#pragma unroll
+        for (int j = 0; j < BPT; ++j) {
+            const int b = tid + j * PLAN_THREADS;
+            if (b >= nblk) continue;
+#pragma unroll
+            for (int q = 0; q < PLAN_FIELDS; ++q) {
+                v[q] += b < me ? x[j][q] : 0;  // blocks before this one
+                v[PLAN_FIELDS + q] += x[j][q];  // all blocks
+            }
+        }
+        block_excl_scan<2 * PLAN_FIELDS>(v, tot, red);  // (only the totals are used)
+        const int all[PLAN_FIELDS] = {tot[PLAN_FIELDS], tot[PLAN_FIELDS + 1],
+                                      tot[PLAN_FIELDS + 2]};
+#pragma unroll
+        for (int q = 0; q < PLAN_FIELDS; ++q) carry[q] = tot[q];
+        status = bad == seq ? CQ_ERR_KEY_RANGE : 0;
+        nl = mode == MODE_STATIC ? 0 : (all[0] + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
+        if (me == 0 && tid == 0) plan_publish(st, sc, all, status, mode, workers);
+    } else {
+#pragma unroll
+        for (int q = 0; q < PLAN_FIELDS; ++q) carry[q] = sc.partials[me * PLAN_FIELDS + q];
+        const PlanTotals t = *sc.tot;
+        status = t.status;
+        nl = t.n_light_buckets;
+    }
+    plan_range(st, sc, gb, ge, carry, true, status, nl, seq, mode, workers, red);
 }
 
 // Whole-batch key check (used when a batch spans several sub-batches, so
@@ -1687,10 +1733,15 @@ hipError_t launch_plan(State st, Scratch sc, int32_t seq, int mode, int32_t work
     const int64_t nblk = (G + PLAN_CHUNK - 1) / PLAN_CHUNK;
     hipLaunchKernelGGL(k_plan_reduce, dim3((unsigned)nblk), dim3(PLAN_THREADS), 0, s, G, mode,
                        sc);
+    if (nblk <= PLAN_SCAN_IN_BLOCK_MAX) {
+        hipLaunchKernelGGL(k_plan_down<true>, dim3((unsigned)nblk), dim3(PLAN_THREADS), 0, s, st,
+                           sc, seq, mode, workers, (int32_t)nblk);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(PLAN_THREADS), 0, s, (int32_t)nblk, st, sc, seq,
                        mode, workers);
-    hipLaunchKernelGGL(k_plan_down, dim3((unsigned)nblk), dim3(PLAN_THREADS), 0, s, st, sc, seq,
-                       mode, workers);
+    hipLaunchKernelGGL(k_plan_down<false>, dim3((unsigned)nblk), dim3(PLAN_THREADS), 0, s, st, sc,
+                       seq, mode, workers, (int32_t)nblk);
     return hipGetLastError();
 }
 

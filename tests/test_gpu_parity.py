@@ -95,10 +95,13 @@ def test_heavy_groups_with_large_window():
         p.close()
 
 
-@pytest.mark.parametrize("G", [1000, 32768, 32769, 100_000])
+@pytest.mark.parametrize("G", [1000, 32768, 32769, 100_000, 2_621_440, 2_621_441, 3_000_000])
 def test_histogram_paths(G):
-    """Direct-indexed LDS counters with the plan fused into the histogram
-    (G <= 32768), and the LDS hash with the three-launch plan (larger G)."""
+    """Direct-indexed LDS counters (G <= 32768) with the plan inside the
+    reorder pass or in a launch of its own, and the LDS hash with the
+    multi-block plan (larger G): block sums, then the per-group writes with
+    every block scanning the sums itself (up to 1024 blocks of 2560 groups,
+    G <= 2,621,440), or with a scan launch between them (beyond)."""
     note(f"case: histogram path G={G}")
     rng = np.random.default_rng(G)
     p = Pair(G, 64)
