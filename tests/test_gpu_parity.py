@@ -130,11 +130,16 @@ def test_unaligned_and_ragged_inputs():
     p.close()
 
 
-def test_bad_key_rejects_batch_and_keeps_state():
-    note("case: bad key")
+@pytest.mark.parametrize("G", [100, 20_000, 100_000, 3_000_000],
+                         ids=["in-pass-plan", "plan-launch", "two-launch-plan",
+                              "three-launch-plan"])
+def test_bad_key_rejects_batch_and_keeps_state(G):
+    """A bad key rejects its whole batch and leaves every window as it was,
+    on each of the four plan paths."""
+    note(f"case: bad key G={G}")
     import torch
     rng = np.random.default_rng(11)
-    G, W = 100, 5
+    W = 5
     p = Pair(G, W)
     k = rng.integers(0, G, 5000).astype(np.int32)
     v = rng.integers(0, 100, 5000).astype(np.int32)
