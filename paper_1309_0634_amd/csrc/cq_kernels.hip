@@ -644,13 +644,18 @@ __device__ int pass_local_plan(const State &st, const Scratch &sc, int32_t seq, 
     const bool track = me == 0;
     Top2 top;
 #pragma unroll
-    for (int j = 0; j < PL_PER; ++j) {
-        int x[PLAN_FIELDS];
-        key_fields(kv[j], mode, x);
-        sA += x[0];
-        sB += x[1] | (x[2] << 16);
-        if (track && kv[j] > 0)
-            top.add(((unsigned long long)(uint32_t)kv[j] << 32) | (uint32_t)(g0 + j));
+    for (int q = 0; q < PL_PER / 4; ++q) {
+        if (4 * q >= R) break;  // (R is the same in every thread: a uniform branch)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = 4 * q + e;
+            int x[PLAN_FIELDS];
+            key_fields(kv[j], mode, x);
+            sA += x[0];
+            sB += x[1] | (x[2] << 16);
+            if (track && kv[j] > 0)
+                top.add(((unsigned long long)(uint32_t)kv[j] << 32) | (uint32_t)(g0 + j));
+        }
     }
     // the run's counts into LDS (zeros past G included): the bucket loop
     // below reads them back there rather than keeping every count live
@@ -963,8 +968,13 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(const int32_t *__restrict
         }
     }
     __syncthreads();
+    // two staged tuples per 16-byte store (the tile starts 32 KB-aligned;
+    // an odd last tuple of a ragged tile is stored alone)
     int2 *dst = sc.sdat + base;
-    for (int i = tid; i < tile_n; i += PASS_THREADS) dst[i] = stage[i];
+    const int4 *st4 = reinterpret_cast<const int4 *>(stage);
+    int4 *dst4 = reinterpret_cast<int4 *>(dst);
+    for (int i = tid; i < tile_n / 2; i += PASS_THREADS) dst4[i] = st4[i];
+    if ((tile_n & 1) && tid == 0) dst[tile_n - 1] = stage[tile_n - 1];
     int32_t *row = sc.rowstart + (int64_t)blockIdx.x * (NB + 1);
     for (int b = tid; b <= NB; b += PASS_THREADS) row[b] = ts[b];
     phase_mark(sc, PHASE_PASS, 4);
