@@ -1067,12 +1067,11 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
     // LDS read instead of a binary search over the runs: mark each
     // non-empty run's tile at its first position, then a running maximum
     // over the positions (tile ids grow with position).  lr is free until
-    // the ranks.
+    // the ranks; the caller cleared it before the barrier that stored the
+    // runs.
     uint8_t *rt = reinterpret_cast<uint8_t *>(lr);
     {
         constexpr int PPT = LIGHT_CAP / UPD_THREADS;
-        for (int p = tid; p < size; p += blockDim.x) rt[p] = 0;
-        __syncthreads();
         for (int r = tid; r < tiles; r += blockDim.x)
             if (rp[r + 1] > rp[r]) rt[rp[r]] = (uint8_t)r;
         __syncthreads();
@@ -1455,6 +1454,9 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_balanced(State st, Scrat
                 if (j < KPT && i < m) kpo[i] = pp[j];
             }
         }
+        if (light)  // the light bucket's run table (LIGHT_CAP bytes) starts clear
+            for (int i = threadIdx.x; i < LIGHT_CAP / 4; i += UPD_THREADS)
+                reinterpret_cast<uint32_t *>(smem + U_LR)[i] = 0;
         const int size = runs_store<UPD_THREADS>(tiles, rr, rs, rp, red);
         if (b == first) phase_mark(sc, PHASE_UPDATE, 1);
         if (light)
