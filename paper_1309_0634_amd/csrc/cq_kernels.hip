@@ -1126,7 +1126,6 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
         ev[p] = e.y;
         pz[p] = (int16_t)p0;
         hd[p] = -1;
-        acc[p] = 0;
     }
     for (int i = tid; i < size; i += UPD_THREADS)
 #pragma unroll
@@ -1137,19 +1136,30 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
     const int chunk = (size + UPD_WAVES - 1) / UPD_WAVES;
     const int c0 = min(size, wv * chunk), c1 = min(size, c0 + chunk);
     uint16_t *mycw = cw + wv * LIGHT_CAP;
-    const int pbits = size > 1 ? 32 - __clz(size - 1) : 0;  // bits of positions < size
+    // The lanes of a round that hold one group elect one of them through a
+    // per-wave byte table indexed by the group's start position (in `acc`,
+    // which is free until the ring update and cleared after the ranks), as
+    // the reorder pass does for buckets: 6 ballots over the elected lane id.
+    uint8_t *lead = reinterpret_cast<uint8_t *>(acc) + wv * LIGHT_CAP;
     for (int r0 = c0; r0 < c1; r0 += 64) {
         const int p = r0 + lane;
         const bool valid = p < c1 && pz[p] >= 0;
         const int p0 = valid ? pz[p] : 0;
+        if (valid)
+            __hip_atomic_store(lead + p0, (uint8_t)lane, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WAVEFRONT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int L = valid ? (int)__hip_atomic_load(lead + p0, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WAVEFRONT)
+                            : 0;
         uint64_t m = ballot(valid);
 #pragma unroll
-        for (int bit = 0; bit < LIGHT_BITS; ++bit) {
-            if (bit < pbits) {
-                const bool on = (p0 >> bit) & 1;
-                const uint64_t bb = ballot(on);
-                m &= on ? bb : ~bb;
-            }
+        for (int bit = 0; bit < 6; ++bit) {
+            const bool on = (L >> bit) & 1;
+            const uint64_t bb = ballot(on);
+            m &= on ? bb : ~bb;
         }
         if (valid) {
             const uint64_t below = m & lanemask_lt();
@@ -1160,7 +1170,9 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
     }
     __syncthreads();
     // each group's count per wave -> the wave's offset inside the group
+    // (and the sum deltas cleared: the leader tables are done with)
     for (int i = tid; i < size; i += blockDim.x) {
+        acc[i] = 0;
         int sacc = 0;
 #pragma unroll
         for (int w = 0; w < UPD_WAVES; ++w) {
