@@ -1102,9 +1102,23 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
         const int p = tid + j * UPD_THREADS;
+        st_e[j] = make_int2(a, 0);
         if (p < size) {
             const int r = rt[p];
             st_e[j] = sc.sdat[rs[r] + (p - rp[r])];
+        }
+    }
+    // Without the LDS copy, each tuple's group bounds in the staged order
+    // are read from global memory all at once, before any is used (a key
+    // outside the bucket reads group a's, and is flagged below).
+    int32_t l0v[SPT], l1v[SPT];
+    if constexpr (!IN_LDS) {
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) {
+            const int32_t g = st_e[j].x;
+            const int32_t gc = g >= a && g < z ? g : a;
+            l0v[j] = lp(gc);
+            l1v[j] = lp(gc + 1);
         }
     }
 #pragma unroll
@@ -1115,8 +1129,8 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
         const int32_t g = e.x;
         int32_t p0 = -1;
         if (g >= a && g < z) {
-            const int32_t l0 = lp(g);
-            if (lp(g + 1) > l0) p0 = l0 - s0;
+            const int32_t l0 = IN_LDS ? lp(g) : l0v[j];
+            if ((IN_LDS ? lp(g + 1) : l1v[j]) > l0) p0 = l0 - s0;
         }
         if (p0 < 0 || p0 >= size) {  // impossible for a well-formed plan
             atomicOr(sc.fault, FAULT_LIGHT_SIZE);
@@ -1209,6 +1223,19 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
     int32_t *cells[SPT];
     int32_t olds[SPT];
     bool keep[SPT];  // the old value counts: a survivor whose window is not replaced
+    // (without the LDS copy, each position's group bounds and old ring
+    // pointer are read from global memory all at once, group a where the
+    // position has none)
+    int32_t kq[SPT], oq[SPT];
+    if constexpr (!IN_LDS) {
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) {
+            const int p = tid + j * UPD_THREADS;
+            const int32_t g = p < size && pz[p] >= 0 ? ek[p] : a;
+            kq[j] = lp(g + 1) - lp(g);
+            oq[j] = po(g);
+        }
+    }
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
         const int p = tid + j * UPD_THREADS;
@@ -1222,11 +1249,12 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
         for (int k = 1; k < UPD_WAVES; ++k) w += p >= k * chunk ? 1 : 0;
         const int32_t g = ek[p];
         const int32_t rank = cw[w * LIGHT_CAP + p0] + lr[p];
-        const int32_t kg = lp(g + 1) - lp(g);
+        const int32_t kg = IN_LDS ? lp(g + 1) - lp(g) : kq[j];
         if (rank == 0) hd[p0] = (int16_t)p;
         const int32_t need = kg < W ? kg : W;
         if (rank >= kg - need && rank < kg) {
-            const uint32_t slot = ((uint32_t)po(g) + (uint32_t)rank) % (uint32_t)W;
+            const uint32_t slot =
+                ((uint32_t)(IN_LDS ? po(g) : oq[j]) + (uint32_t)rank) % (uint32_t)W;
             cells[j] = st.ring + (int64_t)g * W + slot;
             keep[j] = kg < W;
         }
@@ -1261,12 +1289,28 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
             }
         }
     } else {
-        for (int i = tid; i < size; i += blockDim.x) {
-            const int32_t g = hd[i] >= 0 ? ek[hd[i]] : -1;
+        // the touched groups' state, all read before any is used (group a
+        // where a position heads no group)
+        int32_t gh[SPT], kh[SPT], th[SPT], nh[SPT];
+        int64_t sh[SPT];
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) {
+            const int i = tid + j * UPD_THREADS;
+            gh[j] = i < size && hd[i] >= 0 ? ek[hd[i]] : -1;
+            const int32_t g = gh[j] >= 0 ? gh[j] : a;
+            kh[j] = lp(g + 1) - lp(g);
+            sh[j] = st.sum[g];
+            th[j] = sc.tidx[g];
+            nh[j] = sc.ncnt[g];
+        }
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) {
+            const int i = tid + j * UPD_THREADS;
+            const int32_t g = gh[j];
             if (g >= 0) {
-                const int64_t s = (lp(g + 1) - lp(g) >= W ? 0 : st.sum[g]) + acc[i];
+                const int64_t s = (kh[j] >= W ? 0 : sh[j]) + acc[i];
                 st.sum[g] = s;
-                if (out.n_touched) emit_one(out, sc.tidx[g], g, s, sc.ncnt[g]);
+                if (out.n_touched) emit_one(out, th[j], g, s, nh[j]);
             }
         }
     }
