@@ -157,12 +157,16 @@ int cq_policy_stats(cq_query *q, int64_t *out);
  * under that technique).  The mapping is given and returned as ordered
  * lists: worker w's groups are wlist[wstart[w] .. wstart[w+1]) (wstart has
  * workers+1 entries, wlist `groups`; every group exactly once).  counts[g]
- * are the batch's tuples of group g.  *moves receives the number of groups
- * moved.  Returns CQ_OK or CQ_ERR_INVALID (bad arguments or mapping).
+ * are the batch's tuples of group g.  keys[0 .. n) are the batch's group
+ * ids in arrival order (host array): probCheck reads the tuples of the most
+ * loaded worker in that order (Figure alg3) and needs them, with counts
+ * equal to their histogram; the other techniques ignore them (keys may be
+ * NULL with n = 0).  *moves receives the number of groups moved.  Returns
+ * CQ_OK or CQ_ERR_INVALID (bad arguments, mapping, or keys).
  */
 int cq_policy_apply(int32_t policy, int32_t workers, int64_t groups, const int32_t *counts,
-                    int32_t *wstart, int32_t *wlist, int64_t threshold, double pot,
-                    int32_t max_keys, int64_t *moves);
+                    const int32_t *keys, int64_t n, int32_t *wstart, int32_t *wlist,
+                    int64_t threshold, double pot, int32_t max_keys, int64_t *moves);
 
 /*
  * cq_push_batch -- apply one batch of n tuples (Section 3.1: one iteration
@@ -174,7 +178,11 @@ int cq_policy_apply(int32_t policy, int32_t workers, int64_t groups, const int32
  *   n            : 0 .. CQ_MAX_BATCH; n = 0 is a valid batch touching nothing.
  *   stream       : hipStream_t (void*), NULL = default stream.
  * Enqueues the whole update on `stream` and returns without waiting for the
- * device (unless the scratch must grow, see cq_reserve).  Host-side errors
+ * device; the only exception is a query under one of the Section 4
+ * techniques (cq_set_partition), whose host step waits for the batch's
+ * histogram.  Every working buffer was sized by cq_create, so the call
+ * allocates nothing (cq_set_telemetry's records are allocated at the first
+ * push after they are turned on).  Host-side errors
  * (q NULL, n out of range, NULL arrays with n > 0) return CQ_ERR_INVALID and
  * enqueue nothing.  A key outside [0, groups) is found on the device: the
  * whole batch is rejected, the windows are left unchanged, and the next

@@ -21,9 +21,11 @@ Where the paper leaves a choice open, these readings are taken:
     gap (moving it cannot shrink it: the figures' loop would not end), when
     it holds no tuple (except getFirst, which takes the first group as it
     is), when tmin's list is full (max_keys groups), or after G moves;
-  * probCheck: limit = pot * tpt[tmax] / (groups of tmax); the group is the
-    first in tmax's list whose count reaches the limit (counts stand in for
-    a scan of the tuples in arrival order);
+  * probCheck: limit = pot * tpt[tmax] / (groups of tmax), a real number;
+    the tuples of tmax (the batch's tuples whose group tmax owns at that
+    moment) are read in arrival order with a running count per group, and
+    the group whose count first reaches the limit is the one moved.  A
+    fresh read starts at every iteration of the loop;
   * shift: for tmax > tmin every thread in (tmin, tmax] hands the first
     group of its list to the end of the previous thread's list, otherwise
     every thread in [tmax, tmin) hands its last group to the front of the
@@ -70,7 +72,7 @@ def least_loaded(tpt):
     return best
 
 
-def _choose(policy, lst, counts, tpt, tmax, tmin, pot):
+def _choose(policy, lst, counts, tpt, tmax, tmin, pot, keys):
     """The group of tmax that the technique moves (None: no candidate)."""
     if policy == GETFIRST:
         return lst[0]
@@ -82,10 +84,16 @@ def _choose(policy, lst, counts, tpt, tmax, tmin, pot):
                 best = g
         return best
     if policy == PROBCHECK:
+        # read the tuples of tmax in arrival order; stop when a group has
+        # appeared `limit` times
         limit = pot * tpt[tmax] / len(lst)
-        for g in lst:
-            if counts[g] >= limit:
-                return g
+        mine = set(lst)
+        seen = {}
+        for key in keys:
+            if key in mine:
+                seen[key] = seen.get(key, 0) + 1
+                if seen[key] >= limit:
+                    return key
         return None
     if policy == BESTBALANCE:
         # the group whose move leaves the pair closest to equal
@@ -98,7 +106,7 @@ def _choose(policy, lst, counts, tpt, tmax, tmin, pot):
     raise ValueError(policy)
 
 
-def _pair_loop(policy, lists, counts, tpt, threshold, pot, max_keys, groups):
+def _pair_loop(policy, lists, counts, tpt, threshold, pot, max_keys, groups, keys):
     """Figures alg1-alg4: pair the most and least loaded threads and move one
     group between them until the gap is within the threshold."""
     moves = 0
@@ -107,7 +115,7 @@ def _pair_loop(policy, lists, counts, tpt, threshold, pot, max_keys, groups):
         gap = tpt[tmax] - tpt[tmin]
         if gap <= threshold:
             break
-        g = _choose(policy, lists[tmax], counts, tpt, tmax, tmin, pot)
+        g = _choose(policy, lists[tmax], counts, tpt, tmax, tmin, pot, keys)
         if g is None:
             break
         c = counts[g]
@@ -172,17 +180,23 @@ def _shift_local(lists, counts, tpt, threshold, max_keys):
     return moves
 
 
-def rebalance(policy, lists, counts, threshold=1000, pot=0.5, max_keys=2048):
+def rebalance(policy, lists, counts, threshold=1000, pot=0.5, max_keys=2048, keys=None):
     """One round of technique ``policy`` on ``lists`` (modified in place) for
-    a batch with ``counts[g]`` tuples of group g; returns the moves made."""
+    a batch with ``counts[g]`` tuples of group g; returns the moves made.
+    ``keys`` are the batch's group ids in arrival order, which probCheck
+    reads (the others need only the counts)."""
     counts = [int(c) for c in counts]
+    if policy == PROBCHECK:
+        if keys is None:
+            raise ValueError("probCheck reads the batch's tuples: pass keys")
+        keys = [int(k) for k in keys]
     groups = sum(len(lst) for lst in lists)
     tpt = tuples_per_thread(lists, counts)
     if policy == SHIFTLOCAL:
         return _shift_local(lists, counts, tpt, threshold, max_keys)
     if policy == SHIFT:
         return _shift(lists, counts, tpt, threshold, max_keys, groups)
-    return _pair_loop(policy, lists, counts, tpt, threshold, pot, max_keys, groups)
+    return _pair_loop(policy, lists, counts, tpt, threshold, pot, max_keys, groups, keys)
 
 
 def to_csr(lists):

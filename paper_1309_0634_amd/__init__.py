@@ -88,8 +88,8 @@ def lib() -> ctypes.CDLL:
             "cq_server_stats": ([P, pdbl], ctypes.c_int),
             "cq_server_destroy": ([P], ctypes.c_int),
             "cq_policy_stats": ([P, pi64], ctypes.c_int),
-            "cq_policy_apply": ([i32, i32, i64, P, P, P, i64, ctypes.c_double, i32, pi64],
-                                ctypes.c_int),
+            "cq_policy_apply": ([i32, i32, i64, P, P, i64, P, P, i64, ctypes.c_double, i32,
+                                 pi64], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -120,20 +120,24 @@ def _dptr(t) -> Optional[int]:
 
 
 def policy_apply(policy: int, counts, wstart, wlist, threshold: int = 1000, pot: float = 0.5,
-                 max_keys: int = STATIC_KEYS_MAX):
+                 max_keys: int = STATIC_KEYS_MAX, keys=None):
     """One host-side balancing step (cq_policy_apply) on numpy arrays: the
-    mapping ``wstart``/``wlist`` (int32, CSR, modified in place) and the
-    batch's per-group ``counts`` (int32).  Returns the number of moves."""
+    mapping ``wstart``/``wlist`` (int32, CSR, modified in place), the
+    batch's per-group ``counts`` (int32) and, for probCheck, the batch's
+    ``keys`` in arrival order (int32).  Returns the number of moves."""
     import numpy as np
-    for a in (counts, wstart, wlist):
+    arrays = (counts, wstart, wlist) + (() if keys is None else (keys,))
+    for a in arrays:
         if not (isinstance(a, np.ndarray) and a.dtype == np.int32 and a.flags.c_contiguous):
             raise TypeError("policy_apply takes C-contiguous int32 numpy arrays")
     if counts.shape[0] != wlist.shape[0]:
         raise ValueError("counts and wlist must both have one entry per group")
+    n = 0 if keys is None else int(keys.shape[0])
     moves = ctypes.c_int64(0)
     _check(lib().cq_policy_apply(int(policy), int(wstart.shape[0] - 1), int(wlist.shape[0]),
-                                 counts.ctypes.data, wstart.ctypes.data, wlist.ctypes.data,
-                                 int(threshold), float(pot), int(max_keys), ctypes.byref(moves)),
+                                 counts.ctypes.data, keys.ctypes.data if n else None, n,
+                                 wstart.ctypes.data, wlist.ctypes.data, int(threshold),
+                                 float(pot), int(max_keys), ctypes.byref(moves)),
            "cq_policy_apply")
     return moves.value
 

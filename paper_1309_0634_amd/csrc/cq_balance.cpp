@@ -18,10 +18,13 @@
 //    (checkAll, probCheck, bestBalance: nothing to balance with it; getFirst
 //    moves empty groups, which is what taking the first group does), when
 //    tmin already owns max_keys groups, or after G moves.
-//  - probCheck's limit is pot * tpt[tmax] / (groups of tmax) and its group
-//    is the first in tmax's list whose batch count reaches it: the host has
-//    each group's count for the batch but not the tuples in arrival order
-//    (the reorder runs on the GPU).
+//  - probCheck's limit is pot * tpt[tmax] / (groups of tmax), a real
+//    number; the technique reads tmax's tuples in arrival order and stops
+//    at the first group that has appeared limit times.  That group is the
+//    one whose ceil(limit)-th tuple comes earliest in the batch, so the step
+//    indexes each group's tuple positions once (a counting sort of the
+//    batch's keys) and then compares one position per group of tmax,
+//    instead of rereading the tuples at every move.
 //  - shift moves the head of each list in (tmin, tmax] to the tail of the
 //    list before it, or the tail of each list in [tmax, tmin) to the head of
 //    the list after it, so lists stay runs of consecutive ids; a worker with
@@ -95,7 +98,7 @@ void Balancer::move(int32_t g, int32_t from, int32_t to, bool to_head) {
     ++last_moves;
 }
 
-int64_t Balancer::step(int policy, const int32_t *k) {
+int64_t Balancer::step(int policy, const int32_t *k, const int32_t *keys, int64_t n) {
     std::vector<int64_t> tpt(T, 0);
     for (int32_t w = 0; w < T; ++w)
         for (int32_t g : lists[w]) tpt[w] += k[g];
@@ -120,6 +123,17 @@ int64_t Balancer::step(int policy, const int32_t *k) {
             }
         }
         return last_moves;
+    }
+    // probCheck: the arrival positions of each group's tuples, grouped by
+    // group (pstart[g] .. pstart[g+1]) in arrival order
+    std::vector<int64_t> pstart, ppos;
+    if (policy == CQ_PARTITION_PROBCHECK) {
+        pstart.assign(G + 1, 0);
+        for (int64_t i = 0; i < n; ++i) ++pstart[keys[i] + 1];
+        for (int64_t g = 0; g < G; ++g) pstart[g + 1] += pstart[g];
+        ppos.resize(n);
+        std::vector<int64_t> fill(pstart.begin(), pstart.end() - 1);
+        for (int64_t i = 0; i < n; ++i) ppos[fill[keys[i]]++] = i;
     }
     Loads L(tpt);
     while (last_moves < G) {
@@ -161,12 +175,20 @@ int64_t Balancer::step(int policy, const int32_t *k) {
                     g = h;
                 }
         } else if (policy == CQ_PARTITION_PROBCHECK) {
+            // a group "appears limit times" at its ceil(limit)-th tuple; the
+            // scan of tmax's tuples stops at the earliest such position
             const double limit = pot * (double)L.tpt[tmax] / (double)src.size();
-            for (int32_t h : src)
-                if ((double)k[h] >= limit) {
+            const int64_t need = (int64_t)std::ceil(limit);
+            int64_t first = INT64_MAX;
+            for (int32_t h : src) {
+                const int64_t have = pstart[h + 1] - pstart[h];
+                if (need < 1 || have < need) continue;
+                const int64_t at = ppos[pstart[h] + need - 1];
+                if (at < first) {
+                    first = at;
                     g = h;
-                    break;
                 }
+            }
         } else if (policy == CQ_PARTITION_BESTBALANCE) {
             int64_t best = INT64_MAX;
             for (int32_t h : src) {
@@ -227,19 +249,29 @@ bool Balancer::import_csr(int32_t workers, int64_t groups, const int32_t *wstart
 }  // namespace cq
 
 extern "C" int cq_policy_apply(int32_t policy, int32_t workers, int64_t groups,
-                               const int32_t *counts, int32_t *wstart, int32_t *wlist,
-                               int64_t threshold, double pot, int32_t max_keys,
-                               int64_t *moves) {
+                               const int32_t *counts, const int32_t *keys, int64_t n,
+                               int32_t *wstart, int32_t *wlist, int64_t threshold, double pot,
+                               int32_t max_keys, int64_t *moves) {
     if (policy < CQ_PARTITION_GETFIRST || policy > CQ_PARTITION_SHIFTLOCAL) return CQ_ERR_INVALID;
     if (!counts || !wstart || !wlist || !moves || threshold < 0 || !(pot > 0.0 && pot <= 1.0) ||
-        max_keys < 1 || workers < 1 || groups < 1)
+        max_keys < 1 || workers < 1 || groups < 1 || n < 0 || (n > 0 && !keys))
         return CQ_ERR_INVALID;
+    if (policy == CQ_PARTITION_PROBCHECK) {
+        // the tuples must be given, and must be the ones counted
+        std::vector<int64_t> seen(groups, 0);
+        for (int64_t i = 0; i < n; ++i) {
+            if (keys[i] < 0 || keys[i] >= groups) return CQ_ERR_INVALID;
+            ++seen[keys[i]];
+        }
+        for (int64_t g = 0; g < groups; ++g)
+            if (seen[g] != counts[g]) return CQ_ERR_INVALID;
+    }
     cq::Balancer b;
     if (!b.import_csr(workers, groups, wstart, wlist)) return CQ_ERR_INVALID;
     b.threshold = threshold;
     b.pot = pot;
     b.max_keys = max_keys;
-    *moves = b.step(policy, counts);
+    *moves = b.step(policy, counts, keys, n);
     b.export_csr(wstart, wlist, nullptr);
     return CQ_OK;
 }

@@ -22,8 +22,10 @@ struct Balancer {
     // Initial mapping: contiguous id ranges of (almost) equal size.
     void reset(int32_t workers, int64_t groups);
     // One balancing step of `policy` (a CQ_PARTITION_* technique) on the
-    // batch counts k[G]; returns the number of groups moved.
-    int64_t step(int policy, const int32_t *k);
+    // batch counts k[G]; probCheck also reads the batch's n group ids in
+    // arrival order (keys, each in [0, G)).  Returns the number of groups
+    // moved.
+    int64_t step(int policy, const int32_t *k, const int32_t *keys = nullptr, int64_t n = 0);
     // Lists as CSR: wstart[T+1], wlist[G]; lidx[g] = position in its list.
     void export_csr(int32_t *wstart, int32_t *wlist, int32_t *lidx) const;
     bool import_csr(int32_t workers, int64_t groups, const int32_t *wstart, const int32_t *wlist);

@@ -96,6 +96,12 @@ __device__ __forceinline__ void plan_group(const State &st, const Scratch &sc, i
 // heavy flag | touched flag << 16), wave totals meet in LDS, and a running
 // carry links the chunks.
 constexpr int PLAN_R = 10;
+// The packed field (heavy flag | touched flag << 16) is summed over at most
+// one chunk of PLAN_THREADS * PLAN_R groups at a time (the running carry
+// keeps the fields apart): the heavy half must stay below 2^16 and the
+// whole sum below 2^31.
+static_assert((int64_t)PLAN_THREADS * PLAN_R * 65537 < (1LL << 31),
+              "packed per-chunk field sums fit an int, heavy count below 2^16");
 
 // Top two (count << 32 | group) pairs of this thread's groups.
 struct Top2 {
@@ -312,8 +318,12 @@ constexpr int PS_UNROLL = 16;
 __global__ __launch_bounds__(PS_THREADS) void k_plan_small(State st, Scratch sc, int32_t seq,
                                                           int mode, int32_t workers) {
     if (sc.seqp) seq = *sc.seqp;  // captured for replay: the argument would be stale
-    __shared__ int red[4 * (PS_THREADS / 64)];
-    __shared__ unsigned long long red_top[2 * (PS_THREADS / 64)];
+    // The three fields (light tuples, heavy groups, touched groups) are
+    // summed in separate ints: up to 32768 touched groups do not fit a
+    // 16-bit half of a packed field.
+    constexpr int NW = PS_THREADS / 64;
+    __shared__ int red[2 * PLAN_FIELDS * NW];
+    __shared__ unsigned long long red_top[2 * NW];
     const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
     const int G = (int)st.G;
     const int gb = blockIdx.x * PS_THREADS;
@@ -332,8 +342,9 @@ __global__ __launch_bounds__(PS_THREADS) void k_plan_small(State st, Scratch sc,
     const int32_t kg = g < G ? sc.k[g] : 0;
     const int32_t po = (g < G && kg > 0) ? st.pos[g] : 0;
     const int32_t c0 = (g < G && kg > 0) ? st.cnt[g] : 0;
-    // fields: A = light tuples, B = heavy flag | touched flag << 16
-    int bA = 0, bB = 0, tA = 0, tB = 0;
+    // per field: the sum over the groups before this block (b) and over all
+    // groups (t) of this thread's share of the histogram
+    int b[PLAN_FIELDS] = {0, 0, 0}, t[PLAN_FIELDS] = {0, 0, 0};
     const bool track = blockIdx.x == 0;
     Top2 top;
     for (int h0 = 0; h0 < G; h0 += PS_THREADS * PS_UNROLL) {
@@ -348,59 +359,55 @@ __global__ __launch_bounds__(PS_THREADS) void k_plan_small(State st, Scratch sc,
             const int h = h0 + u * PS_THREADS + tid;
             int x[PLAN_FIELDS];
             key_fields(kv[u], mode, x);
-            const int A = x[0], B = x[1] | (x[2] << 16);
-            tA += A;
-            tB += B;
-            if (h < gb) {
-                bA += A;
-                bB += B;
+#pragma unroll
+            for (int f = 0; f < PLAN_FIELDS; ++f) {
+                t[f] += x[f];
+                b[f] += h < gb ? x[f] : 0;
             }
             if (track && kv[u] > 0)
                 top.add(((unsigned long long)(uint32_t)kv[u] << 32) | (uint32_t)h);
         }
     }
     // own group's exclusive position inside the block
-    int x[PLAN_FIELDS];
+    int x[PLAN_FIELDS], incl[PLAN_FIELDS];
     key_fields(kg, mode, x);
-    const int A = x[0], B = x[1] | (x[2] << 16);
-    const int iA = wave_incl_add(A), iB = wave_incl_add(B);
-    const int sbA = wave_total(wave_incl_add(bA)), sbB = wave_total(wave_incl_add(bB));
-    const int stA = wave_total(wave_incl_add(tA)), stB = wave_total(wave_incl_add(tB));
-    if (lane == 0) {
-        red[4 * wv] = sbA;
-        red[4 * wv + 1] = sbB;
-        red[4 * wv + 2] = stA;
-        red[4 * wv + 3] = stB;
-    }
-    __shared__ int wtot[2 * (PS_THREADS / 64)];
-    if (lane == 63) {
-        wtot[2 * wv] = iA;
-        wtot[2 * wv + 1] = iB;
-    }
-    __syncthreads();
-    int BA = 0, BB = 0, TA = 0, TB = 0, wA = 0, wB = 0;
 #pragma unroll
-    for (int w = 0; w < PS_THREADS / 64; ++w) {
-        BA += red[4 * w];
-        BB += red[4 * w + 1];
-        TA += red[4 * w + 2];
-        TB += red[4 * w + 3];
-        if (w < wv) {
-            wA += wtot[2 * w];
-            wB += wtot[2 * w + 1];
+    for (int f = 0; f < PLAN_FIELDS; ++f) {
+        incl[f] = wave_incl_add(x[f]);
+        const int sb = wave_total(wave_incl_add(b[f]));
+        const int stt = wave_total(wave_incl_add(t[f]));
+        if (lane == 0) {
+            red[(2 * wv) * PLAN_FIELDS + f] = sb;
+            red[(2 * wv + 1) * PLAN_FIELDS + f] = stt;
         }
     }
-    const int eB = BB + wB + iB - B;
-    const int ex[PLAN_FIELDS] = {BA + wA + iA - A, eB & 0xffff, eB >> 16};
-    const int tot[PLAN_FIELDS] = {TA, TB & 0xffff, TB >> 16};
-    const int32_t nl = mode == MODE_STATIC ? 0 : (TA + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
+    __shared__ int wtot[PLAN_FIELDS * NW];
+    if (lane == 63) {
+#pragma unroll
+        for (int f = 0; f < PLAN_FIELDS; ++f) wtot[wv * PLAN_FIELDS + f] = incl[f];
+    }
+    __syncthreads();
+    int ex[PLAN_FIELDS], tot[PLAN_FIELDS];
+#pragma unroll
+    for (int f = 0; f < PLAN_FIELDS; ++f) {
+        int before_block = 0, all = 0, before_wave = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            before_block += red[(2 * w) * PLAN_FIELDS + f];
+            all += red[(2 * w + 1) * PLAN_FIELDS + f];
+            before_wave += w < wv ? wtot[w * PLAN_FIELDS + f] : 0;
+        }
+        ex[f] = before_block + before_wave + incl[f] - x[f];
+        tot[f] = all;
+    }
+    const int32_t nl = mode == MODE_STATIC ? 0 : (tot[0] + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
     if (blockIdx.x == 0 && tid == 0) plan_publish(st, sc, tot, status, mode, workers);
     if (g < G) {
         sc.lpre[g] = ex[0];
         if (kg > 0) plan_group(st, sc, g, kg, ex, po, c0, nl, seq, mode, workers);
     }
     if (track) {
-        top2_block(top, red_top, PS_THREADS / 64);
+        top2_block(top, red_top, NW);
         if (tid == 0) {
             sc.hot[0] = top.a ? (int32_t)(uint32_t)top.a : -1;
             sc.hot[1] = top.b ? (int32_t)(uint32_t)top.b : -1;
@@ -587,6 +594,10 @@ __global__ void k_validate(const int32_t *__restrict__ keys, int64_t n, int64_t 
 // block reads it then).  Barriers inside; call uniformly.
 // Groups whose plan one pass workgroup writes per step of its in-block plan.
 constexpr int OWN_CAP = 1024;
+// The in-block plan sums the packed field (heavy flag | touched flag << 16)
+// over all groups of the batch: at most PASS_LOCAL_G of each.
+static_assert((int64_t)PASS_LOCAL_G * 65537 < (1LL << 31),
+              "packed whole-histogram field sums fit an int, heavy count below 2^16");
 
 // `load_tile` issues the tile's own loads.  It runs after the loads the plan
 // waits on (the bad-key flag, the histogram, the owned groups' state), so the

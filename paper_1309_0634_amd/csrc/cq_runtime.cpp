@@ -48,6 +48,8 @@ struct cq_query {
     Balancer bal;
     int32_t *m_owner = nullptr, *m_wstart = nullptr, *m_wlist = nullptr, *m_lidx = nullptr;
     int32_t *h_counts = nullptr;  // pinned: a batch's histogram, then its rejection flag
+    int32_t *h_keys = nullptr;    // pinned: a sub-batch's keys (probCheck reads its tuples)
+    int64_t h_keys_n = 0;         // keys in h_keys
     int32_t *h_map = nullptr;     // pinned: owner, wstart, wlist, lidx on their way up
     hipEvent_t ev_counts = nullptr, ev_map = nullptr;
     bool map_pending = false;     // an upload from h_map may still be running
@@ -172,7 +174,8 @@ void free_all(cq_query *q) {
     dfree(q->m_lidx);
     if (q->h_counts) (void)hipHostFree(q->h_counts);
     if (q->h_map) (void)hipHostFree(q->h_map);
-    q->h_counts = q->h_map = nullptr;
+    if (q->h_keys) (void)hipHostFree(q->h_keys);
+    q->h_counts = q->h_map = q->h_keys = nullptr;
     if (q->ev_counts) (void)hipEventDestroy(q->ev_counts);
     if (q->ev_map) (void)hipEventDestroy(q->ev_map);
     q->ev_counts = q->ev_map = nullptr;
@@ -265,6 +268,9 @@ int policy_buffers(cq_query *q) {
         e = hipHostMalloc(reinterpret_cast<void **>(&q->h_map),
                           sizeof(int32_t) * (size_t)(3 * G + NB_MAX + 1), hipHostMallocDefault);
     if (e == hipSuccess && rc == CQ_OK)
+        e = hipHostMalloc(reinterpret_cast<void **>(&q->h_keys), sizeof(int32_t) * (size_t)SUB,
+                          hipHostMallocDefault);
+    if (e == hipSuccess && rc == CQ_OK)
         e = hipEventCreateWithFlags(&q->ev_counts, hipEventDisableTiming);
     if (e == hipSuccess && rc == CQ_OK) e = hipEventCreateWithFlags(&q->ev_map, hipEventDisableTiming);
     if (rc == CQ_OK) rc = from_hip(e);
@@ -275,7 +281,8 @@ int policy_buffers(cq_query *q) {
         dfree(q->m_lidx);
         if (q->h_counts) (void)hipHostFree(q->h_counts);
         if (q->h_map) (void)hipHostFree(q->h_map);
-        q->h_counts = q->h_map = nullptr;
+        if (q->h_keys) (void)hipHostFree(q->h_keys);
+        q->h_counts = q->h_map = q->h_keys = nullptr;
         if (q->ev_counts) (void)hipEventDestroy(q->ev_counts);
         if (q->ev_map) (void)hipEventDestroy(q->ev_map);
         q->ev_counts = q->ev_map = nullptr;
@@ -304,14 +311,22 @@ int policy_upload(cq_query *q, hipStream_t s) {
     return from_hip(e);
 }
 
-// After the histogram of a batch: its counts and rejection flag on their
-// way to the host.
-int policy_fetch(cq_query *q, const Scratch &sc, hipStream_t s) {
+// After the histogram of a (sub-)batch of m tuples: its counts and
+// rejection flag on their way to the host, and under probCheck its keys
+// too (the technique reads the most loaded worker's tuples in arrival
+// order).
+int policy_fetch(cq_query *q, const Scratch &sc, const int32_t *keys, int64_t m,
+                 hipStream_t s) {
     const int64_t G = q->st.G;
     hipError_t e = hipMemcpyAsync(q->h_counts, sc.k, sizeof(int32_t) * (size_t)G,
                                   hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(q->h_counts + G, sc.bad, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    q->h_keys_n = 0;
+    if (e == hipSuccess && q->policy == CQ_PARTITION_PROBCHECK && m > 0) {
+        e = hipMemcpyAsync(q->h_keys, keys, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost, s);
+        q->h_keys_n = m;
+    }
     if (e == hipSuccess) e = hipEventRecord(q->ev_counts, s);
     return from_hip(e);
 }
@@ -322,7 +337,12 @@ int policy_step(cq_query *q, int32_t seq, hipStream_t s) {
     if (hipEventSynchronize(q->ev_counts) != hipSuccess) return CQ_ERR_HIP;
     q->bal.last_moves = 0;
     if (q->h_counts[q->st.G] == seq) return CQ_OK;  // rejected batch: nothing happened
-    const int64_t moved = q->bal.step(q->policy, q->h_counts);
+    if (q->kmod && q->h_keys_n > 0) {  // the groups the query sees
+        const uint32_t G = (uint32_t)q->st.G;
+        for (int64_t i = 0; i < q->h_keys_n; ++i)
+            q->h_keys[i] = (int32_t)((uint32_t)q->h_keys[i] % G);
+    }
+    const int64_t moved = q->bal.step(q->policy, q->h_counts, q->h_keys, q->h_keys_n);
     q->policy_total += moved;
     return moved ? policy_upload(q, s) : CQ_OK;
 }
@@ -351,7 +371,7 @@ int front(cq_query *q, const int32_t *keys, const int32_t *values, int64_t m, co
     if (!have_hist)
         rc = timed(q, CQ_KERNEL_HIST, s,
                    [&] { return launch_hist(keys, m, q->st.G, sc, seq, s); });
-    if (rc == CQ_OK && sc.owner) rc = policy_fetch(q, sc, s);
+    if (rc == CQ_OK && sc.owner) rc = policy_fetch(q, sc, keys, m, s);
     if (rc == CQ_OK && !plan_fused(q->st.G))
         rc = timed(q, CQ_KERNEL_PLAN, s,
                    [&] { return launch_plan(q->st, sc, seq, q->mode, q->workers, s); });

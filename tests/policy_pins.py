@@ -2,7 +2,8 @@
 and to properties the figures fix, independently of any implementation.
 
 Each ``pin_*`` takes ``rebalance(policy, lists, counts, threshold, pot,
-max_keys) -> moves`` (lists modified in place), so the same checks run on
+max_keys, keys) -> moves`` (lists modified in place; ``keys`` are the
+batch's group ids in arrival order, which probCheck reads), so the same checks run on
 the oracle (``oracle.policies``), on the library's host step, and on
 deliberately broken copies of the oracle, where at least one must fail.
 
@@ -20,10 +21,20 @@ PAIR_POLICIES = (GETFIRST, CHECKALL, PROBCHECK, BESTBALANCE)
 ALL_POLICIES = PAIR_POLICIES + (SHIFT, SHIFTLOCAL)
 
 
-def _run(rebalance, policy, lists, counts, threshold, pot=0.5, max_keys=2048):
+def _run(rebalance, policy, lists, counts, threshold, pot=0.5, max_keys=2048, keys=None):
     lists = [list(x) for x in lists]
-    moves = rebalance(policy, lists, list(counts), threshold, pot, max_keys)
+    moves = rebalance(policy, lists, list(counts), threshold, pot, max_keys, keys)
     return lists, moves
+
+
+def _arrivals(*runs):
+    """Batch keys in arrival order from (group, repeat) runs, and the counts
+    they imply (one entry per group id up to the largest)."""
+    keys = [g for g, r in runs for _ in range(r)]
+    counts = [0] * (max(keys) + 1)
+    for g in keys:
+        counts[g] += 1
+    return keys, counts
 
 
 def pin_getfirst_worked():
@@ -62,18 +73,46 @@ def pin_checkall_worked():
 
 
 def pin_probcheck_worked():
-    """Figure alg3: limit = pot * tpt[tmax] / ngroups; the first group that
-    reaches it moves."""
+    """Figure alg3: limit = pot * tpt[tmax] / ngroups; the tuples of tmax are
+    read in arrival order and the first group to appear limit times moves."""
     def check(rebalance):
-        # tpt = [1000, 0], limit 0.5*1000/4 = 125: group 1 (400) moves ->
-        # [600, 400]; limit 0.5*600/3 = 100: group 0 (100) moves -> [500, 500]
-        lists, moves = _run(rebalance, PROBCHECK, [[0, 1, 2, 3], [4]],
-                            [100, 400, 500, 0, 0], 100, pot=0.5)
-        assert (lists, moves) == ([[2, 3], [4, 1, 0]], 2), (lists, moves)
-        # pot = 1: the limit is the average (1000/4 = 250): group 2 first
-        lists, moves = _run(rebalance, PROBCHECK, [[0, 1, 2, 3], [4]],
-                            [100, 200, 500, 200, 0], 100, pot=1.0)
-        assert lists[1] == [4, 2] and moves >= 1, (lists, moves)
+        # tpt = [1000, 0], limit 0.5*1000/4 = 125.  Group 2's first 130
+        # tuples arrive first, so it reaches 125 before group 1 (which a
+        # scan of the list in id order would take): group 2 (500) moves ->
+        # [500, 500], done.
+        keys, counts = _arrivals((2, 130), (0, 100), (1, 400), (2, 370))
+        counts += [0] * (5 - len(counts))
+        lists, moves = _run(rebalance, PROBCHECK, [[0, 1, 2, 3], [4]], counts, 100, pot=0.5,
+                            keys=keys)
+        assert (lists, moves) == ([[0, 1, 3], [4, 2]], 1), (lists, moves)
+        # tpt = [600, 0], limit 0.5*600/3 = 100: group 2 (100 tuples, all
+        # arriving first) reaches exactly 100 -> moves: [500, 100]; limit
+        # 0.5*500/2 = 125, thread 0's tuples are groups 1 then 0: group 1
+        # (300) moves -> [200, 400]; now tmax = 1 with groups [3, 2, 1],
+        # limit 0.5*400/3 = 66.7, group 2 arrives first again -> back to
+        # thread 0: [300, 300].  (Counts in list order would move group 0
+        # first, then stop at group 1 = 300 >= gap 200.)
+        keys, counts = _arrivals((2, 100), (1, 300), (0, 200))
+        counts += [0] * (4 - len(counts))
+        lists, moves = _run(rebalance, PROBCHECK, [[0, 1, 2], [3]], counts, 50, pot=0.5,
+                            keys=keys)
+        assert (lists, moves) == ([[0, 2], [3, 1]], 3), (lists, moves)
+        # pot = 1: the limit is the average (1000/4 = 250): groups 1 and 3
+        # arrive first but hold only 200 each; group 2 reaches 250
+        keys, counts = _arrivals((1, 200), (3, 200), (2, 500), (0, 100))
+        counts += [0] * (5 - len(counts))
+        lists, moves = _run(rebalance, PROBCHECK, [[0, 1, 2, 3], [4]], counts, 100, pot=1.0,
+                            keys=keys)
+        assert (lists, moves) == ([[0, 1, 3], [4, 2]], 1), (lists, moves)
+        # only tmax's tuples are read: group 2 (thread 1) arrives first and
+        # is skipped; group 1 reaches 0.5*600/2 = 150 and moves to tmin =
+        # thread 2 -> [100, 300, 500]; then tmax = 2 (groups 3, 1), limit
+        # 125: group 1 again, 500 >= gap 400: stop
+        keys, counts = _arrivals((2, 300), (1, 500), (0, 100))
+        counts += [0] * (4 - len(counts))
+        lists, moves = _run(rebalance, PROBCHECK, [[0, 1], [2], [3]], counts, 50, pot=0.5,
+                            keys=keys)
+        assert (lists, moves) == ([[0], [2], [3, 1]], 1), (lists, moves)
     return check
 
 
@@ -134,10 +173,11 @@ def pin_shiftlocal_worked():
     return check
 
 
-def _zipf_counts(rng, groups, n, s):
+def _zipf_keys(rng, groups, n, s):
+    """Batch keys in arrival order (Zipf over permuted ids) and their counts."""
     p = 1.0 / np.arange(1, groups + 1) ** s
-    keys = rng.choice(groups, size=n, p=p / p.sum())
-    return np.bincount(rng.permutation(groups)[keys], minlength=groups)
+    keys = rng.permutation(groups)[rng.choice(groups, size=n, p=p / p.sum())]
+    return keys, np.bincount(keys, minlength=groups)
 
 
 def pin_properties():
@@ -154,10 +194,11 @@ def pin_properties():
             for policy in ALL_POLICIES:
                 lists = [list(range(first[w], first[w + 1])) for w in range(T)]
                 for batch in range(4):
-                    counts = _zipf_counts(rng, G, int(rng.integers(0, 3000)), 1.2)
+                    keys, counts = _zipf_keys(rng, G, int(rng.integers(0, 3000)), 1.2)
                     before = [sum(int(counts[g]) for g in x) for x in lists]
                     cap = max(len(x) for x in lists) + 3
-                    moves = rebalance(policy, lists, [int(c) for c in counts], 50, 0.5, cap)
+                    moves = rebalance(policy, lists, [int(c) for c in counts], 50, 0.5, cap,
+                                      keys)
                     flat = sorted(g for x in lists for g in x)
                     assert flat == list(range(G)), (policy, lists)
                     assert all(len(x) <= cap for x in lists)

@@ -42,7 +42,7 @@ class Tracked:
         counts = np.bincount(keys, minlength=self.groups)
         tpt = OP.tuples_per_thread(self.lists, counts)
         moves = OP.rebalance(self.policy, self.lists, counts.tolist(), self.threshold,
-                             self.pot, cq.STATIC_KEYS_MAX)
+                             self.pot, cq.STATIC_KEYS_MAX, np.asarray(keys).tolist())
         self.total += moves
         return moves, max(tpt), min(tpt), self.total
 
@@ -95,7 +95,8 @@ def test_skew_stream_all_techniques(s):
     ora.close()
 
 
-@pytest.mark.parametrize("policy", [cq.PARTITION_GETFIRST, cq.PARTITION_SHIFT])
+@pytest.mark.parametrize("policy", [cq.PARTITION_GETFIRST, cq.PARTITION_PROBCHECK,
+                                    cq.PARTITION_SHIFT])
 def test_pipelined_call_under_technique(policy):
     """cq_push_batches: the host step runs between the batches of one call."""
     import torch

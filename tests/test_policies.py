@@ -23,13 +23,14 @@ def L():
         return cq.lib()
 
 
-def lib_rebalance(policy, lists, counts, threshold, pot, max_keys):
+def lib_rebalance(policy, lists, counts, threshold, pot, max_keys, keys=None):
     """The library's host step, through the C-ABI, on list form."""
     wstart, wlist = O.to_csr(lists)
     ws = np.asarray(wstart, dtype=np.int32)
     wl = np.asarray(wlist, dtype=np.int32)
     moves = cq.policy_apply(policy, np.asarray(counts, dtype=np.int32), ws, wl,
-                            threshold, pot, max_keys)
+                            threshold, pot, max_keys,
+                            None if keys is None else np.asarray(keys, dtype=np.int32))
     lists[:] = O.from_csr(ws.tolist(), wl.tolist())
     return moves
 
@@ -70,9 +71,10 @@ def test_library_matches_oracle(policy, case, L):
     wl = np.asarray(O.to_csr(ref)[1], dtype=np.int32)
     total = 0
     for batch in range(6):
-        counts = np.bincount(_zipf_keys(rng, G, n, s), minlength=G).astype(np.int32)
-        want = O.rebalance(policy, ref, counts.tolist(), thr, 0.5, cap)
-        got = cq.policy_apply(policy, counts, ws, wl, thr, 0.5, cap)
+        keys = _zipf_keys(rng, G, n, s).astype(np.int32)
+        counts = np.bincount(keys, minlength=G).astype(np.int32)
+        want = O.rebalance(policy, ref, counts.tolist(), thr, 0.5, cap, keys.tolist())
+        got = cq.policy_apply(policy, counts, ws, wl, thr, 0.5, cap, keys)
         assert got == want, (batch, got, want)
         assert O.from_csr(ws.tolist(), wl.tolist()) == ref, batch
         total += got
@@ -102,12 +104,13 @@ def test_policy_apply_cost_is_modest(L):
     import time
     rng = np.random.default_rng([20130909, 5])
     T, G = 16384, 10000
-    counts = np.bincount(_zipf_keys(rng, G, 1 << 20, 1.5), minlength=G).astype(np.int32)
+    keys = _zipf_keys(rng, G, 1 << 20, 1.5).astype(np.int32)
+    counts = np.bincount(keys, minlength=G).astype(np.int32)
     for policy in sorted(O.NAMES):
         ws = np.asarray(O.to_csr(O.initial_lists(T, G))[0], np.int32)
         wl = np.arange(G, dtype=np.int32)
         t = time.perf_counter()
-        cq.policy_apply(policy, counts, ws, wl)
+        cq.policy_apply(policy, counts, ws, wl, keys=keys)
         assert time.perf_counter() - t < 5.0, O.NAMES[policy]
 
 
@@ -120,7 +123,19 @@ POLICY_MUTANTS = {
     "checkall_last_on_ties": ("counts[g] > counts[best]:", "counts[g] >= counts[best]:"),
     "probcheck_limit_over_all_groups": ("limit = pot * tpt[tmax] / len(lst)",
                                         "limit = pot * tpt[tmax] / len(counts)"),
-    "probcheck_strict": ("if counts[g] >= limit:", "if counts[g] > limit:"),
+    "probcheck_strict": ("if seen[key] >= limit:", "if seen[key] > limit:"),
+    "probcheck_list_order": ("""        mine = set(lst)
+        seen = {}
+        for key in keys:
+            if key in mine:
+                seen[key] = seen.get(key, 0) + 1
+                if seen[key] >= limit:
+                    return key
+        return None""", """        for g in lst:
+            if counts[g] >= limit:
+                return g
+        return None"""),
+    "probcheck_reads_every_tuple": ("            if key in mine:\n", "            if True:\n"),
     "bestbalance_one_sided": ("d = abs((tpt[tmax] - counts[g]) - (tpt[tmin] + counts[g]))",
                               "d = abs(tpt[tmax] - tpt[tmin] - counts[g])"),
     "move_equal_to_gap": ("if c >= gap or", "if c > gap or"),
