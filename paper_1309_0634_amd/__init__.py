@@ -46,6 +46,11 @@ def lib() -> ctypes.CDLL:
     """The loaded libcq.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch first: its wheel ships a HIP runtime with the same soname as
+        # the system one the library links against, so whichever loads first
+        # serves the whole process; torch does not start on the other one,
+        # and the library runs on torch's (one runtime, shared pointers).
+        import torch  # noqa: F401
         if not os.path.exists(LIBRARY):
             raise ImportError(f"{LIBRARY} is missing: build it with "
                               "`python -c 'import __graft_entry__ as g; g.build()'`")
