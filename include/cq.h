@@ -219,6 +219,35 @@ int cq_push_batch_results(cq_query *q, const int32_t *keys, const int32_t *value
                           int32_t *ids, int64_t *sums, int32_t *counts, double *avgs,
                           int64_t *n_touched, void *stream);
 
+/*
+ * cq_push_batch_results_noalloc -- cq_push_batch_results for callers that
+ * cannot allocate device memory while they run: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, same state change and same results; the call allocates
+ * nothing.  Its working memory (histogram, plan, reordered tiles) is one
+ * fixed area of CQ_NOALLOC_SCRATCH_BYTES per GPU, a file-scope device array
+ * that each GPU the library runs on holds until the process ends; the
+ * caller still passes the inputs and the result buffers.
+ * Limits: n <= CQ_NOALLOC_MAX_BATCH tuples, a query of at most
+ * CQ_NOALLOC_MAX_GROUPS groups in the balanced partition (no Section 4
+ * technique); anything beyond returns CQ_ERR_INVALID with nothing enqueued.
+ * Every call on one GPU shares that area: calls that overlap on one GPU
+ * (any query, any stream, not ordered one after the other) race and give
+ * undefined results.  Each call first clears what must start at zero, so a
+ * sequence of ordered calls (also replays of a captured one) is exact.  A
+ * bad key rejects the batch (*n_touched = CQ_ERR_KEY_RANGE, state
+ * unchanged).  After this call cq_results, cq_status and cq_batch_plan
+ * return CQ_ERR_INVALID until the query's next push through another entry
+ * point.  Telemetry is not recorded.  Returns CQ_OK, CQ_ERR_INVALID or
+ * CQ_ERR_HIP.
+ */
+#define CQ_NOALLOC_MAX_BATCH 262144       /* 2^18 tuples */
+#define CQ_NOALLOC_MAX_GROUPS 16384
+#define CQ_NOALLOC_SCRATCH_BYTES 3145728  /* 3 MiB */
+int cq_push_batch_results_noalloc(cq_query *q, const int32_t *keys, const int32_t *values,
+                                  int64_t n, int32_t *ids, int64_t *sums, int32_t *counts,
+                                  double *avgs, int64_t *n_touched, void *stream);
+
 /* Limits of cq_push_batch_tuples. */
 #define CQ_TUPLE_MAX_WINDOW 1024
 #define CQ_TUPLE_MAX_PASSES 64

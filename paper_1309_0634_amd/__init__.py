@@ -31,6 +31,8 @@ TUPLE_MAX_PASSES = 64
 MAX_BATCH = 1 << 30
 MAX_WINDOW = (1 << 22) - 1
 PIPE_MAX = 1 << 20
+NOALLOC_MAX_BATCH = 1 << 18
+NOALLOC_MAX_GROUPS = 16384
 
 _lib: Optional[ctypes.CDLL] = None
 
@@ -65,6 +67,7 @@ def lib() -> ctypes.CDLL:
             "cq_push_batch": ([P, P, P, i64, P], ctypes.c_int),
             "cq_results": ([P, P, P, P, P, P, P], ctypes.c_int),
             "cq_push_batch_results": ([P, P, P, i64, P, P, P, P, P, P], ctypes.c_int),
+            "cq_push_batch_results_noalloc": ([P, P, P, i64, P, P, P, P, P, P], ctypes.c_int),
             "cq_status": ([P], ctypes.c_int),
             "cq_destroy": ([P], ctypes.c_int),
             "cq_strerror": ([ctypes.c_int], ctypes.c_char_p),
@@ -235,6 +238,20 @@ class Query:
             self._h, _dptr(keys) if n else None, _dptr(values) if n else None, int(n),
             _dptr(ids), _dptr(sums), _dptr(counts), _dptr(avgs), _dptr(n_touched),
             _stream_handle(stream)), "cq_push_batch_results")
+        self.last_n = int(n)
+
+    def push_results_noalloc_into(self, keys, values, ids, sums, counts, avgs, n_touched,
+                                  stream=None):
+        """push_results_into through the allocation-free entry point
+        (cq_push_batch_results_noalloc): at most NOALLOC_MAX_BATCH tuples,
+        at most NOALLOC_MAX_GROUPS groups, balanced partition."""
+        n = keys.numel()
+        if values.numel() != n:
+            raise ValueError("keys and values differ in length")
+        _check(lib().cq_push_batch_results_noalloc(
+            self._h, _dptr(keys) if n else None, _dptr(values) if n else None, int(n),
+            _dptr(ids), _dptr(sums), _dptr(counts), _dptr(avgs), _dptr(n_touched),
+            _stream_handle(stream)), "cq_push_batch_results_noalloc")
         self.last_n = int(n)
 
     def push_tuples_into(self, keys, values, sums, counts, avgs, passes=0, stream=None):

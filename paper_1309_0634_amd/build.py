@@ -9,7 +9,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIBRARY = os.path.join(PKG, "libcq.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("cq_kernels.hip", "cq_tuples.hip", "cq_runtime.cpp", "cq_balance.cpp", "cq_server.cpp", "cq_multi.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("cq_kernels.hip", "cq_tuples.hip", "cq_runtime.cpp", "cq_balance.cpp", "cq_server.cpp", "cq_multi.cpp", "cq_noalloc.hip")]
 ARCH = os.environ.get("CQ_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

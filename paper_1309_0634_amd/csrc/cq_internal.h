@@ -222,6 +222,12 @@ bool query_capturable(const cq_query *q);
 int query_set_graph(cq_query *q, bool on, hipStream_t s);
 void query_replayed(cq_query *q, int64_t n, hipStream_t s);
 void query_ran_on(cq_query *q, hipStream_t s);
+// Working memory of the allocation-free push (cq_noalloc.hip): the scratch
+// area's address on `device` (current), and the batch-local buffers carved
+// out of it; launch_noalloc_clear zeroes the histogram and bad-key flag.
+char *noalloc_base(int device);
+Scratch noalloc_set(char *base);
+hipError_t launch_noalloc_clear(const Scratch &sc, hipStream_t s);
 // Workgroups of the per-group phase (one trace record each).
 int64_t update_grid(int64_t n, int mode, int32_t workers);
 // Histogram workgroups launched by launch_hist for a sub-batch of n.

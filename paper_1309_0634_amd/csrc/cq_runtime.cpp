@@ -59,6 +59,9 @@ struct cq_query {
     // per-tuple results: arrival index of each staged tuple, count before
     // the sub-batch (allocated by the first per-tuple push)
     int32_t *pt_sidx = nullptr, *pt_pcnt = nullptr;
+    // the last push was cq_push_batch_results_noalloc: its plan lives in the
+    // shared scratch area, so cq_results / cq_status / cq_batch_plan refuse
+    bool noalloc_last = false;
 };
 
 namespace {
@@ -399,6 +402,7 @@ int push(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n, hip
         return CQ_ERR_HIP;
     q->last_stream = s;
     q->pushed = true;
+    q->noalloc_last = false;
     q->last_n = n;
     q->last_mode = q->mode;
     q->last_workers = q->workers;
@@ -662,6 +666,38 @@ int cq_push_batch_results(cq_query *q, const int32_t *keys, const int32_t *value
     return push(q, keys, values, n, reinterpret_cast<hipStream_t>(stream), &out);
 }
 
+int cq_push_batch_results_noalloc(cq_query *q, const int32_t *keys, const int32_t *values,
+                                  int64_t n, int32_t *ids, int64_t *sums, int32_t *counts,
+                                  double *avgs, int64_t *n_touched, void *stream) {
+    if (!q || n < 0 || n > CQ_NOALLOC_MAX_BATCH || !n_touched) return CQ_ERR_INVALID;
+    if (n > 0 && (!keys || !values)) return CQ_ERR_INVALID;
+    if (q->st.G > CQ_NOALLOC_MAX_GROUPS || q->mode != MODE_BALANCED || q->policy)
+        return CQ_ERR_INVALID;
+    DeviceGuard guard(q->device);
+    char *base = noalloc_base(q->device);
+    if (!base) return CQ_ERR_HIP;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Scratch sc = noalloc_set(base);
+    sc.fault = q->sc.fault;
+    sc.hot = q->sc.hot;
+    sc.kmod = q->kmod;
+    q->last_stream = s;
+    q->pushed = true;
+    q->noalloc_last = true;
+    q->last_n = n;
+    if (n == 0) return from_hip(launch_set_touched(n_touched, 0, s));
+    // The scratch area keeps whatever the previous call on this device left:
+    // the histogram and the bad-key flag are cleared first, and the flag's
+    // batch number is the constant 1, so a replayed capture stays valid.
+    const int32_t seq = 1;
+    const Out out = {ids, sums, counts, avgs, n_touched};
+    hipError_t e = launch_noalloc_clear(sc, s);
+    if (e == hipSuccess) e = launch_hist(keys, n, q->st.G, sc, seq, s);
+    if (e == hipSuccess) e = launch_pass(keys, values, n, q->st, sc, seq, MODE_BALANCED, 0, s);
+    if (e == hipSuccess) e = launch_update(q->st, sc, n, MODE_BALANCED, 0, out, s);
+    return from_hip(e);
+}
+
 int cq_push_batch_tuples(cq_query *q, const int32_t *keys, const int32_t *values, int64_t n,
                          int32_t passes, int64_t *sums, int32_t *counts, double *avgs,
                          void *stream) {
@@ -706,6 +742,7 @@ int cq_push_batches(cq_query *q, int32_t count, const int32_t *const *keys,
         return CQ_ERR_HIP;
     const int32_t seq0 = q->seq + 1;
     q->seq += count;
+    q->noalloc_last = false;
     // Batch i uses buffer set i mod 2.  Batch i+1's histogram is computed
     // by extra workgroups of batch i's update launch (it only needs its own
     // set's histogram, cleared by batch i-1's update), so a batch costs two
@@ -754,7 +791,7 @@ int cq_push_batches(cq_query *q, int32_t count, const int32_t *const *keys,
 
 int cq_results(cq_query *q, int32_t *ids, int64_t *sums, int32_t *counts, double *avgs,
                int64_t *n_touched, void *stream) {
-    if (!q || !n_touched) return CQ_ERR_INVALID;
+    if (!q || !n_touched || q->noalloc_last) return CQ_ERR_INVALID;
     DeviceGuard guard(q->device);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int64_t cap = std::min<int64_t>(q->st.G, q->last_n);
@@ -767,7 +804,7 @@ int cq_results(cq_query *q, int32_t *ids, int64_t *sums, int32_t *counts, double
 }
 
 int cq_status(cq_query *q) {
-    if (!q) return CQ_ERR_INVALID;
+    if (!q || q->noalloc_last) return CQ_ERR_INVALID;
     DeviceGuard guard(q->device);
     hipError_t e = hipStreamSynchronize(q->last_stream);
     if (e != hipSuccess) return from_hip(e);
@@ -862,7 +899,7 @@ int cq_phase_trace(cq_query *q, int32_t kind, int64_t *out, int64_t cap, int64_t
 }
 
 int cq_batch_plan(cq_query *q, int64_t *out) {
-    if (!q || !out) return CQ_ERR_INVALID;
+    if (!q || !out || q->noalloc_last) return CQ_ERR_INVALID;
     DeviceGuard guard(q->device);
     hipError_t e = hipStreamSynchronize(q->last_stream);
     if (e != hipSuccess) return from_hip(e);
