@@ -51,6 +51,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_ADD_PEAK = 256 * 64 * 2.4e9
 SWEEP = (0.0, 0.5, 1.0, 1.5, 2.0)
 HEADLINE_S = 1.5
+STAGED = 200   # distinct device-resident batches per setting, cycled
 METRIC = "tuples/sec and HBM GB/s at Zipf s=0..2, balanced vs static; p99 batch latency"
 
 
@@ -526,6 +527,17 @@ def copy_calibration(torch, mib: int):
     del src, dst
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(batches_host, cfg, budget_s, threads=1):
     """The CPU oracle over the headline batches (cycled, continuing one
     stream) until about `budget_s` seconds of work.  Returns (batches, s)."""
@@ -588,9 +600,14 @@ def main():
     rows = []
     headline = None
     for s in sweep:
-        cfg = skew(s, batches=args.warmup + args.steps)
+        cfg = skew(s)
         ds = DeviceStream(cfg, dev)
-        batches = [ds.batch(b) for b in range(args.warmup + args.steps)]
+        # STAGED distinct batches (1.6 GiB, several times the 256 MB
+        # last-level cache), cycled: warm-up and timed pushes never find the
+        # inputs of a recent batch still cached, whatever --steps is
+        staged = [ds.batch(b) for b in range(STAGED)]
+        batches = [staged[i % STAGED] for i in range(args.warmup + args.steps)]
+        del staged
         torch.cuda.synchronize()
         bytes_per = algorithmic_bytes(torch, [k for k, _ in batches], cfg.groups, cfg.window,
                                       cfg.batch)
@@ -650,7 +667,8 @@ def main():
     if args.tuple_passes:
         pt = per_tuple(torch, cq, batches, cfg, min(args.warmup, 5), min(args.steps, 40),
                        [int(x) for x in args.tuple_passes.split(",")])
-    host = None if args.no_cpu else [(k.cpu().numpy(), v.cpu().numpy()) for k, v in batches]
+    host = None if args.no_cpu else [(k.cpu().numpy(), v.cpu().numpy())
+                                     for k, v in batches[:STAGED]]
     del batches
     torch.cuda.empty_cache()
     tech = None
@@ -667,6 +685,7 @@ def main():
     if not args.no_cpu:
         done, t = cpu_baseline(host, cfg, args.cpu_budget)
         cpu = {"value": done * cfg.batch / t, "unit": "tuples/s", "cores": 1, "kind": "oracle",
+               "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
                "sample": f"{done} batches of the s=1.5 stream (the {len(host)} headline batches "
                          f"of 1,048,576 tuples, cycled), C oracle, one thread, {t:.1f} s"}
         nthreads = min(16, os.cpu_count() or 1)

@@ -60,6 +60,8 @@ def test_key_mod_matches_reduced_keys(G, W):
         s, c, a = q.push_tuples(to_dev(k), to_dev(v))
         ws, wc, wa = o.push_tuples(reduced(k, G).astype(np.int32), v)
         assert np.array_equal(s.cpu().numpy(), ws) and np.array_equal(c.cpu().numpy(), wc)
+        assert np.array_equal(a.cpu().numpy().view(np.int64),
+                              np.asarray(wa, np.float64).view(np.int64))
     q.close()
     o.close()
 

@@ -235,6 +235,40 @@ def test_skew_config_full_run_balanced(s):
     p.close()
 
 
+@pytest.mark.parametrize("s", [0.0, 0.5, 1.0, 1.5, 2.0])
+def test_skew_bench_arrays_full_run_balanced(s):
+    """The arrays the benchmark times: its 200 device-drawn batches of the
+    10,000-group, W=1000, 1,048,576-tuple Zipf stream (DeviceStream), in the
+    order the benchmark cycles them (all 200, then the first 10 again), each
+    batch copied to the host for the oracle."""
+    note(f"case: bench arrays s={s}, 210 pushes, balanced")
+    from workloads import DeviceStream
+    cfg = skew(s)
+    ds = DeviceStream(cfg, device())
+    p = Pair(cfg.groups, cfg.window, oracle_threads=4)
+    for i in range(cfg.batches + 10):
+        dk, dv = ds.batch(i % cfg.batches)
+        k, v = dk.cpu().numpy(), dv.cpu().numpy()
+        p.step(k, v, f"bench arrays s={s} push {i}", dkeys=dk, dvalues=dv)
+    plan = p.q.batch_plan()
+    assert plan["fault"] == 0 and plan["status"] == 0
+    p.close()
+
+
+def test_skew_config_full_run_static():
+    """All 200 batches of the s=1.5 skew stream under the static partition
+    (the baseline the benchmark reports beside the balanced one)."""
+    note("case: skew stream s=1.5, all 200 batches, static")
+    cfg = skew(1.5)
+    p = Pair(cfg.groups, cfg.window, cq.PARTITION_STATIC, 0, oracle_threads=4)
+    for b in range(cfg.batches):
+        k, v = host_batch(cfg, b)
+        p.step(k, v, f"static s=1.5 batch {b}")
+    plan = p.q.batch_plan()
+    assert plan["fault"] == 0 and plan["status"] == 0
+    p.close()
+
+
 def test_skew_sorted_ids_worst_case_for_static():
     """DS2-like order (hot keys are the smallest ids): the static worker that
     owns the first range gets nearly all the load; results stay identical."""
