@@ -9,15 +9,20 @@ All batches are generated on the device and resident in HBM before timing.
 Reported: tuples/s and algorithmic HBM GB/s for s in {0, 0.5, 1, 1.5, 2},
 balanced vs static partition, p50/p99 batch latency, and the imbalance of
 the per-group phase (per-CU busy-time spread, per-workgroup tuple loads).
-The headline value is one cq_push_batch_results call per batch; the same
-batches through cq_push_batches, 8 per call, are reported beside it.  The headline value
-is s=1.5, balanced.  Throughput, batch latency (an event pair per batch)
-and kernel durations (the library's per-launch events) come from three
+The headline value is s=1.5, balanced, with the batches pushed eight per
+cq_push_batches call (--per-call): every batch's results are emitted into
+its own buffers, and eight batches share one set of launches.  The same
+batches one cq_push_batch_results call each are reported beside it, and the
+static partition runs one batch per call.  Throughput, batch latency (an
+event pair per call: a batch's results are complete when its call's work
+is) and kernel durations (the library's per-launch events) come from
 separate runs over the same batches, because events are stream markers
 with idle time of their own.  The roofline object is for the
-longest-running kernel of the headline run; its `traffic` is the HBM bytes
-per launch recorded from rocprofv3 counters in profiles/traffic_<kind>.md,
-or null when that record was taken on other kernel sources.  The
+longest-running kernel of the headline run (one launch processes one
+call's batches), beside the end-to-end fraction (algorithmic bytes over
+the whole time per batch); its `traffic` is the HBM bytes per launch
+recorded from rocprofv3 counters in profiles/traffic_<kind>.md, or null
+when that record was taken on other kernel sources.  The
 cpu_baseline is the CPU oracle timed on a bounded sample of the same
 headline batches (one thread; a second figure with one thread per host
 core up to 16).
@@ -72,41 +77,56 @@ def algorithmic_bytes(torch, keys_list, groups, window, n):
     return out
 
 
-def run_mode(torch, cq, batches, cfg, mode, warmup, steps, kind="clean"):
-    """Warm up, then run `steps` batches (push + emit) with no host syncs in
-    between, on a fresh query.  kind "clean": nothing but the batches is
-    enqueued (the throughput figure); "latency": an event pair around every
-    batch (p50/p99 batch latency); "kernels": the library's per-launch event
-    timing (per-kernel durations).  Events are markers in the stream and
-    cost idle time of their own, so each kind is a separate run."""
+def run_mode(torch, cq, batches, cfg, mode, warmup, steps, kind="clean", per_call=1):
+    """Warm up, then run `steps` batches (push + emit of every batch) with
+    no host syncs in between, on a fresh query: one cq_push_batch_results
+    call per batch (per_call 1) or cq_push_batches calls of per_call
+    batches each, every batch's results into its own buffers.  kind
+    "clean": nothing but the batches is enqueued (the throughput figure);
+    "latency": an event pair around every call (a batch's results are
+    complete when its call's work is, so with several batches per call the
+    call's latency is each of its batches' latency); "kernels": the
+    library's per-launch event timing.  Events are markers in the stream
+    and cost idle time of their own, so each kind is a separate run."""
     dev = batches[0][0].device
     q = cq.Query(cfg.groups, cfg.window, partition=mode)
     cap = min(cfg.groups, cfg.batch)
-    ids = torch.empty(cap, dtype=torch.int32, device=dev)
-    sums = torch.empty(cap, dtype=torch.int64, device=dev)
-    counts = torch.empty(cap, dtype=torch.int32, device=dev)
-    avgs = torch.empty(cap, dtype=torch.float64, device=dev)
-    nt = torch.empty(1, dtype=torch.int64, device=dev)
-    for b in range(warmup):
-        k, v = batches[b]
-        q.push_results_into(k, v, ids, sums, counts, avgs, nt)
+
+    def outs_():
+        return (torch.empty(cap, dtype=torch.int32, device=dev),
+                torch.empty(cap, dtype=torch.int64, device=dev),
+                torch.empty(cap, dtype=torch.int32, device=dev),
+                torch.empty(cap, dtype=torch.float64, device=dev),
+                torch.empty(1, dtype=torch.int64, device=dev))
+    outs = [outs_() for _ in range(per_call)]
+
+    def push(i0, i1):
+        if per_call == 1:
+            for i in range(i0, i1):
+                q.push_results_into(*batches[i], *outs[0])
+        else:
+            q.push_batches_into(batches[i0:i1], outs[:i1 - i0])
+
+    for i0 in range(0, warmup, per_call):
+        push(i0, min(warmup, i0 + per_call))
     torch.cuda.synchronize()
     if kind == "kernels":
         q.set_telemetry(cq.TELEMETRY_KERNEL_TIMES)
         q.kernel_times()
     res = {}
+    calls = [(i0, min(warmup + steps, i0 + per_call))
+             for i0 in range(warmup, warmup + steps, per_call)]
     if kind == "latency":
-        starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-        ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        starts = [torch.cuda.Event(enable_timing=True) for _ in calls]
+        ends = [torch.cuda.Event(enable_timing=True) for _ in calls]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(steps):
-        k, v = batches[warmup + i]
+    for c, (i0, i1) in enumerate(calls):
         if kind == "latency":
-            starts[i].record()
-        q.push_results_into(k, v, ids, sums, counts, avgs, nt)
+            starts[c].record()
+        push(i0, i1)
         if kind == "latency":
-            ends[i].record()
+            ends[c].record()
     torch.cuda.synchronize()
     res["wall_s"] = time.perf_counter() - t0
     if kind == "latency":
@@ -460,36 +480,6 @@ def imbalance(torch, cq, batches, cfg, mode, warmup=3):
             "wg_tuples_max_over_mean": round(float(max(loads) / np.mean(loads)), 3)}
 
 
-def run_pipelined(torch, cq, batches, cfg, warmup, steps, per_call=8):
-    """The same batches through cq_push_batches, per_call batches per call
-    (each batch's results into its own buffers).  Returns (wall seconds for
-    `steps` batches, per-call event latencies in ms)."""
-    dev = batches[0][0].device
-    q = cq.Query(cfg.groups, cfg.window)
-    cap = min(cfg.groups, cfg.batch)
-    outs = [(torch.empty(cap, dtype=torch.int32, device=dev),
-             torch.empty(cap, dtype=torch.int64, device=dev),
-             torch.empty(cap, dtype=torch.int32, device=dev),
-             torch.empty(cap, dtype=torch.float64, device=dev),
-             torch.empty(1, dtype=torch.int64, device=dev)) for _ in range(per_call)]
-    w = per_call if len(batches) >= 2 * per_call else 0  # one warm-up call
-    if w:
-        q.push_batches_into(batches[:w], outs)
-    torch.cuda.synchronize()
-    calls = min(steps, len(batches) - w) // per_call
-    if calls == 0:
-        q.close()
-        return None
-    t0 = time.perf_counter()
-    for c in range(calls):
-        s0 = w + c * per_call
-        q.push_batches_into(batches[s0:s0 + per_call], outs)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    q.close()
-    return wall, calls * per_call
-
-
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1309_0634_amd", "csrc", f)
                   for f in ("cq_kernels.hip", "cq_device.h", "cq_internal.h")]
 PROFILES = os.path.join(ROOT, "profiles")
@@ -579,6 +569,8 @@ def main():
     ap.add_argument("--serving", default="10,50,100,250,500",
                     help="arrival rates (batches/s) of the serving loop ('' skips it)")
     ap.add_argument("--serving-seconds", type=float, default=3.0)
+    ap.add_argument("--per-call", type=int, default=8,
+                    help="batches per cq_push_batches call of the balanced partition")
     ap.add_argument("--calibrate", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -617,11 +609,16 @@ def main():
                  if nm in args.modes.split(",")]
         for mode, name in modes:
             is_head = (s == HEADLINE_S and mode == cq.PARTITION_BALANCED)
-            r = run_mode(torch, cq, batches, cfg, mode, args.warmup, args.steps)
-            lat = run_mode(torch, cq, batches, cfg, mode, args.warmup, args.steps, "latency")
+            # the balanced partition runs PER_CALL batches per cq_push_batches
+            # call (every batch's results emitted); the static baseline one
+            # batch per call
+            pc = args.per_call if mode == cq.PARTITION_BALANCED else 1
+            r = run_mode(torch, cq, batches, cfg, mode, args.warmup, args.steps, per_call=pc)
+            lat = run_mode(torch, cq, batches, cfg, mode, args.warmup, args.steps, "latency",
+                           per_call=pc)
             tuples = args.steps * cfg.batch
             row = {
-                "s": s, "partition": name,
+                "s": s, "partition": name, "batches_per_call": pc,
                 "tuples_per_s": tuples / r["wall_s"],
                 "alg_GBps": timed_bytes / r["wall_s"] / 1e9,
                 "ms_per_batch": 1e3 * r["wall_s"] / args.steps,
@@ -633,16 +630,20 @@ def main():
                 "touched": int(r["plan"]["touched"]),
                 "imbalance": imbalance(torch, cq, batches, cfg, mode),
             }
+            if pc > 1:  # the same batches one call each, for comparison
+                r1 = run_mode(torch, cq, batches, cfg, mode, args.warmup, args.steps)
+                l1 = run_mode(torch, cq, batches, cfg, mode, args.warmup, args.steps, "latency")
+                row["one_batch_per_call"] = {
+                    "tuples_per_s": tuples / r1["wall_s"],
+                    "ms_per_batch": 1e3 * r1["wall_s"] / args.steps,
+                    "p50_batch_ms": float(np.percentile(l1["lat_ms"], 50)),
+                    "p99_batch_ms": float(np.percentile(l1["lat_ms"], 99))}
             rows.append(row)
             print(json.dumps({"progress": row}), file=sys.stderr, flush=True)
             if is_head:
-                kr = run_mode(torch, cq, batches, cfg, mode, args.warmup, args.steps, "kernels")
+                kr = run_mode(torch, cq, batches, cfg, mode, args.warmup, args.steps, "kernels",
+                              per_call=pc)
                 r["kernels"] = kr["kernels"]
-                pr = run_pipelined(torch, cq, batches, cfg, args.warmup, args.steps)
-                if pr:
-                    pw, pn = pr
-                    row["pipelined_8_per_call"] = {"tuples_per_s": pn * cfg.batch / pw,
-                                                   "ms_per_batch": 1e3 * pw / pn, "batches": pn}
                 headline = (row, r, timed_bytes, cfg, batches)
         if not (s == HEADLINE_S):
             del batches
@@ -653,16 +654,24 @@ def main():
         sys.exit(2)
     row, r, timed_bytes, cfg, batches = headline
     headline = None
-    kern = r["kernels"]
+    kern = {k: v for k, v in r["kernels"].items() if v[1] > 0}
     dom = max(kern, key=lambda k: kern[k][0])
     dom_ms, dom_launches = kern[dom]
     avg_bytes = timed_bytes / args.steps
-    achieved = avg_bytes / (dom_ms / dom_launches * 1e-3) / 1e9
+    # one launch of each kernel processes one call's batches
+    per_launch = avg_bytes * args.steps / dom_launches
+    achieved = per_launch / (dom_ms / dom_launches * 1e-3) / 1e9
     traffic = measured_traffic(dom)
+    e2e = avg_bytes / (row["ms_per_batch"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom, "kernel_avg_us": round(1e3 * dom_ms / dom_launches, 2),
-                "kernel_times_ms": {k: round(v[0], 3) for k, v in kern.items()}}
+                "batches_per_launch": row["batches_per_call"],
+                "alg_bytes_per_launch": round(per_launch),
+                "end_to_end_GBps": round(e2e, 1),
+                "end_to_end_frac": round(e2e / HBM_PEAK_GBS, 4),
+                "kernel_times_ms": {k: round(v[0], 3) for k, v in kern.items()},
+                "kernel_launches": {k: v[1] for k, v in kern.items()}}
     pt = None
     if args.tuple_passes:
         pt = per_tuple(torch, cq, batches, cfg, min(args.warmup, 5), min(args.steps, 40),
@@ -709,9 +718,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "zipf_skew_g10000_w1000_n1048576_s1.5_balanced",
                    "groups": cfg.groups, "window": cfg.window, "batch": cfg.batch,
-                   "zipf_s": HEADLINE_S, "partition": "balanced", "parallelism": "1gpu"},
+                   "zipf_s": HEADLINE_S, "partition": "balanced",
+                   "batches_per_call": row["batches_per_call"], "parallelism": "1gpu"},
         "alg_GBps": row["alg_GBps"],
-        "pipelined_8_per_call": row.get("pipelined_8_per_call"),
+        "one_batch_per_call": row.get("one_batch_per_call"),
         "p50_batch_ms": row["p50_batch_ms"],
         "p99_batch_ms": row["p99_batch_ms"],
         "imbalance_s1.5": {r["partition"]: r["imbalance"] for r in rows if r["s"] == HEADLINE_S},

@@ -480,7 +480,9 @@ int cq_server_destroy(cq_server *srv);
 #define CQ_KERNEL_OTHER     4 /* whole-batch checks and collection    */
 #define CQ_KERNEL_PLAN      5 /* scans over groups + balancer plan    */
 #define CQ_KERNEL_TUPLES    6 /* per-tuple results (cq_push_batch_tuples) */
-#define CQ_KERNEL_KINDS     7
+#define CQ_KERNEL_PREP      7 /* several batches: survivors to their places */
+#define CQ_KERNEL_APPLY     8 /* several batches: windows, results, rings */
+#define CQ_KERNEL_KINDS     9
 
 /*
  * cq_set_telemetry -- turn measurement on (flags) or off (0).  Imbalance
@@ -516,7 +518,9 @@ int cq_worker_trace(cq_query *q, int64_t *rec, int64_t cap, int64_t *count);
  * workgroup, 0 = not reached).  kind 0: histogram (slots 0-2) and, where
  * the plan is a launch of its own, the plan (slots 3-4); kind 1: reorder
  * pass (slots 0-4; with the plan inside the pass, slots 5-7 mark its
- * steps); kind 2: per-group update (slots 0-5).  *count receives the
+ * steps); kind 2: per-group update (slots 0-5); several batches per call
+ * (cq_push_batches): kind 0 slots 3-7 the plan, kind 3 the survivor launch
+ * (slots 0-5), kind 4 the apply launch (slots 0-7).  *count receives the
  * number of records available (4096).  Needs CQ_TELEMETRY_PHASES.  Returns
  * CQ_OK, CQ_ERR_INVALID or CQ_ERR_HIP.
  */

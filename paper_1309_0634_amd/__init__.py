@@ -25,7 +25,7 @@ POLICIES = {"getFirst": PARTITION_GETFIRST, "checkAll": PARTITION_CHECKALL,
             "shift": PARTITION_SHIFT, "shiftLocal": PARTITION_SHIFTLOCAL}
 STATIC_KEYS_MAX = 2048
 TELEMETRY_KERNEL_TIMES, TELEMETRY_WORKERS, TELEMETRY_PHASES = 1, 2, 4
-KERNEL_KINDS = ("hist", "pass", "update", "emit", "other", "plan", "tuples")
+KERNEL_KINDS = ("hist", "pass", "update", "emit", "other", "plan", "tuples", "prep", "apply")
 TUPLE_MAX_WINDOW = 1024
 TUPLE_MAX_PASSES = 64
 MAX_BATCH = 1 << 30

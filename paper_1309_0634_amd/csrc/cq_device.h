@@ -123,6 +123,15 @@ __device__ __forceinline__ int32_t view_key(int32_t raw, uint64_t m, int64_t G) 
     return (int32_t)__umul64hi(low, (uint64_t)G);
 }
 
+// Marks a loaded value as used here, so that the compiler keeps its load
+// where it was issued (beside the others) rather than sinking it into the
+// branch that uses it, where it would wait alone.
+__device__ __forceinline__ void keep(int32_t &x) { __asm__ volatile("" : "+v"(x)); }
+__device__ __forceinline__ void keep(int4 &x) {
+    __asm__ volatile("" : "+v"(x.x), "+v"(x.y), "+v"(x.z), "+v"(x.w));
+}
+__device__ __forceinline__ void keep(int64_t &x) { __asm__ volatile("" : "+v"(x)); }
+
 // Largest r in [0, m) with pre[r] <= p (pre ascending, pre[0] = 0 <= p).
 __device__ __forceinline__ int upper_run(const int32_t *pre, int m, int p) {
     int lo = 0, hi = m - 1;

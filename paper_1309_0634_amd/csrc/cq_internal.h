@@ -147,7 +147,9 @@ struct Scratch {
 constexpr int PHASE_HIST_PLAN = 0;
 constexpr int PHASE_PASS = 1;
 constexpr int PHASE_UPDATE = 2;
-constexpr int PHASE_KINDS = 3;
+constexpr int PHASE_SB_PREP = 3;   // several-batch survivor launch
+constexpr int PHASE_SB_APPLY = 4;  // several-batch apply launch
+constexpr int PHASE_KINDS = 5;
 constexpr int PHASE_BLOCKS = 4096;
 constexpr int PHASE_SLOTS = 8;
 
@@ -160,11 +162,117 @@ struct Out {
     int64_t *n_touched;
 };
 
+// Several consecutive batches through one set of launches (cq_push_batches
+// with at most PASS_LOCAL_G groups, balanced partition): up to SB_K batches
+// of at most SUB tuples each share a histogram, a plan, a reorder, a
+// survivor (prep) and an apply launch.  Each batch keeps its own balanced
+// plan; the survivors of all batches -- a group's last min(k, W) tuples of
+// each batch, which are the only ones any emitted window holds -- get
+// consecutive places per group (batch by batch, arrival order), so that
+// every batch's window sums are differences of prefix sums.
+constexpr int SB_K = 8;
+// histogram blocks of the several-batch path count SBH_KPT keys per thread
+// (four single-batch tiles) of one batch: a quarter of the flush atomics
+constexpr int SBH_KPT = 4 * HIST_KPT;
+constexpr int SBH_TILE = HIST_THREADS * SBH_KPT;
+// plan: one group per thread in blocks of SBP_THREADS; per block SBP_F field
+// sums and two (count << 32 | group) words
+constexpr int SBP_THREADS = 1024;
+constexpr int SBP_F = 2 * SB_K + 2;
+constexpr int SBP_PART = SBP_F + 4;
+// apply work per bucket: survivors plus old window values, at most
+// APPLY_CAP per range of small groups; a group over APPLY_BUDGET is handled
+// alone
+constexpr int APPLY_BUDGET = 2048;
+constexpr int APPLY_CAP = 2 * APPLY_BUDGET;
+constexpr int APPLY_THREADS = 256;
+constexpr int APPLY_GPT = 4;                                // groups per thread in a flat range
+constexpr int APPLY_FLAT_G = APPLY_THREADS * APPLY_GPT;     // groups per flat range
+constexpr int APPLY_EPT = APPLY_CAP / APPLY_THREADS;        // elements per thread
+static_assert(APPLY_CAP % APPLY_THREADS == 0, "whole elements per thread");
+// Workgroups of the survivor and apply launches, which loop over their
+// items: as many as the device runs at once (256 CUs; four and two per CU
+// fit their registers and LDS).
+constexpr int SB_PREP_GRID = 1024;
+constexpr int SB_PASS_GRID = 256;
+constexpr int SB_APPLY_GRID = 512;
+
+// Buffers of the several-batch path, one slice per batch where marked.
+struct SbBufs {
+    int32_t *kh;        // [G][SB_K] per-batch histograms, a group's counts together;
+                        // zero between uses
+    int32_t *sbad;      // [SB_K] sequence number of the last call whose batch b had a bad key
+    int32_t *bucket;    // [SB_K][G]
+    int32_t *lpre;      // [SB_K][G + 1]
+    int32_t *tidx;      // [SB_K][G]
+    int32_t *bstart;    // [SB_K][NB_MAX + 1]
+    int32_t *hkey;      // [SB_K][NB_MAX]
+    int2 *sdat;         // [SB_K][SUB]
+    int32_t *rowstart;  // [SB_K][PASS_TILES_MAX * (NB_MAX + 1)]
+    PlanTotals *tot;    // [SB_K]
+    int32_t *so;        // [SB_K][G] first place of batch b's survivors of group g
+    int32_t *gsb;       // [G + 1] first place of group g's survivors
+    int32_t *astart;    // [sb_apply_max() + 1] first group of each apply range
+    int32_t *xs;        // [SB_K * SUB] survivors' values, by group, batch, arrival
+    int32_t *ntot;      // [2] apply ranges, survivors
+    int64_t *tb;        // [SB_K][G] sum of a heavy item's survivors (batch, group)
+    int32_t *part;      // [plan blocks][SBP_PART] plan fields summed per block, top two groups
+    int32_t *fault;     // the query's fault bits
+};
+
+// The batches of one several-batch call (kernel argument).
+struct SbBatches {
+    const int32_t *keys[SB_K];
+    const int32_t *values[SB_K];
+    int64_t n[SB_K];
+    int32_t htile0[SB_K + 1];   // histogram tiles before each batch
+    int32_t ptile0[SB_K + 1];   // reorder tiles before each batch
+    uint32_t vec;               // bit b: batch b's keys are 16-byte aligned
+    int32_t K;
+    Out out[SB_K];
+};
+
+// Batch b's slice of the several-batch buffers as a Scratch (with the
+// query's shared pointers from `base`).
+__host__ __device__ inline Scratch sb_set(const SbBufs &sb, const Scratch &base, int b,
+                                          int64_t G) {
+    Scratch s = base;
+    s.k = nullptr;  // (the counters are interleaved by group: sb.kh[g * SB_K + b])
+    s.bad = sb.sbad + b;
+    s.bucket = sb.bucket + (int64_t)b * G;
+    s.lpre = sb.lpre + (int64_t)b * (G + 1);
+    s.tidx = sb.tidx + (int64_t)b * G;
+    s.bstart = sb.bstart + (int64_t)b * (NB_MAX + 1);
+    s.hkey = sb.hkey + (int64_t)b * NB_MAX;
+    s.sdat = sb.sdat + (int64_t)b * SUB;
+    s.rowstart = sb.rowstart + (int64_t)b * PASS_TILES_MAX * (NB_MAX + 1);
+    s.tot = sb.tot + b;
+    s.sidx = nullptr;
+    s.pcnt = nullptr;
+    s.trace = nullptr;
+    return s;
+}
+// Apply ranges of one call at most (survivors plus old values, at most two
+// per tuple, in ranges of APPLY_BUDGET).
+inline int64_t sb_apply_max() { return (int64_t)SB_K * SUB * 2 / APPLY_BUDGET + 2; }
+// The five launches of `in.K` batches (seq: the call's sequence number).
+hipError_t launch_sb_hist(State st, Scratch base, SbBufs sb, const SbBatches &in, int32_t seq,
+                          hipStream_t s);
+hipError_t launch_sb_plan(State st, Scratch base, SbBufs sb, const SbBatches &in, int32_t seq,
+                          hipStream_t s);
+hipError_t launch_sb_pass(State st, Scratch base, SbBufs sb, const SbBatches &in, int32_t seq,
+                          hipStream_t s);
+hipError_t launch_sb_prep(State st, Scratch base, SbBufs sb, const SbBatches &in,
+                          hipStream_t s);
+hipError_t launch_sb_apply(State st, Scratch base, SbBufs sb, const SbBatches &in, int32_t seq,
+                           hipStream_t s);
+
 constexpr int32_t FAULT_LIGHT_SIZE = 1;
 constexpr int32_t FAULT_BUCKETS = 2;
 constexpr int32_t FAULT_STATIC_KEYS = 4;
 constexpr int32_t FAULT_TUPLE_RUNS = 8;   // a bucket's runs disagree with its plan
 constexpr int32_t FAULT_PASSES = 16;      // repeated window scans disagreed
+constexpr int32_t FAULT_APPLY = 32;       // an apply range over its element budget
 
 // Per-tuple results (the paper's aggregate after every insertion): one
 // entry per tuple, in arrival order; any pointer may be null.  passes = 0:

@@ -236,24 +236,28 @@ __device__ void plan_publish(const State &st, const Scratch &sc, const int (&tot
 }
 
 // ----------------------------------------------------- k_hist_plan (small G)
-// Histogram blocks of HIST_THREADS threads over HIST_TILE consecutive tuples
-// each (every thread's keys loaded together), LDS counters indexed by key;
-// the block that finishes last plans the whole sub-batch (G <= PLAN_CHUNK).
-__global__ __launch_bounds__(HIST_THREADS) void k_hist_small(const int32_t *__restrict__ keys,
-                                                             int64_t n, bool vec, int32_t G,
-                                                             Scratch sc, int32_t seq) {
-    if (sc.seqp) seq = *sc.seqp;  // captured for replay: the argument would be stale
-    extern __shared__ int32_t cntr[];
+// Histogram tile `tile` (of `ntiles` counted into the same counters) of
+// HIST_THREADS * KPT consecutive tuples of keys[0, n), one block of
+// HIST_THREADS threads (every thread's KPT keys loaded together), LDS
+// counters indexed by key (`cntr`, G of them), added to kout[g * kstride]; a
+// bad key stores `seq` in *badout.
+template <int KPT>
+__device__ __forceinline__ void hist_small_tile(const int32_t *__restrict__ keys, int64_t n,
+                                                bool vec, int32_t G, const Scratch &sc,
+                                                int32_t seq, int tile, int ntiles,
+                                                int32_t *kout, int kstride, int32_t *badout,
+                                                int32_t *cntr) {
+    static_assert(KPT % 4 == 0, "keys loaded four at a time");
     const int tid = threadIdx.x;
     phase_mark(sc, PHASE_HIST_PLAN, 0);
     // the previous sub-batch's two most frequent groups are counted in
     // registers: a Zipf-hot key would otherwise serialise LDS atomics
     const int32_t hot0 = sc.hot[0], hot1 = sc.hot[1];
     for (int g = tid; g < G; g += HIST_THREADS) cntr[g] = 0;
-    const int64_t base = (int64_t)blockIdx.x * HIST_TILE;
-    int32_t v[HIST_KPT];
+    const int64_t base = (int64_t)tile * HIST_THREADS * KPT;
+    int32_t v[KPT];
 #pragma unroll
-    for (int j = 0; j < HIST_KPT / 4; ++j) {
+    for (int j = 0; j < KPT / 4; ++j) {
         const int64_t i = base + 4 * ((int64_t)j * HIST_THREADS + tid);
         if (vec && i + 3 < n) {
             const int4 x = *reinterpret_cast<const int4 *>(keys + i);
@@ -265,12 +269,12 @@ __global__ __launch_bounds__(HIST_THREADS) void k_hist_small(const int32_t *__re
     }
     if (sc.kmod) {
 #pragma unroll
-        for (int j = 0; j < HIST_KPT; ++j) v[j] = view_key(v[j], sc.kmod, G);
+        for (int j = 0; j < KPT; ++j) v[j] = view_key(v[j], sc.kmod, G);
     }
     __syncthreads();
     int bad = 0, c0 = 0, c1 = 0;
 #pragma unroll
-    for (int j = 0; j < HIST_KPT / 4; ++j) {
+    for (int j = 0; j < KPT / 4; ++j) {
         const int64_t i = base + 4 * ((int64_t)j * HIST_THREADS + tid);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -289,18 +293,28 @@ __global__ __launch_bounds__(HIST_THREADS) void k_hist_small(const int32_t *__re
         if (c1) atomicAdd(&cntr[hot1], c1);
     }
     if (__syncthreads_or(bad)) {
-        if (tid == 0) atomicExch(sc.bad, seq);
+        if (tid == 0) atomicExch(badout, seq);
     }
     phase_mark(sc, PHASE_HIST_PLAN, 1);
     // blocks start their flush at evenly spread groups, so that they do not
     // all hit the same counters at the same time
-    const int off = (int)(((int64_t)blockIdx.x * G / gridDim.x) & ~63);
+    const int off = (int)(((int64_t)tile * G / ntiles) & ~63);
     for (int i = tid; i < G; i += HIST_THREADS) {
         const int g = i + off < G ? i + off : i + off - G;
         const int32_t c = cntr[g];
-        if (c) atomicAdd(&sc.k[g], c);
+        if (c) atomicAdd(&kout[(int64_t)g * kstride], c);
     }
     phase_mark(sc, PHASE_HIST_PLAN, 2);
+}
+
+// Histogram blocks over one sub-batch, tile = block.
+__global__ __launch_bounds__(HIST_THREADS) void k_hist_small(const int32_t *__restrict__ keys,
+                                                             int64_t n, bool vec, int32_t G,
+                                                             Scratch sc, int32_t seq) {
+    if (sc.seqp) seq = *sc.seqp;  // captured for replay: the argument would be stale
+    extern __shared__ int32_t cntr[];
+    hist_small_tile<HIST_KPT>(keys, n, vec, G, sc, seq, (int)blockIdx.x, (int)gridDim.x, sc.k, 1,
+                              sc.bad, cntr);
 }
 
 // ------------------------------------------------- plan (G <= 32768) --
@@ -835,87 +849,30 @@ __device__ void pass_owned_writes(const State &st, const Scratch &sc, const int4
 // Multisplit pass.  LOCAL: the plan is computed in the block (above) and
 // bucket ids come from LDS; otherwise they are read from the plan's global
 // per-group buckets.
-template <bool LOCAL>
-__global__ __launch_bounds__(PASS_THREADS) void k_pass(const int32_t *__restrict__ keys,
-                                                       const int32_t *__restrict__ values,
-                                                       int64_t n, State st, Scratch sc,
-                                                       int32_t seq, int mode, int32_t workers) {
-    if (sc.seqp) seq = *sc.seqp;  // captured for replay: the argument would be stale
-    // per-wave bucket counters and the reordered tile; during an in-block
-    // plan the same bytes hold the group counts
-    __shared__ __align__(16) char pool[P_BYTES];
+// The multisplit of one tile whose keys, values and bucket ids (NB: none)
+// are in registers: ranks inside each wave's chunk, tile-wide bucket
+// offsets, the reordered tile written back contiguously and its row of
+// bucket starts.  `after_clear` runs after the first barrier,
+// `before_stores` before the first global store.  The LDS arrays are the
+// caller's.
+template <typename F, typename H>
+__device__ __forceinline__ void pass_split(const int32_t (&key)[PASS_ROUNDS],
+                                           const int32_t (&val)[PASS_ROUNDS],
+                                           const int32_t (&bk)[PASS_ROUNDS],
+                                           int32_t (&lr)[PASS_ROUNDS], int NB, int64_t base,
+                                           int tile_n, int tile, const Scratch &sc, char *pool,
+                                           int32_t *ts, int *red, uint16_t *gbk,
+                                           F &&after_clear, H &&before_stores) {
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     uint16_t (*wc)[NB_MAX] = reinterpret_cast<uint16_t (*)[NB_MAX]>(pool + P_WC);
     int2 *stage = reinterpret_cast<int2 *>(pool + P_STAGE);
-    __shared__ int32_t ts[NB_MAX + 1];
-    __shared__ int red[PASS_WAVES];
-    // group -> bucket ids during an in-block plan; then, in both variants,
-    // one LEAD-byte leader table per wave for the multisplit
-    __shared__ __align__(16) uint16_t gbk[PASS_LOCAL_G];
-    __shared__ int pred[2 * PASS_WAVES];
-    __shared__ unsigned long long ptop[2 * PASS_WAVES];
-    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-    const int64_t base = (int64_t)blockIdx.x * PASS_TILE;
-    const int tile_n = (int)min((int64_t)PASS_TILE, n - base);
-    phase_mark(sc, PHASE_PASS, 0);
-    int32_t key[PASS_ROUNDS], val[PASS_ROUNDS], bk[PASS_ROUNDS], lr[PASS_ROUNDS];
-    // Raw keys, loaded unconditionally from an index clamped into the batch
-    // (n >= 1), so that no load waits on another; lanes past n are masked
-    // where the keys are first used, and the group view is applied there.
-    auto load_tile = [&]() {
-#pragma unroll
-        for (int r = 0; r < PASS_ROUNDS; ++r) {
-            const int64_t i = min(base + wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane, n - 1);
-            key[r] = keys[i];
-            val[r] = values[i];
-        }
-    };
-    int NB;
-    int own_n = 0;
-    int32_t po0 = 0, c00 = 0, nl = 0;
-    if (LOCAL) {
-        NB = pass_local_plan(st, sc, seq, mode, workers, gbk, reinterpret_cast<int32_t *>(pool),
-                             reinterpret_cast<int4 *>(pool + P_STAGE), pred, ptop, own_n, po0,
-                             c00, nl, load_tile);
-        if (NB < 0) return;
-        if (NB > LEAD) {  // no plan makes this many buckets
-            if (tid == 0) atomicOr(sc.fault, FAULT_BUCKETS);
-            return;
-        }
-#pragma unroll
-        for (int r = 0; r < PASS_ROUNDS; ++r) {
-            const int64_t i = base + wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane;
-            key[r] = view_key(key[r], sc.kmod, st.G);
-            bk[r] = (i < n && (uint32_t)key[r] < (uint32_t)st.G) ? gbk[key[r]] : NB;
-            lr[r] = 0;
-        }
-    } else {
-        load_tile();
-        const PlanTotals t = *sc.tot;
-        if (t.status) return;
-        NB = t.n_buckets;
-        if (NB > LEAD) {  // no plan makes this many buckets
-            if (tid == 0) atomicOr(sc.fault, FAULT_BUCKETS);
-            return;
-        }
-#pragma unroll
-        for (int r = 0; r < PASS_ROUNDS; ++r) {
-            const int64_t i = base + wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane;
-            key[r] = view_key(key[r], sc.kmod, st.G);
-            bk[r] = (i < n) ? sc.bucket[key[r]] : NB;
-            lr[r] = 0;
-        }
-    }
     // clear the per-wave counters two at a time, row by row (no division by
     // NB; a row may be cleared one entry past NB, which NB_MAX leaves room for)
     for (int p = tid; 2 * p < NB; p += PASS_THREADS)
 #pragma unroll
         for (int w = 0; w < PASS_WAVES; ++w) reinterpret_cast<uint32_t *>(wc[w])[p] = 0;
     __syncthreads();
-    // the plan's per-group writes (fields in the staging area, which is
-    // written only after two more barriers)
-    if (LOCAL && own_n > 0)
-        pass_owned_writes(st, sc, reinterpret_cast<const int4 *>(pool + P_STAGE), own_n, po0,
-                          c00, nl, seq, mode, workers);
+    after_clear();
     phase_mark(sc, PHASE_PASS, 1);
     // The lanes of a round that share a bucket elect one of them: each
     // writes its lane id into the wave's table at its bucket and, after a
@@ -981,14 +938,114 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(const int32_t *__restrict
     __syncthreads();
     // two staged tuples per 16-byte store (the tile starts 32 KB-aligned;
     // an odd last tuple of a ragged tile is stored alone)
+    before_stores();
+    // (fixed trip counts, stores predicated: the number of stores in flight
+    // is then known where later loads are waited for)
     int2 *dst = sc.sdat + base;
     const int4 *st4 = reinterpret_cast<const int4 *>(stage);
     int4 *dst4 = reinterpret_cast<int4 *>(dst);
-    for (int i = tid; i < tile_n / 2; i += PASS_THREADS) dst4[i] = st4[i];
+#pragma unroll
+    for (int j = 0; j < PASS_TILE / 2 / PASS_THREADS; ++j) {
+        const int i = tid + j * PASS_THREADS;
+        if (i < tile_n / 2) dst4[i] = st4[i];
+    }
     if ((tile_n & 1) && tid == 0) dst[tile_n - 1] = stage[tile_n - 1];
-    int32_t *row = sc.rowstart + (int64_t)blockIdx.x * (NB + 1);
-    for (int b = tid; b <= NB; b += PASS_THREADS) row[b] = ts[b];
+    int32_t *row = sc.rowstart + (int64_t)tile * (NB + 1);
+#pragma unroll
+    for (int j = 0; j < (NB_MAX + PASS_THREADS) / PASS_THREADS; ++j) {
+        const int b = tid + j * PASS_THREADS;
+        if (b <= NB) row[b] = ts[b];
+    }
     phase_mark(sc, PHASE_PASS, 4);
+}
+
+// One tile (`tile`: its index in the sub-batch) per block.
+template <bool LOCAL>
+__device__ __forceinline__ void pass_tile(const int32_t *__restrict__ keys,
+                                          const int32_t *__restrict__ values, int64_t n,
+                                          const State &st, const Scratch &sc, int32_t seq,
+                                          int mode, int32_t workers, int tile) {
+    // per-wave bucket counters and the reordered tile; during an in-block
+    // plan the same bytes hold the group counts
+    __shared__ __align__(16) char pool[P_BYTES];
+    __shared__ int32_t ts[NB_MAX + 1];
+    __shared__ int red[PASS_WAVES];
+    // group -> bucket ids during an in-block plan; then, in both variants,
+    // one LEAD-byte leader table per wave for the multisplit
+    __shared__ __align__(16) uint16_t gbk[PASS_LOCAL_G];
+    __shared__ int pred[2 * PASS_WAVES];
+    __shared__ unsigned long long ptop[2 * PASS_WAVES];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const int64_t base = (int64_t)tile * PASS_TILE;
+    const int tile_n = (int)min((int64_t)PASS_TILE, n - base);
+    phase_mark(sc, PHASE_PASS, 0);
+    int32_t key[PASS_ROUNDS], val[PASS_ROUNDS], bk[PASS_ROUNDS], lr[PASS_ROUNDS];
+    // Raw keys, loaded unconditionally from an index clamped into the batch
+    // (n >= 1), so that no load waits on another; lanes past n are masked
+    // where the keys are first used, and the group view is applied there.
+    auto load_tile = [&]() {
+#pragma unroll
+        for (int r = 0; r < PASS_ROUNDS; ++r) {
+            const int64_t i = min(base + wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane, n - 1);
+            key[r] = keys[i];
+            val[r] = values[i];
+        }
+    };
+    int NB;
+    int own_n = 0;
+    int32_t po0 = 0, c00 = 0, nl = 0;
+    if (LOCAL) {
+        NB = pass_local_plan(st, sc, seq, mode, workers, gbk, reinterpret_cast<int32_t *>(pool),
+                             reinterpret_cast<int4 *>(pool + P_STAGE), pred, ptop, own_n, po0,
+                             c00, nl, load_tile);
+        if (NB < 0) return;
+        if (NB > LEAD) {  // no plan makes this many buckets
+            if (tid == 0) atomicOr(sc.fault, FAULT_BUCKETS);
+            return;
+        }
+#pragma unroll
+        for (int r = 0; r < PASS_ROUNDS; ++r) {
+            const int64_t i = base + wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane;
+            key[r] = view_key(key[r], sc.kmod, st.G);
+            bk[r] = (i < n && (uint32_t)key[r] < (uint32_t)st.G) ? gbk[key[r]] : NB;
+            lr[r] = 0;
+        }
+    } else {
+        load_tile();
+        const PlanTotals t = *sc.tot;
+        if (t.status) return;
+        NB = t.n_buckets;
+        if (NB > LEAD) {  // no plan makes this many buckets
+            if (tid == 0) atomicOr(sc.fault, FAULT_BUCKETS);
+            return;
+        }
+#pragma unroll
+        for (int r = 0; r < PASS_ROUNDS; ++r) {
+            const int64_t i = base + wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane;
+            key[r] = view_key(key[r], sc.kmod, st.G);
+            bk[r] = (i < n) ? sc.bucket[key[r]] : NB;
+            lr[r] = 0;
+        }
+    }
+    pass_split(
+        key, val, bk, lr, NB, base, tile_n, tile, sc, pool, ts, red, gbk,
+        [&]() {
+            // the plan's per-group writes (fields in the staging area, which
+            // is written only after two more barriers)
+            if (LOCAL && own_n > 0)
+                pass_owned_writes(st, sc, reinterpret_cast<const int4 *>(pool + P_STAGE), own_n,
+                                  po0, c00, nl, seq, mode, workers);
+        },
+        [] {});
+}
+
+template <bool LOCAL>
+__global__ __launch_bounds__(PASS_THREADS) void k_pass(const int32_t *__restrict__ keys,
+                                                       const int32_t *__restrict__ values,
+                                                       int64_t n, State st, Scratch sc,
+                                                       int32_t seq, int mode, int32_t workers) {
+    if (sc.seqp) seq = *sc.seqp;  // captured for replay: the argument would be stale
+    pass_tile<LOCAL>(keys, values, n, st, sc, seq, mode, workers, (int)blockIdx.x);
 }
 
 // ------------------------------------------------------------- k_update --
@@ -1039,19 +1096,20 @@ static_assert(LIGHT_CAP <= 32768, "16-bit positions");
 static_assert(PASS_TILES_MAX <= 256, "8-bit run indices");
 static_assert(LIGHT_CAP % UPD_THREADS == 0, "whole positions per thread");
 
-// Light bucket b: groups [bstart[b], bstart[b+1]) packed by the plan, fewer
-// than LIGHT_CAP tuples, read in arrival order.  Each wave takes a
-// contiguous chunk; in every 64-lane round the lanes holding the same group
-// find each other with ballots over the group's start position, so a
-// tuple's rank among its group's earlier tuples is exact and stable.  Every
-// tuple among its group's last W goes to ring slot (pos + rank) mod W.
+// The tuples of light bucket [a, z) (groups packed by the plan, fewer than
+// LIGHT_CAP tuples, runs already in rs/rp), read in arrival order into LDS
+// (ek, ev, pz) and ranked: each wave takes a contiguous chunk; in every
+// 64-lane round the lanes holding the same group find each other with
+// ballots over the group's start position, so a tuple's rank among its
+// group's earlier tuples is exact and stable (light_rank_of).  Returns false
+// for an empty bucket or a malformed plan (flagged).
 // IN_LDS: the bucket's groups span at most LIGHT_SPAN ids and their
-// staged-range starts and old ring pointers were prefetched into LDS (a
-// template parameter, so that each read is a plain LDS or global load, never
-// a generic one that the compiler must wait on as both).
+// staged-range starts were prefetched into LDS (a template parameter, so
+// that each read is a plain LDS or global load, never a generic one that the
+// compiler must wait on as both).
 template <bool IN_LDS>
-__device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const State &st,
-                            const Scratch &sc, const Out &out, char *smem) {
+__device__ bool light_rank(int32_t a, int32_t z, int size, int tiles, const Scratch &sc,
+                           char *smem) {
     const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
     const int32_t *rs = reinterpret_cast<const int32_t *>(smem + U_RS);
     const int32_t *rp = reinterpret_cast<const int32_t *>(smem + U_RP);
@@ -1063,16 +1121,14 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
     uint16_t *cw = reinterpret_cast<uint16_t *>(smem + U_CW);
     long long *acc = reinterpret_cast<long long *>(smem + U_ACC);
     const int32_t *klp = reinterpret_cast<const int32_t *>(smem + U_KLP);
-    const int32_t *kpo = reinterpret_cast<const int32_t *>(smem + U_KPO);
     constexpr bool in_lds = IN_LDS;
-    // staged-range start (relative to the bucket) and old ring pointer of g
+    // staged-range start of g (relative to the bucket)
     auto lp = [&](int32_t g) { return in_lds ? klp[g - a] : sc.lpre[g]; };
-    auto po = [&](int32_t g) { return in_lds ? kpo[g - a] : sc.pold[g]; };
     const int32_t s0 = lp(a);
-    if (size <= 0) return 0;
+    if (size <= 0) return false;
     if (size > LIGHT_CAP || lp(z) - s0 != size) {
         if (tid == 0) atomicOr(sc.fault, FAULT_LIGHT_SIZE);
-        return 0;
+        return false;
     }
     // run (tile) of every bucket position, so the gather below needs one
     // LDS read instead of a binary search over the runs: mark each
@@ -1207,6 +1263,47 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
         }
     }
     __syncthreads();
+    return true;
+}
+
+// The rank of the tuple at bucket position p among its group's tuples
+// (arrival order), after light_rank: its wave's offset inside the group
+// plus its rank inside the wave's chunk.
+__device__ __forceinline__ int32_t light_rank_of(const char *smem, int size, int p) {
+    const int16_t *pz = reinterpret_cast<const int16_t *>(smem + U_PZ);
+    const uint16_t *lr = reinterpret_cast<const uint16_t *>(smem + U_LR);
+    const uint16_t *cw = reinterpret_cast<const uint16_t *>(smem + U_CW);
+    const int chunk = (size + UPD_WAVES - 1) / UPD_WAVES;
+    int w = 0;  // the wave whose chunk holds p
+#pragma unroll
+    for (int k = 1; k < UPD_WAVES; ++k) w += p >= k * chunk ? 1 : 0;
+    return cw[w * LIGHT_CAP + pz[p]] + lr[p];
+}
+
+// Light bucket b: groups [bstart[b], bstart[b+1]) packed by the plan, fewer
+// than LIGHT_CAP tuples, ranked by light_rank.  Every tuple among its
+// group's last W goes to ring slot (pos + rank) mod W and the group's sum
+// gains (new value - value overwritten).
+template <bool IN_LDS>
+__device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const State &st,
+                            const Scratch &sc, const Out &out, char *smem) {
+    if (!light_rank<IN_LDS>(a, z, size, tiles, sc, smem)) return 0;
+    const int tid = threadIdx.x;
+    int32_t *ek = reinterpret_cast<int32_t *>(smem + U_EK);
+    int32_t *ev = reinterpret_cast<int32_t *>(smem + U_EV);
+    int16_t *pz = reinterpret_cast<int16_t *>(smem + U_PZ);
+    uint16_t *lr = reinterpret_cast<uint16_t *>(smem + U_LR);
+    int16_t *hd = reinterpret_cast<int16_t *>(smem + U_HD);
+    uint16_t *cw = reinterpret_cast<uint16_t *>(smem + U_CW);
+    long long *acc = reinterpret_cast<long long *>(smem + U_ACC);
+    const int32_t *klp = reinterpret_cast<const int32_t *>(smem + U_KLP);
+    const int32_t *kpo = reinterpret_cast<const int32_t *>(smem + U_KPO);
+    constexpr bool in_lds = IN_LDS;
+    auto lp = [&](int32_t g) { return in_lds ? klp[g - a] : sc.lpre[g]; };
+    auto po = [&](int32_t g) { return in_lds ? kpo[g - a] : sc.pold[g]; };
+    const int32_t s0 = lp(a);
+    const int chunk = (size + UPD_WAVES - 1) / UPD_WAVES;
+    constexpr int SPT = LIGHT_CAP / UPD_THREADS;
     const int32_t W = st.W;
     phase_mark(sc, PHASE_UPDATE, 3);
     // the touched groups' sums, counts and output slots are loaded now, so
@@ -1769,6 +1866,973 @@ __global__ void k_reset_totals(Scratch sc) {
     *sc.tot = t;
 }
 
+// ======================================================= several batches --
+// Up to SB_K consecutive batches of one query share five launches:
+//
+//   k_sb_hist   every batch's key histogram (the tiles of all batches).
+//   k_sb_plan   every batch's own balanced plan (buckets, output positions),
+//               and the places of the survivors: a tuple can be in a window
+//               emitted for its own batch or a later one only if it is
+//               among its group's last W tuples of its batch (a tuple that
+//               is not is more than W places from the end of every later
+//               batch too), so each group's survivors of every batch get
+//               consecutive places, batch by batch, in arrival order.
+//   k_sb_pass   every tile of every batch reordered by its batch's plan.
+//   k_sb_prep   per (batch, bucket): each tuple's rank inside its group,
+//               survivors written to their places.
+//   k_sb_apply  per range of groups: with C the group's tuples in batches
+//               0..b of the call and S = its window before the call (W
+//               values, oldest first; never-written slots hold 0) followed
+//               by its new tuples in arrival order, batch b's window is
+//               S[C, C + W): its new part is the last min(W, C) survivors
+//               up to the end of batch b's, consecutive places; its old
+//               part (C < W) is the window sum before the call minus
+//               S[0, C).  Both are differences of prefix sums.  The final
+//               window goes to the ring (Section 3.2: slot nextPos).
+
+// Batch of tile t, given the tiles before each batch (K batches).
+__device__ __forceinline__ int sb_batch_of(const int32_t *tile0, int K, int t) {
+    int b = 0;
+    while (b + 1 < K && tile0[b + 1] <= t) ++b;
+    return b;
+}
+
+__global__ __launch_bounds__(HIST_THREADS) void k_sb_hist(Scratch base, SbBufs sb,
+                                                          SbBatches in, int32_t G,
+                                                          int32_t seq) {
+    extern __shared__ int32_t cntr[];
+    const int t = (int)blockIdx.x;
+    const int b = sb_batch_of(in.htile0, in.K, t);
+    hist_small_tile<SBH_KPT>(in.keys[b], in.n[b], (in.vec >> b) & 1u, G, base, seq,
+                             t - in.htile0[b], in.htile0[b + 1] - in.htile0[b], sb.kh + b, SB_K,
+                             sb.sbad + b, cntr);
+}
+
+// The plan of every batch and the survivors' places, one group per thread.
+// Every block sums the fields of all groups itself (those before its first
+// group give its carries, all of them the totals), so no block waits on
+// another.  Fields per batch: light tuples, and heavy groups | touched
+// groups << 12; then survivors and apply work (survivors plus old values
+// read) per group.
+static_assert(SUB / HEAVY_MIN < (1 << 12) && (int64_t)PASS_LOCAL_G << 12 < (1LL << 31),
+              "heavy groups of a batch fit 12 bits, touched groups the rest of an int");
+
+struct SbGroup {
+    int32_t k[SB_K];  // tuples per batch (0 for a rejected batch)
+    int32_t cnt0;     // window count before the call
+};
+
+__device__ __forceinline__ void sb_fields(const SbGroup &q, int K, int32_t W, int (&x)[SBP_F],
+                                          int32_t &kg) {
+    int m = 0;
+    kg = 0;
+#pragma unroll
+    for (int b = 0; b < SB_K; ++b) {
+        const int32_t k = b < K ? q.k[b] : 0;
+        const bool heavy = k >= HEAVY_MIN;
+        x[2 * b] = (k > 0 && !heavy) ? k : 0;
+        x[2 * b + 1] = (heavy ? 1 : 0) | (k > 0 ? 1 << 12 : 0);
+        m += min(k, W);
+        kg += k;
+    }
+    const int lold = (kg > 0 && q.cnt0 > 0) ? min(W, kg) : 0;
+    x[2 * SB_K] = m;
+    x[2 * SB_K + 1] = m + lold;
+}
+
+// U groups' counters and window counts: every load issued before any is
+// used (indexes clamped; groups at or past `end` count nothing).
+template <int U>
+__device__ __forceinline__ void sb_load_groups(const SbBufs &sb, const State &st,
+                                               const bool (&valid)[SB_K], int K, int h0,
+                                               int stride, int end, SbGroup (&q)[U]) {
+    static_assert(SB_K == 8, "two int4 loads per group");
+    int4 ka[U], kb[U];
+    int32_t cn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int h = min(h0 + u * stride, (int)st.G - 1);
+        const int4 *p = reinterpret_cast<const int4 *>(sb.kh + (int64_t)h * SB_K);
+        ka[u] = p[0];
+        kb[u] = p[1];
+        cn[u] = st.cnt[h];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        keep(ka[u]);
+        keep(kb[u]);
+        keep(cn[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const bool in = h0 + u * stride < end;
+        const int32_t v[SB_K] = {ka[u].x, ka[u].y, ka[u].z, ka[u].w,
+                                 kb[u].x, kb[u].y, kb[u].z, kb[u].w};
+#pragma unroll
+        for (int b = 0; b < SB_K; ++b) q[u].k[b] = (in && b < K && valid[b]) ? v[b] : 0;
+        q[u].cnt0 = in ? cn[u] : 0;
+    }
+}
+
+// Plan, first launch: each block's sums of the fields over its groups (one
+// per thread), and its two most frequent groups.
+__global__ __launch_bounds__(SBP_THREADS) void k_sb_sums(State st, Scratch base, SbBufs sb,
+                                                         SbBatches in, int32_t seq) {
+    constexpr int NW = SBP_THREADS / 64;
+    __shared__ int wsum[NW][SBP_F];
+    __shared__ unsigned long long red_top[2 * NW];
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+    const int K = in.K;
+    const int32_t W = st.W;
+    const int g = (int)blockIdx.x * SBP_THREADS + tid;
+    phase_mark(base, PHASE_HIST_PLAN, 3);
+    bool valid[SB_K];
+#pragma unroll
+    for (int b = 0; b < SB_K; ++b) valid[b] = b < K && sb.sbad[b] != seq;
+    SbGroup own[1];
+    sb_load_groups<1>(sb, st, valid, K, g, 0, (int)st.G, own);
+    int x[SBP_F];
+    int32_t kg;
+    sb_fields(own[0], K, W, x, kg);
+#pragma unroll
+    for (int f = 0; f < SBP_F; ++f) {
+        const int t = wave_total(wave_incl_add(x[f]));
+        if (lane == 0) wsum[wv][f] = t;
+    }
+    Top2 top;
+    if (kg > 0) top.add(((unsigned long long)(uint32_t)kg << 32) | (uint32_t)g);
+    top2_block(top, red_top, NW);  // (its barriers also order wsum)
+    if (tid < SBP_F) {
+        int t = 0;
+        for (int w = 0; w < NW; ++w) t += wsum[w][tid];
+        sb.part[(int64_t)blockIdx.x * SBP_PART + tid] = t;
+    }
+    if (tid == 0) {
+        reinterpret_cast<unsigned long long *>(sb.part + (int64_t)blockIdx.x * SBP_PART +
+                                               SBP_F)[0] = top.a;
+        reinterpret_cast<unsigned long long *>(sb.part + (int64_t)blockIdx.x * SBP_PART +
+                                               SBP_F)[1] = top.b;
+    }
+    phase_mark(base, PHASE_HIST_PLAN, 4);
+}
+
+// Plan, second launch: every batch's own balanced plan and the survivors'
+// places, one group per thread, from the blocks' sums (those of the blocks
+// before this one give its carries, all of them the totals).
+__global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base, SbBufs sb,
+                                                         SbBatches in, int32_t seq) {
+    constexpr int NW = SBP_THREADS / 64;
+    __shared__ int wown[NW][SBP_F];
+    __shared__ int wbase[NW][SBP_F];  // exclusive field values at each wave's first group
+    __shared__ int ftot[SBP_F];       // field totals over all groups
+    __shared__ int bpre[SBP_F];       // field sums of the blocks before this one
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+    const int K = in.K;
+    const int G = (int)st.G;
+    const int32_t W = st.W;
+    const int nblk = (int)gridDim.x;
+    const int gb = (int)blockIdx.x * SBP_THREADS, g = gb + tid;
+    phase_mark(base, PHASE_HIST_PLAN, 5);
+    bool valid[SB_K];
+#pragma unroll
+    for (int b = 0; b < SB_K; ++b) valid[b] = b < K && sb.sbad[b] != seq;
+    SbGroup own[1];
+    sb_load_groups<1>(sb, st, valid, K, g, 0, G, own);
+    if (tid < SBP_F) {  // thread f: field f summed over the blocks before and all blocks
+        int p = 0, t = 0;
+        for (int k = 0; k < nblk; ++k) {
+            const int v = sb.part[(int64_t)k * SBP_PART + tid];
+            p += k < (int)blockIdx.x ? v : 0;
+            t += v;
+        }
+        bpre[tid] = p;
+        ftot[tid] = t;
+    }
+    int wex[SBP_F];
+    int32_t own_work;
+    {
+        int x[SBP_F];
+        int32_t kg;
+        sb_fields(own[0], K, W, x, kg);
+#pragma unroll
+        for (int f = 0; f < SBP_F; ++f) {
+            const int incl = wave_incl_add(x[f]);
+            if (lane == 63) wown[wv][f] = incl;
+            wex[f] = incl - x[f];
+        }
+        own_work = x[2 * SB_K + 1];
+    }
+    __syncthreads();
+    if (tid < SBP_F) {  // thread f: field f's value at each wave's start
+        const int f = tid;
+        int run = bpre[f];
+        for (int w = 0; w < NW; ++w) {
+            wbase[w][f] = run;
+            run += wown[w][f];
+        }
+    }
+    __syncthreads();
+    auto ex = [&](int f) { return wbase[wv][f] + wex[f]; };
+    auto tot = [&](int f) { return ftot[f]; };
+    phase_mark(base, PHASE_HIST_PLAN, 6);
+    if (g < G) {
+        int m_before = 0;  // survivors of this group in the batches before b
+#pragma unroll
+        for (int b = 0; b < SB_K; ++b) {
+            if (b >= K || !valid[b]) continue;
+            const Scratch sc = sb_set(sb, base, b, G);
+            const int32_t k = own[0].k[b];
+            const int exl = ex(2 * b), exh = ex(2 * b + 1) & 0xfff, ext = ex(2 * b + 1) >> 12;
+            const int32_t nl = (tot(2 * b) + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
+            sc.lpre[g] = exl;
+            sb.so[(int64_t)b * G + g] = ex(2 * SB_K) + m_before;
+            if (k > 0) {
+                sc.tidx[g] = ext;
+                if (k >= HEAVY_MIN) {
+                    sc.bucket[g] = nl + exh;
+                    if ((uint32_t)exh < (uint32_t)NB_MAX) sc.hkey[exh] = g;
+                } else {
+                    sc.bucket[g] = (exl + k - 1) / LIGHT_BUDGET;
+                    const int32_t m = (exl + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
+                    if ((int64_t)m * LIGHT_BUDGET <= (int64_t)exl + k - 1 &&
+                        (uint32_t)m < (uint32_t)NB_MAX)
+                        sc.bstart[m] = g;
+                }
+                // the last batch's touched list serves cq_results after the call
+                if (b == K - 1) base.touched[ext] = g;
+            }
+            m_before += min(k, W);
+        }
+        sb.gsb[g] = ex(2 * SB_K);
+        // apply ranges: range r starts at the group whose work holds place
+        // r * APPLY_BUDGET
+        const int a0 = ex(2 * SB_K + 1), a1 = a0 + own_work;
+        for (int r = (a0 + APPLY_BUDGET - 1) / APPLY_BUDGET; r * APPLY_BUDGET < a1; ++r)
+            sb.astart[r] = g;
+    }
+    if (blockIdx.x == 0) {
+        // batch b's totals by thread b (an unrolled loop: the batches'
+        // arguments are indexed by constants)
+#pragma unroll
+        for (int b = 0; b < SB_K; ++b) {
+            if (tid != b || b >= K) continue;
+            const Scratch sc = sb_set(sb, base, b, G);
+            PlanTotals t;
+            const int32_t nl = (tot(2 * b) + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
+            t.n_light_buckets = valid[b] ? nl : 0;
+            t.n_heavy = valid[b] ? tot(2 * b + 1) & 0xfff : 0;
+            t.light_tuples = valid[b] ? tot(2 * b) : 0;
+            t.n_touched = valid[b] ? tot(2 * b + 1) >> 12 : 0;
+            t.status = valid[b] ? 0 : CQ_ERR_KEY_RANGE;
+            t.n_buckets = t.n_light_buckets + t.n_heavy;
+            t.tiles = (int32_t)((in.n[b] + PASS_TILE - 1) / PASS_TILE);
+            t.sub_touched = t.n_touched;
+            *sc.tot = t;
+            if (valid[b]) {
+                sc.lpre[G] = t.light_tuples;
+                sc.bstart[nl] = G;
+            }
+            if (in.out[b].n_touched) *in.out[b].n_touched = t.status ? t.status : t.n_touched;
+            if (b == K - 1) *base.tot = t;
+            if (t.n_buckets > NB_MAX) atomicOr(base.fault, FAULT_BUCKETS);
+        }
+        if (tid == SB_K) {
+            const int na = (tot(2 * SB_K + 1) + APPLY_BUDGET - 1) / APPLY_BUDGET;
+            sb.gsb[G] = tot(2 * SB_K);
+            sb.ntot[0] = na;
+            sb.ntot[1] = tot(2 * SB_K);
+            sb.astart[na] = G;
+        }
+        if (tid == SB_K + 1) {  // the call's two most frequent groups, for the next histogram
+            Top2 top;
+            for (int k = 0; k < nblk; ++k) {
+                const unsigned long long *p = reinterpret_cast<const unsigned long long *>(
+                    sb.part + (int64_t)k * SBP_PART + SBP_F);
+                top.add(p[0]);
+                top.add(p[1]);
+            }
+            base.hot[0] = top.a ? (int32_t)(uint32_t)top.a : -1;
+            base.hot[1] = top.b ? (int32_t)(uint32_t)top.b : -1;
+        }
+    }
+    phase_mark(base, PHASE_HIST_PLAN, 7);
+}
+
+// The reorder of every tile of every batch: one workgroup per CU works
+// through a contiguous run of tiles, two tiles ahead: while tile t is
+// reordered in LDS, the keys and values of tile t + 2 are on their way and
+// the buckets of tile t + 1 are being gathered, so each tile waits only on
+// its own LDS work.
+__global__ __launch_bounds__(PASS_THREADS) void k_sb_pass(State st, Scratch base, SbBufs sb,
+                                                          SbBatches in, int32_t seq) {
+    __shared__ __align__(16) char pool[P_BYTES];
+    __shared__ int32_t ts[NB_MAX + 1];
+    __shared__ int red[PASS_WAVES];
+    __shared__ __align__(16) uint16_t gbk[PASS_LOCAL_G];  // leader tables
+    constexpr int R = PASS_ROUNDS;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const int K = in.K;
+    const int64_t G = st.G;
+    const int T = in.ptile0[K];
+    const int per = (T + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int t_begin = (int)blockIdx.x * per, t_end = min(T, t_begin + per);
+    if (t_begin >= t_end) return;
+    // position of this thread's round r inside a tile
+    auto pos = [&](int r) { return wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane; };
+    auto load_kv = [&](int t, int32_t (&k)[R], int32_t (&v)[R]) {
+        const int b = sb_batch_of(in.ptile0, K, t);
+        const int64_t n = in.n[b];
+        const int64_t tb = (int64_t)(t - in.ptile0[b]) * PASS_TILE;
+        const int32_t *kp = in.keys[b], *vp = in.values[b];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t i = min(tb + pos(r), n - 1);
+            k[r] = kp[i];
+            v[r] = vp[i];
+        }
+    };
+    // tile t's group views and buckets: loads issued here and first used in
+    // the next iteration (positions past the batch are masked there), so
+    // that they stay in flight meanwhile
+    auto gather = [&](int t, int32_t (&k)[R], int32_t (&bk)[R]) {
+        const int b = sb_batch_of(in.ptile0, K, t);
+        const int32_t *bucket = sb.bucket + (int64_t)b * G;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            k[r] = view_key(k[r], base.kmod, G);
+            // (a rejected batch's keys may be out of range: clamped, unused)
+            const int32_t kc = (uint32_t)k[r] < (uint32_t)G ? k[r] : 0;
+            bk[r] = bucket[kc];
+        }
+    };
+    int32_t kA[R], vA[R], bA[R], kB[R], vB[R], bB[R], kC[R], vC[R], lr[R];
+    // Tile t's keys, values, buckets and plan totals are in registers when
+    // its iteration starts.  During it, tile t + 2's keys and values and tile
+    // t + 1's buckets and totals are loaded; they are waited for only after
+    // tile t's LDS work and before its stores, so that no wait at the top of
+    // an iteration has stores or younger loads in front of it.  (Past the
+    // run the last tile is loaded again and not used: every load stays
+    // unconditional.)
+    load_kv(t_begin, kA, vA);
+    load_kv(min(t_begin + 1, t_end - 1), kB, vB);
+    gather(t_begin, kA, bA);
+    PlanTotals tA = sb.tot[sb_batch_of(in.ptile0, K, t_begin)];
+    for (int t = t_begin; t < t_end; ++t) {
+        phase_mark(base, PHASE_PASS, 0);
+        const int tn = min(t + 1, t_end - 1);
+        load_kv(min(t + 2, t_end - 1), kC, vC);
+        gather(tn, kB, bB);
+        PlanTotals tB = sb.tot[sb_batch_of(in.ptile0, K, tn)];
+        const int b = sb_batch_of(in.ptile0, K, t);
+        const int64_t tb = (int64_t)(t - in.ptile0[b]) * PASS_TILE;
+        const int tile_n = (int)min((int64_t)PASS_TILE, in.n[b] - tb);
+        auto arrive = [&]() {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                keep(kC[r]);
+                keep(vC[r]);
+                keep(bB[r]);
+            }
+            keep(tB.status);
+            keep(tB.n_buckets);
+        };
+        const int32_t nA = tA.n_buckets;
+        if (!tA.status && nA <= LEAD) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                bA[r] = tb + pos(r) < in.n[b] ? bA[r] : nA;
+                lr[r] = 0;
+            }
+            const Scratch sc = sb_set(sb, base, b, G);
+            pass_split(kA, vA, bA, lr, nA, tb, tile_n, t - in.ptile0[b], sc, pool, ts, red, gbk,
+                       [] {}, arrive);
+        } else {
+            if (!tA.status && tid == 0) atomicOr(base.fault, FAULT_BUCKETS);  // (no plan makes
+            arrive();                                                          // this many)
+        }
+        __syncthreads();  // (the next tile reuses the LDS)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            kA[r] = kB[r];
+            vA[r] = vB[r];
+            bA[r] = bB[r];
+            kB[r] = kC[r];
+            vB[r] = vC[r];
+        }
+        tA = tB;
+    }
+}
+
+// Per (batch, bucket) item: the bucket's tuples are ranked inside their
+// groups as in the single-batch update (a heavy group's runs are already in
+// rank order), and each survivor's value goes to its place.  A heavy item
+// also leaves the sum of its survivors, which is the group's whole window
+// for that batch when the batch holds at least W of its tuples.
+__global__ __launch_bounds__(UPD_THREADS) void k_sb_prep(State st, Scratch base, SbBufs sb,
+                                                         SbBatches in) {
+    __shared__ __align__(16) char smem[U_BYTES];
+    __shared__ int red[UPD_THREADS / 64];
+    __shared__ long long red_ll[UPD_THREADS / 64];
+    __shared__ int items0[SB_K + 1];
+    __shared__ int32_t kso[LIGHT_SPAN];  // places of a light bucket's groups' survivors
+    const int tid = threadIdx.x;
+    const int K = in.K;
+    const int64_t G = st.G;
+    const int32_t W = st.W;
+    phase_mark(base, PHASE_SB_PREP, 0);
+    if (tid < SB_K) {  // every batch's item count, loaded together
+        const PlanTotals t = sb.tot[tid < K ? tid : 0];
+        items0[tid + 1] = (tid < K && !t.status) ? t.n_buckets : 0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        items0[0] = 0;
+        for (int b = 0; b < SB_K; ++b) items0[b + 1] += items0[b];
+    }
+    __syncthreads();
+    const int items = items0[K];
+    int32_t *rs = reinterpret_cast<int32_t *>(smem + U_RS);
+    int32_t *rp = reinterpret_cast<int32_t *>(smem + U_RP);
+    int32_t *klp = reinterpret_cast<int32_t *>(smem + U_KLP);
+    phase_mark(base, PHASE_SB_PREP, 1);
+    for (int it = (int)blockIdx.x; it < items; it += (int)gridDim.x) {
+        const bool first_item = it == (int)blockIdx.x;
+        const int b = sb_batch_of(items0, K, it);
+        const Scratch sc = sb_set(sb, base, b, G);
+        const int32_t *so = sb.so + (int64_t)b * G;
+        const PlanTotals t = *sc.tot;
+        const int kk = it - items0[b];
+        const int NB = t.n_buckets, nl = t.n_light_buckets;
+        const int tiles = (int)((in.n[b] + PASS_TILE - 1) / PASS_TILE);
+        const bool light = kk < nl;
+        int32_t a = 0, z = 0, g = 0;
+        if (light) {
+            a = sc.bstart[kk];
+            z = sc.bstart[kk + 1];
+        } else {
+            g = sc.hkey[kk - nl];
+        }
+        RunRows<UPD_THREADS> rr;
+        runs_load<UPD_THREADS>(sc, kk, NB, tiles, rr);
+        constexpr int KPT = LIGHT_SPAN / UPD_THREADS;
+        const int m = z - a;
+        const bool pre = light && m <= LIGHT_SPAN;
+        if (pre) {  // the groups' staged starts and survivors' places, for LDS
+            int32_t pl[KPT + 1], ps[KPT];
+#pragma unroll
+            for (int j = 0; j <= KPT; ++j) pl[j] = sc.lpre[a + min(tid + j * UPD_THREADS, m)];
+#pragma unroll
+            for (int j = 0; j < KPT; ++j)
+                ps[j] = so[a + max(0, min(tid + j * UPD_THREADS, m - 1))];
+#pragma unroll
+            for (int j = 0; j <= KPT; ++j) {
+                const int i = tid + j * UPD_THREADS;
+                if (i <= m) klp[i] = pl[j];
+                if (j < KPT && i < m) kso[i] = ps[j];
+            }
+        }
+        if (light)  // the light bucket's run table (LIGHT_CAP bytes) starts clear
+            for (int i = tid; i < LIGHT_CAP / 4; i += UPD_THREADS)
+                reinterpret_cast<uint32_t *>(smem + U_LR)[i] = 0;
+        const int size = runs_store<UPD_THREADS>(tiles, rr, rs, rp, red);
+        if (first_item) phase_mark(base, PHASE_SB_PREP, 2);
+        if (light) {
+            const bool ok = pre ? light_rank<true>(a, z, size, tiles, sc, smem)
+                                : light_rank<false>(a, z, size, tiles, sc, smem);
+            if (first_item) phase_mark(base, PHASE_SB_PREP, 3);
+            if (ok) {
+                const int32_t *ek = reinterpret_cast<const int32_t *>(smem + U_EK);
+                const int32_t *ev = reinterpret_cast<const int32_t *>(smem + U_EV);
+                const int16_t *pz = reinterpret_cast<const int16_t *>(smem + U_PZ);
+                constexpr int SPT = LIGHT_CAP / UPD_THREADS;
+                int32_t gq[SPT], k0[SPT], k1[SPT], dst[SPT];
+#pragma unroll
+                for (int j = 0; j < SPT; ++j) {
+                    const int p = tid + j * UPD_THREADS;
+                    gq[j] = p < size && pz[p] >= 0 ? ek[p] : -1;
+                    const int32_t gc = gq[j] >= 0 ? gq[j] : a;
+                    k0[j] = pre ? klp[gc - a] : sc.lpre[gc];
+                    k1[j] = pre ? klp[gc - a + 1] : sc.lpre[gc + 1];
+                    dst[j] = pre ? kso[gc - a] : so[gc];
+                }
+#pragma unroll
+                for (int j = 0; j < SPT; ++j) {
+                    if (gq[j] < 0) continue;
+                    const int p = tid + j * UPD_THREADS;
+                    const int32_t k = k1[j] - k0[j];
+                    const int32_t r = light_rank_of(smem, size, p);
+                    const int32_t first = k - min(k, W);  // rank of the first survivor
+                    if (r >= first) sb.xs[dst[j] + (r - first)] = ev[p];
+                }
+            }
+        } else if (size > 0) {
+            const int32_t first = size - min(size, W);
+            const int32_t base_x = so[g] - first;
+            constexpr int HU = 4;
+            long long acc = 0;
+            for (int p0 = first + tid; p0 < size; p0 += HU * UPD_THREADS) {
+                int32_t v[HU];
+#pragma unroll
+                for (int u = 0; u < HU; ++u) {
+                    const int p = min(p0 + u * UPD_THREADS, size - 1);
+                    const int r = upper_run(rp, tiles, p);
+                    v[u] = sc.sdat[rs[r] + (p - rp[r])].y;
+                }
+#pragma unroll
+                for (int u = 0; u < HU; ++u)
+                    if (p0 + u * UPD_THREADS < size) {
+                        sb.xs[base_x + p0 + u * UPD_THREADS] = v[u];
+                        acc += v[u];
+                    }
+            }
+            const long long tsum = block_sum_ll(acc, red_ll);
+            if (tid == 0) sb.tb[(int64_t)b * G + g] = tsum;
+        }
+        if (first_item) phase_mark(base, PHASE_SB_PREP, 4);
+        __syncthreads();
+    }
+    phase_mark(base, PHASE_SB_PREP, 5);
+}
+
+// Exclusive prefix over the block of one int64 per thread (APPLY_THREADS
+// threads); `total` gets the block's sum.  Barriers inside.
+__device__ __forceinline__ long long apply_excl_scan(long long v, long long *lds,
+                                                     long long &total) {
+    constexpr int NW = APPLY_THREADS / 64;
+    const int lane = lane_id(), wid = threadIdx.x >> 6;
+    long long x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long y = __shfl_up(x, o, 64);
+        x += lane >= o ? y : 0;
+    }
+    if (lane == 63) lds[wid] = x;
+    __syncthreads();
+    long long before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const long long t = lds[w];
+        before += w < wid ? t : 0;
+        all += t;
+    }
+    __syncthreads();
+    total = all;
+    return before + x - v;
+}
+
+// One group's facts for the apply step (every load issued before any is
+// used; a group past the range reads group 0's and counts nothing).
+struct ApplyGroup {
+    int32_t k[SB_K];
+    int32_t tix[SB_K];  // output position per batch (meaningful where k > 0)
+    int32_t pos0, cnt0;
+    int64_t sum0;
+    int32_t gs, m;      // first place and number of its survivors
+    int32_t kg, lold;   // tuples in the call; old window values read
+};
+
+template <int U>
+__device__ __forceinline__ void apply_load(const SbBufs &sb, const State &st,
+                                           const bool (&valid)[SB_K], int K, int g0,
+                                           int stride, int end, ApplyGroup (&q)[U]) {
+    int4 ka[U], kb[U];
+    int32_t tx[U][SB_K];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int g = g0 + u * stride < end ? g0 + u * stride : 0;
+        const int4 *p = reinterpret_cast<const int4 *>(sb.kh + (int64_t)g * SB_K);
+        ka[u] = p[0];
+        kb[u] = p[1];
+        q[u].pos0 = st.pos[g];
+        q[u].cnt0 = st.cnt[g];
+        q[u].sum0 = st.sum[g];
+        q[u].gs = sb.gsb[g];
+        q[u].m = sb.gsb[g + 1];
+#pragma unroll
+        for (int b = 0; b < SB_K; ++b) tx[u][b] = sb.tidx[(int64_t)(b < K ? b : 0) * st.G + g];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        keep(ka[u]);
+        keep(kb[u]);
+        keep(q[u].pos0);
+        keep(q[u].cnt0);
+        keep(q[u].sum0);
+        keep(q[u].gs);
+        keep(q[u].m);
+#pragma unroll
+        for (int b = 0; b < SB_K; ++b) keep(tx[u][b]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const bool in = g0 + u * stride < end;
+        const int32_t v[SB_K] = {ka[u].x, ka[u].y, ka[u].z, ka[u].w,
+                                 kb[u].x, kb[u].y, kb[u].z, kb[u].w};
+        q[u].kg = 0;
+#pragma unroll
+        for (int b = 0; b < SB_K; ++b) {
+            q[u].k[b] = (in && b < K && valid[b]) ? v[b] : 0;
+            q[u].tix[b] = tx[u][b];
+            q[u].kg += q[u].k[b];
+        }
+        q[u].m -= q[u].gs;
+        q[u].lold = (q[u].kg > 0 && q[u].cnt0 > 0) ? min(st.W, q[u].kg) : 0;
+        if (!in) q[u].kg = q[u].lold = q[u].m = 0;
+    }
+}
+
+// Old window value i (0 = oldest) of a group: slot (pos0 + i) mod W; the
+// slots a window that never filled has not reached yet hold 0 and are not
+// read.
+__device__ __forceinline__ int32_t apply_old(const State &st, int g, int32_t pos0, int32_t cnt0,
+                                             int32_t i) {
+    const int32_t W = st.W;
+    if (i < W - cnt0) return 0;
+    const uint32_t slot = ((uint32_t)pos0 + (uint32_t)i) % (uint32_t)W;
+    return st.ring[(int64_t)g * W + slot];
+}
+
+// Results of every batch of group g, its final state, and its counters
+// cleared.  newpart(b, e, win): the sum of its survivors at places
+// [e - win, e) (relative to its first); oldsum(b, c): its old window values
+// 0 .. c-1.
+template <typename FN, typename FO>
+__device__ __forceinline__ void apply_emit(const State &st, const SbBufs &sb,
+                                           const SbBatches &in, const ApplyGroup &q, int g,
+                                           FN &&newpart, FO &&oldsum) {
+    const int32_t W = st.W;
+    int32_t c = 0, e = 0;  // tuples so far; end of the survivors' places so far
+    int64_t s = q.sum0;
+#pragma unroll
+    for (int b = 0; b < SB_K; ++b) {
+        const int32_t k = q.k[b];
+        if (k <= 0) continue;
+        c += k;
+        e += min(k, W);
+        s = newpart(b, e, min(W, c)) + (c < W ? q.sum0 - oldsum(b, c) : 0);
+        const int32_t cnt = (int32_t)min((int64_t)W, (int64_t)q.cnt0 + c);
+        emit_one(in.out[b], q.tix[b], g, s, cnt);
+    }
+    st.sum[g] = s;
+    st.pos[g] = (int32_t)(((uint32_t)q.pos0 + (uint32_t)q.kg) % (uint32_t)W);
+    st.cnt[g] = (int32_t)min((int64_t)W, (int64_t)q.cnt0 + q.kg);
+    // the group's counters, rejected batches' included, start the next call clear
+    int4 *kp = reinterpret_cast<int4 *>(sb.kh + (int64_t)g * SB_K);
+    kp[0] = make_int4(0, 0, 0, 0);
+    kp[1] = make_int4(0, 0, 0, 0);
+}
+
+// LDS of an apply workgroup (bytes).
+constexpr int A_P = 0;                                     // i64[APPLY_CAP + 1] prefix sums
+constexpr int A_OWN = A_P + 8 * (APPLY_CAP + 8);           // u16[APPLY_CAP] group of each element
+constexpr int A_GX = A_OWN + 2 * APPLY_CAP;                // i32[APPLY_FLAT_G + 1] survivor starts
+constexpr int A_GO = A_GX + 4 * (APPLY_FLAT_G + 4);        // i32[APPLY_FLAT_G + 1] old-value starts
+constexpr int A_GP = A_GO + 4 * (APPLY_FLAT_G + 4);        // i32[APPLY_FLAT_G] pos0
+constexpr int A_GC = A_GP + 4 * APPLY_FLAT_G;              // i32[APPLY_FLAT_G] cnt0
+constexpr int A_GK = A_GC + 4 * APPLY_FLAT_G;              // i32[APPLY_FLAT_G] tuples in the call
+constexpr int A_BYTES = A_GK + 4 * APPLY_FLAT_G;
+static_assert(2 * APPLY_FLAT_G < 65536, "element owners fit 16 bits");
+
+// Groups [c0, c1) (at most APPLY_FLAT_G; survivors plus old values read at
+// most APPLY_CAP): every survivor and old value in one prefix sum.  Groups
+// go to threads strided (group i to thread i mod APPLY_THREADS), so that a
+// wave's loads and stores of per-group data and results are consecutive;
+// elements go to threads in consecutive runs of APPLY_EPT for the scans and
+// strided for the ring writes.  Each element's group comes from a running
+// maximum over marks at the groups' first elements (survivors: group index;
+// old values: ng + group index, so that the maximum keeps growing across
+// the two regions).
+__device__ void apply_flat(const State &st, const SbBufs &sb, const SbBatches &in,
+                           const bool (&valid)[SB_K], int c0, int c1, char *smem,
+                           long long *red, const Scratch &base, bool mark) {
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
+    const int32_t W = st.W;
+    long long *P = reinterpret_cast<long long *>(smem + A_P);
+    uint16_t *own = reinterpret_cast<uint16_t *>(smem + A_OWN);
+    int32_t *gx = reinterpret_cast<int32_t *>(smem + A_GX);
+    int32_t *go = reinterpret_cast<int32_t *>(smem + A_GO);
+    int32_t *gp = reinterpret_cast<int32_t *>(smem + A_GP);
+    int32_t *gc = reinterpret_cast<int32_t *>(smem + A_GC);
+    int32_t *gk = reinterpret_cast<int32_t *>(smem + A_GK);
+    const int ng = c1 - c0;
+    // this thread's groups: c0 + tid + APPLY_THREADS * j
+    ApplyGroup q[APPLY_GPT];
+    apply_load<APPLY_GPT>(sb, st, valid, in.K, c0 + tid, APPLY_THREADS, c1, q);
+    const int32_t x0 = sb.gsb[c0], x1 = sb.gsb[c1];
+    if (mark) phase_mark(base, PHASE_SB_APPLY, 2);
+    // old-value offsets: group i = tid + APPLY_THREADS * j comes after every
+    // group of the rows before j and the threads before tid in row j
+    int lo[APPLY_GPT], lt[APPLY_GPT];
+#pragma unroll
+    for (int j = 0; j < APPLY_GPT; ++j) lo[j] = q[j].lold;
+    block_excl_scan<APPLY_GPT>(lo, lt, reinterpret_cast<int *>(red));
+    int ox = 0;
+#pragma unroll
+    for (int j = 0; j < APPLY_GPT; ++j) {
+        lo[j] += ox;
+        ox += lt[j];
+    }
+    const int mx = x1 - x0;
+    if (mx + ox > APPLY_CAP) {  // impossible for a well-formed plan
+        if (tid == 0) atomicOr(sb.fault, FAULT_APPLY);
+        return;
+    }
+    for (int e = tid; e < mx + ox; e += APPLY_THREADS) own[e] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < APPLY_GPT; ++j) {
+        const int i = tid + APPLY_THREADS * j;
+        if (i < ng) {
+            gx[i] = q[j].gs - x0;
+            go[i] = lo[j];
+            gp[i] = q[j].pos0;
+            gc[i] = q[j].cnt0;
+            gk[i] = q[j].kg;
+            if (q[j].m > 0) own[q[j].gs - x0] = (uint16_t)i;
+            if (q[j].lold > 0) own[mx + lo[j]] = (uint16_t)(ng + i);
+        }
+    }
+    if (tid == 0) {
+        gx[ng] = mx;
+        go[ng] = ox;
+    }
+    __syncthreads();
+    // every element's group (running maximum), APPLY_EPT consecutive
+    // elements per thread, written back for the strided ring writes
+    int ow[APPLY_EPT], mloc = 0;
+#pragma unroll
+    for (int i = 0; i < APPLY_EPT; ++i) {
+        const int e = APPLY_EPT * tid + i;
+        mloc = max(mloc, e < mx + ox ? (int)own[e] : 0);
+        ow[i] = mloc;
+    }
+    {
+        const int incl = wave_incl_max(mloc);
+        int *wm = reinterpret_cast<int *>(red);
+        if (lane == 63) wm[wid] = incl;
+        __syncthreads();
+        int before = __shfl_up(incl, 1, 64);
+        if (lane == 0) before = 0;
+        for (int w = 0; w < wid; ++w) before = max(before, wm[w]);
+#pragma unroll
+        for (int i = 0; i < APPLY_EPT; ++i) {
+            ow[i] = max(ow[i], before);
+            const int e = APPLY_EPT * tid + i;
+            if (e < mx) own[e] = (uint16_t)ow[i];
+        }
+        __syncthreads();
+    }
+    // survivors [0, mx) then old values [mx, mx + ox), all loaded before any
+    // is used
+    int32_t v[APPLY_EPT];
+#pragma unroll
+    for (int i = 0; i < APPLY_EPT; ++i) {
+        const int e = APPLY_EPT * tid + i;
+        v[i] = 0;
+        if (e < mx) {
+            v[i] = sb.xs[x0 + e];
+        } else if (e < mx + ox) {
+            const int j = ow[i] - ng;
+            v[i] = apply_old(st, c0 + j, gp[j], gc[j], e - mx - go[j]);
+        }
+    }
+    if (mark) phase_mark(base, PHASE_SB_APPLY, 3);
+    long long loc = 0;
+#pragma unroll
+    for (int i = 0; i < APPLY_EPT; ++i) loc += v[i];
+    long long tot;
+    long long run = apply_excl_scan(loc, red, tot);
+    if (mark) phase_mark(base, PHASE_SB_APPLY, 4);
+#pragma unroll
+    for (int i = 0; i < APPLY_EPT; ++i) {
+        const int e = APPLY_EPT * tid + i;
+        if (e < mx + ox) P[e] = run;
+        run += v[i];
+    }
+    if (tid == 0) P[mx + ox] = tot;
+    __syncthreads();  // (every old value has been read: the ring may change now)
+    // the final window, the last min(W, kg) survivors, into the ring;
+    // consecutive elements by consecutive lanes
+    for (int e = tid; e < mx; e += APPLY_THREADS) {
+        const int j = own[e];
+        const int32_t m = gx[j + 1] - gx[j], kg = gk[j], r = e - gx[j];
+        if (r >= m - min(W, kg)) {
+            const int32_t rank = kg - (m - r);
+            const uint32_t slot = ((uint32_t)gp[j] + (uint32_t)rank) % (uint32_t)W;
+            st.ring[(int64_t)(c0 + j) * W + slot] = (int32_t)(P[e + 1] - P[e]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < APPLY_GPT; ++j) {
+        const int i = tid + APPLY_THREADS * j;
+        if (i >= ng || q[j].kg == 0) continue;
+        const int xs0 = gx[i], os0 = mx + go[i];
+        apply_emit(st, sb, in, q[j], c0 + i,
+                   [&](int, int32_t e, int32_t win) { return P[xs0 + e] - P[xs0 + e - win]; },
+                   [&](int, int32_t c) { return q[j].lold ? P[os0 + c] - P[os0] : 0LL; });
+    }
+    __syncthreads();
+}
+
+// Group g alone (more survivors plus old values than one range holds).
+// Batch b's window sum: the survivors at places [lo_b, hi_b) plus, while
+// fewer than W tuples have arrived in the call, the window before the call
+// less its first c_b values.  A batch holding at least max(W, HEAVY_MIN) of
+// its tuples was a heavy item whose survivors' sum the prep step left; the
+// others are summed here, each thread adding what it reads to every batch
+// whose range holds it.
+__device__ void apply_big(const State &st, const SbBufs &sb, const SbBatches &in,
+                          const bool (&valid)[SB_K], int g, long long *red) {
+    constexpr int NW = APPLY_THREADS / 64;
+    const int tid = threadIdx.x;
+    const int32_t W = st.W;
+    ApplyGroup qq[1];
+    apply_load<1>(sb, st, valid, in.K, g, 0, g + 1, qq);
+    const ApplyGroup &q = qq[0];
+    int32_t lo[SB_K], hi[SB_K], cb[SB_K];
+    bool whole[SB_K];  // the batch's own survivors are the window: its sum is known
+    bool need_x = false, need_o = false;
+    int64_t tb[SB_K];
+    {
+        int32_t c = 0, e = 0;
+#pragma unroll
+        for (int b = 0; b < SB_K; ++b) {
+            const int32_t k = q.k[b];
+            c += k;
+            e += min(k, W);
+            hi[b] = e;
+            lo[b] = e - min(W, c);
+            cb[b] = (k > 0 && c < W && q.lold) ? c : 0;
+            whole[b] = k >= W && k >= HEAVY_MIN;
+            need_x |= k > 0 && !whole[b];
+            need_o |= cb[b] > 0;
+            tb[b] = sb.tb[(int64_t)(b < in.K ? b : 0) * st.G + g];
+        }
+    }
+    long long an[SB_K], ao[SB_K];
+#pragma unroll
+    for (int b = 0; b < SB_K; ++b) an[b] = ao[b] = 0;
+    constexpr int U = 8;
+    if (need_o) {
+        for (int i0 = tid; i0 < q.lold; i0 += U * APPLY_THREADS) {
+            int32_t v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                v[u] = apply_old(st, g, q.pos0, q.cnt0, min(i0 + u * APPLY_THREADS, q.lold - 1));
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * APPLY_THREADS;
+#pragma unroll
+                for (int b = 0; b < SB_K; ++b) ao[b] += (i < q.lold && i < cb[b]) ? v[u] : 0;
+            }
+        }
+    }
+    __syncthreads();  // (every old value has been read: the ring may change now)
+    // the survivors: summed where a batch needs them, and the final window,
+    // the last min(W, kg), written to the ring as they are read
+    const int32_t keep_from = q.m - min(W, q.kg);
+    const int32_t x_from = need_x ? 0 : keep_from;
+    for (int e0 = x_from + tid; e0 < q.m; e0 += U * APPLY_THREADS) {
+        int32_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = sb.xs[q.gs + min(e0 + u * APPLY_THREADS, q.m - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * APPLY_THREADS;
+            if (e >= q.m) break;
+            if (need_x) {
+#pragma unroll
+                for (int b = 0; b < SB_K; ++b)
+                    an[b] += (!whole[b] && e >= lo[b] && e < hi[b]) ? v[u] : 0;
+            }
+            if (e >= keep_from) {
+                const int32_t rank = q.kg - (q.m - e);
+                const uint32_t slot = ((uint32_t)q.pos0 + (uint32_t)rank) % (uint32_t)W;
+                st.ring[(int64_t)g * W + slot] = v[u];
+            }
+        }
+    }
+    // block sums of the 2 * SB_K partial sums
+    const int lane = lane_id(), wid = tid >> 6;
+#pragma unroll
+    for (int b = 0; b < SB_K; ++b) {
+        const long long sn = wave_sum_ll(an[b]), so = wave_sum_ll(ao[b]);
+        if (lane == 0) {
+            red[(2 * b) * NW + wid] = sn;
+            red[(2 * b + 1) * NW + wid] = so;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        long long tn[SB_K], to[SB_K];
+#pragma unroll
+        for (int b = 0; b < SB_K; ++b) {
+            tn[b] = to[b] = 0;
+            for (int w = 0; w < NW; ++w) {
+                tn[b] += red[(2 * b) * NW + w];
+                to[b] += red[(2 * b + 1) * NW + w];
+            }
+            if (whole[b]) tn[b] = tb[b];
+        }
+        apply_emit(st, sb, in, q, g, [&](int b, int32_t, int32_t) { return tn[b]; },
+                   [&](int b, int32_t) { return to[b]; });
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(APPLY_THREADS) void k_sb_apply(State st, Scratch base, SbBufs sb,
+                                                            SbBatches in, int32_t seq) {
+    __shared__ __align__(16) char smem[A_BYTES];
+    __shared__ long long red[2 * SB_K * (APPLY_THREADS / 64)];
+    const int K = in.K;
+    const int G = (int)st.G;
+    bool valid[SB_K];
+#pragma unroll
+    for (int b = 0; b < SB_K; ++b) valid[b] = b < K && sb.sbad[b] != seq;
+    // a rejected batch's counters of groups no other batch touched are
+    // cleared here (those of touched groups are cleared with the group)
+    if ((int)blockIdx.x < K && !valid[blockIdx.x])
+        for (int g = threadIdx.x; g < G; g += APPLY_THREADS)
+            sb.kh[(int64_t)g * SB_K + blockIdx.x] = 0;
+    const int na = sb.ntot[0];
+    phase_mark(base, PHASE_SB_APPLY, 0);
+    // two items per range: its first group alone when that group is over the
+    // budget, and the rest (so that a big group and the small ones after it
+    // run in different workgroups)
+    for (int it = (int)blockIdx.x; it < 2 * na; it += (int)gridDim.x) {
+        const bool mark = it == (int)blockIdx.x;
+        const int r = it >> 1;
+        const bool big_item = (it & 1) == 0;
+        const int a = sb.astart[r], z = sb.astart[r + 1];
+        if (a >= z) continue;
+        // only the first group of a range can be over the budget alone
+        const int32_t m = sb.gsb[a + 1] - sb.gsb[a];
+        int32_t kg = 0;
+        {
+            int32_t v[SB_K];
+            const int4 *p = reinterpret_cast<const int4 *>(sb.kh + (int64_t)a * SB_K);
+            const int4 x = p[0], y = p[1];
+            v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+            v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+#pragma unroll
+            for (int b = 0; b < SB_K; ++b) kg += valid[b] ? v[b] : 0;
+        }
+        const int32_t lold = (kg > 0 && st.cnt[a] > 0) ? min(st.W, kg) : 0;
+        const bool big = m + lold > APPLY_BUDGET;
+        if (mark) phase_mark(base, PHASE_SB_APPLY, 1);
+        if (big_item) {
+            if (big) apply_big(st, sb, in, valid, a, red);
+            if (mark) phase_mark(base, PHASE_SB_APPLY, 6);
+            continue;
+        }
+        for (int c0 = big ? a + 1 : a; c0 < z; c0 += APPLY_FLAT_G)
+            apply_flat(st, sb, in, valid, c0, min(z, c0 + APPLY_FLAT_G), smem, red, base,
+                       mark && c0 == (big ? a + 1 : a));
+        if (mark) phase_mark(base, PHASE_SB_APPLY, 5);
+    }
+    phase_mark(base, PHASE_SB_APPLY, 7);
+}
+
 // ------------------------------------------------------------ launchers --
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
@@ -1914,6 +2978,64 @@ hipError_t launch_set_seq(Scratch sc, int32_t v, hipStream_t s) {
 
 hipError_t launch_reset_totals(Scratch sc, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_totals, dim3(1), dim3(1), 0, s, sc);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------- several batches --
+
+hipError_t launch_sb_hist(State st, Scratch base, SbBufs sb, const SbBatches &in, int32_t seq,
+                          hipStream_t s) {
+    const int grid = in.htile0[in.K];
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sb_hist, dim3((unsigned)grid), dim3(HIST_THREADS), (size_t)st.G * 4, s,
+                       base, sb, in, (int32_t)st.G, seq);
+    return hipGetLastError();
+}
+
+hipError_t launch_sb_plan(State st, Scratch base, SbBufs sb, const SbBatches &in, int32_t seq,
+                          hipStream_t s) {
+    const int64_t grid = (st.G + SBP_THREADS - 1) / SBP_THREADS;
+    hipLaunchKernelGGL(k_sb_sums, dim3((unsigned)grid), dim3(SBP_THREADS), 0, s, st, base, sb,
+                       in, seq);
+    hipLaunchKernelGGL(k_sb_plan, dim3((unsigned)grid), dim3(SBP_THREADS), 0, s, st, base, sb,
+                       in, seq);
+    return hipGetLastError();
+}
+
+hipError_t launch_sb_pass(State st, Scratch base, SbBufs sb, const SbBatches &in, int32_t seq,
+                          hipStream_t s) {
+    const int tiles = in.ptile0[in.K];
+    if (tiles <= 0) return hipSuccess;
+    // one workgroup per CU (the reorder's LDS), each over a run of tiles
+    const int grid = std::min(tiles, SB_PASS_GRID);
+    hipLaunchKernelGGL(k_sb_pass, dim3((unsigned)grid), dim3(PASS_THREADS), 0, s, st, base, sb,
+                       in, seq);
+    return hipGetLastError();
+}
+
+hipError_t launch_sb_prep(State st, Scratch base, SbBufs sb, const SbBatches &in,
+                          hipStream_t s) {
+    // workgroups loop over the items (at most one per bucket of each batch,
+    // known on the device only): a workgroup that finds none still costs its
+    // dispatch, so the grid is what the device holds at once, not the bound
+    int64_t items = 0;
+    for (int b = 0; b < in.K; ++b)
+        items += in.n[b] ? (in.n[b] + LIGHT_BUDGET - 1) / LIGHT_BUDGET + in.n[b] / HEAVY_MIN + 1
+                         : 0;
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(items, SB_PREP_GRID));
+    hipLaunchKernelGGL(k_sb_prep, dim3((unsigned)grid), dim3(UPD_THREADS), 0, s, st, base, sb,
+                       in);
+    return hipGetLastError();
+}
+
+hipError_t launch_sb_apply(State st, Scratch base, SbBufs sb, const SbBatches &in, int32_t seq,
+                           hipStream_t s) {
+    int64_t tuples = 0;
+    for (int b = 0; b < in.K; ++b) tuples += in.n[b];
+    const int64_t ranges = (2 * tuples + APPLY_BUDGET - 1) / APPLY_BUDGET + 1;
+    const int64_t grid = std::max<int64_t>(in.K, std::min<int64_t>(ranges, SB_APPLY_GRID));
+    hipLaunchKernelGGL(k_sb_apply, dim3((unsigned)grid), dim3(APPLY_THREADS), 0, s, st, base,
+                       sb, in, seq);
     return hipGetLastError();
 }
 

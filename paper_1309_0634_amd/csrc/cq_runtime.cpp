@@ -62,6 +62,9 @@ struct cq_query {
     // the last push was cq_push_batch_results_noalloc: its plan lives in the
     // shared scratch area, so cq_results / cq_status / cq_batch_plan refuse
     bool noalloc_last = false;
+    // several batches per set of launches (allocated by the first such call)
+    SbBufs sb{};
+    bool have_sb = false;
 };
 
 namespace {
@@ -152,6 +155,51 @@ int alloc_set(Scratch &b, int64_t G) {
     return from_hip(e);
 }
 
+// Buffers of the several-batch path.
+void free_sb(SbBufs &b) {
+    dfree(b.kh);
+    dfree(b.sbad);
+    dfree(b.bucket);
+    dfree(b.lpre);
+    dfree(b.tidx);
+    dfree(b.bstart);
+    dfree(b.hkey);
+    dfree(b.sdat);
+    dfree(b.rowstart);
+    dfree(b.tot);
+    dfree(b.so);
+    dfree(b.gsb);
+    dfree(b.astart);
+    dfree(b.xs);
+    dfree(b.ntot);
+    dfree(b.tb);
+    dfree(b.part);
+}
+
+int alloc_sb(SbBufs &b, int64_t G) {
+    int rc = dalloc(&b.kh, G * SB_K);
+    if (rc == CQ_OK) rc = dalloc(&b.sbad, SB_K);
+    if (rc == CQ_OK) rc = dalloc(&b.bucket, SB_K * G);
+    if (rc == CQ_OK) rc = dalloc(&b.lpre, SB_K * (G + 1));
+    if (rc == CQ_OK) rc = dalloc(&b.tidx, SB_K * G);
+    if (rc == CQ_OK) rc = dalloc(&b.bstart, SB_K * (int64_t)(NB_MAX + 1));
+    if (rc == CQ_OK) rc = dalloc(&b.hkey, SB_K * (int64_t)NB_MAX);
+    if (rc == CQ_OK) rc = dalloc(&b.sdat, SB_K * (int64_t)SUB);
+    if (rc == CQ_OK) rc = dalloc(&b.rowstart, SB_K * (int64_t)PASS_TILES_MAX * (NB_MAX + 1));
+    if (rc == CQ_OK) rc = dalloc(&b.tot, SB_K);
+    if (rc == CQ_OK) rc = dalloc(&b.so, SB_K * G);
+    if (rc == CQ_OK) rc = dalloc(&b.gsb, G + 1);
+    if (rc == CQ_OK) rc = dalloc(&b.astart, sb_apply_max() + 1);
+    if (rc == CQ_OK) rc = dalloc(&b.xs, SB_K * (int64_t)SUB);
+    if (rc == CQ_OK) rc = dalloc(&b.ntot, 2);
+    if (rc == CQ_OK) rc = dalloc(&b.tb, SB_K * G);
+    if (rc == CQ_OK) rc = dalloc(&b.part, (G + SBP_THREADS - 1) / SBP_THREADS * SBP_PART);
+    if (rc != CQ_OK) return rc;
+    hipError_t e = hipMemset(b.kh, 0, sizeof(int32_t) * (size_t)(G * SB_K));
+    if (e == hipSuccess) e = hipMemset(b.sbad, 0, sizeof(int32_t) * SB_K);
+    return from_hip(e);
+}
+
 void free_all(cq_query *q) {
     dfree(q->st.ring);
     dfree(q->st.pos);
@@ -184,6 +232,8 @@ void free_all(cq_query *q) {
     q->ev_counts = q->ev_map = nullptr;
     dfree(q->pt_sidx);
     dfree(q->pt_pcnt);
+    free_sb(q->sb);
+    q->have_sb = false;
 }
 
 int ensure_trace(cq_query *q, int64_t records) {
@@ -468,6 +518,82 @@ int ensure_alt(cq_query *q) {
     return CQ_OK;
 }
 
+// Whether cq_push_batches takes the several-batch path: up to PASS_LOCAL_G
+// groups, the balanced partition, no technique, no capture, no per-workgroup
+// records (kernel times and phase clocks are recorded).
+bool sb_eligible(const cq_query *q) {
+    return q->st.G <= PASS_LOCAL_G && q->mode == MODE_BALANCED && !q->policy && !q->graph &&
+           !(q->telemetry & CQ_TELEMETRY_WORKERS);
+}
+
+int ensure_sb(cq_query *q) {
+    if (q->have_sb) return CQ_OK;
+    int rc = alloc_sb(q->sb, q->st.G);
+    if (rc == CQ_OK) rc = from_hip(hipDeviceSynchronize());
+    if (rc != CQ_OK) {
+        free_sb(q->sb);
+        return rc;
+    }
+    q->have_sb = true;
+    return CQ_OK;
+}
+
+// cq_push_batches in groups of up to SB_K batches, five launches each.
+int push_sb(cq_query *q, int32_t count, const int32_t *const *keys,
+            const int32_t *const *values, const int64_t *n, int32_t *const *ids,
+            int64_t *const *sums, int32_t *const *counts, double *const *avgs,
+            int64_t *const *n_touched, hipStream_t s) {
+    int rc = ensure_sb(q);
+    if (rc == CQ_OK) rc = prepare_telemetry(q, SUB);
+    if (rc != CQ_OK) return rc;
+    const Scratch base = set_of(q, 0);
+    q->sb.fault = q->sc.fault;
+    for (int32_t c0 = 0; c0 < count && rc == CQ_OK; c0 += SB_K) {
+        SbBatches in{};
+        in.K = std::min<int32_t>(SB_K, count - c0);
+        int32_t ht = 0, pt = 0;
+        for (int b = 0; b < in.K; ++b) {
+            const int32_t i = c0 + b;
+            in.keys[b] = keys[i];
+            in.values[b] = values[i];
+            in.n[b] = n[i];
+            in.htile0[b] = ht;
+            in.ptile0[b] = pt;
+            ht += (int32_t)((n[i] + SBH_TILE - 1) / SBH_TILE);
+            pt += (int32_t)((n[i] + PASS_TILE - 1) / PASS_TILE);
+            if (((uintptr_t)keys[i] & 15u) == 0) in.vec |= 1u << b;
+            in.out[b] = {ids ? ids[i] : nullptr, sums ? sums[i] : nullptr,
+                         counts ? counts[i] : nullptr, avgs ? avgs[i] : nullptr, n_touched[i]};
+        }
+        in.htile0[in.K] = ht;
+        in.ptile0[in.K] = pt;
+        const int32_t seq = ++q->seq;
+        rc = timed(q, CQ_KERNEL_HIST, s, [&] { return launch_sb_hist(q->st, base, q->sb, in, seq, s); });
+        if (rc == CQ_OK)
+            rc = timed(q, CQ_KERNEL_PLAN, s,
+                       [&] { return launch_sb_plan(q->st, base, q->sb, in, seq, s); });
+        if (rc == CQ_OK)
+            rc = timed(q, CQ_KERNEL_PASS, s,
+                       [&] { return launch_sb_pass(q->st, base, q->sb, in, seq, s); });
+        if (rc == CQ_OK)
+            rc = timed(q, CQ_KERNEL_PREP, s,
+                       [&] { return launch_sb_prep(q->st, base, q->sb, in, s); });
+        if (rc == CQ_OK)
+            rc = timed(q, CQ_KERNEL_APPLY, s,
+                       [&] { return launch_sb_apply(q->st, base, q->sb, in, seq, s); });
+    }
+    // cq_results, cq_status and cq_batch_plan read the last batch's plan,
+    // which the several-batch plan also leaves in buffer set 0
+    q->cur = 0;
+    q->last_n = n[count - 1];
+    q->last_stream = s;
+    q->pushed = true;
+    q->noalloc_last = false;
+    q->last_mode = q->mode;
+    q->last_workers = q->workers;
+    return rc;
+}
+
 }  // namespace
 
 namespace cq {
@@ -733,6 +859,9 @@ int cq_push_batches(cq_query *q, int32_t count, const int32_t *const *keys,
     }
     if (q->mode == MODE_STATIC && !static_ok(q->st.G, q->workers)) return CQ_ERR_INVALID;
     DeviceGuard guard(q->device);
+    if (sb_eligible(q))
+        return push_sb(q, count, keys, values, n, ids, sums, counts, avgs, n_touched,
+                       reinterpret_cast<hipStream_t>(stream));
     int rc = ensure_alt(q);
     if (rc == CQ_OK) rc = prepare_telemetry(q, SUB);
     if (rc != CQ_OK) return rc;

@@ -108,11 +108,6 @@ __device__ void bitonic_sort(int32_t *a, int m) {
     }
 }
 
-// Marks a loaded value as used here, so that the compiler keeps its load
-// where it was issued (beside the others) rather than sinking it into the
-// branch that uses it, where it would wait alone.
-__device__ __forceinline__ void keep(int32_t &x) { __asm__ volatile("" : "+v"(x)); }
-
 // Slot x of group g's eviction order (the slot insertion x overwrites).
 __device__ __forceinline__ int32_t old_slot(const int32_t *row, int32_t po, int x, int32_t W) {
     return row[((uint32_t)po + (uint32_t)x) % (uint32_t)W];
