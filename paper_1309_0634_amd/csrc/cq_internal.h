@@ -180,22 +180,16 @@ constexpr int SBH_TILE = HIST_THREADS * SBH_KPT;
 constexpr int SBP_THREADS = 1024;
 constexpr int SBP_F = 2 * SB_K + 2;
 constexpr int SBP_PART = SBP_F + 4;
-// apply work per bucket: survivors plus old window values, at most
-// APPLY_CAP per range of small groups; a group over APPLY_BUDGET is handled
-// alone
+// apply: a group whose survivors plus old window values read exceed
+// APPLY_BUDGET is summed by a whole workgroup, every other one by one wave
 constexpr int APPLY_BUDGET = 2048;
-constexpr int APPLY_CAP = 2 * APPLY_BUDGET;
 constexpr int APPLY_THREADS = 256;
-constexpr int APPLY_GPT = 4;                                // groups per thread in a flat range
-constexpr int APPLY_FLAT_G = APPLY_THREADS * APPLY_GPT;     // groups per flat range
-constexpr int APPLY_EPT = APPLY_CAP / APPLY_THREADS;        // elements per thread
-static_assert(APPLY_CAP % APPLY_THREADS == 0, "whole elements per thread");
 // Workgroups of the survivor and apply launches, which loop over their
 // items: as many as the device runs at once (256 CUs; four and two per CU
 // fit their registers and LDS).
 constexpr int SB_PREP_GRID = 1024;
 constexpr int SB_PASS_GRID = 256;
-constexpr int SB_APPLY_GRID = 512;
+constexpr int SB_APPLY_GRID = 1024;
 
 // Buffers of the several-batch path, one slice per batch where marked.
 struct SbBufs {
@@ -212,9 +206,10 @@ struct SbBufs {
     PlanTotals *tot;    // [SB_K]
     int32_t *so;        // [SB_K][G] first place of batch b's survivors of group g
     int32_t *gsb;       // [G + 1] first place of group g's survivors
-    int32_t *astart;    // [sb_apply_max() + 1] first group of each apply range
+    int32_t *big;       // [G] the groups over APPLY_BUDGET, in group order
+    int32_t *gbig;      // [G] 1 for those groups, else 0
     int32_t *xs;        // [SB_K * SUB] survivors' values, by group, batch, arrival
-    int32_t *ntot;      // [2] apply ranges, survivors
+    int32_t *ntot;      // [2] groups over APPLY_BUDGET, survivors
     int64_t *tb;        // [SB_K][G] sum of a heavy item's survivors (batch, group)
     int32_t *part;      // [plan blocks][SBP_PART] plan fields summed per block, top two groups
     int32_t *fault;     // the query's fault bits
@@ -252,9 +247,6 @@ __host__ __device__ inline Scratch sb_set(const SbBufs &sb, const Scratch &base,
     s.trace = nullptr;
     return s;
 }
-// Apply ranges of one call at most (survivors plus old values, at most two
-// per tuple, in ranges of APPLY_BUDGET).
-inline int64_t sb_apply_max() { return (int64_t)SB_K * SUB * 2 / APPLY_BUDGET + 2; }
 // The five launches of `in.K` batches (seq: the call's sequence number).
 hipError_t launch_sb_hist(State st, Scratch base, SbBufs sb, const SbBatches &in, int32_t seq,
                           hipStream_t s);

@@ -1880,15 +1880,16 @@ __global__ void k_reset_totals(Scratch sc) {
 //   k_sb_pass   every tile of every batch reordered by its batch's plan.
 //   k_sb_prep   per (batch, bucket): each tuple's rank inside its group,
 //               survivors written to their places.
-//   k_sb_apply  per range of groups: with C the group's tuples in batches
-//               0..b of the call and S = its window before the call (W
-//               values, oldest first; never-written slots hold 0) followed
-//               by its new tuples in arrival order, batch b's window is
-//               S[C, C + W): its new part is the last min(W, C) survivors
-//               up to the end of batch b's, consecutive places; its old
-//               part (C < W) is the window sum before the call minus
-//               S[0, C).  Both are differences of prefix sums.  The final
-//               window goes to the ring (Section 3.2: slot nextPos).
+//   k_sb_apply  per group (one wave each; a workgroup for a group with
+//               more than APPLY_BUDGET values to read): with C the group's
+//               tuples in batches 0..b of the call and S = its window
+//               before the call (W values, oldest first; never-written
+//               slots hold 0) followed by its new tuples in arrival order,
+//               batch b's window is S[C, C + W): its new part is the last
+//               min(W, C) survivors up to the end of batch b's, consecutive
+//               places; its old part (C < W) is the window sum before the
+//               call minus S[0, C).  The final window goes to the ring
+//               (Section 3.2: slot nextPos).
 
 // Batch of tile t, given the tiles before each batch (K batches).
 __device__ __forceinline__ int sb_batch_of(const int32_t *tile0, int K, int t) {
@@ -1912,8 +1913,8 @@ __global__ __launch_bounds__(HIST_THREADS) void k_sb_hist(Scratch base, SbBufs s
 // Every block sums the fields of all groups itself (those before its first
 // group give its carries, all of them the totals), so no block waits on
 // another.  Fields per batch: light tuples, and heavy groups | touched
-// groups << 12; then survivors and apply work (survivors plus old values
-// read) per group.
+// groups << 12; then survivors per group, and 1 for a group whose
+// survivors plus old values read exceed APPLY_BUDGET.
 static_assert(SUB / HEAVY_MIN < (1 << 12) && (int64_t)PASS_LOCAL_G << 12 < (1LL << 31),
               "heavy groups of a batch fit 12 bits, touched groups the rest of an int");
 
@@ -1937,7 +1938,7 @@ __device__ __forceinline__ void sb_fields(const SbGroup &q, int K, int32_t W, in
     }
     const int lold = (kg > 0 && q.cnt0 > 0) ? min(W, kg) : 0;
     x[2 * SB_K] = m;
-    x[2 * SB_K + 1] = m + lold;
+    x[2 * SB_K + 1] = m + lold > APPLY_BUDGET ? 1 : 0;
 }
 
 // U groups' counters and window counts: every load issued before any is
@@ -2049,7 +2050,7 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
         ftot[tid] = t;
     }
     int wex[SBP_F];
-    int32_t own_work;
+    int32_t own_big;
     {
         int x[SBP_F];
         int32_t kg;
@@ -2060,7 +2061,7 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
             if (lane == 63) wown[wv][f] = incl;
             wex[f] = incl - x[f];
         }
-        own_work = x[2 * SB_K + 1];
+        own_big = x[2 * SB_K + 1];
     }
     __syncthreads();
     if (tid < SBP_F) {  // thread f: field f's value at each wave's start
@@ -2104,11 +2105,8 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
             m_before += min(k, W);
         }
         sb.gsb[g] = ex(2 * SB_K);
-        // apply ranges: range r starts at the group whose work holds place
-        // r * APPLY_BUDGET
-        const int a0 = ex(2 * SB_K + 1), a1 = a0 + own_work;
-        for (int r = (a0 + APPLY_BUDGET - 1) / APPLY_BUDGET; r * APPLY_BUDGET < a1; ++r)
-            sb.astart[r] = g;
+        sb.gbig[g] = own_big;
+        if (own_big) sb.big[ex(2 * SB_K + 1)] = g;
     }
     if (blockIdx.x == 0) {
         // batch b's totals by thread b (an unrolled loop: the batches'
@@ -2137,11 +2135,9 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
             if (t.n_buckets > NB_MAX) atomicOr(base.fault, FAULT_BUCKETS);
         }
         if (tid == SB_K) {
-            const int na = (tot(2 * SB_K + 1) + APPLY_BUDGET - 1) / APPLY_BUDGET;
             sb.gsb[G] = tot(2 * SB_K);
-            sb.ntot[0] = na;
+            sb.ntot[0] = tot(2 * SB_K + 1);
             sb.ntot[1] = tot(2 * SB_K);
-            sb.astart[na] = G;
         }
         if (tid == SB_K + 1) {  // the call's two most frequent groups, for the next histogram
             Top2 top;
@@ -2263,19 +2259,41 @@ __global__ __launch_bounds__(PASS_THREADS) void k_sb_pass(State st, Scratch base
     }
 }
 
-// Per (batch, bucket) item: the bucket's tuples are ranked inside their
-// groups as in the single-batch update (a heavy group's runs are already in
-// rank order), and each survivor's value goes to its place.  A heavy item
-// also leaves the sum of its survivors, which is the group's whole window
-// for that batch when the batch holds at least W of its tuples.
+// LDS of one survivor wave (bytes): per run of its bucket (one per tile) the
+// first bucket position and the staged start; per bucket position its run;
+// per group (indexed by its first position in the bucket) a leader byte and
+// the tuples ranked so far.
+constexpr int SPW_P = 0;                                 // i32[PASS_TILES_MAX + 1]
+constexpr int SPW_S = SPW_P + 4 * (PASS_TILES_MAX + 4);  // i32[PASS_TILES_MAX]
+constexpr int SPW_RT = SPW_S + 4 * PASS_TILES_MAX;       // u8[LIGHT_CAP]
+constexpr int SPW_LEAD = SPW_RT + LIGHT_CAP;             // u8[LIGHT_CAP]
+constexpr int SPW_CNT = SPW_LEAD + LIGHT_CAP;            // u16[LIGHT_CAP]
+constexpr int SPW_BYTES = SPW_CNT + 2 * LIGHT_CAP;
+static_assert(PASS_TILES_MAX == 4 * 64, "four runs per lane");
+static_assert(PASS_TILES_MAX <= 256, "run ids fit a byte");
+static_assert(LIGHT_CAP % 512 == 0, "light buckets in halves of eight rounds");
+
+// LDS accesses of other lanes of the wave seen from here on.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Survivors, one (batch, bucket) item per wave.  A light bucket's tuples
+// are read in arrival order (its runs in tile order), ranked inside their
+// groups in rounds of 64 (the lanes of a round that share a group elect a
+// leader through a byte table, 6 ballots over its lane id, as the reorder
+// does), and each group's last min(k, W) written to their places.  A heavy
+// bucket holds one group: its last min(k, W) tuples are copied, and their
+// sum kept (the group's whole window for that batch when the batch holds at
+// least W of its tuples).
 __global__ __launch_bounds__(UPD_THREADS) void k_sb_prep(State st, Scratch base, SbBufs sb,
                                                          SbBatches in) {
-    __shared__ __align__(16) char smem[U_BYTES];
-    __shared__ int red[UPD_THREADS / 64];
-    __shared__ long long red_ll[UPD_THREADS / 64];
+    constexpr int WPB = UPD_THREADS / 64;
+    __shared__ __align__(16) char smem[WPB * SPW_BYTES];
     __shared__ int items0[SB_K + 1];
-    __shared__ int32_t kso[LIGHT_SPAN];  // places of a light bucket's groups' survivors
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
     const int K = in.K;
     const int64_t G = st.G;
     const int32_t W = st.W;
@@ -2291,12 +2309,16 @@ __global__ __launch_bounds__(UPD_THREADS) void k_sb_prep(State st, Scratch base,
     }
     __syncthreads();
     const int items = items0[K];
-    int32_t *rs = reinterpret_cast<int32_t *>(smem + U_RS);
-    int32_t *rp = reinterpret_cast<int32_t *>(smem + U_RP);
-    int32_t *klp = reinterpret_cast<int32_t *>(smem + U_KLP);
+    char *my = smem + wv * SPW_BYTES;
+    int32_t *P = reinterpret_cast<int32_t *>(my + SPW_P);
+    int32_t *RS = reinterpret_cast<int32_t *>(my + SPW_S);
+    uint8_t *rt = reinterpret_cast<uint8_t *>(my + SPW_RT);
+    uint8_t *lead = reinterpret_cast<uint8_t *>(my + SPW_LEAD);
+    uint16_t *cnt = reinterpret_cast<uint16_t *>(my + SPW_CNT);
+    const int NWV = (int)gridDim.x * WPB;
     phase_mark(base, PHASE_SB_PREP, 1);
-    for (int it = (int)blockIdx.x; it < items; it += (int)gridDim.x) {
-        const bool first_item = it == (int)blockIdx.x;
+    for (int it = (int)blockIdx.x * WPB + wv; it < items; it += NWV) {
+        wave_lds_sync();  // (the previous item's reads of the tables are done)
         const int b = sb_batch_of(items0, K, it);
         const Scratch sc = sb_set(sb, base, b, G);
         const int32_t *so = sb.so + (int64_t)b * G;
@@ -2305,91 +2327,151 @@ __global__ __launch_bounds__(UPD_THREADS) void k_sb_prep(State st, Scratch base,
         const int NB = t.n_buckets, nl = t.n_light_buckets;
         const int tiles = (int)((in.n[b] + PASS_TILE - 1) / PASS_TILE);
         const bool light = kk < nl;
-        int32_t a = 0, z = 0, g = 0;
-        if (light) {
-            a = sc.bstart[kk];
-            z = sc.bstart[kk + 1];
-        } else {
-            g = sc.hkey[kk - nl];
+        // the bucket's runs, lane l holding tiles 4l .. 4l+3, and its facts,
+        // loaded together
+        int32_t rs4[4], rl4[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int tt = 4 * lane + j, tc = min(tt, tiles - 1);
+            const int32_t *row = sc.rowstart + (int64_t)tc * (NB + 1);
+            const int32_t r0 = row[kk], r1 = row[kk + 1];
+            rs4[j] = tc * PASS_TILE + r0;
+            rl4[j] = tt < tiles ? r1 - r0 : 0;
         }
-        RunRows<UPD_THREADS> rr;
-        runs_load<UPD_THREADS>(sc, kk, NB, tiles, rr);
-        constexpr int KPT = LIGHT_SPAN / UPD_THREADS;
-        const int m = z - a;
-        const bool pre = light && m <= LIGHT_SPAN;
-        if (pre) {  // the groups' staged starts and survivors' places, for LDS
-            int32_t pl[KPT + 1], ps[KPT];
+        const int32_t fa = light ? sc.bstart[kk] : sc.hkey[kk - nl];
+        const int32_t fz = light ? sc.bstart[kk + 1] : 0;
+        int size;
+        {
+            const int loc = rl4[0] + rl4[1] + rl4[2] + rl4[3];
+            const int incl = wave_incl_add(loc);
+            size = wave_total(incl);
+            int ex = incl - loc;
 #pragma unroll
-            for (int j = 0; j <= KPT; ++j) pl[j] = sc.lpre[a + min(tid + j * UPD_THREADS, m)];
-#pragma unroll
-            for (int j = 0; j < KPT; ++j)
-                ps[j] = so[a + max(0, min(tid + j * UPD_THREADS, m - 1))];
-#pragma unroll
-            for (int j = 0; j <= KPT; ++j) {
-                const int i = tid + j * UPD_THREADS;
-                if (i <= m) klp[i] = pl[j];
-                if (j < KPT && i < m) kso[i] = ps[j];
+            for (int j = 0; j < 4; ++j) {
+                P[4 * lane + j] = ex;
+                RS[4 * lane + j] = rs4[j];
+                ex += rl4[j];
             }
+            if (lane == 0) P[PASS_TILES_MAX] = size;
         }
-        if (light)  // the light bucket's run table (LIGHT_CAP bytes) starts clear
-            for (int i = tid; i < LIGHT_CAP / 4; i += UPD_THREADS)
-                reinterpret_cast<uint32_t *>(smem + U_LR)[i] = 0;
-        const int size = runs_store<UPD_THREADS>(tiles, rr, rs, rp, red);
-        if (first_item) phase_mark(base, PHASE_SB_PREP, 2);
-        if (light) {
-            const bool ok = pre ? light_rank<true>(a, z, size, tiles, sc, smem)
-                                : light_rank<false>(a, z, size, tiles, sc, smem);
-            if (first_item) phase_mark(base, PHASE_SB_PREP, 3);
-            if (ok) {
-                const int32_t *ek = reinterpret_cast<const int32_t *>(smem + U_EK);
-                const int32_t *ev = reinterpret_cast<const int32_t *>(smem + U_EV);
-                const int16_t *pz = reinterpret_cast<const int16_t *>(smem + U_PZ);
-                constexpr int SPT = LIGHT_CAP / UPD_THREADS;
-                int32_t gq[SPT], k0[SPT], k1[SPT], dst[SPT];
-#pragma unroll
-                for (int j = 0; j < SPT; ++j) {
-                    const int p = tid + j * UPD_THREADS;
-                    gq[j] = p < size && pz[p] >= 0 ? ek[p] : -1;
-                    const int32_t gc = gq[j] >= 0 ? gq[j] : a;
-                    k0[j] = pre ? klp[gc - a] : sc.lpre[gc];
-                    k1[j] = pre ? klp[gc - a + 1] : sc.lpre[gc + 1];
-                    dst[j] = pre ? kso[gc - a] : so[gc];
-                }
-#pragma unroll
-                for (int j = 0; j < SPT; ++j) {
-                    if (gq[j] < 0) continue;
-                    const int p = tid + j * UPD_THREADS;
-                    const int32_t k = k1[j] - k0[j];
-                    const int32_t r = light_rank_of(smem, size, p);
-                    const int32_t first = k - min(k, W);  // rank of the first survivor
-                    if (r >= first) sb.xs[dst[j] + (r - first)] = ev[p];
-                }
-            }
-        } else if (size > 0) {
+        if (size <= 0) continue;
+        if (!light) {
+            const int32_t g = fa;
             const int32_t first = size - min(size, W);
             const int32_t base_x = so[g] - first;
-            constexpr int HU = 4;
+            wave_lds_sync();
+            constexpr int HU = 8;
             long long acc = 0;
-            for (int p0 = first + tid; p0 < size; p0 += HU * UPD_THREADS) {
+            for (int p0 = first + lane; p0 < size; p0 += HU * 64) {
                 int32_t v[HU];
 #pragma unroll
                 for (int u = 0; u < HU; ++u) {
-                    const int p = min(p0 + u * UPD_THREADS, size - 1);
-                    const int r = upper_run(rp, tiles, p);
-                    v[u] = sc.sdat[rs[r] + (p - rp[r])].y;
+                    const int p = min(p0 + u * 64, size - 1);
+                    const int r = upper_run(P, tiles, p);
+                    v[u] = sc.sdat[RS[r] + (p - P[r])].y;
                 }
 #pragma unroll
                 for (int u = 0; u < HU; ++u)
-                    if (p0 + u * UPD_THREADS < size) {
-                        sb.xs[base_x + p0 + u * UPD_THREADS] = v[u];
+                    if (p0 + u * 64 < size) {
+                        sb.xs[base_x + p0 + u * 64] = v[u];
                         acc += v[u];
                     }
             }
-            const long long tsum = block_sum_ll(acc, red_ll);
-            if (tid == 0) sb.tb[(int64_t)b * G + g] = tsum;
+            acc = wave_sum_ll(acc);
+            if (lane == 0) sb.tb[(int64_t)b * G + g] = acc;
+            continue;
         }
-        if (first_item) phase_mark(base, PHASE_SB_PREP, 4);
-        __syncthreads();
+        const int32_t a = fa, z = fz;
+        const int32_t s0 = sc.lpre[a];
+        if (size > LIGHT_CAP || sc.lpre[z] - s0 != size) {  // impossible for a well-formed plan
+            if (lane == 0) atomicOr(sc.fault, FAULT_LIGHT_SIZE);
+            continue;
+        }
+        // every position's run: each non-empty run's id at its first
+        // position, then a running maximum (run ids grow with position);
+        // lane l owns positions 16l .. 16l+15 here
+        constexpr int PPL = LIGHT_CAP / 64;
+#pragma unroll
+        for (int j = 0; j < PPL / 4; ++j)
+            reinterpret_cast<uint32_t *>(rt)[lane * (PPL / 4) + j] = 0;
+#pragma unroll
+        for (int j = 0; j < 2 * LIGHT_CAP / 4 / 64; ++j)
+            reinterpret_cast<uint32_t *>(cnt)[lane + 64 * j] = 0;
+        wave_lds_sync();
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (rl4[j] > 0) rt[P[4 * lane + j]] = (uint8_t)(4 * lane + j);
+        wave_lds_sync();
+        {
+            int mloc = 0, loc[PPL];
+#pragma unroll
+            for (int i = 0; i < PPL; ++i) {
+                mloc = max(mloc, (int)rt[PPL * lane + i]);
+                loc[i] = mloc;
+            }
+            const int incl = wave_incl_max(mloc);
+            int before = __shfl_up(incl, 1, 64);
+            if (lane == 0) before = 0;
+            wave_lds_sync();
+#pragma unroll
+            for (int i = 0; i < PPL; ++i) rt[PPL * lane + i] = (uint8_t)max(before, loc[i]);
+        }
+        wave_lds_sync();
+        // rounds of 64 positions in arrival order, in halves of eight
+        for (int h = 0; h < size; h += 512) {
+            constexpr int RH = 8;
+            int2 e[RH];
+#pragma unroll
+            for (int r = 0; r < RH; ++r) {
+                const int p = min(h + r * 64 + lane, size - 1);
+                const int tt = rt[p];
+                e[r] = sc.sdat[RS[tt] + (p - P[tt])];
+            }
+            int32_t l0[RH], l1[RH], dst[RH];
+#pragma unroll
+            for (int r = 0; r < RH; ++r) {
+                const int32_t g = e[r].x;
+                const int32_t gc = g >= a && g < z ? g : a;
+                l0[r] = sc.lpre[gc];
+                l1[r] = sc.lpre[gc + 1];
+                dst[r] = so[gc];
+            }
+#pragma unroll
+            for (int r = 0; r < RH; ++r) {
+                const int p = h + r * 64 + lane;
+                const int32_t g = e[r].x;
+                bool valid = p < size && g >= a && g < z && l1[r] > l0[r];
+                const int p0 = valid ? l0[r] - s0 : 0;
+                if (valid && (p0 < 0 || p0 >= size)) {  // impossible for a well-formed plan
+                    atomicOr(sc.fault, FAULT_LIGHT_SIZE);
+                    valid = false;
+                }
+                if (valid)
+                    __hip_atomic_store(lead + p0, (uint8_t)lane, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
+                wave_lds_sync();
+                const int L = valid ? (int)__hip_atomic_load(lead + p0, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_WAVEFRONT)
+                                    : 0;
+                uint64_t m = ballot(valid);
+#pragma unroll
+                for (int bit = 0; bit < 6; ++bit) {
+                    const bool on = (L >> bit) & 1;
+                    const uint64_t bb = ballot(on);
+                    m &= on ? bb : ~bb;
+                }
+                if (valid) {
+                    const uint64_t below = m & lanemask_lt();
+                    const int c = cnt[p0];
+                    const int32_t rank = c + __popcll(below);
+                    if (below == 0) cnt[p0] = (uint16_t)(c + __popcll(m));
+                    const int32_t k = l1[r] - l0[r];
+                    const int32_t first = k - min(k, W);  // rank of the first survivor
+                    if (rank >= first) sb.xs[dst[r] + (rank - first)] = e[r].y;
+                }
+                wave_lds_sync();
+            }
+        }
     }
     phase_mark(base, PHASE_SB_PREP, 5);
 }
@@ -2492,197 +2574,65 @@ __device__ __forceinline__ int32_t apply_old(const State &st, int g, int32_t pos
     return st.ring[(int64_t)g * W + slot];
 }
 
-// Results of every batch of group g, its final state, and its counters
-// cleared.  newpart(b, e, win): the sum of its survivors at places
-// [e - win, e) (relative to its first); oldsum(b, c): its old window values
-// 0 .. c-1.
-template <typename FN, typename FO>
-__device__ __forceinline__ void apply_emit(const State &st, const SbBufs &sb,
-                                           const SbBatches &in, const ApplyGroup &q, int g,
-                                           FN &&newpart, FO &&oldsum) {
-    const int32_t W = st.W;
-    int32_t c = 0, e = 0;  // tuples so far; end of the survivors' places so far
-    int64_t s = q.sum0;
+// Batch `bl`'s facts of group q for the calling lane (the batches' values
+// are wave-uniform; a lane picks one): its tuples, the group's tuples in
+// batches 0..bl, its output position and whether it was whole.
+struct LaneBatch {
+    int32_t k, c, tix;
+    bool whole;
+};
+
+__device__ __forceinline__ LaneBatch lane_batch(const ApplyGroup &q, int bl, int32_t W) {
+    LaneBatch r = {0, 0, 0, false};
+    int32_t c = 0;
 #pragma unroll
     for (int b = 0; b < SB_K; ++b) {
-        const int32_t k = q.k[b];
-        if (k <= 0) continue;
-        c += k;
-        e += min(k, W);
-        s = newpart(b, e, min(W, c)) + (c < W ? q.sum0 - oldsum(b, c) : 0);
-        const int32_t cnt = (int32_t)min((int64_t)W, (int64_t)q.cnt0 + c);
-        emit_one(in.out[b], q.tix[b], g, s, cnt);
+        c += q.k[b];
+        if (bl == b) {
+            r.k = q.k[b];
+            r.c = c;
+            r.tix = q.tix[b];
+            r.whole = q.k[b] >= W && q.k[b] >= HEAVY_MIN;
+        }
     }
-    st.sum[g] = s;
-    st.pos[g] = (int32_t)(((uint32_t)q.pos0 + (uint32_t)q.kg) % (uint32_t)W);
-    st.cnt[g] = (int32_t)min((int64_t)W, (int64_t)q.cnt0 + q.kg);
-    // the group's counters, rejected batches' included, start the next call clear
-    int4 *kp = reinterpret_cast<int4 *>(sb.kh + (int64_t)g * SB_K);
-    kp[0] = make_int4(0, 0, 0, 0);
-    kp[1] = make_int4(0, 0, 0, 0);
+    return r;
 }
 
-// LDS of an apply workgroup (bytes).
-constexpr int A_P = 0;                                     // i64[APPLY_CAP + 1] prefix sums
-constexpr int A_OWN = A_P + 8 * (APPLY_CAP + 8);           // u16[APPLY_CAP] group of each element
-constexpr int A_GX = A_OWN + 2 * APPLY_CAP;                // i32[APPLY_FLAT_G + 1] survivor starts
-constexpr int A_GO = A_GX + 4 * (APPLY_FLAT_G + 4);        // i32[APPLY_FLAT_G + 1] old-value starts
-constexpr int A_GP = A_GO + 4 * (APPLY_FLAT_G + 4);        // i32[APPLY_FLAT_G] pos0
-constexpr int A_GC = A_GP + 4 * APPLY_FLAT_G;              // i32[APPLY_FLAT_G] cnt0
-constexpr int A_GK = A_GC + 4 * APPLY_FLAT_G;              // i32[APPLY_FLAT_G] tuples in the call
-constexpr int A_BYTES = A_GK + 4 * APPLY_FLAT_G;
-static_assert(2 * APPLY_FLAT_G < 65536, "element owners fit 16 bits");
-
-// Groups [c0, c1) (at most APPLY_FLAT_G; survivors plus old values read at
-// most APPLY_CAP): every survivor and old value in one prefix sum.  Groups
-// go to threads strided (group i to thread i mod APPLY_THREADS), so that a
-// wave's loads and stores of per-group data and results are consecutive;
-// elements go to threads in consecutive runs of APPLY_EPT for the scans and
-// strided for the ring writes.  Each element's group comes from a running
-// maximum over marks at the groups' first elements (survivors: group index;
-// old values: ng + group index, so that the maximum keeps growing across
-// the two regions).
-__device__ void apply_flat(const State &st, const SbBufs &sb, const SbBatches &in,
-                           const bool (&valid)[SB_K], int c0, int c1, char *smem,
-                           long long *red, const Scratch &base, bool mark) {
-    const int tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
+// Batch bl's result of group g (s: its window's sum without the part from
+// before the call) by the calling lane, and, by the lane of the group's last
+// batch, its final state and its counters cleared.  Returns the window sum.
+__device__ __forceinline__ void apply_emit_lane(const State &st, const SbBufs &sb,
+                                                const Out *outs, const ApplyGroup &q, int g,
+                                                const LaneBatch &lb, int bl, long long s) {
     const int32_t W = st.W;
-    long long *P = reinterpret_cast<long long *>(smem + A_P);
-    uint16_t *own = reinterpret_cast<uint16_t *>(smem + A_OWN);
-    int32_t *gx = reinterpret_cast<int32_t *>(smem + A_GX);
-    int32_t *go = reinterpret_cast<int32_t *>(smem + A_GO);
-    int32_t *gp = reinterpret_cast<int32_t *>(smem + A_GP);
-    int32_t *gc = reinterpret_cast<int32_t *>(smem + A_GC);
-    int32_t *gk = reinterpret_cast<int32_t *>(smem + A_GK);
-    const int ng = c1 - c0;
-    // this thread's groups: c0 + tid + APPLY_THREADS * j
-    ApplyGroup q[APPLY_GPT];
-    apply_load<APPLY_GPT>(sb, st, valid, in.K, c0 + tid, APPLY_THREADS, c1, q);
-    const int32_t x0 = sb.gsb[c0], x1 = sb.gsb[c1];
-    if (mark) phase_mark(base, PHASE_SB_APPLY, 2);
-    // old-value offsets: group i = tid + APPLY_THREADS * j comes after every
-    // group of the rows before j and the threads before tid in row j
-    int lo[APPLY_GPT], lt[APPLY_GPT];
+    s += lb.c < W ? q.sum0 : 0;
+    if (lb.k > 0) emit_one(outs[bl], lb.tix, g, s, (int32_t)min((int64_t)W, (int64_t)q.cnt0 + lb.c));
+    int last = 0;
 #pragma unroll
-    for (int j = 0; j < APPLY_GPT; ++j) lo[j] = q[j].lold;
-    block_excl_scan<APPLY_GPT>(lo, lt, reinterpret_cast<int *>(red));
-    int ox = 0;
-#pragma unroll
-    for (int j = 0; j < APPLY_GPT; ++j) {
-        lo[j] += ox;
-        ox += lt[j];
+    for (int b = 0; b < SB_K; ++b)
+        if (q.k[b] > 0) last = b;
+    if (bl == last && lb.k > 0) {
+        st.sum[g] = s;
+        st.pos[g] = (int32_t)(((uint32_t)q.pos0 + (uint32_t)q.kg) % (uint32_t)W);
+        st.cnt[g] = (int32_t)min((int64_t)W, (int64_t)q.cnt0 + q.kg);
+        // the group's counters, rejected batches' included, start the next
+        // call clear
+        int4 *kp = reinterpret_cast<int4 *>(sb.kh + (int64_t)g * SB_K);
+        kp[0] = make_int4(0, 0, 0, 0);
+        kp[1] = make_int4(0, 0, 0, 0);
     }
-    const int mx = x1 - x0;
-    if (mx + ox > APPLY_CAP) {  // impossible for a well-formed plan
-        if (tid == 0) atomicOr(sb.fault, FAULT_APPLY);
-        return;
-    }
-    for (int e = tid; e < mx + ox; e += APPLY_THREADS) own[e] = 0;
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < APPLY_GPT; ++j) {
-        const int i = tid + APPLY_THREADS * j;
-        if (i < ng) {
-            gx[i] = q[j].gs - x0;
-            go[i] = lo[j];
-            gp[i] = q[j].pos0;
-            gc[i] = q[j].cnt0;
-            gk[i] = q[j].kg;
-            if (q[j].m > 0) own[q[j].gs - x0] = (uint16_t)i;
-            if (q[j].lold > 0) own[mx + lo[j]] = (uint16_t)(ng + i);
-        }
-    }
-    if (tid == 0) {
-        gx[ng] = mx;
-        go[ng] = ox;
-    }
-    __syncthreads();
-    // every element's group (running maximum), APPLY_EPT consecutive
-    // elements per thread, written back for the strided ring writes
-    int ow[APPLY_EPT], mloc = 0;
-#pragma unroll
-    for (int i = 0; i < APPLY_EPT; ++i) {
-        const int e = APPLY_EPT * tid + i;
-        mloc = max(mloc, e < mx + ox ? (int)own[e] : 0);
-        ow[i] = mloc;
-    }
-    {
-        const int incl = wave_incl_max(mloc);
-        int *wm = reinterpret_cast<int *>(red);
-        if (lane == 63) wm[wid] = incl;
-        __syncthreads();
-        int before = __shfl_up(incl, 1, 64);
-        if (lane == 0) before = 0;
-        for (int w = 0; w < wid; ++w) before = max(before, wm[w]);
-#pragma unroll
-        for (int i = 0; i < APPLY_EPT; ++i) {
-            ow[i] = max(ow[i], before);
-            const int e = APPLY_EPT * tid + i;
-            if (e < mx) own[e] = (uint16_t)ow[i];
-        }
-        __syncthreads();
-    }
-    // survivors [0, mx) then old values [mx, mx + ox), all loaded before any
-    // is used
-    int32_t v[APPLY_EPT];
-#pragma unroll
-    for (int i = 0; i < APPLY_EPT; ++i) {
-        const int e = APPLY_EPT * tid + i;
-        v[i] = 0;
-        if (e < mx) {
-            v[i] = sb.xs[x0 + e];
-        } else if (e < mx + ox) {
-            const int j = ow[i] - ng;
-            v[i] = apply_old(st, c0 + j, gp[j], gc[j], e - mx - go[j]);
-        }
-    }
-    if (mark) phase_mark(base, PHASE_SB_APPLY, 3);
-    long long loc = 0;
-#pragma unroll
-    for (int i = 0; i < APPLY_EPT; ++i) loc += v[i];
-    long long tot;
-    long long run = apply_excl_scan(loc, red, tot);
-    if (mark) phase_mark(base, PHASE_SB_APPLY, 4);
-#pragma unroll
-    for (int i = 0; i < APPLY_EPT; ++i) {
-        const int e = APPLY_EPT * tid + i;
-        if (e < mx + ox) P[e] = run;
-        run += v[i];
-    }
-    if (tid == 0) P[mx + ox] = tot;
-    __syncthreads();  // (every old value has been read: the ring may change now)
-    // the final window, the last min(W, kg) survivors, into the ring;
-    // consecutive elements by consecutive lanes
-    for (int e = tid; e < mx; e += APPLY_THREADS) {
-        const int j = own[e];
-        const int32_t m = gx[j + 1] - gx[j], kg = gk[j], r = e - gx[j];
-        if (r >= m - min(W, kg)) {
-            const int32_t rank = kg - (m - r);
-            const uint32_t slot = ((uint32_t)gp[j] + (uint32_t)rank) % (uint32_t)W;
-            st.ring[(int64_t)(c0 + j) * W + slot] = (int32_t)(P[e + 1] - P[e]);
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < APPLY_GPT; ++j) {
-        const int i = tid + APPLY_THREADS * j;
-        if (i >= ng || q[j].kg == 0) continue;
-        const int xs0 = gx[i], os0 = mx + go[i];
-        apply_emit(st, sb, in, q[j], c0 + i,
-                   [&](int, int32_t e, int32_t win) { return P[xs0 + e] - P[xs0 + e - win]; },
-                   [&](int, int32_t c) { return q[j].lold ? P[os0 + c] - P[os0] : 0LL; });
-    }
-    __syncthreads();
 }
 
-// Group g alone (more survivors plus old values than one range holds).
-// Batch b's window sum: the survivors at places [lo_b, hi_b) plus, while
-// fewer than W tuples have arrived in the call, the window before the call
-// less its first c_b values.  A batch holding at least max(W, HEAVY_MIN) of
-// its tuples was a heavy item whose survivors' sum the prep step left; the
-// others are summed here, each thread adding what it reads to every batch
-// whose range holds it.
+// Group g by a whole workgroup (its survivors plus old values read exceed
+// APPLY_BUDGET).  Batch b's window sum: the survivors at places [lo_b, hi_b)
+// plus, while fewer than W tuples have arrived in the call, the window before
+// the call less its first c_b values.  A batch holding at least
+// max(W, HEAVY_MIN) of its tuples was a heavy item whose survivors' sum the
+// prep step left; the others are summed here, each thread adding what it
+// reads to (survivors) or subtracting it from (old values) every batch whose
+// range holds it.
 __device__ void apply_big(const State &st, const SbBufs &sb, const SbBatches &in,
-                          const bool (&valid)[SB_K], int g, long long *red) {
+                          const Out *outs, const bool (&valid)[SB_K], int g, long long *red) {
     constexpr int NW = APPLY_THREADS / 64;
     const int tid = threadIdx.x;
     const int32_t W = st.W;
@@ -2692,7 +2642,6 @@ __device__ void apply_big(const State &st, const SbBufs &sb, const SbBatches &in
     int32_t lo[SB_K], hi[SB_K], cb[SB_K];
     bool whole[SB_K];  // the batch's own survivors are the window: its sum is known
     bool need_x = false, need_o = false;
-    int64_t tb[SB_K];
     {
         int32_t c = 0, e = 0;
 #pragma unroll
@@ -2706,13 +2655,12 @@ __device__ void apply_big(const State &st, const SbBufs &sb, const SbBatches &in
             whole[b] = k >= W && k >= HEAVY_MIN;
             need_x |= k > 0 && !whole[b];
             need_o |= cb[b] > 0;
-            tb[b] = sb.tb[(int64_t)(b < in.K ? b : 0) * st.G + g];
         }
     }
-    long long an[SB_K], ao[SB_K];
+    long long acc[SB_K];
 #pragma unroll
-    for (int b = 0; b < SB_K; ++b) an[b] = ao[b] = 0;
-    constexpr int U = 8;
+    for (int b = 0; b < SB_K; ++b) acc[b] = 0;
+    constexpr int U = 4;
     if (need_o) {
         for (int i0 = tid; i0 < q.lold; i0 += U * APPLY_THREADS) {
             int32_t v[U];
@@ -2723,7 +2671,7 @@ __device__ void apply_big(const State &st, const SbBufs &sb, const SbBatches &in
             for (int u = 0; u < U; ++u) {
                 const int i = i0 + u * APPLY_THREADS;
 #pragma unroll
-                for (int b = 0; b < SB_K; ++b) ao[b] += (i < q.lold && i < cb[b]) ? v[u] : 0;
+                for (int b = 0; b < SB_K; ++b) acc[b] -= (i < q.lold && i < cb[b]) ? v[u] : 0;
             }
         }
     }
@@ -2732,6 +2680,9 @@ __device__ void apply_big(const State &st, const SbBufs &sb, const SbBatches &in
     // the last min(W, kg), written to the ring as they are read
     const int32_t keep_from = q.m - min(W, q.kg);
     const int32_t x_from = need_x ? 0 : keep_from;
+    const uint32_t slot0 =
+        (uint32_t)(((int64_t)q.pos0 + q.kg - min(W, q.kg)) % (int64_t)W);  // of keep_from
+    int32_t *ring = st.ring + (int64_t)g * W;
     for (int e0 = x_from + tid; e0 < q.m; e0 += U * APPLY_THREADS) {
         int32_t v[U];
 #pragma unroll
@@ -2743,49 +2694,169 @@ __device__ void apply_big(const State &st, const SbBufs &sb, const SbBatches &in
             if (need_x) {
 #pragma unroll
                 for (int b = 0; b < SB_K; ++b)
-                    an[b] += (!whole[b] && e >= lo[b] && e < hi[b]) ? v[u] : 0;
+                    acc[b] += (!whole[b] && e >= lo[b] && e < hi[b]) ? v[u] : 0;
             }
             if (e >= keep_from) {
-                const int32_t rank = q.kg - (q.m - e);
-                const uint32_t slot = ((uint32_t)q.pos0 + (uint32_t)rank) % (uint32_t)W;
-                st.ring[(int64_t)g * W + slot] = v[u];
+                uint32_t slot = slot0 + (uint32_t)(e - keep_from);
+                slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
+                ring[slot] = v[u];
             }
         }
     }
-    // block sums of the 2 * SB_K partial sums
+    // block sums of the SB_K partial sums
     const int lane = lane_id(), wid = tid >> 6;
 #pragma unroll
     for (int b = 0; b < SB_K; ++b) {
-        const long long sn = wave_sum_ll(an[b]), so = wave_sum_ll(ao[b]);
-        if (lane == 0) {
-            red[(2 * b) * NW + wid] = sn;
-            red[(2 * b + 1) * NW + wid] = so;
-        }
+        const long long t = wave_sum_ll(acc[b]);
+        if (lane == 0) red[b * NW + wid] = t;
     }
     __syncthreads();
-    if (tid == 0) {
-        long long tn[SB_K], to[SB_K];
-#pragma unroll
-        for (int b = 0; b < SB_K; ++b) {
-            tn[b] = to[b] = 0;
-            for (int w = 0; w < NW; ++w) {
-                tn[b] += red[(2 * b) * NW + w];
-                to[b] += red[(2 * b + 1) * NW + w];
-            }
-            if (whole[b]) tn[b] = tb[b];
-        }
-        apply_emit(st, sb, in, q, g, [&](int b, int32_t, int32_t) { return tn[b]; },
-                   [&](int b, int32_t) { return to[b]; });
+    if (tid < SB_K) {  // thread b: batch b
+        const LaneBatch lb = lane_batch(q, tid, W);
+        long long t = 0;
+        for (int w = 0; w < NW; ++w) t += red[tid * NW + w];
+        if (lb.whole) t = sb.tb[(int64_t)(tid < in.K ? tid : 0) * st.G + g];
+        apply_emit_lane(st, sb, outs, q, g, lb, tid, t);
     }
     __syncthreads();
 }
 
+// A 64-bit value of lane l (a wave-uniform lane).
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Group g by one wave.  A (one int per lane): lanes 0-7 the group's
+// counters of batches 0-7, 8-15 its output positions, 16 pos, 17 cnt, 18 and
+// 19 its first survivor place and the next group's, 20 and up its flag of
+// a workgroup's group; B (one int64 per lane):
+// lanes 0-7 the heavy items' survivor sums, 8 the window sum.  Each lane
+// keeps a partial window sum per batch: survivors at places [lo_b, hi_b)
+// added, old values [0, cb_b) subtracted (batch b's window sum is then that
+// plus, while fewer than W tuples have arrived in the call, the sum before
+// it); the eight are reduced by halving, lane 8b ending with batch b's.
+__device__ void apply_wave(const State &st, const SbBufs &sb, const SbBatches &in,
+                           const Out *outs, const bool (&valid)[SB_K], int g, int32_t A,
+                           int64_t B) {
+    const int lane = lane_id();
+    const int32_t W = st.W;
+    ApplyGroup q;
+    q.kg = 0;
+#pragma unroll
+    for (int b = 0; b < SB_K; ++b) {
+        const int32_t k = __builtin_amdgcn_readlane(A, b);
+        q.k[b] = (b < in.K && valid[b]) ? k : 0;
+        q.tix[b] = __builtin_amdgcn_readlane(A, 8 + b);
+        q.kg += q.k[b];
+    }
+    if (q.kg == 0) return;
+    q.pos0 = __builtin_amdgcn_readlane(A, 16);
+    q.cnt0 = __builtin_amdgcn_readlane(A, 17);
+    q.gs = __builtin_amdgcn_readlane(A, 18);
+    q.m = __builtin_amdgcn_readlane(A, 19) - q.gs;
+    q.sum0 = readlane64(B, 8);
+    q.lold = q.cnt0 > 0 ? min(W, q.kg) : 0;
+    int32_t lo[SB_K], hi[SB_K], cb[SB_K];
+    bool whole[SB_K];  // the batch's own survivors are the window: its sum is known
+    bool need_x = false;
+    {
+        int32_t c = 0, e = 0;
+#pragma unroll
+        for (int b = 0; b < SB_K; ++b) {
+            const int32_t k = q.k[b];
+            c += k;
+            e += min(k, W);
+            hi[b] = e;
+            lo[b] = e - min(W, c);
+            cb[b] = (k > 0 && c < W && q.lold) ? c : 0;
+            whole[b] = k >= W && k >= HEAVY_MIN;
+            need_x |= k > 0 && !whole[b];
+        }
+    }
+    long long acc[SB_K];
+#pragma unroll
+    for (int b = 0; b < SB_K; ++b) acc[b] = 0;
+    constexpr int U = 4;
+    int32_t *ring = st.ring + (int64_t)g * W;
+    // old value i (i < W) sits in slot pos0 + i mod W; slots a window that
+    // never filled has not reached hold 0 and are not read
+    const int32_t unread = W - q.cnt0;
+    for (int i0 = lane; i0 < q.lold; i0 += U * 64) {
+        int32_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t i = min(i0 + u * 64, q.lold - 1);
+            uint32_t slot = (uint32_t)q.pos0 + (uint32_t)i;
+            slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
+            v[u] = i < unread ? 0 : ring[slot];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * 64;
+#pragma unroll
+            for (int b = 0; b < SB_K; ++b) acc[b] -= (i < q.lold && i < cb[b]) ? v[u] : 0;
+        }
+    }
+    // (the old values have all been read: the ring may change now) the
+    // survivors, summed where a batch needs them, and the final window, the
+    // last min(W, kg), written to the ring as they are read
+    const int32_t keep_from = q.m - min(W, q.kg);
+    const int32_t x_from = need_x ? 0 : keep_from;
+    const uint32_t slot0 =
+        (uint32_t)(((int64_t)q.pos0 + q.kg - min(W, q.kg)) % (int64_t)W);  // of keep_from
+    for (int e0 = x_from + lane; e0 < q.m; e0 += U * 64) {
+        int32_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = sb.xs[q.gs + min(e0 + u * 64, q.m - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * 64;
+            if (e >= q.m) break;
+#pragma unroll
+            for (int b = 0; b < SB_K; ++b)
+                acc[b] += (!whole[b] && e >= lo[b] && e < hi[b]) ? v[u] : 0;
+            if (e >= keep_from) {
+                uint32_t slot = slot0 + (uint32_t)(e - keep_from);
+                slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
+                ring[slot] = v[u];
+            }
+        }
+    }
+    // halving: after the step over lane bit 5 a lane holds four batches'
+    // partial sums (0-3 or 4-7), after bit 4 two, after bit 3 one
+#pragma unroll
+    for (int h = SB_K / 2, off = 32; h >= 1; h >>= 1, off >>= 1) {
+        const bool up = lane & off;
+#pragma unroll
+        for (int j = 0; j < h; ++j) {
+            const long long give = up ? acc[j] : acc[j + h];
+            const long long keep_ = up ? acc[j + h] : acc[j];
+            acc[j] = keep_ + __shfl_xor(give, off, 64);
+        }
+    }
+#pragma unroll
+    for (int off = 4; off >= 1; off >>= 1) acc[0] += __shfl_xor(acc[0], off, 64);
+    // lane 8b: batch b (a whole batch's sum is in lane b's B)
+    const int bl = lane >> 3;
+    const LaneBatch lb = lane_batch(q, bl, W);
+    const long long tbl = __shfl(B, bl, 64);
+    if ((lane & 7) == 0) apply_emit_lane(st, sb, outs, q, g, lb, bl, lb.whole ? tbl : acc[0]);
+}
+
 __global__ __launch_bounds__(APPLY_THREADS) void k_sb_apply(State st, Scratch base, SbBufs sb,
                                                             SbBatches in, int32_t seq) {
-    __shared__ __align__(16) char smem[A_BYTES];
-    __shared__ long long red[2 * SB_K * (APPLY_THREADS / 64)];
+    __shared__ long long red[SB_K * (APPLY_THREADS / 64)];
+    __shared__ Out outs[SB_K];  // (indexed by lane: the argument's copy is per batch)
+    constexpr int WPB = APPLY_THREADS / 64;
     const int K = in.K;
     const int G = (int)st.G;
+    const int lane = lane_id();
+#pragma unroll
+    for (int b = 0; b < SB_K; ++b)
+        if ((int)threadIdx.x == b) outs[b] = in.out[b];
+    __syncthreads();
     bool valid[SB_K];
 #pragma unroll
     for (int b = 0; b < SB_K; ++b) valid[b] = b < K && sb.sbad[b] != seq;
@@ -2794,41 +2865,54 @@ __global__ __launch_bounds__(APPLY_THREADS) void k_sb_apply(State st, Scratch ba
     if ((int)blockIdx.x < K && !valid[blockIdx.x])
         for (int g = threadIdx.x; g < G; g += APPLY_THREADS)
             sb.kh[(int64_t)g * SB_K + blockIdx.x] = 0;
-    const int na = sb.ntot[0];
     phase_mark(base, PHASE_SB_APPLY, 0);
-    // two items per range: its first group alone when that group is over the
-    // budget, and the rest (so that a big group and the small ones after it
-    // run in different workgroups)
-    for (int it = (int)blockIdx.x; it < 2 * na; it += (int)gridDim.x) {
-        const bool mark = it == (int)blockIdx.x;
-        const int r = it >> 1;
-        const bool big_item = (it & 1) == 0;
-        const int a = sb.astart[r], z = sb.astart[r + 1];
-        if (a >= z) continue;
-        // only the first group of a range can be over the budget alone
-        const int32_t m = sb.gsb[a + 1] - sb.gsb[a];
-        int32_t kg = 0;
-        {
-            int32_t v[SB_K];
-            const int4 *p = reinterpret_cast<const int4 *>(sb.kh + (int64_t)a * SB_K);
-            const int4 x = p[0], y = p[1];
-            v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-            v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+    // the groups over APPLY_BUDGET first, by whole workgroups
+    const int nbig = sb.ntot[0];
+    for (int i = (int)blockIdx.x; i < nbig; i += (int)gridDim.x) {
+        apply_big(st, sb, in, outs, valid, sb.big[i], red);
+        if (i == (int)blockIdx.x) phase_mark(base, PHASE_SB_APPLY, 1);
+    }
+    phase_mark(base, PHASE_SB_APPLY, 2);
+    // then every other group by one wave: all facts of a wave's groups (w +
+    // j * NW for wave w of NW) are loaded together
+    const int NWV = (int)gridDim.x * WPB;
+    const int w = (int)blockIdx.x * WPB + ((int)threadIdx.x >> 6);
+    constexpr int J = 4;
+    int32_t A[J];
+    int64_t B[J];
 #pragma unroll
-            for (int b = 0; b < SB_K; ++b) kg += valid[b] ? v[b] : 0;
+    for (int j = 0; j < J; ++j) {
+        const int g = min(w + j * NWV, G - 1);
+        const int b = lane & 7;
+        const int bb = b < K ? b : 0;
+        const int32_t *pa = lane < 8    ? sb.kh + (int64_t)g * SB_K + b
+                            : lane < 16 ? sb.tidx + (int64_t)bb * G + g
+                            : lane == 16 ? st.pos + g
+                            : lane == 17 ? st.cnt + g
+                            : lane == 18 ? sb.gsb + g
+                            : lane == 19 ? sb.gsb + g + 1
+                                         : sb.gbig + g;
+        const int64_t *pb = lane < 8 ? sb.tb + (int64_t)bb * G + g : st.sum + g;
+        A[j] = *pa;
+        B[j] = *pb;
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        keep(A[j]);
+        keep(B[j]);
+    }
+    // (one copy of the group code: the facts move down a slot per group)
+#pragma unroll 1
+    for (int j = 0; j < J; ++j) {
+        const int g = w + j * NWV;
+        if (g >= G) break;
+        if (!__builtin_amdgcn_readlane(A[0], 20))  // (else a workgroup's)
+            apply_wave(st, sb, in, outs, valid, g, A[0], B[0]);
+#pragma unroll
+        for (int i = 0; i + 1 < J; ++i) {
+            A[i] = A[i + 1];
+            B[i] = B[i + 1];
         }
-        const int32_t lold = (kg > 0 && st.cnt[a] > 0) ? min(st.W, kg) : 0;
-        const bool big = m + lold > APPLY_BUDGET;
-        if (mark) phase_mark(base, PHASE_SB_APPLY, 1);
-        if (big_item) {
-            if (big) apply_big(st, sb, in, valid, a, red);
-            if (mark) phase_mark(base, PHASE_SB_APPLY, 6);
-            continue;
-        }
-        for (int c0 = big ? a + 1 : a; c0 < z; c0 += APPLY_FLAT_G)
-            apply_flat(st, sb, in, valid, c0, min(z, c0 + APPLY_FLAT_G), smem, red, base,
-                       mark && c0 == (big ? a + 1 : a));
-        if (mark) phase_mark(base, PHASE_SB_APPLY, 5);
     }
     phase_mark(base, PHASE_SB_APPLY, 7);
 }
@@ -3015,14 +3099,15 @@ hipError_t launch_sb_pass(State st, Scratch base, SbBufs sb, const SbBatches &in
 
 hipError_t launch_sb_prep(State st, Scratch base, SbBufs sb, const SbBatches &in,
                           hipStream_t s) {
-    // workgroups loop over the items (at most one per bucket of each batch,
-    // known on the device only): a workgroup that finds none still costs its
+    // waves loop over the items (at most one per bucket of each batch, known
+    // on the device only): a workgroup that finds none still costs its
     // dispatch, so the grid is what the device holds at once, not the bound
     int64_t items = 0;
     for (int b = 0; b < in.K; ++b)
         items += in.n[b] ? (in.n[b] + LIGHT_BUDGET - 1) / LIGHT_BUDGET + in.n[b] / HEAVY_MIN + 1
                          : 0;
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(items, SB_PREP_GRID));
+    const int64_t grid = std::max<int64_t>(
+        1, std::min<int64_t>((items + UPD_THREADS / 64 - 1) / (UPD_THREADS / 64), SB_PREP_GRID));
     hipLaunchKernelGGL(k_sb_prep, dim3((unsigned)grid), dim3(UPD_THREADS), 0, s, st, base, sb,
                        in);
     return hipGetLastError();
@@ -3030,12 +3115,11 @@ hipError_t launch_sb_prep(State st, Scratch base, SbBufs sb, const SbBatches &in
 
 hipError_t launch_sb_apply(State st, Scratch base, SbBufs sb, const SbBatches &in, int32_t seq,
                            hipStream_t s) {
-    int64_t tuples = 0;
-    for (int b = 0; b < in.K; ++b) tuples += in.n[b];
-    const int64_t ranges = (2 * tuples + APPLY_BUDGET - 1) / APPLY_BUDGET + 1;
-    const int64_t grid = std::max<int64_t>(in.K, std::min<int64_t>(ranges, SB_APPLY_GRID));
-    hipLaunchKernelGGL(k_sb_apply, dim3((unsigned)grid), dim3(APPLY_THREADS), 0, s, st, base,
-                       sb, in, seq);
+    static_assert(SB_APPLY_GRID >= SB_K, "a workgroup per batch clears a rejected batch");
+    static_assert((int64_t)SB_APPLY_GRID * (APPLY_THREADS / 64) * 4 >= PASS_LOCAL_G,
+                  "four groups per wave at most");
+    hipLaunchKernelGGL(k_sb_apply, dim3(SB_APPLY_GRID), dim3(APPLY_THREADS), 0, s, st, base, sb,
+                       in, seq);
     return hipGetLastError();
 }
 

@@ -169,7 +169,8 @@ void free_sb(SbBufs &b) {
     dfree(b.tot);
     dfree(b.so);
     dfree(b.gsb);
-    dfree(b.astart);
+    dfree(b.big);
+    dfree(b.gbig);
     dfree(b.xs);
     dfree(b.ntot);
     dfree(b.tb);
@@ -189,7 +190,8 @@ int alloc_sb(SbBufs &b, int64_t G) {
     if (rc == CQ_OK) rc = dalloc(&b.tot, SB_K);
     if (rc == CQ_OK) rc = dalloc(&b.so, SB_K * G);
     if (rc == CQ_OK) rc = dalloc(&b.gsb, G + 1);
-    if (rc == CQ_OK) rc = dalloc(&b.astart, sb_apply_max() + 1);
+    if (rc == CQ_OK) rc = dalloc(&b.big, G);
+    if (rc == CQ_OK) rc = dalloc(&b.gbig, G);
     if (rc == CQ_OK) rc = dalloc(&b.xs, SB_K * (int64_t)SUB);
     if (rc == CQ_OK) rc = dalloc(&b.ntot, 2);
     if (rc == CQ_OK) rc = dalloc(&b.tb, SB_K * G);
