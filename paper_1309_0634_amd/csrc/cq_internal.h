@@ -172,14 +172,24 @@ struct Out {
 // every batch's window sums are differences of prefix sums.
 constexpr int SB_K = 8;
 // histogram blocks of the several-batch path count SBH_KPT keys per thread
-// (four single-batch tiles) of one batch: a quarter of the flush atomics
+// of one batch and store every group's count (16 bits) of their tile; the
+// plan sums a group's tiles
 constexpr int SBH_KPT = 4 * HIST_KPT;
 constexpr int SBH_TILE = HIST_THREADS * SBH_KPT;
-// plan: one group per thread in blocks of SBP_THREADS; per block SBP_F field
-// sums and two (count << 32 | group) words
-constexpr int SBP_THREADS = 1024;
+constexpr int SBH_TILES = (SUB + SBH_TILE - 1) / SBH_TILE;  // per batch at most
+static_assert(SBH_TILE < 65536, "a tile's count of a group fits 16 bits");
+// plan: one group per thread in blocks of SBP_THREADS; per block of the first
+// launch SBP_F field sums and two (count << 32 | group) words
+constexpr int SBP_THREADS = 256;
 constexpr int SBP_F = 2 * SB_K + 2;
 constexpr int SBP_PART = SBP_F + 4;
+// the plan's first launch: blocks of SBS_GROUPS groups
+constexpr int SBS_GROUPS = 64;
+constexpr int SBS_THREADS = SB_K * SBS_GROUPS / 2;
+constexpr int SBS_BLOCKS_MAX = (PASS_LOCAL_G + SBS_GROUPS - 1) / SBS_GROUPS;
+static_assert(SBS_BLOCKS_MAX % 64 == 0, "the plan's lanes stride over whole rows of blocks");
+static_assert(SBP_THREADS % SBS_GROUPS == 0, "a plan block covers whole sums blocks");
+static_assert(SBP_PART % 2 == 0, "the top-two words of a block's partials are 8-byte aligned");
 // apply: a group whose survivors plus old window values read exceed
 // APPLY_BUDGET is summed by a whole workgroup, every other one by one wave
 constexpr int APPLY_BUDGET = 2048;
@@ -193,8 +203,9 @@ constexpr int SB_APPLY_GRID = 1024;
 
 // Buffers of the several-batch path, one slice per batch where marked.
 struct SbBufs {
-    int32_t *kh;        // [G][SB_K] per-batch histograms, a group's counts together;
-                        // zero between uses
+    uint32_t *kt;       // [SB_K][SBH_TILES][(G + 1) / 2] per histogram tile, groups
+                        // 2i and 2i + 1 in the low and high 16 bits of word i
+    int32_t *kh;        // [G][SB_K] per-batch histograms, a group's counts together
     int32_t *sbad;      // [SB_K] sequence number of the last call whose batch b had a bad key
     int32_t *bucket;    // [SB_K][G]
     int32_t *lpre;      // [SB_K][G + 1]

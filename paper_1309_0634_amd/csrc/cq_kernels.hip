@@ -239,14 +239,15 @@ __device__ void plan_publish(const State &st, const Scratch &sc, const int (&tot
 // Histogram tile `tile` (of `ntiles` counted into the same counters) of
 // HIST_THREADS * KPT consecutive tuples of keys[0, n), one block of
 // HIST_THREADS threads (every thread's KPT keys loaded together), LDS
-// counters indexed by key (`cntr`, G of them), added to kout[g * kstride]; a
-// bad key stores `seq` in *badout.
+// counters indexed by key (`cntr`, G of them), added to kout[g * kstride],
+// or, with `dense`, every group's count stored there (16 bits, two groups a
+// word); a bad key stores `seq` in *badout.
 template <int KPT>
 __device__ __forceinline__ void hist_small_tile(const int32_t *__restrict__ keys, int64_t n,
                                                 bool vec, int32_t G, const Scratch &sc,
                                                 int32_t seq, int tile, int ntiles,
                                                 int32_t *kout, int kstride, int32_t *badout,
-                                                int32_t *cntr) {
+                                                int32_t *cntr, uint32_t *dense = nullptr) {
     static_assert(KPT % 4 == 0, "keys loaded four at a time");
     const int tid = threadIdx.x;
     phase_mark(sc, PHASE_HIST_PLAN, 0);
@@ -296,6 +297,15 @@ __device__ __forceinline__ void hist_small_tile(const int32_t *__restrict__ keys
         if (tid == 0) atomicExch(badout, seq);
     }
     phase_mark(sc, PHASE_HIST_PLAN, 1);
+    if (dense) {
+        for (int i = tid; 2 * i < G; i += HIST_THREADS) {
+            const uint32_t lo = (uint32_t)cntr[2 * i];
+            const uint32_t hi = 2 * i + 1 < G ? (uint32_t)cntr[2 * i + 1] : 0u;
+            dense[i] = lo | hi << 16;
+        }
+        phase_mark(sc, PHASE_HIST_PLAN, 2);
+        return;
+    }
     // blocks start their flush at evenly spread groups, so that they do not
     // all hit the same counters at the same time
     const int off = (int)(((int64_t)tile * G / ntiles) & ~63);
@@ -1904,9 +1914,10 @@ __global__ __launch_bounds__(HIST_THREADS) void k_sb_hist(Scratch base, SbBufs s
     extern __shared__ int32_t cntr[];
     const int t = (int)blockIdx.x;
     const int b = sb_batch_of(in.htile0, in.K, t);
-    hist_small_tile<SBH_KPT>(in.keys[b], in.n[b], (in.vec >> b) & 1u, G, base, seq,
-                             t - in.htile0[b], in.htile0[b + 1] - in.htile0[b], sb.kh + b, SB_K,
-                             sb.sbad + b, cntr);
+    const int tile = t - in.htile0[b];
+    hist_small_tile<SBH_KPT>(in.keys[b], in.n[b], (in.vec >> b) & 1u, G, base, seq, tile,
+                             in.htile0[b + 1] - in.htile0[b], nullptr, 0, sb.sbad + b, cntr,
+                             sb.kt + ((int64_t)b * SBH_TILES + tile) * ((G + 1) / 2));
 }
 
 // The plan of every batch and the survivors' places, one group per thread.
@@ -1975,44 +1986,74 @@ __device__ __forceinline__ void sb_load_groups(const SbBufs &sb, const State &st
     }
 }
 
-// Plan, first launch: each block's sums of the fields over its groups (one
-// per thread), and its two most frequent groups.
-__global__ __launch_bounds__(SBP_THREADS) void k_sb_sums(State st, Scratch base, SbBufs sb,
+// Plan, first launch: per block of SBS_GROUPS groups, every group's count per
+// batch (its histogram tiles summed: thread (pair, batch) sums the tiles of
+// two groups of one batch, all its loads in flight together), stored for
+// the later steps; then the block's sums of the fields over its groups and
+// its two most frequent groups (wave 0, one group per lane).
+__global__ __launch_bounds__(SBS_THREADS) void k_sb_sums(State st, Scratch base, SbBufs sb,
                                                          SbBatches in, int32_t seq) {
-    constexpr int NW = SBP_THREADS / 64;
-    __shared__ int wsum[NW][SBP_F];
-    __shared__ unsigned long long red_top[2 * NW];
-    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+    static_assert(SBS_GROUPS == 64 && SBS_THREADS == SB_K * SBS_GROUPS / 2,
+                  "a thread per (pair of groups, batch); a lane per group after");
+    __shared__ int32_t kc[SB_K][SBS_GROUPS];
+    const int tid = threadIdx.x, lane = lane_id();
     const int K = in.K;
+    const int G = (int)st.G;
     const int32_t W = st.W;
-    const int g = (int)blockIdx.x * SBP_THREADS + tid;
+    const int g0 = (int)blockIdx.x * SBS_GROUPS;
     phase_mark(base, PHASE_HIST_PLAN, 3);
+    {
+        const int pair = tid % (SBS_GROUPS / 2), b = tid / (SBS_GROUPS / 2);
+        int nt = 0;
+#pragma unroll
+        for (int bb = 0; bb < SB_K; ++bb)
+            if (b == bb && bb < K) nt = in.htile0[bb + 1] - in.htile0[bb];
+        const int64_t row = (G + 1) / 2;
+        const int64_t wi = min((int64_t)g0 / 2 + pair, row - 1);
+        const uint32_t *p = sb.kt + (int64_t)b * SBH_TILES * row + wi;
+        uint32_t w[SBH_TILES];
+#pragma unroll
+        for (int t = 0; t < SBH_TILES; ++t) w[t] = p[(int64_t)min(t, max(nt - 1, 0)) * row];
+        int32_t lo = 0, hi = 0;
+#pragma unroll
+        for (int t = 0; t < SBH_TILES; ++t)
+            if (t < nt) {
+                lo += (int32_t)(w[t] & 0xffffu);
+                hi += (int32_t)(w[t] >> 16);
+            }
+        kc[b][2 * pair] = lo;
+        kc[b][2 * pair + 1] = hi;
+    }
+    __syncthreads();
+    if (tid >= 64) return;
+    const int g = g0 + tid;
     bool valid[SB_K];
 #pragma unroll
     for (int b = 0; b < SB_K; ++b) valid[b] = b < K && sb.sbad[b] != seq;
-    SbGroup own[1];
-    sb_load_groups<1>(sb, st, valid, K, g, 0, (int)st.G, own);
+    SbGroup own;
+#pragma unroll
+    for (int b = 0; b < SB_K; ++b) own.k[b] = (g < G && valid[b]) ? kc[b][tid] : 0;
+    own.cnt0 = g < G ? st.cnt[g] : 0;
+    if (g < G) {
+        int4 *kp = reinterpret_cast<int4 *>(sb.kh + (int64_t)g * SB_K);
+        kp[0] = make_int4(kc[0][tid], kc[1][tid], kc[2][tid], kc[3][tid]);
+        kp[1] = make_int4(kc[4][tid], kc[5][tid], kc[6][tid], kc[7][tid]);
+    }
     int x[SBP_F];
     int32_t kg;
-    sb_fields(own[0], K, W, x, kg);
+    sb_fields(own, K, W, x, kg);
+    int32_t *part = sb.part + (int64_t)blockIdx.x * SBP_PART;
 #pragma unroll
     for (int f = 0; f < SBP_F; ++f) {
         const int t = wave_total(wave_incl_add(x[f]));
-        if (lane == 0) wsum[wv][f] = t;
+        if (lane == 0) part[f] = t;
     }
     Top2 top;
     if (kg > 0) top.add(((unsigned long long)(uint32_t)kg << 32) | (uint32_t)g);
-    top2_block(top, red_top, NW);  // (its barriers also order wsum)
-    if (tid < SBP_F) {
-        int t = 0;
-        for (int w = 0; w < NW; ++w) t += wsum[w][tid];
-        sb.part[(int64_t)blockIdx.x * SBP_PART + tid] = t;
-    }
-    if (tid == 0) {
-        reinterpret_cast<unsigned long long *>(sb.part + (int64_t)blockIdx.x * SBP_PART +
-                                               SBP_F)[0] = top.a;
-        reinterpret_cast<unsigned long long *>(sb.part + (int64_t)blockIdx.x * SBP_PART +
-                                               SBP_F)[1] = top.b;
+    top2_wave(top);
+    if (lane == 0) {
+        reinterpret_cast<unsigned long long *>(part + SBP_F)[0] = top.a;
+        reinterpret_cast<unsigned long long *>(part + SBP_F)[1] = top.b;
     }
     phase_mark(base, PHASE_HIST_PLAN, 4);
 }
@@ -2027,11 +2068,13 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
     __shared__ int wbase[NW][SBP_F];  // exclusive field values at each wave's first group
     __shared__ int ftot[SBP_F];       // field totals over all groups
     __shared__ int bpre[SBP_F];       // field sums of the blocks before this one
+    __shared__ __align__(8) int32_t parts[SBS_BLOCKS_MAX * SBP_PART];  // every sums block's
     const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
     const int K = in.K;
     const int G = (int)st.G;
     const int32_t W = st.W;
-    const int nblk = (int)gridDim.x;
+    const int nblk = (G + SBS_GROUPS - 1) / SBS_GROUPS;  // sums blocks
+    const int kfirst = (int)blockIdx.x * (SBP_THREADS / SBS_GROUPS);  // this block's first
     const int gb = (int)blockIdx.x * SBP_THREADS, g = gb + tid;
     phase_mark(base, PHASE_HIST_PLAN, 5);
     bool valid[SB_K];
@@ -2039,15 +2082,34 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
     for (int b = 0; b < SB_K; ++b) valid[b] = b < K && sb.sbad[b] != seq;
     SbGroup own[1];
     sb_load_groups<1>(sb, st, valid, K, g, 0, G, own);
-    if (tid < SBP_F) {  // thread f: field f summed over the blocks before and all blocks
+    {  // every block's partials, loaded together
+        constexpr int PER = (SBS_BLOCKS_MAX * SBP_PART + SBP_THREADS - 1) / SBP_THREADS;
+        const int np = nblk * SBP_PART;
+        int32_t v[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) v[j] = sb.part[min(tid + j * SBP_THREADS, np - 1)];
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            if (tid + j * SBP_THREADS < np) parts[tid + j * SBP_THREADS] = v[j];
+    }
+    __syncthreads();
+    // field f summed over the sums blocks before this block and over all,
+    // by wave f mod NW, its lanes striding over the blocks
+    for (int f = wv; f < SBP_F; f += NW) {
         int p = 0, t = 0;
-        for (int k = 0; k < nblk; ++k) {
-            const int v = sb.part[(int64_t)k * SBP_PART + tid];
-            p += k < (int)blockIdx.x ? v : 0;
+#pragma unroll
+        for (int j = 0; j < SBS_BLOCKS_MAX / 64; ++j) {
+            const int k = lane + 64 * j;
+            const int v = k < nblk ? parts[k * SBP_PART + f] : 0;
+            p += k < kfirst ? v : 0;
             t += v;
         }
-        bpre[tid] = p;
-        ftot[tid] = t;
+        p = wave_total(wave_incl_add(p));
+        t = wave_total(wave_incl_add(t));
+        if (lane == 0) {
+            bpre[f] = p;
+            ftot[f] = t;
+        }
     }
     int wex[SBP_F];
     int32_t own_big;
@@ -2139,16 +2201,23 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
             sb.ntot[0] = tot(2 * SB_K + 1);
             sb.ntot[1] = tot(2 * SB_K);
         }
-        if (tid == SB_K + 1) {  // the call's two most frequent groups, for the next histogram
+        if (wv == NW - 1) {  // the call's two most frequent groups, for the next histogram
             Top2 top;
-            for (int k = 0; k < nblk; ++k) {
-                const unsigned long long *p = reinterpret_cast<const unsigned long long *>(
-                    sb.part + (int64_t)k * SBP_PART + SBP_F);
-                top.add(p[0]);
-                top.add(p[1]);
+#pragma unroll
+            for (int j = 0; j < SBS_BLOCKS_MAX / 64; ++j) {
+                const int k = lane + 64 * j;
+                if (k < nblk) {
+                    const unsigned long long *p = reinterpret_cast<const unsigned long long *>(
+                        parts + k * SBP_PART + SBP_F);
+                    top.add(p[0]);
+                    top.add(p[1]);
+                }
             }
-            base.hot[0] = top.a ? (int32_t)(uint32_t)top.a : -1;
-            base.hot[1] = top.b ? (int32_t)(uint32_t)top.b : -1;
+            top2_wave(top);
+            if (lane == 0) {
+                base.hot[0] = top.a ? (int32_t)(uint32_t)top.a : -1;
+                base.hot[1] = top.b ? (int32_t)(uint32_t)top.b : -1;
+            }
         }
     }
     phase_mark(base, PHASE_HIST_PLAN, 7);
@@ -2159,12 +2228,24 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
 // reordered in LDS, the keys and values of tile t + 2 are on their way and
 // the buckets of tile t + 1 are being gathered, so each tile waits only on
 // its own LDS work.
+// A reorder workgroup's tiles: batch, tile index inside it, its tuples and
+// arrays (looked up once, not per prefetch).
+struct SbTile {
+    const int32_t *keys, *values;
+    int64_t n;
+    int32_t b, tile;
+};
+constexpr int SB_PASS_PER = 8;  // tiles per reorder workgroup at most
+static_assert(SB_K * PASS_TILES_MAX <= SB_PASS_PER * SB_PASS_GRID,
+              "every workgroup's tiles fit its table");
+
 __global__ __launch_bounds__(PASS_THREADS) void k_sb_pass(State st, Scratch base, SbBufs sb,
                                                           SbBatches in, int32_t seq) {
     __shared__ __align__(16) char pool[P_BYTES];
     __shared__ int32_t ts[NB_MAX + 1];
     __shared__ int red[PASS_WAVES];
     __shared__ __align__(16) uint16_t gbk[PASS_LOCAL_G];  // leader tables
+    __shared__ SbTile tl[SB_PASS_PER];
     constexpr int R = PASS_ROUNDS;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const int K = in.K;
@@ -2173,26 +2254,32 @@ __global__ __launch_bounds__(PASS_THREADS) void k_sb_pass(State st, Scratch base
     const int per = (T + (int)gridDim.x - 1) / (int)gridDim.x;
     const int t_begin = (int)blockIdx.x * per, t_end = min(T, t_begin + per);
     if (t_begin >= t_end) return;
+    if (tid < t_end - t_begin) {
+        const int t = t_begin + tid;
+        SbTile x = {nullptr, nullptr, 0, 0, 0};
+#pragma unroll
+        for (int b = 0; b < SB_K; ++b)
+            if (b < K && in.ptile0[b] <= t && t < in.ptile0[b + 1])
+                x = {in.keys[b], in.values[b], in.n[b], b, t - in.ptile0[b]};
+        tl[tid] = x;
+    }
+    __syncthreads();
     // position of this thread's round r inside a tile
     auto pos = [&](int r) { return wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane; };
-    auto load_kv = [&](int t, int32_t (&k)[R], int32_t (&v)[R]) {
-        const int b = sb_batch_of(in.ptile0, K, t);
-        const int64_t n = in.n[b];
-        const int64_t tb = (int64_t)(t - in.ptile0[b]) * PASS_TILE;
-        const int32_t *kp = in.keys[b], *vp = in.values[b];
+    auto load_kv = [&](const SbTile &x, int32_t (&k)[R], int32_t (&v)[R]) {
+        const int64_t tb = (int64_t)x.tile * PASS_TILE;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int64_t i = min(tb + pos(r), n - 1);
-            k[r] = kp[i];
-            v[r] = vp[i];
+            const int64_t i = min(tb + pos(r), x.n - 1);
+            k[r] = x.keys[i];
+            v[r] = x.values[i];
         }
     };
-    // tile t's group views and buckets: loads issued here and first used in
+    // a tile's group views and buckets: loads issued here and first used in
     // the next iteration (positions past the batch are masked there), so
     // that they stay in flight meanwhile
-    auto gather = [&](int t, int32_t (&k)[R], int32_t (&bk)[R]) {
-        const int b = sb_batch_of(in.ptile0, K, t);
-        const int32_t *bucket = sb.bucket + (int64_t)b * G;
+    auto gather = [&](const SbTile &x, int32_t (&k)[R], int32_t (&bk)[R]) {
+        const int32_t *bucket = sb.bucket + (int64_t)x.b * G;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             k[r] = view_key(k[r], base.kmod, G);
@@ -2201,6 +2288,7 @@ __global__ __launch_bounds__(PASS_THREADS) void k_sb_pass(State st, Scratch base
             bk[r] = bucket[kc];
         }
     };
+    auto tile_of = [&](int t) { return tl[min(t, t_end - 1) - t_begin]; };
     int32_t kA[R], vA[R], bA[R], kB[R], vB[R], bB[R], kC[R], vC[R], lr[R];
     // Tile t's keys, values, buckets and plan totals are in registers when
     // its iteration starts.  During it, tile t + 2's keys and values and tile
@@ -2209,19 +2297,35 @@ __global__ __launch_bounds__(PASS_THREADS) void k_sb_pass(State st, Scratch base
     // an iteration has stores or younger loads in front of it.  (Past the
     // run the last tile is loaded again and not used: every load stays
     // unconditional.)
-    load_kv(t_begin, kA, vA);
-    load_kv(min(t_begin + 1, t_end - 1), kB, vB);
-    gather(t_begin, kA, bA);
-    PlanTotals tA = sb.tot[sb_batch_of(in.ptile0, K, t_begin)];
+    {
+        const SbTile x0 = tile_of(t_begin);
+        load_kv(x0, kA, vA);
+        load_kv(tile_of(t_begin + 1), kB, vB);
+        gather(x0, kA, bA);
+    }
+    PlanTotals tA = sb.tot[tile_of(t_begin).b];
+    // (waited for here, so that no load of this prologue is still counted
+    // where the loop's first tile starts: the top of every iteration then
+    // waits on nothing, not even the previous tile's stores)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        keep(kA[r]);
+        keep(vA[r]);
+        keep(bA[r]);
+        keep(kB[r]);
+        keep(vB[r]);
+    }
+    keep(tA.status);
+    keep(tA.n_buckets);
     for (int t = t_begin; t < t_end; ++t) {
         phase_mark(base, PHASE_PASS, 0);
-        const int tn = min(t + 1, t_end - 1);
-        load_kv(min(t + 2, t_end - 1), kC, vC);
-        gather(tn, kB, bB);
-        PlanTotals tB = sb.tot[sb_batch_of(in.ptile0, K, tn)];
-        const int b = sb_batch_of(in.ptile0, K, t);
-        const int64_t tb = (int64_t)(t - in.ptile0[b]) * PASS_TILE;
-        const int tile_n = (int)min((int64_t)PASS_TILE, in.n[b] - tb);
+        const SbTile x = tile_of(t), x1 = tile_of(t + 1), x2 = tile_of(t + 2);
+        load_kv(x2, kC, vC);
+        gather(x1, kB, bB);
+        PlanTotals tB = sb.tot[x1.b];
+        const int b = x.b;
+        const int64_t tb = (int64_t)x.tile * PASS_TILE;
+        const int tile_n = (int)min((int64_t)PASS_TILE, x.n - tb);
         auto arrive = [&]() {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -2236,12 +2340,12 @@ __global__ __launch_bounds__(PASS_THREADS) void k_sb_pass(State st, Scratch base
         if (!tA.status && nA <= LEAD) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                bA[r] = tb + pos(r) < in.n[b] ? bA[r] : nA;
+                bA[r] = tb + pos(r) < x.n ? bA[r] : nA;
                 lr[r] = 0;
             }
             const Scratch sc = sb_set(sb, base, b, G);
-            pass_split(kA, vA, bA, lr, nA, tb, tile_n, t - in.ptile0[b], sc, pool, ts, red, gbk,
-                       [] {}, arrive);
+            pass_split(kA, vA, bA, lr, nA, tb, tile_n, x.tile, sc, pool, ts, red, gbk, [] {},
+                       arrive);
         } else {
             if (!tA.status && tid == 0) atomicOr(base.fault, FAULT_BUCKETS);  // (no plan makes
             arrive();                                                          // this many)
@@ -2600,7 +2704,7 @@ __device__ __forceinline__ LaneBatch lane_batch(const ApplyGroup &q, int bl, int
 
 // Batch bl's result of group g (s: its window's sum without the part from
 // before the call) by the calling lane, and, by the lane of the group's last
-// batch, its final state and its counters cleared.  Returns the window sum.
+// batch, its final state.
 __device__ __forceinline__ void apply_emit_lane(const State &st, const SbBufs &sb,
                                                 const Out *outs, const ApplyGroup &q, int g,
                                                 const LaneBatch &lb, int bl, long long s) {
@@ -2615,11 +2719,6 @@ __device__ __forceinline__ void apply_emit_lane(const State &st, const SbBufs &s
         st.sum[g] = s;
         st.pos[g] = (int32_t)(((uint32_t)q.pos0 + (uint32_t)q.kg) % (uint32_t)W);
         st.cnt[g] = (int32_t)min((int64_t)W, (int64_t)q.cnt0 + q.kg);
-        // the group's counters, rejected batches' included, start the next
-        // call clear
-        int4 *kp = reinterpret_cast<int4 *>(sb.kh + (int64_t)g * SB_K);
-        kp[0] = make_int4(0, 0, 0, 0);
-        kp[1] = make_int4(0, 0, 0, 0);
     }
 }
 
@@ -2860,11 +2959,6 @@ __global__ __launch_bounds__(APPLY_THREADS) void k_sb_apply(State st, Scratch ba
     bool valid[SB_K];
 #pragma unroll
     for (int b = 0; b < SB_K; ++b) valid[b] = b < K && sb.sbad[b] != seq;
-    // a rejected batch's counters of groups no other batch touched are
-    // cleared here (those of touched groups are cleared with the group)
-    if ((int)blockIdx.x < K && !valid[blockIdx.x])
-        for (int g = threadIdx.x; g < G; g += APPLY_THREADS)
-            sb.kh[(int64_t)g * SB_K + blockIdx.x] = 0;
     phase_mark(base, PHASE_SB_APPLY, 0);
     // the groups over APPLY_BUDGET first, by whole workgroups
     const int nbig = sb.ntot[0];
@@ -3078,11 +3172,12 @@ hipError_t launch_sb_hist(State st, Scratch base, SbBufs sb, const SbBatches &in
 
 hipError_t launch_sb_plan(State st, Scratch base, SbBufs sb, const SbBatches &in, int32_t seq,
                           hipStream_t s) {
-    const int64_t grid = (st.G + SBP_THREADS - 1) / SBP_THREADS;
-    hipLaunchKernelGGL(k_sb_sums, dim3((unsigned)grid), dim3(SBP_THREADS), 0, s, st, base, sb,
-                       in, seq);
-    hipLaunchKernelGGL(k_sb_plan, dim3((unsigned)grid), dim3(SBP_THREADS), 0, s, st, base, sb,
-                       in, seq);
+    const int64_t gs = (st.G + SBS_GROUPS - 1) / SBS_GROUPS;
+    const int64_t gp = (st.G + SBP_THREADS - 1) / SBP_THREADS;
+    hipLaunchKernelGGL(k_sb_sums, dim3((unsigned)gs), dim3(SBS_THREADS), 0, s, st, base, sb, in,
+                       seq);
+    hipLaunchKernelGGL(k_sb_plan, dim3((unsigned)gp), dim3(SBP_THREADS), 0, s, st, base, sb, in,
+                       seq);
     return hipGetLastError();
 }
 
@@ -3115,7 +3210,6 @@ hipError_t launch_sb_prep(State st, Scratch base, SbBufs sb, const SbBatches &in
 
 hipError_t launch_sb_apply(State st, Scratch base, SbBufs sb, const SbBatches &in, int32_t seq,
                            hipStream_t s) {
-    static_assert(SB_APPLY_GRID >= SB_K, "a workgroup per batch clears a rejected batch");
     static_assert((int64_t)SB_APPLY_GRID * (APPLY_THREADS / 64) * 4 >= PASS_LOCAL_G,
                   "four groups per wave at most");
     hipLaunchKernelGGL(k_sb_apply, dim3(SB_APPLY_GRID), dim3(APPLY_THREADS), 0, s, st, base, sb,

@@ -157,6 +157,7 @@ int alloc_set(Scratch &b, int64_t G) {
 
 // Buffers of the several-batch path.
 void free_sb(SbBufs &b) {
+    dfree(b.kt);
     dfree(b.kh);
     dfree(b.sbad);
     dfree(b.bucket);
@@ -179,6 +180,7 @@ void free_sb(SbBufs &b) {
 
 int alloc_sb(SbBufs &b, int64_t G) {
     int rc = dalloc(&b.kh, G * SB_K);
+    if (rc == CQ_OK) rc = dalloc(&b.kt, (int64_t)SB_K * SBH_TILES * ((G + 1) / 2));
     if (rc == CQ_OK) rc = dalloc(&b.sbad, SB_K);
     if (rc == CQ_OK) rc = dalloc(&b.bucket, SB_K * G);
     if (rc == CQ_OK) rc = dalloc(&b.lpre, SB_K * (G + 1));
@@ -195,7 +197,7 @@ int alloc_sb(SbBufs &b, int64_t G) {
     if (rc == CQ_OK) rc = dalloc(&b.xs, SB_K * (int64_t)SUB);
     if (rc == CQ_OK) rc = dalloc(&b.ntot, 2);
     if (rc == CQ_OK) rc = dalloc(&b.tb, SB_K * G);
-    if (rc == CQ_OK) rc = dalloc(&b.part, (G + SBP_THREADS - 1) / SBP_THREADS * SBP_PART);
+    if (rc == CQ_OK) rc = dalloc(&b.part, (G + SBS_GROUPS - 1) / SBS_GROUPS * SBP_PART);
     if (rc != CQ_OK) return rc;
     hipError_t e = hipMemset(b.kh, 0, sizeof(int32_t) * (size_t)(G * SB_K));
     if (e == hipSuccess) e = hipMemset(b.sbad, 0, sizeof(int32_t) * SB_K);
