@@ -171,6 +171,16 @@ struct Out {
 // consecutive places per group (batch by batch, arrival order), so that
 // every batch's window sums are differences of prefix sums.
 constexpr int SB_K = 8;
+// The several-batch path's buckets: a group with at least SB_HEAVY_MIN
+// tuples of a batch is heavy, the others are packed into buckets of about
+// SB_LIGHT_BUDGET tuples (fewer than SB_LIGHT_CAP).  Fewer, larger buckets
+// than the single-batch path's: the reorder's per-wave counters then leave
+// room for two workgroups per CU.
+constexpr int SB_LIGHT_BUDGET = 1024;
+constexpr int SB_HEAVY_MIN = 1024;
+constexpr int SB_LIGHT_CAP = SB_LIGHT_BUDGET + SB_HEAVY_MIN;
+constexpr int SB_NB_MAX = SUB / SB_LIGHT_BUDGET + SUB / SB_HEAVY_MIN + 2;
+static_assert(SB_NB_MAX <= NB_MAX, "the bucket tables are sized for the single-batch bound");
 // histogram blocks of the several-batch path count SBH_KPT keys per thread
 // of one batch and store every group's count (16 bits) of their tile; the
 // plan sums a group's tiles
@@ -194,11 +204,11 @@ static_assert(SBP_PART % 2 == 0, "the top-two words of a block's partials are 8-
 // APPLY_BUDGET is summed by a whole workgroup, every other one by one wave
 constexpr int APPLY_BUDGET = 2048;
 constexpr int APPLY_THREADS = 256;
-// Workgroups of the survivor and apply launches, which loop over their
-// items: as many as the device runs at once (256 CUs; four and two per CU
-// fit their registers and LDS).
+// Workgroups of the reorder, survivor and apply launches, which loop over
+// their items: as many as the device runs at once (256 CUs; two, four and
+// four per CU fit their registers and LDS).
 constexpr int SB_PREP_GRID = 1024;
-constexpr int SB_PASS_GRID = 256;
+constexpr int SB_PASS_GRID = 512;
 constexpr int SB_APPLY_GRID = 1024;
 
 // Buffers of the several-batch path, one slice per batch where marked.

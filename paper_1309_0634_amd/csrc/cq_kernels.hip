@@ -865,17 +865,17 @@ __device__ void pass_owned_writes(const State &st, const Scratch &sc, const int4
 // bucket starts.  `after_clear` runs after the first barrier,
 // `before_stores` before the first global store.  The LDS arrays are the
 // caller's.
-template <typename F, typename H>
+template <int NBM, int LEADB, typename F, typename H>
 __device__ __forceinline__ void pass_split(const int32_t (&key)[PASS_ROUNDS],
                                            const int32_t (&val)[PASS_ROUNDS],
                                            const int32_t (&bk)[PASS_ROUNDS],
                                            int32_t (&lr)[PASS_ROUNDS], int NB, int64_t base,
-                                           int tile_n, int tile, const Scratch &sc, char *pool,
-                                           int32_t *ts, int *red, uint16_t *gbk,
-                                           F &&after_clear, H &&before_stores) {
+                                           int tile_n, int tile, const Scratch &sc,
+                                           uint16_t *wcp, int2 *stage, int32_t *ts, int *red,
+                                           uint8_t *leadp, F &&after_clear, H &&before_stores) {
+    static_assert(NBM % 2 == 0, "per-wave counter rows are cleared as 32-bit pairs");
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-    uint16_t (*wc)[NB_MAX] = reinterpret_cast<uint16_t (*)[NB_MAX]>(pool + P_WC);
-    int2 *stage = reinterpret_cast<int2 *>(pool + P_STAGE);
+    uint16_t (*wc)[NBM] = reinterpret_cast<uint16_t (*)[NBM]>(wcp);
     // clear the per-wave counters two at a time, row by row (no division by
     // NB; a row may be cleared one entry past NB, which NB_MAX leaves room for)
     for (int p = tid; 2 * p < NB; p += PASS_THREADS)
@@ -891,7 +891,7 @@ __device__ __forceinline__ void pass_split(const int32_t (&key)[PASS_ROUNDS],
     // on the entry by design, and a plain read could be folded into the
     // lane's own write).  Matching that 6-bit id takes 6 ballots instead of
     // one per bit of the bucket id.
-    uint8_t *lead = reinterpret_cast<uint8_t *>(gbk) + wave * LEAD;
+    uint8_t *lead = leadp + wave * LEADB;
 #pragma unroll
     for (int r = 0; r < PASS_ROUNDS; ++r) {
         const int b = bk[r];
@@ -962,7 +962,7 @@ __device__ __forceinline__ void pass_split(const int32_t (&key)[PASS_ROUNDS],
     if ((tile_n & 1) && tid == 0) dst[tile_n - 1] = stage[tile_n - 1];
     int32_t *row = sc.rowstart + (int64_t)tile * (NB + 1);
 #pragma unroll
-    for (int j = 0; j < (NB_MAX + PASS_THREADS) / PASS_THREADS; ++j) {
+    for (int j = 0; j < (NBM + PASS_THREADS) / PASS_THREADS; ++j) {
         const int b = tid + j * PASS_THREADS;
         if (b <= NB) row[b] = ts[b];
     }
@@ -1037,8 +1037,9 @@ __device__ __forceinline__ void pass_tile(const int32_t *__restrict__ keys,
             lr[r] = 0;
         }
     }
-    pass_split(
-        key, val, bk, lr, NB, base, tile_n, tile, sc, pool, ts, red, gbk,
+    pass_split<NB_MAX, LEAD>(
+        key, val, bk, lr, NB, base, tile_n, tile, sc, reinterpret_cast<uint16_t *>(pool + P_WC),
+        reinterpret_cast<int2 *>(pool + P_STAGE), ts, red, reinterpret_cast<uint8_t *>(gbk),
         [&]() {
             // the plan's per-group writes (fields in the staging area, which
             // is written only after two more barriers)
@@ -1926,7 +1927,7 @@ __global__ __launch_bounds__(HIST_THREADS) void k_sb_hist(Scratch base, SbBufs s
 // another.  Fields per batch: light tuples, and heavy groups | touched
 // groups << 12; then survivors per group, and 1 for a group whose
 // survivors plus old values read exceed APPLY_BUDGET.
-static_assert(SUB / HEAVY_MIN < (1 << 12) && (int64_t)PASS_LOCAL_G << 12 < (1LL << 31),
+static_assert(SUB / SB_HEAVY_MIN < (1 << 12) && (int64_t)PASS_LOCAL_G << 12 < (1LL << 31),
               "heavy groups of a batch fit 12 bits, touched groups the rest of an int");
 
 struct SbGroup {
@@ -1941,7 +1942,7 @@ __device__ __forceinline__ void sb_fields(const SbGroup &q, int K, int32_t W, in
 #pragma unroll
     for (int b = 0; b < SB_K; ++b) {
         const int32_t k = b < K ? q.k[b] : 0;
-        const bool heavy = k >= HEAVY_MIN;
+        const bool heavy = k >= SB_HEAVY_MIN;
         x[2 * b] = (k > 0 && !heavy) ? k : 0;
         x[2 * b + 1] = (heavy ? 1 : 0) | (k > 0 ? 1 << 12 : 0);
         m += min(k, W);
@@ -2146,19 +2147,19 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
             const Scratch sc = sb_set(sb, base, b, G);
             const int32_t k = own[0].k[b];
             const int exl = ex(2 * b), exh = ex(2 * b + 1) & 0xfff, ext = ex(2 * b + 1) >> 12;
-            const int32_t nl = (tot(2 * b) + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
+            const int32_t nl = (tot(2 * b) + SB_LIGHT_BUDGET - 1) / SB_LIGHT_BUDGET;
             sc.lpre[g] = exl;
             sb.so[(int64_t)b * G + g] = ex(2 * SB_K) + m_before;
             if (k > 0) {
                 sc.tidx[g] = ext;
-                if (k >= HEAVY_MIN) {
+                if (k >= SB_HEAVY_MIN) {
                     sc.bucket[g] = nl + exh;
-                    if ((uint32_t)exh < (uint32_t)NB_MAX) sc.hkey[exh] = g;
+                    if ((uint32_t)exh < (uint32_t)SB_NB_MAX) sc.hkey[exh] = g;
                 } else {
-                    sc.bucket[g] = (exl + k - 1) / LIGHT_BUDGET;
-                    const int32_t m = (exl + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
-                    if ((int64_t)m * LIGHT_BUDGET <= (int64_t)exl + k - 1 &&
-                        (uint32_t)m < (uint32_t)NB_MAX)
+                    sc.bucket[g] = (exl + k - 1) / SB_LIGHT_BUDGET;
+                    const int32_t m = (exl + SB_LIGHT_BUDGET - 1) / SB_LIGHT_BUDGET;
+                    if ((int64_t)m * SB_LIGHT_BUDGET <= (int64_t)exl + k - 1 &&
+                        (uint32_t)m < (uint32_t)SB_NB_MAX)
                         sc.bstart[m] = g;
                 }
                 // the last batch's touched list serves cq_results after the call
@@ -2178,7 +2179,7 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
             if (tid != b || b >= K) continue;
             const Scratch sc = sb_set(sb, base, b, G);
             PlanTotals t;
-            const int32_t nl = (tot(2 * b) + LIGHT_BUDGET - 1) / LIGHT_BUDGET;
+            const int32_t nl = (tot(2 * b) + SB_LIGHT_BUDGET - 1) / SB_LIGHT_BUDGET;
             t.n_light_buckets = valid[b] ? nl : 0;
             t.n_heavy = valid[b] ? tot(2 * b + 1) & 0xfff : 0;
             t.light_tuples = valid[b] ? tot(2 * b) : 0;
@@ -2194,7 +2195,7 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
             }
             if (in.out[b].n_touched) *in.out[b].n_touched = t.status ? t.status : t.n_touched;
             if (b == K - 1) *base.tot = t;
-            if (t.n_buckets > NB_MAX) atomicOr(base.fault, FAULT_BUCKETS);
+            if (t.n_buckets > SB_NB_MAX) atomicOr(base.fault, FAULT_BUCKETS);
         }
         if (tid == SB_K) {
             sb.gsb[G] = tot(2 * SB_K);
@@ -2239,12 +2240,20 @@ constexpr int SB_PASS_PER = 8;  // tiles per reorder workgroup at most
 static_assert(SB_K * PASS_TILES_MAX <= SB_PASS_PER * SB_PASS_GRID,
               "every workgroup's tiles fit its table");
 
-__global__ __launch_bounds__(PASS_THREADS) void k_sb_pass(State st, Scratch base, SbBufs sb,
-                                                          SbBatches in, int32_t seq) {
-    __shared__ __align__(16) char pool[P_BYTES];
-    __shared__ int32_t ts[NB_MAX + 1];
+// LDS of a reorder workgroup (bytes): per-wave counters, then the reordered
+// tile, whose bytes hold the per-wave leader tables until the ranks are done
+constexpr int SBL_LEAD = (SB_NB_MAX + 15) & ~15;                // leader bytes per wave
+constexpr int SBL_WC = 0;                                       // u16[PASS_WAVES][SB_NB_MAX]
+constexpr int SBL_STAGE = (SBL_WC + 2 * PASS_WAVES * SB_NB_MAX + 15) & ~15;  // int2[PASS_TILE]
+constexpr int SBL_BYTES = SBL_STAGE + 8 * PASS_TILE;
+static_assert(PASS_WAVES * SBL_LEAD <= 8 * PASS_TILE, "leader tables fit the tile's bytes");
+
+// (registers for four waves per SIMD: two workgroups per CU)
+__global__ __launch_bounds__(PASS_THREADS, 4) void k_sb_pass(State st, Scratch base, SbBufs sb,
+                                                             SbBatches in, int32_t seq) {
+    __shared__ __align__(16) char pool[SBL_BYTES];
+    __shared__ int32_t ts[SB_NB_MAX + 1];
     __shared__ int red[PASS_WAVES];
-    __shared__ __align__(16) uint16_t gbk[PASS_LOCAL_G];  // leader tables
     __shared__ SbTile tl[SB_PASS_PER];
     constexpr int R = PASS_ROUNDS;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
@@ -2337,15 +2346,18 @@ __global__ __launch_bounds__(PASS_THREADS) void k_sb_pass(State st, Scratch base
             keep(tB.n_buckets);
         };
         const int32_t nA = tA.n_buckets;
-        if (!tA.status && nA <= LEAD) {
+        if (!tA.status && nA <= SB_NB_MAX - 2) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 bA[r] = tb + pos(r) < x.n ? bA[r] : nA;
                 lr[r] = 0;
             }
             const Scratch sc = sb_set(sb, base, b, G);
-            pass_split(kA, vA, bA, lr, nA, tb, tile_n, x.tile, sc, pool, ts, red, gbk, [] {},
-                       arrive);
+            pass_split<SB_NB_MAX, SBL_LEAD>(
+                kA, vA, bA, lr, nA, tb, tile_n, x.tile, sc,
+                reinterpret_cast<uint16_t *>(pool + SBL_WC),
+                reinterpret_cast<int2 *>(pool + SBL_STAGE), ts, red,
+                reinterpret_cast<uint8_t *>(pool + SBL_STAGE), [] {}, arrive);
         } else {
             if (!tA.status && tid == 0) atomicOr(base.fault, FAULT_BUCKETS);  // (no plan makes
             arrive();                                                          // this many)
@@ -2369,13 +2381,13 @@ __global__ __launch_bounds__(PASS_THREADS) void k_sb_pass(State st, Scratch base
 // the tuples ranked so far.
 constexpr int SPW_P = 0;                                 // i32[PASS_TILES_MAX + 1]
 constexpr int SPW_S = SPW_P + 4 * (PASS_TILES_MAX + 4);  // i32[PASS_TILES_MAX]
-constexpr int SPW_RT = SPW_S + 4 * PASS_TILES_MAX;       // u8[LIGHT_CAP]
-constexpr int SPW_LEAD = SPW_RT + LIGHT_CAP;             // u8[LIGHT_CAP]
-constexpr int SPW_CNT = SPW_LEAD + LIGHT_CAP;            // u16[LIGHT_CAP]
-constexpr int SPW_BYTES = SPW_CNT + 2 * LIGHT_CAP;
+constexpr int SPW_RT = SPW_S + 4 * PASS_TILES_MAX;       // u8[SB_LIGHT_CAP]
+constexpr int SPW_LEAD = SPW_RT + SB_LIGHT_CAP;          // u8[SB_LIGHT_CAP]
+constexpr int SPW_CNT = SPW_LEAD + SB_LIGHT_CAP;         // u16[SB_LIGHT_CAP]
+constexpr int SPW_BYTES = SPW_CNT + 2 * SB_LIGHT_CAP;
 static_assert(PASS_TILES_MAX == 4 * 64, "four runs per lane");
 static_assert(PASS_TILES_MAX <= 256, "run ids fit a byte");
-static_assert(LIGHT_CAP % 512 == 0, "light buckets in halves of eight rounds");
+static_assert(SB_LIGHT_CAP % 512 == 0, "light buckets in halves of eight rounds");
 
 // LDS accesses of other lanes of the wave seen from here on.
 __device__ __forceinline__ void wave_lds_sync() {
@@ -2487,19 +2499,19 @@ __global__ __launch_bounds__(UPD_THREADS) void k_sb_prep(State st, Scratch base,
         }
         const int32_t a = fa, z = fz;
         const int32_t s0 = sc.lpre[a];
-        if (size > LIGHT_CAP || sc.lpre[z] - s0 != size) {  // impossible for a well-formed plan
+        if (size > SB_LIGHT_CAP || sc.lpre[z] - s0 != size) {  // impossible for a well-formed plan
             if (lane == 0) atomicOr(sc.fault, FAULT_LIGHT_SIZE);
             continue;
         }
         // every position's run: each non-empty run's id at its first
         // position, then a running maximum (run ids grow with position);
         // lane l owns positions 16l .. 16l+15 here
-        constexpr int PPL = LIGHT_CAP / 64;
+        constexpr int PPL = SB_LIGHT_CAP / 64;
 #pragma unroll
         for (int j = 0; j < PPL / 4; ++j)
             reinterpret_cast<uint32_t *>(rt)[lane * (PPL / 4) + j] = 0;
 #pragma unroll
-        for (int j = 0; j < 2 * LIGHT_CAP / 4 / 64; ++j)
+        for (int j = 0; j < 2 * SB_LIGHT_CAP / 4 / 64; ++j)
             reinterpret_cast<uint32_t *>(cnt)[lane + 64 * j] = 0;
         wave_lds_sync();
 #pragma unroll
@@ -2696,7 +2708,7 @@ __device__ __forceinline__ LaneBatch lane_batch(const ApplyGroup &q, int bl, int
             r.k = q.k[b];
             r.c = c;
             r.tix = q.tix[b];
-            r.whole = q.k[b] >= W && q.k[b] >= HEAVY_MIN;
+            r.whole = q.k[b] >= W && q.k[b] >= SB_HEAVY_MIN;
         }
     }
     return r;
@@ -2726,7 +2738,7 @@ __device__ __forceinline__ void apply_emit_lane(const State &st, const SbBufs &s
 // APPLY_BUDGET).  Batch b's window sum: the survivors at places [lo_b, hi_b)
 // plus, while fewer than W tuples have arrived in the call, the window before
 // the call less its first c_b values.  A batch holding at least
-// max(W, HEAVY_MIN) of its tuples was a heavy item whose survivors' sum the
+// max(W, SB_HEAVY_MIN) of its tuples was a heavy item whose survivors' sum the
 // prep step left; the others are summed here, each thread adding what it
 // reads to (survivors) or subtracting it from (old values) every batch whose
 // range holds it.
@@ -2751,7 +2763,7 @@ __device__ void apply_big(const State &st, const SbBufs &sb, const SbBatches &in
             hi[b] = e;
             lo[b] = e - min(W, c);
             cb[b] = (k > 0 && c < W && q.lold) ? c : 0;
-            whole[b] = k >= W && k >= HEAVY_MIN;
+            whole[b] = k >= W && k >= SB_HEAVY_MIN;
             need_x |= k > 0 && !whole[b];
             need_o |= cb[b] > 0;
         }
@@ -2870,7 +2882,7 @@ __device__ void apply_wave(const State &st, const SbBufs &sb, const SbBatches &i
             hi[b] = e;
             lo[b] = e - min(W, c);
             cb[b] = (k > 0 && c < W && q.lold) ? c : 0;
-            whole[b] = k >= W && k >= HEAVY_MIN;
+            whole[b] = k >= W && k >= SB_HEAVY_MIN;
             need_x |= k > 0 && !whole[b];
         }
     }
@@ -3199,7 +3211,7 @@ hipError_t launch_sb_prep(State st, Scratch base, SbBufs sb, const SbBatches &in
     // dispatch, so the grid is what the device holds at once, not the bound
     int64_t items = 0;
     for (int b = 0; b < in.K; ++b)
-        items += in.n[b] ? (in.n[b] + LIGHT_BUDGET - 1) / LIGHT_BUDGET + in.n[b] / HEAVY_MIN + 1
+        items += in.n[b] ? (in.n[b] + SB_LIGHT_BUDGET - 1) / SB_LIGHT_BUDGET + in.n[b] / SB_HEAVY_MIN + 1
                          : 0;
     const int64_t grid = std::max<int64_t>(
         1, std::min<int64_t>((items + UPD_THREADS / 64 - 1) / (UPD_THREADS / 64), SB_PREP_GRID));
