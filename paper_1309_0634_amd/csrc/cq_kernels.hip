@@ -2715,13 +2715,14 @@ __device__ __forceinline__ LaneBatch lane_batch(const ApplyGroup &q, int bl, int
 }
 
 // Batch bl's result of group g (s: its window's sum without the part from
-// before the call) by the calling lane, and, by the lane of the group's last
-// batch, its final state.
+// before the call, unless add_before is false) by the calling lane, and, by
+// the lane of the group's last batch, its final state.
 __device__ __forceinline__ void apply_emit_lane(const State &st, const SbBufs &sb,
                                                 const Out *outs, const ApplyGroup &q, int g,
-                                                const LaneBatch &lb, int bl, long long s) {
+                                                const LaneBatch &lb, int bl, long long s,
+                                                bool add_before = true) {
     const int32_t W = st.W;
-    s += lb.c < W ? q.sum0 : 0;
+    if (add_before) s += lb.c < W ? q.sum0 : 0;
     if (lb.k > 0) emit_one(outs[bl], lb.tix, g, s, (int32_t)min((int64_t)W, (int64_t)q.cnt0 + lb.c));
     int last = 0;
 #pragma unroll
@@ -2889,49 +2890,138 @@ __device__ void apply_wave(const State &st, const SbBufs &sb, const SbBatches &i
     long long acc[SB_K];
 #pragma unroll
     for (int b = 0; b < SB_K; ++b) acc[b] = 0;
-    constexpr int U = 4;
     int32_t *ring = st.ring + (int64_t)g * W;
-    // old value i (i < W) sits in slot pos0 + i mod W; slots a window that
-    // never filled has not reached hold 0 and are not read
     const int32_t unread = W - q.cnt0;
-    for (int i0 = lane; i0 < q.lold; i0 += U * 64) {
-        int32_t v[U];
+    bool any_whole = false;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t i = min(i0 + u * 64, q.lold - 1);
-            uint32_t slot = (uint32_t)q.pos0 + (uint32_t)i;
-            slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
-            v[u] = i < unread ? 0 : ring[slot];
+    for (int b = 0; b < SB_K; ++b) any_whole |= whole[b];
+    if (q.kg <= W && !any_whole) {
+        // Every window of the call reaches back before it: the group's new
+        // tuples x < kg are its survivors, in place x, and tuple x takes
+        // slot pos0 + x mod W, whose old value it evicts.  Batch b's window
+        // sum is the sum before the call plus the differences (new - old) of
+        // tuples x < C_b, so each difference goes to its own batch's segment
+        // (a run of 64 tuples mostly lies in one: that segment is found once
+        // for the run) and the segments are summed in batch order after.
+        int32_t C[SB_K];
+        {
+            int32_t c = 0;
+#pragma unroll
+            for (int b = 0; b < SB_K; ++b) {
+                c += q.k[b];
+                C[b] = c;
+            }
+        }
+        auto seg_of = [&](int32_t x) {  // batch of tuple x (x uniform)
+            int sg = 0;
+#pragma unroll
+            for (int b = 0; b < SB_K; ++b) sg += C[b] <= x ? 1 : 0;
+            return sg;
+        };
+        const int32_t n = q.kg;
+        constexpr int UP = 8;
+        for (int x0 = 0; x0 < n; x0 += UP * 64) {
+            int32_t nv[UP], ov[UP];
+#pragma unroll
+            for (int u = 0; u < UP; ++u) {
+                const int32_t x = min(x0 + u * 64 + lane, n - 1);
+                uint32_t slot = (uint32_t)q.pos0 + (uint32_t)x;
+                slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
+                nv[u] = sb.xs[q.gs + x];
+                ov[u] = x >= unread ? ring[slot] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < UP; ++u) {
+                const int32_t cb = x0 + u * 64;
+                if (cb >= n) break;
+                const int32_t x = cb + lane;
+                const bool in = x < n;
+                if (in) {
+                    uint32_t slot = (uint32_t)q.pos0 + (uint32_t)x;
+                    slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
+                    ring[slot] = nv[u];
+                }
+                const long long d = in ? (long long)nv[u] - (long long)ov[u] : 0LL;
+                const int slo = seg_of(cb), shi = seg_of(min(cb + 63, n - 1));
+                if (slo == shi) {
+#pragma unroll
+                    for (int b = 0; b < SB_K; ++b)
+                        if (b == slo) acc[b] += d;
+                } else {
+#pragma unroll
+                    for (int b = 0; b < SB_K; ++b)
+                        if (b >= slo && b <= shi) {
+                            const int32_t lo_b = b ? C[b - 1] : 0;
+                            acc[b] += (x >= lo_b && x < C[b]) ? d : 0LL;
+                        }
+                }
+            }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * 64;
+        for (int h = SB_K / 2, off = 32; h >= 1; h >>= 1, off >>= 1) {
+            const bool up = lane & off;
 #pragma unroll
-            for (int b = 0; b < SB_K; ++b) acc[b] -= (i < q.lold && i < cb[b]) ? v[u] : 0;
+            for (int j = 0; j < h; ++j) {
+                const long long give = up ? acc[j] : acc[j + h];
+                const long long keep_ = up ? acc[j + h] : acc[j];
+                acc[j] = keep_ + __shfl_xor(give, off, 64);
+            }
         }
+#pragma unroll
+        for (int off = 4; off >= 1; off >>= 1) acc[0] += __shfl_xor(acc[0], off, 64);
+        // window sums: the sum before the call plus the segments up to b
+        const int bl = lane >> 3;
+        long long run = q.sum0, mine = 0;
+#pragma unroll
+        for (int b = 0; b < SB_K; ++b) {
+            run += readlane64(acc[0], 8 * b);
+            mine = bl == b ? run : mine;
+        }
+        const LaneBatch lb = lane_batch(q, bl, W);
+        if ((lane & 7) == 0) apply_emit_lane(st, sb, outs, q, g, lb, bl, mine, false);
+        return;
     }
-    // (the old values have all been read: the ring may change now) the
-    // survivors, summed where a batch needs them, and the final window, the
-    // last min(W, kg), written to the ring as they are read
+    // One pass over the old values [0, lold) and then the survivors [x_from,
+    // m), U per lane in flight: old value i sits in slot pos0 + i mod W
+    // (slots a window that never filled has not reached hold 0 and are not
+    // read); survivors at or past keep_from, the final window, go to the
+    // ring.  A round's loads are all issued before any of its stores, and
+    // every old value comes before every survivor, so no old value is read
+    // after its slot was written.
     const int32_t keep_from = q.m - min(W, q.kg);
     const int32_t x_from = need_x ? 0 : keep_from;
+    const int32_t ne = q.lold + (q.m - x_from);
     const uint32_t slot0 =
         (uint32_t)(((int64_t)q.pos0 + q.kg - min(W, q.kg)) % (int64_t)W);  // of keep_from
-    for (int e0 = x_from + lane; e0 < q.m; e0 += U * 64) {
+    constexpr int U = 8;
+    for (int e0 = lane; e0 < ne; e0 += U * 64) {
         int32_t v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = sb.xs[q.gs + min(e0 + u * 64, q.m - 1)];
+        for (int u = 0; u < U; ++u) {
+            const int32_t e = min(e0 + u * 64, ne - 1);
+            const bool old = e < q.lold;
+            uint32_t slot = (uint32_t)q.pos0 + (uint32_t)e;
+            slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
+            const int32_t *src = old ? ring + slot : sb.xs + q.gs + (x_from + e - q.lold);
+            v[u] = (old && e < unread) ? 0 : *src;
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * 64;
-            if (e >= q.m) break;
+            const int32_t e = e0 + u * 64;
+            if (e >= ne) break;
+            if (e < q.lold) {
 #pragma unroll
-            for (int b = 0; b < SB_K; ++b)
-                acc[b] += (!whole[b] && e >= lo[b] && e < hi[b]) ? v[u] : 0;
-            if (e >= keep_from) {
-                uint32_t slot = slot0 + (uint32_t)(e - keep_from);
-                slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
-                ring[slot] = v[u];
+                for (int b = 0; b < SB_K; ++b) acc[b] -= e < cb[b] ? v[u] : 0;
+            } else {
+                const int32_t p = x_from + e - q.lold;
+#pragma unroll
+                for (int b = 0; b < SB_K; ++b)
+                    acc[b] += (!whole[b] && p >= lo[b] && p < hi[b]) ? v[u] : 0;
+                if (p >= keep_from) {
+                    uint32_t slot = slot0 + (uint32_t)(p - keep_from);
+                    slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
+                    ring[slot] = v[u];
+                }
             }
         }
     }
@@ -2956,11 +3046,10 @@ __device__ void apply_wave(const State &st, const SbBufs &sb, const SbBatches &i
     if ((lane & 7) == 0) apply_emit_lane(st, sb, outs, q, g, lb, bl, lb.whole ? tbl : acc[0]);
 }
 
-__global__ __launch_bounds__(APPLY_THREADS) void k_sb_apply(State st, Scratch base, SbBufs sb,
+__global__ __launch_bounds__(APPLY_THREADS, 4) void k_sb_apply(State st, Scratch base, SbBufs sb,
                                                             SbBatches in, int32_t seq) {
     __shared__ long long red[SB_K * (APPLY_THREADS / 64)];
     __shared__ Out outs[SB_K];  // (indexed by lane: the argument's copy is per batch)
-    constexpr int WPB = APPLY_THREADS / 64;
     const int K = in.K;
     const int G = (int)st.G;
     const int lane = lane_id();
@@ -2972,23 +3061,28 @@ __global__ __launch_bounds__(APPLY_THREADS) void k_sb_apply(State st, Scratch ba
 #pragma unroll
     for (int b = 0; b < SB_K; ++b) valid[b] = b < K && sb.sbad[b] != seq;
     phase_mark(base, PHASE_SB_APPLY, 0);
-    // the groups over APPLY_BUDGET first, by whole workgroups
+    // The groups over APPLY_BUDGET by whole workgroups, the last min(nbig,
+    // grid) ones; every other group by one wave of the workgroups before
+    // those (of all of them when every workgroup has a big group), each wave
+    // taking every NWV-th group, the next one's facts loaded while the
+    // current one is worked on.
     const int nbig = sb.ntot[0];
-    for (int i = (int)blockIdx.x; i < nbig; i += (int)gridDim.x) {
+    const int grid = (int)gridDim.x;
+    const int nbw = min(nbig, grid);
+    const int bw = grid - 1 - (int)blockIdx.x;  // this workgroup's place from the top
+    for (int i = bw; i < nbig; i += grid) {
         apply_big(st, sb, in, outs, valid, sb.big[i], red);
-        if (i == (int)blockIdx.x) phase_mark(base, PHASE_SB_APPLY, 1);
+        if (i == bw) phase_mark(base, PHASE_SB_APPLY, 1);
     }
     phase_mark(base, PHASE_SB_APPLY, 2);
-    // then every other group by one wave: all facts of a wave's groups (w +
-    // j * NW for wave w of NW) are loaded together
-    const int NWV = (int)gridDim.x * WPB;
-    const int w = (int)blockIdx.x * WPB + ((int)threadIdx.x >> 6);
-    constexpr int J = 4;
-    int32_t A[J];
-    int64_t B[J];
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const int g = min(w + j * NWV, G - 1);
+    const int wgs = nbw < grid ? grid - nbw : grid;  // workgroups that take wave groups
+    if ((int)blockIdx.x >= wgs) {
+        phase_mark(base, PHASE_SB_APPLY, 7);
+        return;
+    }
+    const int NWV = wgs * (APPLY_THREADS / 64);
+    auto facts = [&](int g, int32_t &A, int64_t &B) {
+        g = min(g, G - 1);
         const int b = lane & 7;
         const int bb = b < K ? b : 0;
         const int32_t *pa = lane < 8    ? sb.kh + (int64_t)g * SB_K + b
@@ -2999,26 +3093,23 @@ __global__ __launch_bounds__(APPLY_THREADS) void k_sb_apply(State st, Scratch ba
                             : lane == 19 ? sb.gsb + g + 1
                                          : sb.gbig + g;
         const int64_t *pb = lane < 8 ? sb.tb + (int64_t)bb * G + g : st.sum + g;
-        A[j] = *pa;
-        B[j] = *pb;
-    }
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        keep(A[j]);
-        keep(B[j]);
-    }
-    // (one copy of the group code: the facts move down a slot per group)
-#pragma unroll 1
-    for (int j = 0; j < J; ++j) {
-        const int g = w + j * NWV;
-        if (g >= G) break;
-        if (!__builtin_amdgcn_readlane(A[0], 20))  // (else a workgroup's)
-            apply_wave(st, sb, in, outs, valid, g, A[0], B[0]);
-#pragma unroll
-        for (int i = 0; i + 1 < J; ++i) {
-            A[i] = A[i + 1];
-            B[i] = B[i + 1];
-        }
+        A = *pa;
+        B = *pb;
+    };
+    int g = (int)blockIdx.x * (APPLY_THREADS / 64) + ((int)threadIdx.x >> 6);
+    int32_t A0;
+    int64_t B0;
+    facts(g, A0, B0);
+    for (; g < G; g += NWV) {
+        int32_t A1;
+        int64_t B1;
+        facts(g + NWV, A1, B1);
+        keep(A0);
+        keep(B0);
+        if (!__builtin_amdgcn_readlane(A0, 20))  // (else a workgroup's)
+            apply_wave(st, sb, in, outs, valid, g, A0, B0);
+        A0 = A1;
+        B0 = B1;
     }
     phase_mark(base, PHASE_SB_APPLY, 7);
 }
@@ -3222,8 +3313,6 @@ hipError_t launch_sb_prep(State st, Scratch base, SbBufs sb, const SbBatches &in
 
 hipError_t launch_sb_apply(State st, Scratch base, SbBufs sb, const SbBatches &in, int32_t seq,
                            hipStream_t s) {
-    static_assert((int64_t)SB_APPLY_GRID * (APPLY_THREADS / 64) * 4 >= PASS_LOCAL_G,
-                  "four groups per wave at most");
     hipLaunchKernelGGL(k_sb_apply, dim3(SB_APPLY_GRID), dim3(APPLY_THREADS), 0, s, st, base, sb,
                        in, seq);
     return hipGetLastError();
