@@ -232,6 +232,68 @@ def per_tuple(torch, cq, batches, cfg, warmup, steps, passes_list):
     return rows
 
 
+def paper_shape_rows(torch, cq, warmup, steps, tuple_passes):
+    """Tables 1 and 2 and the ten-fold scan at the paper's own setting
+    (Section 5.1): 40,000 groups, W=100, 50,000-tuple batches.  On DS1-,
+    DS2- and DS3-like streams: no balancing (the static ranges), the six
+    Section 4 techniques (threshold 1000, pot 0.5, host step after every
+    batch) on 1,024 static workers (the paper's grid of 4 blocks of 256
+    threads) and on 4,096 (the most a static partition takes: the analogue
+    of its grid of 64 blocks, 16,384 threads), and the device-side balanced
+    partition; then the per-tuple form (rescan after every insertion, once
+    and ten times) on DS2 and DS3.  Whole pushes timed on the host clock
+    around a device synchronisation."""
+    from workloads import host_batch, paper_shape
+    dev = torch.device("cuda", 0)
+    rows, tuples = [], []
+    for dataset in ("DS1", "DS2", "DS3"):
+        cfg = paper_shape(dataset)
+        batches = []
+        for b in range(warmup + steps):
+            k, v = host_batch(cfg, b)
+            batches.append((torch.from_numpy(k).to(dev), torch.from_numpy(v).to(dev)))
+        torch.cuda.synchronize()
+        for workers in (1024, 4096):
+            modes = [(cq.PARTITION_STATIC, "no balance (static)")]
+            modes += [(m, nm) for nm, m in cq.POLICIES.items()]
+            if workers == 1024:
+                modes += [(cq.PARTITION_BALANCED, "balanced (device)")]
+            base = None
+            for mode, name in modes:
+                q = cq.Query(cfg.groups, cfg.window)
+                q.set_policy_params(1000, 0.5)
+                q.set_partition(mode, workers if mode != cq.PARTITION_BALANCED else 0)
+                for b in range(warmup):
+                    q.push(*batches[b])
+                torch.cuda.synchronize()
+                moves0 = q.policy_stats()[3]
+                t0 = time.perf_counter()
+                for b in range(warmup, warmup + steps):
+                    q.push(*batches[b])
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                st = q.policy_stats()
+                q.close()
+                ms = 1e3 * wall / steps
+                base = ms if base is None else base
+                row = {"dataset": dataset, "workers": workers if mode != cq.PARTITION_BALANCED
+                       else None, "partition": name, "ms_per_batch": round(ms, 4),
+                       "tuples_per_s": steps * cfg.batch / wall,
+                       "time_vs_no_balance": round(ms / base, 4)}
+                if mode >= cq.PARTITION_GETFIRST:
+                    row["moves_timed"] = st[3] - moves0
+                    row["last_batch_tpt_max_min"] = [st[1], st[2]]
+                rows.append(row)
+                print(json.dumps({"progress": {"paper_shape": row}}), file=sys.stderr, flush=True)
+        if dataset != "DS1" and tuple_passes:
+            for r in per_tuple(torch, cq, batches, cfg, warmup, steps, tuple_passes):
+                r["dataset"] = dataset
+                tuples.append(r)
+        del batches
+    return {"groups": 40_000, "window": 100, "batch": 50_000, "zipf_s": 1.0,
+            "threshold": 1000, "pot": 0.5, "partitions": rows, "per_tuple": tuples}
+
+
 def serving(torch, cq, lambdas, seconds, lanes=8, slots=2, nq=256):
     """The serving loop (cq_server_*): `nq` resident queries (groups
     log-uniform in [100, 1e6], windows in [10, 1e4]) admitted by device
@@ -562,6 +624,8 @@ def main():
     ap.add_argument("--tech-steps", type=int, default=40)
     ap.add_argument("--tuple-passes", default="0,1,10",
                     help="passes of the per-tuple variant to time ('' skips it)")
+    ap.add_argument("--paper-steps", type=int, default=40,
+                    help="timed batches per row at the paper's setting (0 skips it)")
     ap.add_argument("--drift", type=int, default=6,
                     help="timed batches of the large drifting stream (0 skips it)")
     ap.add_argument("--multi", type=int, default=64,
@@ -684,6 +748,11 @@ def main():
     if args.techniques:
         tech = techniques(torch, cq, [float(x) for x in args.techniques.split(",")],
                           min(args.warmup, 5), args.tech_steps)
+    paper = None
+    if args.paper_steps:
+        paper = paper_shape_rows(torch, cq, 5, args.paper_steps,
+                                 [int(x) for x in args.tuple_passes.split(",")]
+                                 if args.tuple_passes else [])
     drift = drifting_run(torch, cq, 2, args.drift) if args.drift else None
     mq = multi(torch, cq, args.multi) if args.multi else None
     serve = None
@@ -731,6 +800,7 @@ def main():
         "sweep": rows,
         "techniques": tech,
         "per_tuple": pt,
+        "paper_shape": paper,
         "drifting": drift,
         "multi_query": mq,
         "serving": serve,

@@ -118,7 +118,7 @@ int cq_reserve(cq_query *q, int64_t max_batch);
  *     (Section 3.1: one iteration of delay).  Groups move whole; no worker
  *     is given more than 2048 groups.  Each push then waits for its
  *     batch's histogram on the host (the GPU keeps working meanwhile), as
- *     the paper's CPU coordinator does.  Only for up to 16384 groups.
+ *     the paper's CPU coordinator does.
  * Results are identical in every mode.  Takes effect at the next push and
  * restarts a technique's mapping from the initial ranges.  Returns CQ_OK
  * or CQ_ERR_INVALID.
@@ -250,6 +250,7 @@ int cq_push_batch_results_noalloc(cq_query *q, const int32_t *keys, const int32_
 
 /* Limits of cq_push_batch_tuples. */
 #define CQ_TUPLE_MAX_WINDOW 1024
+#define CQ_TUPLE_MAX_GROUPS 2097152  /* 2^21 */
 #define CQ_TUPLE_MAX_PASSES 64
 
 /*
@@ -266,8 +267,8 @@ int cq_push_batch_results_noalloc(cq_query *q, const int32_t *keys, const int32_
  *       value); 1 .. CQ_TUPLE_MAX_PASSES = every tuple's window is summed
  *       from scratch that many times (the paper's 1 and 10).  The results
  *       are the same integers either way.
- * Needs the balanced partition, at most 16384 groups and a window of at
- * most CQ_TUPLE_MAX_WINDOW.  The first call allocates 4 MiB + 4 bytes per
+ * Needs the balanced partition, at most CQ_TUPLE_MAX_GROUPS groups and a
+ * window of at most CQ_TUPLE_MAX_WINDOW.  The first call allocates 4 MiB + 4 bytes per
  * group of device memory for the query.  Stream-ordered like cq_push_batch;
  * a rejected batch (bad key) writes no per-tuple entry and cq_status
  * reports it.  cq_results afterwards gives the batch's per-group results.

@@ -28,6 +28,7 @@ TELEMETRY_KERNEL_TIMES, TELEMETRY_WORKERS, TELEMETRY_PHASES = 1, 2, 4
 KERNEL_KINDS = ("hist", "pass", "update", "emit", "other", "plan", "tuples", "prep", "apply")
 TUPLE_MAX_WINDOW = 1024
 TUPLE_MAX_PASSES = 64
+TUPLE_MAX_GROUPS = 1 << 21
 MAX_BATCH = 1 << 30
 MAX_WINDOW = (1 << 22) - 1
 PIPE_MAX = 1 << 20

@@ -125,7 +125,8 @@ __device__ void plan_publish(const State &st, const Scratch &sc, const int (&tot
 
 // Plans groups [gb, ge).  carry[q]: exclusive field values at gb on entry,
 // at ge on exit (same in every thread).  `write`: emit the per-group plan
-// and clear the histogram (else only count).  Per-group plan writes happen
+// and clear the histogram, unless per-tuple results follow (else only
+// count).  Per-group plan writes happen
 // only when `status` is 0.  `lds` holds 2 * waves ints.  Barriers inside.
 __device__ void plan_range(const State &st, const Scratch &sc, int64_t gb, int64_t ge,
                            int (&carry)[PLAN_FIELDS], bool write, int32_t status,
@@ -181,7 +182,9 @@ __device__ void plan_range(const State &st, const Scratch &sc, int64_t gb, int64
                 const int ea = ra + ia - x[0], eb = rb + ib - B;
                 ra += wave_total(ia);
                 rb += wave_total(ib);
-                if (kg) kw[64 * r] = 0;
+                // (the per-tuple step, after the plan, still reads the
+                // counts of an accepted batch: the update clears them then)
+                if (kg && (!sc.pcnt || !ok)) kw[64 * r] = 0;
                 if (!ok || g0 + 64 * r >= ge) continue;
                 int ex[PLAN_FIELDS] = {ea, carry[1] + (eb & 0xffff), carry[2] + (eb >> 16)};
                 lw[64 * r] = ex[0];

@@ -727,7 +727,6 @@ int cq_set_partition(cq_query *q, int32_t mode, int32_t workers) {
     if (mode != CQ_PARTITION_BALANCED && !static_ok(q->st.G, w)) return CQ_ERR_INVALID;
     const bool technique = mode >= CQ_PARTITION_GETFIRST;
     if (technique) {
-        if (q->st.G > PASS_LOCAL_G) return CQ_ERR_INVALID;
         DeviceGuard guard(q->device);
         int rc = policy_buffers(q);
         if (rc != CQ_OK) return rc;
@@ -834,7 +833,7 @@ int cq_push_batch_tuples(cq_query *q, const int32_t *keys, const int32_t *values
     if (!q || n < 0 || n > CQ_MAX_BATCH || passes < 0 || passes > CQ_TUPLE_MAX_PASSES)
         return CQ_ERR_INVALID;
     if (n > 0 && (!keys || !values)) return CQ_ERR_INVALID;
-    if (q->mode != MODE_BALANCED || q->st.G > PASS_LOCAL_G || q->st.W > CQ_TUPLE_MAX_WINDOW)
+    if (q->mode != MODE_BALANCED || q->st.G > CQ_TUPLE_MAX_GROUPS || q->st.W > CQ_TUPLE_MAX_WINDOW)
         return CQ_ERR_INVALID;
     DeviceGuard guard(q->device);
     if (!q->pt_sidx) {

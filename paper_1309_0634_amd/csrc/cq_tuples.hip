@@ -61,7 +61,7 @@ constexpr int H_END = H_PS + 8 * H_SPAN;
 constexpr int T_BYTES = L_END > H_END ? L_END : H_END;
 static_assert(LIGHT_CAP <= 1024, "10-bit arrival positions in the light sort key");
 static_assert(LIGHT_CAP % PT_THREADS == 0, "whole positions per thread");
-static_assert(PASS_LOCAL_G <= (1 << 21), "group offsets fit the light sort key");
+static_assert(CQ_TUPLE_MAX_GROUPS <= (1 << 21), "group offsets fit the light sort key");
 
 // Inclusive scan of a[0, m) (int64, in LDS, in place); each thread scans a
 // contiguous piece.  `red` holds one int64 per wave.  Barriers inside.

@@ -108,6 +108,7 @@ def test_header_constants_match_binding():
     assert val("CQ_KERNEL_TUPLES") == cq.KERNEL_KINDS.index("tuples")
     assert val("CQ_TUPLE_MAX_WINDOW") == cq.TUPLE_MAX_WINDOW
     assert val("CQ_TUPLE_MAX_PASSES") == cq.TUPLE_MAX_PASSES
+    assert val("CQ_TUPLE_MAX_GROUPS") == cq.TUPLE_MAX_GROUPS
     for name, v in cq.POLICIES.items():
         assert val("CQ_PARTITION_" + name.upper()) == v
 

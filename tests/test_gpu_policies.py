@@ -150,9 +150,10 @@ def test_rejected_batch_moves_nothing():
 
 def test_technique_limits_and_switching():
     note("case: technique limits and mode switches")
-    q = cq.Query(20000, 4)
+    q = cq.Query(40000, 4)
     with pytest.raises(cq.CQError):
-        q.set_partition(cq.PARTITION_GETFIRST, 1024)  # more groups than a technique takes
+        q.set_partition(cq.PARTITION_GETFIRST, 16)  # 2,500 groups per worker
+    q.set_partition(cq.PARTITION_GETFIRST, 20)      # 2,000 per worker: taken
     q.close()
     q = cq.Query(4096, 4)
     with pytest.raises(cq.CQError):

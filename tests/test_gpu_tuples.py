@@ -154,7 +154,7 @@ def test_per_tuple_limits():
     with pytest.raises(cq.CQError):
         q.push_tuples(k, v)
     q.close()
-    q = cq.Query(20000, 10)
+    q = cq.Query(cq.TUPLE_MAX_GROUPS + 1, 10)
     with pytest.raises(cq.CQError):
         q.push_tuples(k, v)
     q.close()

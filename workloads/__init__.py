@@ -67,6 +67,25 @@ def skew(s: float, permuted: bool = True, batches: int = 200) -> StreamConfig:
                         permuted=permuted, s_index=idx + (0 if permuted else 50))
 
 
+PAPER_DATASETS = ("DS1", "DS2", "DS3")
+
+
+def paper_shape(dataset: str, s: float = 1.0, batches: int = 2000) -> StreamConfig:
+    """The paper's own setting (Section 5.1): 40,000 groups, W=100, batches
+    of 50,000 tuples (2,000 batches make its 100M-tuple stream).  DS1:
+    round-robin keys; DS2: Zipf(s) with the id order equal to the frequency
+    order; DS3: the same with the ids permuted.  The paper does not state its
+    Zipf exponent; s is a parameter."""
+    if dataset not in PAPER_DATASETS:
+        raise ValueError(dataset)
+    idx = PAPER_DATASETS.index(dataset) * 1000 + int(round(s * 100))
+    if dataset == "DS1":
+        return StreamConfig("paper_g40000_w100_ds1", 6, 40_000, 100, 50_000, batches,
+                            "roundrobin", s_index=idx)
+    return StreamConfig(f"paper_g40000_w100_{dataset.lower()}_s{s:g}", 6, 40_000, 100, 50_000,
+                        batches, "zipf", zipf_s=s, permuted=dataset == "DS3", s_index=idx)
+
+
 def drifting(batches: int = 500) -> StreamConfig:
     """2^20 groups, W=100, 16,777,216-tuple batches, Zipf s=1.2 with the hot
     permutation redrawn every 50 batches, clipped-normal values."""
