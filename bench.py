@@ -22,7 +22,9 @@ longest-running kernel of the headline run (one launch processes one
 call's batches), beside the end-to-end fraction (algorithmic bytes over
 the whole time per batch); its `traffic` is the HBM bytes per launch
 recorded from rocprofv3 counters in profiles/traffic_<kind>.md, or null
-when that record was taken on other kernel sources.  The
+when that record was taken on other kernel sources; the whole path's
+counter bytes per batch (every launch's record) stand beside the
+algorithmic bytes.  The
 cpu_baseline is the CPU oracle timed on a bounded sample of the same
 headline batches (one thread; a second figure with one thread per host
 core up to 16).
@@ -736,6 +738,16 @@ def main():
                 "end_to_end_frac": round(e2e / HBM_PEAK_GBS, 4),
                 "kernel_times_ms": {k: round(v[0], 3) for k, v in kern.items()},
                 "kernel_launches": {k: v[1] for k, v in kern.items()}}
+    # the whole path's counter bytes (every kind's record, per batch), when
+    # every record matches the kernels built now
+    recs = [measured_traffic(k) for k in kern]
+    if all(t is not None for t in recs):
+        path_b = sum(recs) / row["batches_per_call"]
+        roofline["path_traffic_bytes_per_batch"] = round(path_b)
+        roofline["alg_bytes_per_batch"] = round(avg_bytes)
+        roofline["path_traffic_over_alg"] = round(path_b / avg_bytes, 3)
+    else:
+        roofline["path_traffic_bytes_per_batch"] = None
     pt = None
     if args.tuple_passes:
         pt = per_tuple(torch, cq, batches, cfg, min(args.warmup, 5), min(args.steps, 40),
