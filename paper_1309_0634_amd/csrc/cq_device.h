@@ -132,6 +132,39 @@ __device__ __forceinline__ void keep(int4 &x) {
 }
 __device__ __forceinline__ void keep(int64_t &x) { __asm__ volatile("" : "+v"(x)); }
 
+// The valid lanes whose 6-bit value L (a lane id) equals this lane's: six
+// ballots, each lane keeping a ballot or its complement by its own bit of
+// L, on the two 32-bit halves (the ballots are wave-uniform, so each step is
+// a select and an and per half).
+__device__ __forceinline__ uint64_t match_lane_id(bool valid, int L) {
+    const uint64_t v = ballot(valid);
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+    for (int bit = 0; bit < 6; ++bit) {
+        const bool on = (L >> bit) & 1;
+        const uint64_t bb = ballot(on);
+        const uint32_t blo = (uint32_t)bb, bhi = (uint32_t)(bb >> 32);
+        lo &= on ? blo : ~blo;
+        hi &= on ? bhi : ~bhi;
+    }
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Lanes of mask m below this one.
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// A pointer into device memory whose address space the compiler cannot see
+// (held in a struct, or read back from LDS), as a global one: its accesses
+// are then global instructions rather than generic (flat) ones, which would
+// also be counted with the LDS accesses and make every LDS wait wait on them.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *global_ptr(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 // Largest r in [0, m) with pre[r] <= p (pre ascending, pre[0] = 0 <= p).
 __device__ __forceinline__ int upper_run(const int32_t *pre, int m, int p) {
     int lo = 0, hi = m - 1;

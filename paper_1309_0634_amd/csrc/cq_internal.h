@@ -188,6 +188,7 @@ constexpr int SBH_KPT = 4 * HIST_KPT;
 constexpr int SBH_TILE = HIST_THREADS * SBH_KPT;
 constexpr int SBH_TILES = (SUB + SBH_TILE - 1) / SBH_TILE;  // per batch at most
 static_assert(SBH_TILE < 65536, "a tile's count of a group fits 16 bits");
+static_assert(SBH_TILES < 256 && SB_NB_MAX < 65536, "a dropped-tile count and a bucket id share an int");
 // plan: one group per thread in blocks of SBP_THREADS; per block of the first
 // launch SBP_F field sums and two (count << 32 | group) words
 constexpr int SBP_THREADS = 256;
@@ -216,6 +217,8 @@ struct SbBufs {
     uint32_t *kt;       // [SB_K][SBH_TILES][(G + 1) / 2] per histogram tile, groups
                         // 2i and 2i + 1 in the low and high 16 bits of word i
     int32_t *kh;        // [G][SB_K] per-batch histograms, a group's counts together
+    uint8_t *cut;       // [SB_K][G] a heavy group's leading histogram tiles holding
+                        // none of its last W tuples of the batch
     int32_t *sbad;      // [SB_K] sequence number of the last call whose batch b had a bad key
     int32_t *bucket;    // [SB_K][G]
     int32_t *lpre;      // [SB_K][G + 1]

@@ -908,17 +908,11 @@ __device__ __forceinline__ void pass_split(const int32_t (&key)[PASS_ROUNDS],
         const int L = valid ? (int)__hip_atomic_load(lead + b, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_WAVEFRONT)
                             : 0;
-        uint64_t m = ballot(valid);
-#pragma unroll
-        for (int bit = 0; bit < 6; ++bit) {
-            const bool on = (L >> bit) & 1;
-            const uint64_t bb = ballot(on);
-            m &= on ? bb : ~bb;
-        }
+        const uint64_t m = match_lane_id(valid, L);
         if (valid) {
-            const uint64_t below = m & lanemask_lt();
+            const int below = lanes_below(m);
             const int c = wc[wave][b];
-            lr[r] = c + __popcll(below);
+            lr[r] = c + below;
             if (below == 0) wc[wave][b] = (uint16_t)(c + __popcll(m));
         }
     }
@@ -1066,10 +1060,10 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(const int32_t *__restrict
 
 __device__ __forceinline__ void emit_one(const Out &out, int32_t j, int32_t g, int64_t s,
                                          int32_t c) {
-    if (out.ids) out.ids[j] = g;
-    if (out.sums) out.sums[j] = s;
-    if (out.counts) out.counts[j] = c;
-    if (out.avgs) out.avgs[j] = (double)s / (double)c;
+    if (out.ids) global_ptr(out.ids)[j] = g;
+    if (out.sums) global_ptr(out.sums)[j] = s;
+    if (out.counts) global_ptr(out.counts)[j] = c;
+    if (out.avgs) global_ptr(out.avgs)[j] = (double)s / (double)c;
 }
 
 __device__ __forceinline__ void trace_record(int64_t *trace, int rec, unsigned long long t0,
@@ -1249,17 +1243,11 @@ __device__ bool light_rank(int32_t a, int32_t z, int size, int tiles, const Scra
         const int L = valid ? (int)__hip_atomic_load(lead + p0, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_WAVEFRONT)
                             : 0;
-        uint64_t m = ballot(valid);
-#pragma unroll
-        for (int bit = 0; bit < 6; ++bit) {
-            const bool on = (L >> bit) & 1;
-            const uint64_t bb = ballot(on);
-            m &= on ? bb : ~bb;
-        }
+        const uint64_t m = match_lane_id(valid, L);
         if (valid) {
-            const uint64_t below = m & lanemask_lt();
+            const int below = lanes_below(m);
             const int c = mycw[p0];
-            lr[p] = (uint16_t)(c + __popcll(below));
+            lr[p] = (uint16_t)(c + below);
             if (below == 0) mycw[p0] = (uint16_t)(c + __popcll(m));
         }
     }
@@ -2027,6 +2015,24 @@ __global__ __launch_bounds__(SBS_THREADS) void k_sb_sums(State st, Scratch base,
             }
         kc[b][2 * pair] = lo;
         kc[b][2 * pair + 1] = hi;
+        // A heavy group's tuples in a histogram tile followed by at least W
+        // of its tuples in later tiles of the batch cannot be in any window
+        // (each has W later tuples of its own batch): the number of such
+        // leading tiles, for the reorder to drop them.
+        int32_t plo = 0, phi = 0, clo = 0, chi = 0;
+#pragma unroll
+        for (int t = 0; t < SBH_TILES; ++t)
+            if (t < nt) {
+                plo += (int32_t)(w[t] & 0xffffu);
+                phi += (int32_t)(w[t] >> 16);
+                clo += lo - plo >= W ? 1 : 0;
+                chi += hi - phi >= W ? 1 : 0;
+            }
+        const int64_t gl = min((int64_t)g0 + 2 * pair, (int64_t)G - 1);
+        if (g0 + 2 * pair < G)
+            sb.cut[(int64_t)b * G + gl] = (uint8_t)(lo >= SB_HEAVY_MIN ? clo : 0);
+        if (g0 + 2 * pair + 1 < G)
+            sb.cut[(int64_t)b * G + gl + 1] = (uint8_t)(hi >= SB_HEAVY_MIN ? chi : 0);
     }
     __syncthreads();
     if (tid >= 64) return;
@@ -2156,7 +2162,7 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
             if (k > 0) {
                 sc.tidx[g] = ext;
                 if (k >= SB_HEAVY_MIN) {
-                    sc.bucket[g] = nl + exh;
+                    sc.bucket[g] = (nl + exh) | ((int32_t)sb.cut[(int64_t)b * G + g] << 16);
                     if ((uint32_t)exh < (uint32_t)SB_NB_MAX) sc.hkey[exh] = g;
                 } else {
                     sc.bucket[g] = (exl + k - 1) / SB_LIGHT_BUDGET;
@@ -2232,12 +2238,11 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
 // reordered in LDS, the keys and values of tile t + 2 are on their way and
 // the buckets of tile t + 1 are being gathered, so each tile waits only on
 // its own LDS work.
-// A reorder workgroup's tiles: batch, tile index inside it, its tuples and
-// arrays (looked up once, not per prefetch).
+// A reorder workgroup's tiles: batch, tile index inside it, the batch's
+// tuples (looked up once, not per prefetch; the arrays come from the kernel
+// argument, so that their loads stay global rather than generic ones).
 struct SbTile {
-    const int32_t *keys, *values;
-    int64_t n;
-    int32_t b, tile;
+    int32_t n, b, tile;
 };
 constexpr int SB_PASS_PER = 8;  // tiles per reorder workgroup at most
 static_assert(SB_K * PASS_TILES_MAX <= SB_PASS_PER * SB_PASS_GRID,
@@ -2268,23 +2273,24 @@ __global__ __launch_bounds__(PASS_THREADS, 4) void k_sb_pass(State st, Scratch b
     if (t_begin >= t_end) return;
     if (tid < t_end - t_begin) {
         const int t = t_begin + tid;
-        SbTile x = {nullptr, nullptr, 0, 0, 0};
+        SbTile x = {0, 0, 0};
 #pragma unroll
         for (int b = 0; b < SB_K; ++b)
             if (b < K && in.ptile0[b] <= t && t < in.ptile0[b + 1])
-                x = {in.keys[b], in.values[b], in.n[b], b, t - in.ptile0[b]};
+                x = {(int32_t)in.n[b], b, t - in.ptile0[b]};
         tl[tid] = x;
     }
     __syncthreads();
     // position of this thread's round r inside a tile
     auto pos = [&](int r) { return wave * (PASS_TILE / PASS_WAVES) + r * 64 + lane; };
     auto load_kv = [&](const SbTile &x, int32_t (&k)[R], int32_t (&v)[R]) {
-        const int64_t tb = (int64_t)x.tile * PASS_TILE;
+        const int32_t tb = x.tile * PASS_TILE, last = x.n - 1;
+        const int32_t *kp = in.keys[x.b], *vp = in.values[x.b];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int64_t i = min(tb + pos(r), x.n - 1);
-            k[r] = x.keys[i];
-            v[r] = x.values[i];
+            const uint32_t i = (uint32_t)min(tb + pos(r), last);
+            k[r] = kp[i];
+            v[r] = vp[i];
         }
     };
     // a tile's group views and buckets: loads issued here and first used in
@@ -2292,15 +2298,27 @@ __global__ __launch_bounds__(PASS_THREADS, 4) void k_sb_pass(State st, Scratch b
     // that they stay in flight meanwhile
     auto gather = [&](const SbTile &x, int32_t (&k)[R], int32_t (&bk)[R]) {
         const int32_t *bucket = sb.bucket + (int64_t)x.b * G;
+        if (base.kmod) {  // (a uniform branch: the reduction costs nothing when off)
+#pragma unroll
+            for (int r = 0; r < R; ++r) k[r] = view_key(k[r], base.kmod, G);
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            k[r] = view_key(k[r], base.kmod, G);
             // (a rejected batch's keys may be out of range: clamped, unused)
-            const int32_t kc = (uint32_t)k[r] < (uint32_t)G ? k[r] : 0;
+            const uint32_t kc = (uint32_t)k[r] < (uint32_t)G ? (uint32_t)k[r] : 0u;
             bk[r] = bucket[kc];
         }
     };
-    auto tile_of = [&](int t) { return tl[min(t, t_end - 1) - t_begin]; };
+    // (the table's entries are the same in every lane: taken as scalars, so
+    // that loads address them as a scalar base plus a 32-bit offset)
+    auto tile_of = [&](int t) {
+        const SbTile &e = tl[min(t, t_end - 1) - t_begin];
+        SbTile x;
+        x.n = __builtin_amdgcn_readfirstlane(e.n);
+        x.b = __builtin_amdgcn_readfirstlane(e.b);
+        x.tile = __builtin_amdgcn_readfirstlane(e.tile);
+        return x;
+    };
     int32_t kA[R], vA[R], bA[R], kB[R], vB[R], bB[R], kC[R], vC[R], lr[R];
     // Tile t's keys, values, buckets and plan totals are in registers when
     // its iteration starts.  During it, tile t + 2's keys and values and tile
@@ -2352,7 +2370,11 @@ __global__ __launch_bounds__(PASS_THREADS, 4) void k_sb_pass(State st, Scratch b
         if (!tA.status && nA <= SB_NB_MAX - 2) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                bA[r] = tb + pos(r) < x.n ? bA[r] : nA;
+                // (a heavy group's bucket carries the histogram tiles of
+                // the batch whose tuples of it are dropped)
+                const int64_t i = tb + pos(r);
+                bA[r] = i < x.n && (int32_t)(i / SBH_TILE) >= (bA[r] >> 16) ? (bA[r] & 0xffff)
+                                                                          : nA;
                 lr[r] = 0;
             }
             const Scratch sc = sb_set(sb, base, b, G);
@@ -2572,17 +2594,11 @@ __global__ __launch_bounds__(UPD_THREADS) void k_sb_prep(State st, Scratch base,
                 const int L = valid ? (int)__hip_atomic_load(lead + p0, __ATOMIC_RELAXED,
                                                              __HIP_MEMORY_SCOPE_WAVEFRONT)
                                     : 0;
-                uint64_t m = ballot(valid);
-#pragma unroll
-                for (int bit = 0; bit < 6; ++bit) {
-                    const bool on = (L >> bit) & 1;
-                    const uint64_t bb = ballot(on);
-                    m &= on ? bb : ~bb;
-                }
+                const uint64_t m = match_lane_id(valid, L);
                 if (valid) {
-                    const uint64_t below = m & lanemask_lt();
+                    const int below = lanes_below(m);
                     const int c = cnt[p0];
-                    const int32_t rank = c + __popcll(below);
+                    const int32_t rank = c + below;
                     if (below == 0) cnt[p0] = (uint16_t)(c + __popcll(m));
                     const int32_t k = l1[r] - l0[r];
                     const int32_t first = k - min(k, W);  // rank of the first survivor

@@ -158,6 +158,7 @@ int alloc_set(Scratch &b, int64_t G) {
 // Buffers of the several-batch path.
 void free_sb(SbBufs &b) {
     dfree(b.kt);
+    dfree(b.cut);
     dfree(b.kh);
     dfree(b.sbad);
     dfree(b.bucket);
@@ -181,6 +182,7 @@ void free_sb(SbBufs &b) {
 int alloc_sb(SbBufs &b, int64_t G) {
     int rc = dalloc(&b.kh, G * SB_K);
     if (rc == CQ_OK) rc = dalloc(&b.kt, (int64_t)SB_K * SBH_TILES * ((G + 1) / 2));
+    if (rc == CQ_OK) rc = dalloc(&b.cut, (int64_t)SB_K * G);
     if (rc == CQ_OK) rc = dalloc(&b.sbad, SB_K);
     if (rc == CQ_OK) rc = dalloc(&b.bucket, SB_K * G);
     if (rc == CQ_OK) rc = dalloc(&b.lpre, SB_K * (G + 1));
