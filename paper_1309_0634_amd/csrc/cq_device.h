@@ -150,6 +150,13 @@ __device__ __forceinline__ uint64_t match_lane_id(bool valid, int L) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// LDS accesses of other lanes of the wave seen from here on.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Lanes of mask m below this one.
 __device__ __forceinline__ int lanes_below(uint64_t m) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),

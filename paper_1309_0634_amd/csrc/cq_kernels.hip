@@ -1950,28 +1950,35 @@ template <int U>
 __device__ __forceinline__ void sb_load_groups(const SbBufs &sb, const State &st,
                                                const bool (&valid)[SB_K], int K, int h0,
                                                int stride, int end, SbGroup (&q)[U]) {
-    static_assert(SB_K == 8, "two int4 loads per group");
-    int4 ka[U], kb[U];
+    static_assert(SB_K % 4 == 0, "a group's counters load as int4s");
+    constexpr int Q = SB_K / 4;
+    int4 ka[U][Q];
     int32_t cn[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int h = min(h0 + u * stride, (int)st.G - 1);
         const int4 *p = reinterpret_cast<const int4 *>(sb.kh + (int64_t)h * SB_K);
-        ka[u] = p[0];
-        kb[u] = p[1];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) ka[u][j] = p[j];
         cn[u] = st.cnt[h];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        keep(ka[u]);
-        keep(kb[u]);
+#pragma unroll
+        for (int j = 0; j < Q; ++j) keep(ka[u][j]);
         keep(cn[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const bool in = h0 + u * stride < end;
-        const int32_t v[SB_K] = {ka[u].x, ka[u].y, ka[u].z, ka[u].w,
-                                 kb[u].x, kb[u].y, kb[u].z, kb[u].w};
+        int32_t v[SB_K];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            v[4 * j] = ka[u][j].x;
+            v[4 * j + 1] = ka[u][j].y;
+            v[4 * j + 2] = ka[u][j].z;
+            v[4 * j + 3] = ka[u][j].w;
+        }
 #pragma unroll
         for (int b = 0; b < SB_K; ++b) q[u].k[b] = (in && b < K && valid[b]) ? v[b] : 0;
         q[u].cnt0 = in ? cn[u] : 0;
@@ -2046,8 +2053,10 @@ __global__ __launch_bounds__(SBS_THREADS) void k_sb_sums(State st, Scratch base,
     own.cnt0 = g < G ? st.cnt[g] : 0;
     if (g < G) {
         int4 *kp = reinterpret_cast<int4 *>(sb.kh + (int64_t)g * SB_K);
-        kp[0] = make_int4(kc[0][tid], kc[1][tid], kc[2][tid], kc[3][tid]);
-        kp[1] = make_int4(kc[4][tid], kc[5][tid], kc[6][tid], kc[7][tid]);
+#pragma unroll
+        for (int j = 0; j < SB_K / 4; ++j)
+            kp[j] = make_int4(kc[4 * j][tid], kc[4 * j + 1][tid], kc[4 * j + 2][tid],
+                              kc[4 * j + 3][tid]);
     }
     int x[SBP_F];
     int32_t kg;
@@ -2250,10 +2259,11 @@ static_assert(SB_K * PASS_TILES_MAX <= SB_PASS_PER * SB_PASS_GRID,
 
 // LDS of a reorder workgroup (bytes): per-wave counters, then the reordered
 // tile, whose bytes hold the per-wave leader tables until the ranks are done
-constexpr int SBL_LEAD = (SB_NB_MAX + 15) & ~15;                // leader bytes per wave
+constexpr int SBL_LEAD = 2048;                                  // leader bytes per wave
 constexpr int SBL_WC = 0;                                       // u16[PASS_WAVES][SB_NB_MAX]
 constexpr int SBL_STAGE = (SBL_WC + 2 * PASS_WAVES * SB_NB_MAX + 15) & ~15;  // int2[PASS_TILE]
 constexpr int SBL_BYTES = SBL_STAGE + 8 * PASS_TILE;
+static_assert(SB_NB_MAX - 2 <= SBL_LEAD, "a leader entry for every bucket id");
 static_assert(PASS_WAVES * SBL_LEAD <= 8 * PASS_TILE, "leader tables fit the tile's bytes");
 
 // (registers for four waves per SIMD: two workgroups per CU)
@@ -2414,12 +2424,6 @@ static_assert(PASS_TILES_MAX == 4 * 64, "four runs per lane");
 static_assert(PASS_TILES_MAX <= 256, "run ids fit a byte");
 static_assert(SB_LIGHT_CAP % 512 == 0, "light buckets in halves of eight rounds");
 
-// LDS accesses of other lanes of the wave seen from here on.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Survivors, one (batch, bucket) item per wave.  A light bucket's tuples
 // are read in arrival order (its runs in tile order), ranked inside their
@@ -2652,14 +2656,15 @@ template <int U>
 __device__ __forceinline__ void apply_load(const SbBufs &sb, const State &st,
                                            const bool (&valid)[SB_K], int K, int g0,
                                            int stride, int end, ApplyGroup (&q)[U]) {
-    int4 ka[U], kb[U];
+    constexpr int Q = SB_K / 4;
+    int4 ka[U][Q];
     int32_t tx[U][SB_K];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int g = g0 + u * stride < end ? g0 + u * stride : 0;
         const int4 *p = reinterpret_cast<const int4 *>(sb.kh + (int64_t)g * SB_K);
-        ka[u] = p[0];
-        kb[u] = p[1];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) ka[u][j] = p[j];
         q[u].pos0 = st.pos[g];
         q[u].cnt0 = st.cnt[g];
         q[u].sum0 = st.sum[g];
@@ -2670,8 +2675,8 @@ __device__ __forceinline__ void apply_load(const SbBufs &sb, const State &st,
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        keep(ka[u]);
-        keep(kb[u]);
+#pragma unroll
+        for (int j = 0; j < Q; ++j) keep(ka[u][j]);
         keep(q[u].pos0);
         keep(q[u].cnt0);
         keep(q[u].sum0);
@@ -2683,8 +2688,14 @@ __device__ __forceinline__ void apply_load(const SbBufs &sb, const State &st,
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const bool in = g0 + u * stride < end;
-        const int32_t v[SB_K] = {ka[u].x, ka[u].y, ka[u].z, ka[u].w,
-                                 kb[u].x, kb[u].y, kb[u].z, kb[u].w};
+        int32_t v[SB_K];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            v[4 * j] = ka[u][j].x;
+            v[4 * j + 1] = ka[u][j].y;
+            v[4 * j + 2] = ka[u][j].z;
+            v[4 * j + 3] = ka[u][j].w;
+        }
         q[u].kg = 0;
 #pragma unroll
         for (int b = 0; b < SB_K; ++b) {
@@ -2852,6 +2863,14 @@ __device__ void apply_big(const State &st, const SbBufs &sb, const SbBatches &in
     __syncthreads();
 }
 
+// Lanes of a group's facts in the apply step's waves (A: one int per lane;
+// B: one int64 per lane, lanes [0, SB_K) a heavy item's survivor sum, lane
+// SB_K the window sum), and lanes per batch in its reductions.
+constexpr int AF_K = 0, AF_TIX = SB_K, AF_POS = 2 * SB_K, AF_CNT = 2 * SB_K + 1,
+              AF_GS = 2 * SB_K + 2, AF_BIG = 2 * SB_K + 4;
+constexpr int LPB = 64 / SB_K;
+static_assert(AF_BIG < 64 && 64 % SB_K == 0, "a group's facts fit one wave");
+
 // A 64-bit value of lane l (a wave-uniform lane).
 __device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
     const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
@@ -2859,15 +2878,14 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// Group g by one wave.  A (one int per lane): lanes 0-7 the group's
-// counters of batches 0-7, 8-15 its output positions, 16 pos, 17 cnt, 18 and
-// 19 its first survivor place and the next group's, 20 and up its flag of
-// a workgroup's group; B (one int64 per lane):
-// lanes 0-7 the heavy items' survivor sums, 8 the window sum.  Each lane
+// Group g by one wave, its facts in A and B (lanes AF_*: its counters and
+// output positions per batch, pos, cnt, its first survivor place and the
+// next group's, its flag of a workgroup's group; the heavy items' survivor
+// sums and its window sum).  Each lane
 // keeps a partial window sum per batch: survivors at places [lo_b, hi_b)
 // added, old values [0, cb_b) subtracted (batch b's window sum is then that
 // plus, while fewer than W tuples have arrived in the call, the sum before
-// it); the eight are reduced by halving, lane 8b ending with batch b's.
+// it); these are reduced by halving, lane LPB * b ending with batch b's.
 __device__ void apply_wave(const State &st, const SbBufs &sb, const SbBatches &in,
                            const Out *outs, const bool (&valid)[SB_K], int g, int32_t A,
                            int64_t B) {
@@ -2877,17 +2895,17 @@ __device__ void apply_wave(const State &st, const SbBufs &sb, const SbBatches &i
     q.kg = 0;
 #pragma unroll
     for (int b = 0; b < SB_K; ++b) {
-        const int32_t k = __builtin_amdgcn_readlane(A, b);
+        const int32_t k = __builtin_amdgcn_readlane(A, AF_K + b);
         q.k[b] = (b < in.K && valid[b]) ? k : 0;
-        q.tix[b] = __builtin_amdgcn_readlane(A, 8 + b);
+        q.tix[b] = __builtin_amdgcn_readlane(A, AF_TIX + b);
         q.kg += q.k[b];
     }
     if (q.kg == 0) return;
-    q.pos0 = __builtin_amdgcn_readlane(A, 16);
-    q.cnt0 = __builtin_amdgcn_readlane(A, 17);
-    q.gs = __builtin_amdgcn_readlane(A, 18);
-    q.m = __builtin_amdgcn_readlane(A, 19) - q.gs;
-    q.sum0 = readlane64(B, 8);
+    q.pos0 = __builtin_amdgcn_readlane(A, AF_POS);
+    q.cnt0 = __builtin_amdgcn_readlane(A, AF_CNT);
+    q.gs = __builtin_amdgcn_readlane(A, AF_GS);
+    q.m = __builtin_amdgcn_readlane(A, AF_GS + 1) - q.gs;
+    q.sum0 = readlane64(B, SB_K);
     q.lold = q.cnt0 > 0 ? min(W, q.kg) : 0;
     int32_t lo[SB_K], hi[SB_K], cb[SB_K];
     bool whole[SB_K];  // the batch's own survivors are the window: its sum is known
@@ -2987,17 +3005,17 @@ __device__ void apply_wave(const State &st, const SbBufs &sb, const SbBatches &i
             }
         }
 #pragma unroll
-        for (int off = 4; off >= 1; off >>= 1) acc[0] += __shfl_xor(acc[0], off, 64);
+        for (int off = LPB / 2; off >= 1; off >>= 1) acc[0] += __shfl_xor(acc[0], off, 64);
         // window sums: the sum before the call plus the segments up to b
-        const int bl = lane >> 3;
+        const int bl = lane / LPB;
         long long run = q.sum0, mine = 0;
 #pragma unroll
         for (int b = 0; b < SB_K; ++b) {
-            run += readlane64(acc[0], 8 * b);
+            run += readlane64(acc[0], LPB * b);
             mine = bl == b ? run : mine;
         }
         const LaneBatch lb = lane_batch(q, bl, W);
-        if ((lane & 7) == 0) apply_emit_lane(st, sb, outs, q, g, lb, bl, mine, false);
+        if (lane % LPB == 0) apply_emit_lane(st, sb, outs, q, g, lb, bl, mine, false);
         return;
     }
     // One pass over the old values [0, lold) and then the survivors [x_from,
@@ -3057,12 +3075,12 @@ __device__ void apply_wave(const State &st, const SbBufs &sb, const SbBatches &i
         }
     }
 #pragma unroll
-    for (int off = 4; off >= 1; off >>= 1) acc[0] += __shfl_xor(acc[0], off, 64);
-    // lane 8b: batch b (a whole batch's sum is in lane b's B)
-    const int bl = lane >> 3;
+    for (int off = LPB / 2; off >= 1; off >>= 1) acc[0] += __shfl_xor(acc[0], off, 64);
+    // lane LPB * b: batch b (a whole batch's sum is in lane b's B)
+    const int bl = lane / LPB;
     const LaneBatch lb = lane_batch(q, bl, W);
     const long long tbl = __shfl(B, bl, 64);
-    if ((lane & 7) == 0) apply_emit_lane(st, sb, outs, q, g, lb, bl, lb.whole ? tbl : acc[0]);
+    if (lane % LPB == 0) apply_emit_lane(st, sb, outs, q, g, lb, bl, lb.whole ? tbl : acc[0]);
 }
 
 __global__ __launch_bounds__(APPLY_THREADS, 4) void k_sb_apply(State st, Scratch base, SbBufs sb,
@@ -3102,16 +3120,16 @@ __global__ __launch_bounds__(APPLY_THREADS, 4) void k_sb_apply(State st, Scratch
     const int NWV = wgs * (APPLY_THREADS / 64);
     auto facts = [&](int g, int32_t &A, int64_t &B) {
         g = min(g, G - 1);
-        const int b = lane & 7;
+        const int b = lane % SB_K;
         const int bb = b < K ? b : 0;
-        const int32_t *pa = lane < 8    ? sb.kh + (int64_t)g * SB_K + b
-                            : lane < 16 ? sb.tidx + (int64_t)bb * G + g
-                            : lane == 16 ? st.pos + g
-                            : lane == 17 ? st.cnt + g
-                            : lane == 18 ? sb.gsb + g
-                            : lane == 19 ? sb.gsb + g + 1
-                                         : sb.gbig + g;
-        const int64_t *pb = lane < 8 ? sb.tb + (int64_t)bb * G + g : st.sum + g;
+        const int32_t *pa = lane < AF_TIX   ? sb.kh + (int64_t)g * SB_K + b
+                            : lane < AF_POS ? sb.tidx + (int64_t)bb * G + g
+                            : lane == AF_POS ? st.pos + g
+                            : lane == AF_CNT ? st.cnt + g
+                            : lane == AF_GS ? sb.gsb + g
+                            : lane == AF_GS + 1 ? sb.gsb + g + 1
+                                                : sb.gbig + g;
+        const int64_t *pb = lane < SB_K ? sb.tb + (int64_t)bb * G + g : st.sum + g;
         A = *pa;
         B = *pb;
     };
@@ -3125,7 +3143,7 @@ __global__ __launch_bounds__(APPLY_THREADS, 4) void k_sb_apply(State st, Scratch
         facts(g + NWV, A1, B1);
         keep(A0);
         keep(B0);
-        if (!__builtin_amdgcn_readlane(A0, 20))  // (else a workgroup's)
+        if (!__builtin_amdgcn_readlane(A0, AF_BIG))  // (else a workgroup's)
             apply_wave(st, sb, in, outs, valid, g, A0, B0);
         A0 = A1;
         B0 = B1;
