@@ -2765,17 +2765,29 @@ __device__ __forceinline__ void apply_emit_lane(const State &st, const SbBufs &s
     }
 }
 
+// LDS of a workgroup's big group: the sorted boundaries of the batches'
+// survivor ranges and old-value prefixes, and the sums between them.
+struct BigLds {
+    int32_t np, no;
+    int32_t pts[2 * SB_K + 2];
+    int32_t opts[SB_K + 2];
+    unsigned long long seg[2 * SB_K + 1];
+    unsigned long long oseg[SB_K + 1];
+};
+
 // Group g by a whole workgroup (its survivors plus old values read exceed
 // APPLY_BUDGET).  Batch b's window sum: the survivors at places [lo_b, hi_b)
 // plus, while fewer than W tuples have arrived in the call, the window before
 // the call less its first c_b values.  A batch holding at least
-// max(W, SB_HEAVY_MIN) of its tuples was a heavy item whose survivors' sum the
-// prep step left; the others are summed here, each thread adding what it
-// reads to (survivors) or subtracting it from (old values) every batch whose
-// range holds it.
+// max(W, SB_HEAVY_MIN) of its tuples was a heavy item whose survivors' sum
+// the prep step left.  The others come from sums between consecutive
+// boundaries (the lo_b and hi_b of the survivors, the c_b of the old values,
+// sorted): each thread walks its values in increasing place, adds each to a
+// running sum and, where it passes a boundary, adds that sum into the
+// boundary's segment in LDS; batch b's part is then the segments inside its
+// range.
 __device__ void apply_big(const State &st, const SbBufs &sb, const SbBatches &in,
-                          const Out *outs, const bool (&valid)[SB_K], int g, long long *red) {
-    constexpr int NW = APPLY_THREADS / 64;
+                          const Out *outs, const bool (&valid)[SB_K], int g, BigLds &bl) {
     const int tid = threadIdx.x;
     const int32_t W = st.W;
     ApplyGroup qq[1];
@@ -2799,64 +2811,112 @@ __device__ void apply_big(const State &st, const SbBufs &sb, const SbBatches &in
             need_o |= cb[b] > 0;
         }
     }
-    long long acc[SB_K];
+    const int32_t keep_from = q.m - min(W, q.kg);
+    const int32_t x_from = need_x ? 0 : keep_from;
+    if (tid == 0) {
+        // the survivors' boundaries: lo_b and hi_b of the batches summed here
+        // (a batch not summed repeats the previous boundary, so that both
+        // lists ascend), merged by counting, between x_from and m; the old
+        // values' boundaries c_b likewise
+        int32_t a[SB_K], z[SB_K], o[SB_K];
+        int32_t la = x_from, lz = x_from, lc = 0;
 #pragma unroll
-    for (int b = 0; b < SB_K; ++b) acc[b] = 0;
-    constexpr int U = 4;
-    if (need_o) {
-        for (int i0 = tid; i0 < q.lold; i0 += U * APPLY_THREADS) {
+        for (int b = 0; b < SB_K; ++b) {
+            const bool sum_b = q.k[b] > 0 && !whole[b];
+            la = sum_b ? lo[b] : la;
+            lz = sum_b ? hi[b] : lz;
+            lc = cb[b] > 0 ? cb[b] : lc;
+            a[b] = la;
+            z[b] = lz;
+            o[b] = lc;
+        }
+#pragma unroll
+        for (int i = 0; i < SB_K; ++i) {
+            int pa = i, pz = i;
+#pragma unroll
+            for (int j = 0; j < SB_K; ++j) {
+                pa += z[j] < a[i] ? 1 : 0;
+                pz += a[j] <= z[i] ? 1 : 0;
+            }
+            bl.pts[1 + pa] = a[i];
+            bl.pts[1 + pz] = z[i];
+            bl.opts[1 + i] = o[i];
+        }
+        bl.pts[0] = x_from;
+        bl.pts[2 * SB_K + 1] = q.m;
+        bl.np = 2 * SB_K + 2;
+        bl.opts[0] = 0;
+        bl.opts[SB_K + 1] = q.lold;
+        bl.no = SB_K + 2;
+#pragma unroll
+        for (int k = 0; k < 2 * SB_K + 1; ++k) bl.seg[k] = 0;
+#pragma unroll
+        for (int k = 0; k < SB_K + 1; ++k) bl.oseg[k] = 0;
+    }
+    __syncthreads();
+    constexpr int U = 8;
+    // One thread's walk over places [x0, x1) in increasing order: each value
+    // (value(x, false) loads it, value(x, true, v) is told it) added to the
+    // segment [pts[cs], pts[cs + 1]) that holds it.
+    auto walk = [&](const int32_t *pts, unsigned long long *seg, int32_t x0, int32_t x1,
+                    auto &&value) {
+        int cs = 0;
+        int32_t nextb = pts[1];
+        long long cur = 0;
+        for (int e0 = x0 + tid; e0 < x1; e0 += U * APPLY_THREADS) {
             int32_t v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                v[u] = apply_old(st, g, q.pos0, q.cnt0, min(i0 + u * APPLY_THREADS, q.lold - 1));
+            for (int u = 0; u < U; ++u) v[u] = value(min(e0 + u * APPLY_THREADS, x1 - 1), false);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * APPLY_THREADS;
-#pragma unroll
-                for (int b = 0; b < SB_K; ++b) acc[b] -= (i < q.lold && i < cb[b]) ? v[u] : 0;
+                const int32_t x = e0 + u * APPLY_THREADS;
+                if (x >= x1) break;
+                while (x >= nextb) {
+                    if (cur) atomicAdd(&seg[cs], (unsigned long long)cur);
+                    cur = 0;
+                    nextb = pts[++cs + 1];
+                }
+                cur += v[u];
+                value(x, true, v[u]);
             }
         }
-    }
+        if (cur) atomicAdd(&seg[cs], (unsigned long long)cur);
+    };
+    if (need_o)
+        walk(bl.opts, bl.oseg, 0, q.lold, [&](int32_t i, bool store, int32_t = 0) {
+            return store ? 0 : apply_old(st, g, q.pos0, q.cnt0, i);
+        });
     __syncthreads();  // (every old value has been read: the ring may change now)
     // the survivors: summed where a batch needs them, and the final window,
     // the last min(W, kg), written to the ring as they are read
-    const int32_t keep_from = q.m - min(W, q.kg);
-    const int32_t x_from = need_x ? 0 : keep_from;
     const uint32_t slot0 =
         (uint32_t)(((int64_t)q.pos0 + q.kg - min(W, q.kg)) % (int64_t)W);  // of keep_from
     int32_t *ring = st.ring + (int64_t)g * W;
-    for (int e0 = x_from + tid; e0 < q.m; e0 += U * APPLY_THREADS) {
-        int32_t v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = sb.xs[q.gs + min(e0 + u * APPLY_THREADS, q.m - 1)];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * APPLY_THREADS;
-            if (e >= q.m) break;
-            if (need_x) {
-#pragma unroll
-                for (int b = 0; b < SB_K; ++b)
-                    acc[b] += (!whole[b] && e >= lo[b] && e < hi[b]) ? v[u] : 0;
-            }
-            if (e >= keep_from) {
-                uint32_t slot = slot0 + (uint32_t)(e - keep_from);
-                slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
-                ring[slot] = v[u];
-            }
+    walk(bl.pts, bl.seg, x_from, q.m, [&](int32_t p, bool store, int32_t v = 0) {
+        if (!store) return sb.xs[q.gs + p];
+        if (p >= keep_from) {
+            uint32_t slot = slot0 + (uint32_t)(p - keep_from);
+            slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
+            ring[slot] = v;
         }
-    }
-    // block sums of the SB_K partial sums
-    const int lane = lane_id(), wid = tid >> 6;
-#pragma unroll
-    for (int b = 0; b < SB_K; ++b) {
-        const long long t = wave_sum_ll(acc[b]);
-        if (lane == 0) red[b * NW + wid] = t;
-    }
+        return 0;
+    });
     __syncthreads();
     if (tid < SB_K) {  // thread b: batch b
         const LaneBatch lb = lane_batch(q, tid, W);
+        int32_t blo = 0, bhi = 0, bcb = 0;
+#pragma unroll
+        for (int b = 0; b < SB_K; ++b)
+            if (tid == b) {
+                blo = lo[b];
+                bhi = hi[b];
+                bcb = cb[b];
+            }
         long long t = 0;
-        for (int w = 0; w < NW; ++w) t += red[tid * NW + w];
+        for (int k = 0; k + 1 < bl.np; ++k)
+            if (bl.pts[k] >= blo && bl.pts[k + 1] <= bhi) t += (long long)bl.seg[k];
+        for (int k = 0; k + 1 < bl.no; ++k)
+            if (bl.opts[k + 1] <= bcb) t -= (long long)bl.oseg[k];
         if (lb.whole) t = sb.tb[(int64_t)(tid < in.K ? tid : 0) * st.G + g];
         apply_emit_lane(st, sb, outs, q, g, lb, tid, t);
     }
@@ -3085,7 +3145,7 @@ __device__ void apply_wave(const State &st, const SbBufs &sb, const SbBatches &i
 
 __global__ __launch_bounds__(APPLY_THREADS, 4) void k_sb_apply(State st, Scratch base, SbBufs sb,
                                                             SbBatches in, int32_t seq) {
-    __shared__ long long red[SB_K * (APPLY_THREADS / 64)];
+    __shared__ BigLds bigl;
     __shared__ Out outs[SB_K];  // (indexed by lane: the argument's copy is per batch)
     const int K = in.K;
     const int G = (int)st.G;
@@ -3108,7 +3168,7 @@ __global__ __launch_bounds__(APPLY_THREADS, 4) void k_sb_apply(State st, Scratch
     const int nbw = min(nbig, grid);
     const int bw = grid - 1 - (int)blockIdx.x;  // this workgroup's place from the top
     for (int i = bw; i < nbig; i += grid) {
-        apply_big(st, sb, in, outs, valid, sb.big[i], red);
+        apply_big(st, sb, in, outs, valid, sb.big[i], bigl);
         if (i == bw) phase_mark(base, PHASE_SB_APPLY, 1);
     }
     phase_mark(base, PHASE_SB_APPLY, 2);
