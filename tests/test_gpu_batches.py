@@ -177,3 +177,39 @@ def test_bench_arrays_eight_per_call(s):
                         f"s={s} push {c0 + j} (batch {idx[j]})")
     _no_fault(q)
     q.close(), o.close()
+
+
+@pytest.mark.parametrize("G,W", [(1, 1), (1, 3), (2, 1), (3, 4096)])
+def test_degenerate_shapes(G, W):
+    """One to three groups (every key the same few), windows of 1 to 4096,
+    batches of 0, 1 and 2^20 tuples inside one call."""
+    note(f"case: several-batch path, G={G} W={W}")
+    rng = np.random.default_rng([G, W])
+    q, o = cq.Query(G, W), RingOracle(G, W)
+    sizes = [0, 1, 1 << 20, 5, 0, 70000, 1, 3]
+    bs = [(rng.integers(0, G, n).astype(np.int32), rng.integers(-10 ** 6, 10 ** 6, n).astype(np.int32))
+          for n in sizes]
+    check_against_oracle(q, o, G, bs, f"G={G} W={W}")
+    check_against_oracle(q, o, G, bs[:3], f"G={G} W={W} again")
+    _no_fault(q)
+    q.close(), o.close()
+
+
+def test_every_group_touched_at_the_group_limit():
+    """16,384 groups, each touched in every batch (a probe of all groups
+    plus random keys), W=2 and W=700, so every group's window turns over."""
+    from workloads import probe_batch
+    for W in (2, 700):
+        note(f"case: several-batch path, all 16384 groups touched, W={W}")
+        rng = np.random.default_rng(W)
+        G = 16384
+        q, o = cq.Query(G, W), RingOracle(G, W)
+        pk, pv = probe_batch(G)
+        bs = []
+        for i in range(8):
+            k = np.concatenate([pk, rng.integers(0, G, 40000).astype(np.int32)])
+            v = np.concatenate([pv, rng.integers(0, 10 ** 6, 40000).astype(np.int32)])
+            bs.append((k, v))
+        check_against_oracle(q, o, G, bs, f"all touched W={W}")
+        _no_fault(q)
+        q.close(), o.close()
