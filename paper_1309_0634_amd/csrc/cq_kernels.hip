@@ -1301,8 +1301,14 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
     const int32_t *klp = reinterpret_cast<const int32_t *>(smem + U_KLP);
     const int32_t *kpo = reinterpret_cast<const int32_t *>(smem + U_KPO);
     constexpr bool in_lds = IN_LDS;
-    auto lp = [&](int32_t g) { return in_lds ? klp[g - a] : sc.lpre[g]; };
-    auto po = [&](int32_t g) { return in_lds ? kpo[g - a] : sc.pold[g]; };
+    // (the per-group arrays as global pointers: held in a struct, they would
+    // otherwise be accessed as generic memory)
+    const auto lpre = global_ptr(sc.lpre), pold = global_ptr(sc.pold);
+    const auto ncnt = global_ptr(sc.ncnt), tidx = global_ptr(sc.tidx);
+    const auto gsm = global_ptr(st.sum);
+    const auto ring = global_ptr(st.ring);
+    auto lp = [&](int32_t g) { return in_lds ? klp[g - a] : lpre[g]; };
+    auto po = [&](int32_t g) { return in_lds ? kpo[g - a] : pold[g]; };
     const int32_t s0 = lp(a);
     const int chunk = (size + UPD_WAVES - 1) / UPD_WAVES;
     constexpr int SPT = LIGHT_CAP / UPD_THREADS;
@@ -1322,15 +1328,15 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
             const int32_t g = a + tid + j * UPD_THREADS;
             const bool t = g < z && klp[g - a + 1] > klp[g - a];
             const int32_t gl = t ? g : a;
-            gsum[j] = st.sum[gl];  // (raw: read only for a touched group, below)
-            gcnt[j] = sc.ncnt[gl];
-            gtix[j] = sc.tidx[gl];
+            gsum[j] = gsm[gl];  // (raw: read only for a touched group, below)
+            gcnt[j] = ncnt[gl];
+            gtix[j] = tidx[gl];
         }
     }
     // ring update: every survivor's old value is loaded before any store
     // (unconditionally, from the ring's first cell where there is none to
     // read, so that the loads are in flight together)
-    int32_t *cells[SPT];
+    int64_t cells[SPT];  // ring index of the slot a survivor takes (-1: none)
     int32_t olds[SPT];
     bool keep[SPT];  // the old value counts: a survivor whose window is not replaced
     // (without the LDS copy, each position's group bounds and old ring
@@ -1341,7 +1347,8 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
 #pragma unroll
         for (int j = 0; j < SPT; ++j) {
             const int p = tid + j * UPD_THREADS;
-            const int32_t g = p < size && pz[p] >= 0 ? ek[p] : a;
+            const int32_t e = ek[p];  // (read apart from the select: p < LIGHT_CAP)
+            const int32_t g = p < size && pz[p] >= 0 ? e : a;
             kq[j] = lp(g + 1) - lp(g);
             oq[j] = po(g);
         }
@@ -1349,7 +1356,7 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
         const int p = tid + j * UPD_THREADS;
-        cells[j] = nullptr;
+        cells[j] = -1;
         keep[j] = false;
         if (p >= size) continue;
         const int p0 = pz[p];
@@ -1365,21 +1372,21 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
         if (rank >= kg - need && rank < kg) {
             const uint32_t slot =
                 ((uint32_t)(IN_LDS ? po(g) : oq[j]) + (uint32_t)rank) % (uint32_t)W;
-            cells[j] = st.ring + (int64_t)g * W + slot;
+            cells[j] = (int64_t)g * W + slot;
             keep[j] = kg < W;
         }
     }
 #pragma unroll
-    for (int j = 0; j < SPT; ++j) {  // (an index, so that the load stays a global one)
-        const int32_t o = st.ring[cells[j] ? cells[j] - st.ring : 0];
+    for (int j = 0; j < SPT; ++j) {
+        const int32_t o = ring[cells[j] >= 0 ? cells[j] : 0];
         olds[j] = keep[j] ? o : 0;
     }
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
-        if (!cells[j]) continue;
+        if (cells[j] < 0) continue;
         const int p = tid + j * UPD_THREADS;
         const int32_t v = ev[p];
-        *cells[j] = v;
+        ring[cells[j]] = v;
         atomicAdd(reinterpret_cast<unsigned long long *>(&acc[pz[p]]),
                   (unsigned long long)((long long)v - (long long)olds[j]));
     }
@@ -1394,7 +1401,7 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
                 // replaced whole: its new sum is the survivors' sum alone
                 const int64_t s = (klp[g - a + 1] - klp[g - a] < W ? gsum[j] : 0) +
                                   acc[klp[g - a] - s0];
-                st.sum[g] = s;
+                gsm[g] = s;
                 if (out.n_touched) emit_one(out, gtix[j], g, s, gcnt[j]);
             }
         }
@@ -1409,9 +1416,9 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
             gh[j] = i < size && hd[i] >= 0 ? ek[hd[i]] : -1;
             const int32_t g = gh[j] >= 0 ? gh[j] : a;
             kh[j] = lp(g + 1) - lp(g);
-            sh[j] = st.sum[g];
-            th[j] = sc.tidx[g];
-            nh[j] = sc.ncnt[g];
+            sh[j] = gsm[g];
+            th[j] = tidx[g];
+            nh[j] = ncnt[g];
         }
 #pragma unroll
         for (int j = 0; j < SPT; ++j) {
@@ -1419,7 +1426,7 @@ __device__ int light_bucket(int32_t a, int32_t z, int size, int tiles, const Sta
             const int32_t g = gh[j];
             if (g >= 0) {
                 const int64_t s = (kh[j] >= W ? 0 : sh[j]) + acc[i];
-                st.sum[g] = s;
+                gsm[g] = s;
                 if (out.n_touched) emit_one(out, th[j], g, s, nh[j]);
             }
         }
