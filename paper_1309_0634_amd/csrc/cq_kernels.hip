@@ -943,20 +943,22 @@ __device__ __forceinline__ void pass_split(const int32_t (&key)[PASS_ROUNDS],
         }
     }
     __syncthreads();
-    // two staged tuples per 16-byte store (the tile starts 32 KB-aligned;
-    // an odd last tuple of a ragged tile is stored alone)
+    // the staged tuples (those of a bucket; fewer than the tile's when some
+    // were dropped), two per 16-byte store (the tile starts 32 KB-aligned;
+    // an odd last tuple is stored alone)
     before_stores();
     // (fixed trip counts, stores predicated: the number of stores in flight
     // is then known where later loads are waited for)
+    const int kept = ts[NB];
     int2 *dst = sc.sdat + base;
     const int4 *st4 = reinterpret_cast<const int4 *>(stage);
     int4 *dst4 = reinterpret_cast<int4 *>(dst);
 #pragma unroll
     for (int j = 0; j < PASS_TILE / 2 / PASS_THREADS; ++j) {
         const int i = tid + j * PASS_THREADS;
-        if (i < tile_n / 2) dst4[i] = st4[i];
+        if (i < kept / 2) dst4[i] = st4[i];
     }
-    if ((tile_n & 1) && tid == 0) dst[tile_n - 1] = stage[tile_n - 1];
+    if ((kept & 1) && tid == 0) dst[kept - 1] = stage[kept - 1];
     int32_t *row = sc.rowstart + (int64_t)tile * (NB + 1);
 #pragma unroll
     for (int j = 0; j < (NBM + PASS_THREADS) / PASS_THREADS; ++j) {
