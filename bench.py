@@ -9,9 +9,10 @@ All batches are generated on the device and resident in HBM before timing.
 Reported: tuples/s and algorithmic HBM GB/s for s in {0, 0.5, 1, 1.5, 2},
 balanced vs static partition, p50/p99 batch latency, and the imbalance of
 the per-group phase (per-CU busy-time spread, per-workgroup tuple loads).
-The headline value is s=1.5, balanced, with the batches pushed eight per
-cq_push_batches call (--per-call): every batch's results are emitted into
-its own buffers, and eight batches share one set of launches.  The same
+The headline value is s=1.5, balanced, with the batches pushed up to
+sixteen per cq_push_batches call (--per-call; the timed batches are cut
+into calls of near-equal size): every batch's results are emitted into its
+own buffers, and a call's batches share one set of launches.  The same
 batches one cq_push_batch_results call each are reported beside it, and the
 static partition runs one batch per call.  Throughput, batch latency (an
 event pair per call: a batch's results are complete when its call's work
@@ -109,15 +110,20 @@ def run_mode(torch, cq, batches, cfg, mode, warmup, steps, kind="clean", per_cal
         else:
             q.push_batches_into(batches[i0:i1], outs[:i1 - i0])
 
-    for i0 in range(0, warmup, per_call):
-        push(i0, min(warmup, i0 + per_call))
+    def cut(a, z):  # [a, z) in ceil((z - a) / per_call) calls of near-equal size
+        n = z - a
+        k = -(-n // per_call)
+        edges = [a + (n * c) // k for c in range(k + 1)]
+        return list(zip(edges[:-1], edges[1:]))
+
+    for i0, i1 in cut(0, warmup):
+        push(i0, i1)
     torch.cuda.synchronize()
     if kind == "kernels":
         q.set_telemetry(cq.TELEMETRY_KERNEL_TIMES)
         q.kernel_times()
     res = {}
-    calls = [(i0, min(warmup + steps, i0 + per_call))
-             for i0 in range(warmup, warmup + steps, per_call)]
+    calls = cut(warmup, warmup + steps)
     if kind == "latency":
         starts = [torch.cuda.Event(enable_timing=True) for _ in calls]
         ends = [torch.cuda.Event(enable_timing=True) for _ in calls]
@@ -635,7 +641,7 @@ def main():
     ap.add_argument("--serving", default="10,50,100,250,500",
                     help="arrival rates (batches/s) of the serving loop ('' skips it)")
     ap.add_argument("--serving-seconds", type=float, default=3.0)
-    ap.add_argument("--per-call", type=int, default=8,
+    ap.add_argument("--per-call", type=int, default=16,
                     help="batches per cq_push_batches call of the balanced partition")
     ap.add_argument("--calibrate", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (counter calibration)")

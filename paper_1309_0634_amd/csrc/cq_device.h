@@ -32,6 +32,27 @@ __device__ __forceinline__ int wave_incl_add(int x) {
     return x;
 }
 
+// One step of wave_incl_add64: both halves of the source lane's partial sum
+// moved by the DPP control, added as one 64-bit value.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ long long dpp_add64(long long x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)((uint64_t)x >> 32), CTRL,
+                                               ROW_MASK, 0xf, false);
+    return x + (long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// The inclusive prefix sum of wave_incl_add for 64-bit values.
+__device__ __forceinline__ long long wave_incl_add64(long long x) {
+    x = dpp_add64<0x111, 0xf>(x);  // row_shr:1
+    x = dpp_add64<0x112, 0xf>(x);  // row_shr:2
+    x = dpp_add64<0x114, 0xf>(x);  // row_shr:4
+    x = dpp_add64<0x118, 0xf>(x);  // row_shr:8
+    x = dpp_add64<0x142, 0xa>(x);  // row_bcast:15
+    x = dpp_add64<0x143, 0xc>(x);  // row_bcast:31
+    return x;
+}
+
 __device__ __forceinline__ int wave_total(int incl) { return __builtin_amdgcn_readlane(incl, 63); }
 
 // Inclusive running maximum over the 64 lanes of non-negative values (the

@@ -170,7 +170,7 @@ struct Out {
 // each batch, which are the only ones any emitted window holds -- get
 // consecutive places per group (batch by batch, arrival order), so that
 // every batch's window sums are differences of prefix sums.
-constexpr int SB_K = 8;
+constexpr int SB_K = 16;
 // The several-batch path's buckets: a group with at least SB_HEAVY_MIN
 // tuples of a batch is heavy, the others are packed into buckets of about
 // SB_LIGHT_BUDGET tuples (fewer than SB_LIGHT_CAP).  Fewer, larger buckets
@@ -181,11 +181,12 @@ constexpr int SB_HEAVY_MIN = 1024;
 constexpr int SB_LIGHT_CAP = SB_LIGHT_BUDGET + SB_HEAVY_MIN;
 constexpr int SB_NB_MAX = SUB / SB_LIGHT_BUDGET + SUB / SB_HEAVY_MIN + 2;
 static_assert(SB_NB_MAX <= NB_MAX, "the bucket tables are sized for the single-batch bound");
-// histogram blocks of the several-batch path count SBH_KPT keys per thread
-// of one batch and store every group's count (16 bits) of their tile; the
-// plan sums a group's tiles
-constexpr int SBH_KPT = 4 * HIST_KPT;
-constexpr int SBH_TILE = HIST_THREADS * SBH_KPT;
+// histogram blocks of the several-batch path (SBH_THREADS threads) count
+// SBH_KPT keys per thread of one batch and store every group's count (16
+// bits) of their tile; the plan sums a group's tiles
+constexpr int SBH_THREADS = 512;
+constexpr int SBH_KPT = 64;
+constexpr int SBH_TILE = SBH_THREADS * SBH_KPT;
 constexpr int SBH_TILES = (SUB + SBH_TILE - 1) / SBH_TILE;  // per batch at most
 static_assert(SBH_TILE < 65536, "a tile's count of a group fits 16 bits");
 static_assert(SBH_TILES < 256 && SB_NB_MAX < 65536, "a dropped-tile count and a bucket id share an int");
@@ -217,7 +218,7 @@ struct SbBufs {
     uint32_t *kt;       // [SB_K][SBH_TILES][(G + 1) / 2] per histogram tile, groups
                         // 2i and 2i + 1 in the low and high 16 bits of word i
     int32_t *kh;        // [G][SB_K] per-batch histograms, a group's counts together
-    uint8_t *cut;       // [SB_K][G] a heavy group's leading histogram tiles holding
+    uint8_t *cut;       // [G][SB_K] a heavy group's leading histogram tiles holding
                         // none of its last W tuples of the batch
     int32_t *sbad;      // [SB_K] sequence number of the last call whose batch b had a bad key
     int32_t *bucket;    // [SB_K][G]

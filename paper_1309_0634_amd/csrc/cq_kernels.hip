@@ -250,7 +250,7 @@ __device__ __forceinline__ void hist_small_tile(const int32_t *__restrict__ keys
                                                 bool vec, int32_t G, const Scratch &sc,
                                                 int32_t seq, int tile, int ntiles,
                                                 int32_t *kout, int kstride, int32_t *badout,
-                                                int32_t *cntr, uint32_t *dense = nullptr) {
+                                                int32_t *cntr) {
     static_assert(KPT % 4 == 0, "keys loaded four at a time");
     const int tid = threadIdx.x;
     phase_mark(sc, PHASE_HIST_PLAN, 0);
@@ -300,15 +300,6 @@ __device__ __forceinline__ void hist_small_tile(const int32_t *__restrict__ keys
         if (tid == 0) atomicExch(badout, seq);
     }
     phase_mark(sc, PHASE_HIST_PLAN, 1);
-    if (dense) {
-        for (int i = tid; 2 * i < G; i += HIST_THREADS) {
-            const uint32_t lo = (uint32_t)cntr[2 * i];
-            const uint32_t hi = 2 * i + 1 < G ? (uint32_t)cntr[2 * i + 1] : 0u;
-            dense[i] = lo | hi << 16;
-        }
-        phase_mark(sc, PHASE_HIST_PLAN, 2);
-        return;
-    }
     // blocks start their flush at evenly spread groups, so that they do not
     // all hit the same counters at the same time
     const int off = (int)(((int64_t)tile * G / ntiles) & ~63);
@@ -1909,16 +1900,72 @@ __device__ __forceinline__ int sb_batch_of(const int32_t *tile0, int K, int t) {
     return b;
 }
 
-__global__ __launch_bounds__(HIST_THREADS) void k_sb_hist(Scratch base, SbBufs sb,
-                                                          SbBatches in, int32_t G,
-                                                          int32_t seq) {
-    extern __shared__ int32_t cntr[];
-    const int t = (int)blockIdx.x;
+// One histogram tile of one batch per block: its SBH_TILE keys (all of a
+// thread's loads in flight together) counted in LDS as pairs of 16-bit
+// counters, group 2i in the low half of word i and 2i + 1 in the high half
+// (a tile's count of a group fits 16 bits, so a half never carries into the
+// other), the previous call's two most frequent groups in registers; the
+// words are the per-tile table's entries as they stand.
+__global__ __launch_bounds__(SBH_THREADS) void k_sb_hist(Scratch base, SbBufs sb,
+                                                         SbBatches in, int32_t G,
+                                                         int32_t seq) {
+    static_assert(SBH_KPT % 4 == 0, "keys loaded four at a time");
+    extern __shared__ uint32_t cpair[];
+    const int t = (int)blockIdx.x, tid = (int)threadIdx.x;
     const int b = sb_batch_of(in.htile0, in.K, t);
     const int tile = t - in.htile0[b];
-    hist_small_tile<SBH_KPT>(in.keys[b], in.n[b], (in.vec >> b) & 1u, G, base, seq, tile,
-                             in.htile0[b + 1] - in.htile0[b], nullptr, 0, sb.sbad + b, cntr,
-                             sb.kt + ((int64_t)b * SBH_TILES + tile) * ((G + 1) / 2));
+    const int32_t *keys = in.keys[b];
+    const int64_t n = in.n[b];
+    const bool vec = (in.vec >> b) & 1u;
+    const int words = (G + 1) / 2;
+    phase_mark(base, PHASE_HIST_PLAN, 0);
+    const int32_t hot0 = base.hot[0], hot1 = base.hot[1];
+    for (int i = tid; i < words; i += SBH_THREADS) cpair[i] = 0;
+    const int64_t i0 = (int64_t)tile * SBH_TILE;
+    int32_t v[SBH_KPT];
+#pragma unroll
+    for (int j = 0; j < SBH_KPT / 4; ++j) {
+        const int64_t i = i0 + 4 * ((int64_t)j * SBH_THREADS + tid);
+        if (vec && i + 3 < n) {
+            const int4 x = *reinterpret_cast<const int4 *>(keys + i);
+            v[4 * j] = x.x; v[4 * j + 1] = x.y; v[4 * j + 2] = x.z; v[4 * j + 3] = x.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[4 * j + e] = (i + e < n) ? keys[i + e] : 0;
+        }
+    }
+    if (base.kmod) {
+#pragma unroll
+        for (int j = 0; j < SBH_KPT; ++j) v[j] = view_key(v[j], base.kmod, G);
+    }
+    __syncthreads();
+    int bad = 0, c0 = 0, c1 = 0;
+#pragma unroll
+    for (int j = 0; j < SBH_KPT / 4; ++j) {
+        const int64_t i = i0 + 4 * ((int64_t)j * SBH_THREADS + tid);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (i + e >= n) continue;
+            const int32_t key = v[4 * j + e];
+            if (key < 0 || key >= G) bad = 1;
+            else if (key == hot0) ++c0;
+            else if (key == hot1) ++c1;
+            else atomicAdd(&cpair[key >> 1], 1u << ((key & 1) << 4));
+        }
+    }
+    c0 = wave_total(wave_incl_add(c0));
+    c1 = wave_total(wave_incl_add(c1));
+    if (lane_id() == 0) {
+        if (c0) atomicAdd(&cpair[hot0 >> 1], (uint32_t)c0 << ((hot0 & 1) << 4));
+        if (c1) atomicAdd(&cpair[hot1 >> 1], (uint32_t)c1 << ((hot1 & 1) << 4));
+    }
+    if (__syncthreads_or(bad)) {
+        if (tid == 0) atomicExch(sb.sbad + b, seq);
+    }
+    phase_mark(base, PHASE_HIST_PLAN, 1);
+    uint32_t *dense = sb.kt + ((int64_t)b * SBH_TILES + tile) * words;
+    for (int i = tid; i < words; i += SBH_THREADS) dense[i] = cpair[i];
+    phase_mark(base, PHASE_HIST_PLAN, 2);
 }
 
 // The plan of every batch and the survivors' places, one group per thread.
@@ -2046,9 +2093,9 @@ __global__ __launch_bounds__(SBS_THREADS) void k_sb_sums(State st, Scratch base,
             }
         const int64_t gl = min((int64_t)g0 + 2 * pair, (int64_t)G - 1);
         if (g0 + 2 * pair < G)
-            sb.cut[(int64_t)b * G + gl] = (uint8_t)(lo >= SB_HEAVY_MIN ? clo : 0);
+            sb.cut[gl * SB_K + b] = (uint8_t)(lo >= SB_HEAVY_MIN ? clo : 0);
         if (g0 + 2 * pair + 1 < G)
-            sb.cut[(int64_t)b * G + gl + 1] = (uint8_t)(hi >= SB_HEAVY_MIN ? chi : 0);
+            sb.cut[(gl + 1) * SB_K + b] = (uint8_t)(hi >= SB_HEAVY_MIN ? chi : 0);
     }
     __syncthreads();
     if (tid >= 64) return;
@@ -2110,6 +2157,16 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
     for (int b = 0; b < SB_K; ++b) valid[b] = b < K && sb.sbad[b] != seq;
     SbGroup own[1];
     sb_load_groups<1>(sb, st, valid, K, g, 0, G, own);
+    // a heavy item's dropped tiles per batch (a group's SB_K bytes
+    // together), loaded here with the rest rather than in the per-batch loop
+    static_assert(SB_K % 4 == 0, "a group's dropped-tile counts load as words");
+    uint32_t cutw[SB_K / 4];
+    {
+        const uint32_t *cp =
+            reinterpret_cast<const uint32_t *>(sb.cut + (int64_t)min(g, G - 1) * SB_K);
+#pragma unroll
+        for (int j = 0; j < SB_K / 4; ++j) cutw[j] = cp[j];
+    }
     {  // every block's partials, loaded together
         constexpr int PER = (SBS_BLOCKS_MAX * SBP_PART + SBP_THREADS - 1) / SBP_THREADS;
         const int np = nblk * SBP_PART;
@@ -2180,7 +2237,7 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
             if (k > 0) {
                 sc.tidx[g] = ext;
                 if (k >= SB_HEAVY_MIN) {
-                    sc.bucket[g] = (nl + exh) | ((int32_t)sb.cut[(int64_t)b * G + g] << 16);
+                    sc.bucket[g] = (nl + exh) | (int32_t)(((cutw[b / 4] >> (8 * (b % 4))) & 0xffu) << 16);
                     if ((uint32_t)exh < (uint32_t)SB_NB_MAX) sc.hkey[exh] = g;
                 } else {
                     sc.bucket[g] = (exl + k - 1) / SB_LIGHT_BUDGET;
@@ -2198,12 +2255,14 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
         sb.gbig[g] = own_big;
         if (own_big) sb.big[ex(2 * SB_K + 1)] = g;
     }
-    if (blockIdx.x == 0) {
-        // batch b's totals by thread b (an unrolled loop: the batches'
-        // arguments are indexed by constants)
+    {
+        // batch b's totals by thread 0 of block b mod grid, so that no block
+        // writes many (an unrolled loop: the batches' arguments are indexed
+        // by constants)
+        const int grid = (int)gridDim.x;
 #pragma unroll
         for (int b = 0; b < SB_K; ++b) {
-            if (tid != b || b >= K) continue;
+            if (tid != 0 || b >= K || b % grid != (int)blockIdx.x) continue;
             const Scratch sc = sb_set(sb, base, b, G);
             PlanTotals t;
             const int32_t nl = (tot(2 * b) + SB_LIGHT_BUDGET - 1) / SB_LIGHT_BUDGET;
@@ -2224,12 +2283,14 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
             if (b == K - 1) *base.tot = t;
             if (t.n_buckets > SB_NB_MAX) atomicOr(base.fault, FAULT_BUCKETS);
         }
-        if (tid == SB_K) {
+        if (blockIdx.x == 0 && tid == 64) {
             sb.gsb[G] = tot(2 * SB_K);
             sb.ntot[0] = tot(2 * SB_K + 1);
             sb.ntot[1] = tot(2 * SB_K);
         }
-        if (wv == NW - 1) {  // the call's two most frequent groups, for the next histogram
+        // the call's two most frequent groups, for the next histogram, by the
+        // last wave of the last block
+        if (blockIdx.x == gridDim.x - 1 && wv == NW - 1) {
             Top2 top;
 #pragma unroll
             for (int j = 0; j < SBS_BLOCKS_MAX / 64; ++j) {
@@ -2624,321 +2685,12 @@ __global__ __launch_bounds__(UPD_THREADS) void k_sb_prep(State st, Scratch base,
     phase_mark(base, PHASE_SB_PREP, 5);
 }
 
-// Exclusive prefix over the block of one int64 per thread (APPLY_THREADS
-// threads); `total` gets the block's sum.  Barriers inside.
-__device__ __forceinline__ long long apply_excl_scan(long long v, long long *lds,
-                                                     long long &total) {
-    constexpr int NW = APPLY_THREADS / 64;
-    const int lane = lane_id(), wid = threadIdx.x >> 6;
-    long long x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const long long y = __shfl_up(x, o, 64);
-        x += lane >= o ? y : 0;
-    }
-    if (lane == 63) lds[wid] = x;
-    __syncthreads();
-    long long before = 0, all = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        const long long t = lds[w];
-        before += w < wid ? t : 0;
-        all += t;
-    }
-    __syncthreads();
-    total = all;
-    return before + x - v;
-}
-
-// One group's facts for the apply step (every load issued before any is
-// used; a group past the range reads group 0's and counts nothing).
-struct ApplyGroup {
-    int32_t k[SB_K];
-    int32_t tix[SB_K];  // output position per batch (meaningful where k > 0)
-    int32_t pos0, cnt0;
-    int64_t sum0;
-    int32_t gs, m;      // first place and number of its survivors
-    int32_t kg, lold;   // tuples in the call; old window values read
-};
-
-template <int U>
-__device__ __forceinline__ void apply_load(const SbBufs &sb, const State &st,
-                                           const bool (&valid)[SB_K], int K, int g0,
-                                           int stride, int end, ApplyGroup (&q)[U]) {
-    constexpr int Q = SB_K / 4;
-    int4 ka[U][Q];
-    int32_t tx[U][SB_K];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int g = g0 + u * stride < end ? g0 + u * stride : 0;
-        const int4 *p = reinterpret_cast<const int4 *>(sb.kh + (int64_t)g * SB_K);
-#pragma unroll
-        for (int j = 0; j < Q; ++j) ka[u][j] = p[j];
-        q[u].pos0 = st.pos[g];
-        q[u].cnt0 = st.cnt[g];
-        q[u].sum0 = st.sum[g];
-        q[u].gs = sb.gsb[g];
-        q[u].m = sb.gsb[g + 1];
-#pragma unroll
-        for (int b = 0; b < SB_K; ++b) tx[u][b] = sb.tidx[(int64_t)(b < K ? b : 0) * st.G + g];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-#pragma unroll
-        for (int j = 0; j < Q; ++j) keep(ka[u][j]);
-        keep(q[u].pos0);
-        keep(q[u].cnt0);
-        keep(q[u].sum0);
-        keep(q[u].gs);
-        keep(q[u].m);
-#pragma unroll
-        for (int b = 0; b < SB_K; ++b) keep(tx[u][b]);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const bool in = g0 + u * stride < end;
-        int32_t v[SB_K];
-#pragma unroll
-        for (int j = 0; j < Q; ++j) {
-            v[4 * j] = ka[u][j].x;
-            v[4 * j + 1] = ka[u][j].y;
-            v[4 * j + 2] = ka[u][j].z;
-            v[4 * j + 3] = ka[u][j].w;
-        }
-        q[u].kg = 0;
-#pragma unroll
-        for (int b = 0; b < SB_K; ++b) {
-            q[u].k[b] = (in && b < K && valid[b]) ? v[b] : 0;
-            q[u].tix[b] = tx[u][b];
-            q[u].kg += q[u].k[b];
-        }
-        q[u].m -= q[u].gs;
-        q[u].lold = (q[u].kg > 0 && q[u].cnt0 > 0) ? min(st.W, q[u].kg) : 0;
-        if (!in) q[u].kg = q[u].lold = q[u].m = 0;
-    }
-}
-
-// Old window value i (0 = oldest) of a group: slot (pos0 + i) mod W; the
-// slots a window that never filled has not reached yet hold 0 and are not
-// read.
-__device__ __forceinline__ int32_t apply_old(const State &st, int g, int32_t pos0, int32_t cnt0,
-                                             int32_t i) {
-    const int32_t W = st.W;
-    if (i < W - cnt0) return 0;
-    const uint32_t slot = ((uint32_t)pos0 + (uint32_t)i) % (uint32_t)W;
-    return st.ring[(int64_t)g * W + slot];
-}
-
-// Batch `bl`'s facts of group q for the calling lane (the batches' values
-// are wave-uniform; a lane picks one): its tuples, the group's tuples in
-// batches 0..bl, its output position and whether it was whole.
-struct LaneBatch {
-    int32_t k, c, tix;
-    bool whole;
-};
-
-__device__ __forceinline__ LaneBatch lane_batch(const ApplyGroup &q, int bl, int32_t W) {
-    LaneBatch r = {0, 0, 0, false};
-    int32_t c = 0;
-#pragma unroll
-    for (int b = 0; b < SB_K; ++b) {
-        c += q.k[b];
-        if (bl == b) {
-            r.k = q.k[b];
-            r.c = c;
-            r.tix = q.tix[b];
-            r.whole = q.k[b] >= W && q.k[b] >= SB_HEAVY_MIN;
-        }
-    }
-    return r;
-}
-
-// Batch bl's result of group g (s: its window's sum without the part from
-// before the call, unless add_before is false) by the calling lane, and, by
-// the lane of the group's last batch, its final state.
-__device__ __forceinline__ void apply_emit_lane(const State &st, const SbBufs &sb,
-                                                const Out *outs, const ApplyGroup &q, int g,
-                                                const LaneBatch &lb, int bl, long long s,
-                                                bool add_before = true) {
-    const int32_t W = st.W;
-    if (add_before) s += lb.c < W ? q.sum0 : 0;
-    if (lb.k > 0) emit_one(outs[bl], lb.tix, g, s, (int32_t)min((int64_t)W, (int64_t)q.cnt0 + lb.c));
-    int last = 0;
-#pragma unroll
-    for (int b = 0; b < SB_K; ++b)
-        if (q.k[b] > 0) last = b;
-    if (bl == last && lb.k > 0) {
-        st.sum[g] = s;
-        st.pos[g] = (int32_t)(((uint32_t)q.pos0 + (uint32_t)q.kg) % (uint32_t)W);
-        st.cnt[g] = (int32_t)min((int64_t)W, (int64_t)q.cnt0 + q.kg);
-    }
-}
-
-// LDS of a workgroup's big group: the sorted boundaries of the batches'
-// survivor ranges and old-value prefixes, and the sums between them.
-struct BigLds {
-    int32_t np, no;
-    int32_t pts[2 * SB_K + 2];
-    int32_t opts[SB_K + 2];
-    unsigned long long seg[2 * SB_K + 1];
-    unsigned long long oseg[SB_K + 1];
-};
-
-// Group g by a whole workgroup (its survivors plus old values read exceed
-// APPLY_BUDGET).  Batch b's window sum: the survivors at places [lo_b, hi_b)
-// plus, while fewer than W tuples have arrived in the call, the window before
-// the call less its first c_b values.  A batch holding at least
-// max(W, SB_HEAVY_MIN) of its tuples was a heavy item whose survivors' sum
-// the prep step left.  The others come from sums between consecutive
-// boundaries (the lo_b and hi_b of the survivors, the c_b of the old values,
-// sorted): each thread walks its values in increasing place, adds each to a
-// running sum and, where it passes a boundary, adds that sum into the
-// boundary's segment in LDS; batch b's part is then the segments inside its
-// range.
-__device__ void apply_big(const State &st, const SbBufs &sb, const SbBatches &in,
-                          const Out *outs, const bool (&valid)[SB_K], int g, BigLds &bl) {
-    const int tid = threadIdx.x;
-    const int32_t W = st.W;
-    ApplyGroup qq[1];
-    apply_load<1>(sb, st, valid, in.K, g, 0, g + 1, qq);
-    const ApplyGroup &q = qq[0];
-    int32_t lo[SB_K], hi[SB_K], cb[SB_K];
-    bool whole[SB_K];  // the batch's own survivors are the window: its sum is known
-    bool need_x = false, need_o = false;
-    {
-        int32_t c = 0, e = 0;
-#pragma unroll
-        for (int b = 0; b < SB_K; ++b) {
-            const int32_t k = q.k[b];
-            c += k;
-            e += min(k, W);
-            hi[b] = e;
-            lo[b] = e - min(W, c);
-            cb[b] = (k > 0 && c < W && q.lold) ? c : 0;
-            whole[b] = k >= W && k >= SB_HEAVY_MIN;
-            need_x |= k > 0 && !whole[b];
-            need_o |= cb[b] > 0;
-        }
-    }
-    const int32_t keep_from = q.m - min(W, q.kg);
-    const int32_t x_from = need_x ? 0 : keep_from;
-    if (tid == 0) {
-        // the survivors' boundaries: lo_b and hi_b of the batches summed here
-        // (a batch not summed repeats the previous boundary, so that both
-        // lists ascend), merged by counting, between x_from and m; the old
-        // values' boundaries c_b likewise
-        int32_t a[SB_K], z[SB_K], o[SB_K];
-        int32_t la = x_from, lz = x_from, lc = 0;
-#pragma unroll
-        for (int b = 0; b < SB_K; ++b) {
-            const bool sum_b = q.k[b] > 0 && !whole[b];
-            la = sum_b ? lo[b] : la;
-            lz = sum_b ? hi[b] : lz;
-            lc = cb[b] > 0 ? cb[b] : lc;
-            a[b] = la;
-            z[b] = lz;
-            o[b] = lc;
-        }
-#pragma unroll
-        for (int i = 0; i < SB_K; ++i) {
-            int pa = i, pz = i;
-#pragma unroll
-            for (int j = 0; j < SB_K; ++j) {
-                pa += z[j] < a[i] ? 1 : 0;
-                pz += a[j] <= z[i] ? 1 : 0;
-            }
-            bl.pts[1 + pa] = a[i];
-            bl.pts[1 + pz] = z[i];
-            bl.opts[1 + i] = o[i];
-        }
-        bl.pts[0] = x_from;
-        bl.pts[2 * SB_K + 1] = q.m;
-        bl.np = 2 * SB_K + 2;
-        bl.opts[0] = 0;
-        bl.opts[SB_K + 1] = q.lold;
-        bl.no = SB_K + 2;
-#pragma unroll
-        for (int k = 0; k < 2 * SB_K + 1; ++k) bl.seg[k] = 0;
-#pragma unroll
-        for (int k = 0; k < SB_K + 1; ++k) bl.oseg[k] = 0;
-    }
-    __syncthreads();
-    constexpr int U = 8;
-    // One thread's walk over places [x0, x1) in increasing order: each value
-    // (value(x, false) loads it, value(x, true, v) is told it) added to the
-    // segment [pts[cs], pts[cs + 1]) that holds it.
-    auto walk = [&](const int32_t *pts, unsigned long long *seg, int32_t x0, int32_t x1,
-                    auto &&value) {
-        int cs = 0;
-        int32_t nextb = pts[1];
-        long long cur = 0;
-        for (int e0 = x0 + tid; e0 < x1; e0 += U * APPLY_THREADS) {
-            int32_t v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = value(min(e0 + u * APPLY_THREADS, x1 - 1), false);
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int32_t x = e0 + u * APPLY_THREADS;
-                if (x >= x1) break;
-                while (x >= nextb) {
-                    if (cur) atomicAdd(&seg[cs], (unsigned long long)cur);
-                    cur = 0;
-                    nextb = pts[++cs + 1];
-                }
-                cur += v[u];
-                value(x, true, v[u]);
-            }
-        }
-        if (cur) atomicAdd(&seg[cs], (unsigned long long)cur);
-    };
-    if (need_o)
-        walk(bl.opts, bl.oseg, 0, q.lold, [&](int32_t i, bool store, int32_t = 0) {
-            return store ? 0 : apply_old(st, g, q.pos0, q.cnt0, i);
-        });
-    __syncthreads();  // (every old value has been read: the ring may change now)
-    // the survivors: summed where a batch needs them, and the final window,
-    // the last min(W, kg), written to the ring as they are read
-    const uint32_t slot0 =
-        (uint32_t)(((int64_t)q.pos0 + q.kg - min(W, q.kg)) % (int64_t)W);  // of keep_from
-    int32_t *ring = st.ring + (int64_t)g * W;
-    walk(bl.pts, bl.seg, x_from, q.m, [&](int32_t p, bool store, int32_t v = 0) {
-        if (!store) return sb.xs[q.gs + p];
-        if (p >= keep_from) {
-            uint32_t slot = slot0 + (uint32_t)(p - keep_from);
-            slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
-            ring[slot] = v;
-        }
-        return 0;
-    });
-    __syncthreads();
-    if (tid < SB_K) {  // thread b: batch b
-        const LaneBatch lb = lane_batch(q, tid, W);
-        int32_t blo = 0, bhi = 0, bcb = 0;
-#pragma unroll
-        for (int b = 0; b < SB_K; ++b)
-            if (tid == b) {
-                blo = lo[b];
-                bhi = hi[b];
-                bcb = cb[b];
-            }
-        long long t = 0;
-        for (int k = 0; k + 1 < bl.np; ++k)
-            if (bl.pts[k] >= blo && bl.pts[k + 1] <= bhi) t += (long long)bl.seg[k];
-        for (int k = 0; k + 1 < bl.no; ++k)
-            if (bl.opts[k + 1] <= bcb) t -= (long long)bl.oseg[k];
-        if (lb.whole) t = sb.tb[(int64_t)(tid < in.K ? tid : 0) * st.G + g];
-        apply_emit_lane(st, sb, outs, q, g, lb, tid, t);
-    }
-    __syncthreads();
-}
-
-// Lanes of a group's facts in the apply step's waves (A: one int per lane;
-// B: one int64 per lane, lanes [0, SB_K) a heavy item's survivor sum, lane
-// SB_K the window sum), and lanes per batch in its reductions.
-constexpr int AF_K = 0, AF_TIX = SB_K, AF_POS = 2 * SB_K, AF_CNT = 2 * SB_K + 1,
+// Lanes of a group's facts in the apply step's waves (A: one int per lane,
+// lanes [0, SB_K) its tuples per batch; B: one int64 per lane, lanes [0,
+// SB_K) a heavy item's survivor sum, lane SB_K the window sum).
+constexpr int AF_TIX = SB_K, AF_POS = 2 * SB_K, AF_CNT = 2 * SB_K + 1,
               AF_GS = 2 * SB_K + 2, AF_BIG = 2 * SB_K + 4;
-constexpr int LPB = 64 / SB_K;
-static_assert(AF_BIG < 64 && 64 % SB_K == 0, "a group's facts fit one wave");
+static_assert(AF_BIG < 64 && SB_K <= 32, "a group's facts fit one wave, a batch per lane");
 
 // A 64-bit value of lane l (a wave-uniform lane).
 __device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
@@ -2947,209 +2699,297 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// Group g by one wave, its facts in A and B (lanes AF_*: its counters and
-// output positions per batch, pos, cnt, its first survivor place and the
-// next group's, its flag of a workgroup's group; the heavy items' survivor
-// sums and its window sum).  Each lane
-// keeps a partial window sum per batch: survivors at places [lo_b, hi_b)
-// added, old values [0, cb_b) subtracted (batch b's window sum is then that
-// plus, while fewer than W tuples have arrived in the call, the sum before
-// it); these are reduced by halving, lane LPB * b ending with batch b's.
-__device__ void apply_wave(const State &st, const SbBufs &sb, const SbBatches &in,
-                           const Out *outs, const bool (&valid)[SB_K], int g, int32_t A,
-                           int64_t B) {
+// Group g's facts for the calling wave's lanes (a group past the last reads
+// the last group's).
+__device__ __forceinline__ void apply_facts(const State &st, const SbBufs &sb, int K, int g,
+                                            int32_t &A, int64_t &B) {
     const int lane = lane_id();
+    const int G = (int)st.G;
+    g = min(g, G - 1);
+    const int b = lane % SB_K;
+    const int bb = b < K ? b : 0;
+    const int32_t *pa = lane < AF_TIX   ? sb.kh + (int64_t)g * SB_K + b
+                        : lane < AF_POS ? sb.tidx + (int64_t)bb * G + g
+                        : lane == AF_POS ? st.pos + g
+                        : lane == AF_CNT ? st.cnt + g
+                        : lane == AF_GS ? sb.gsb + g
+                        : lane == AF_GS + 1 ? sb.gsb + g + 1
+                                            : sb.gbig + g;
+    const int64_t *pb = lane < SB_K ? sb.tb + (int64_t)bb * G + g : st.sum + g;
+    A = *global_ptr(pa);
+    B = *global_ptr(pb);
+}
+
+// A group's facts as the apply step uses them: the wave-uniform ones, and,
+// in lane b < SB_K, batch b's: its tuples k, the group's tuples in batches
+// 0..b (c), its output position, the places [lo, hi) of the survivors its
+// window holds, the old window values it no longer holds (the first cb,
+// while fewer than W tuples have arrived in the call), whether its own
+// survivors are its whole window (a heavy item whose sum the prep step
+// left) and that sum.  Lanes past SB_K and batches not valid have k = 0.
+struct ApplyFacts {
+    int32_t pos0, cnt0, gs, m, kg, lold;
+    int64_t sum0;
+    int last;  // the group's last batch in the call
+    bool need_x, any_whole;
+    int32_t k, c, tix, lo, hi, cb;
+    int64_t tb;
+    bool whole;
+};
+
+__device__ __forceinline__ ApplyFacts apply_unpack(int32_t A, int64_t B, uint32_t vmask,
+                                                  int32_t W) {
+    const int lane = lane_id();
+    ApplyFacts f;
+    f.k = (lane < SB_K && ((vmask >> lane) & 1u)) ? A : 0;
+    f.c = wave_incl_add(f.k);
+    f.kg = __builtin_amdgcn_readlane(f.c, 63);
+    const uint64_t nz = ballot(f.k > 0);
+    f.last = nz ? 63 - __builtin_clzll(nz) : 0;
+    f.tix = __shfl(A, (AF_TIX + lane) & 63, 64);
+    f.pos0 = __builtin_amdgcn_readlane(A, AF_POS);
+    f.cnt0 = __builtin_amdgcn_readlane(A, AF_CNT);
+    f.gs = __builtin_amdgcn_readlane(A, AF_GS);
+    f.m = __builtin_amdgcn_readlane(A, AF_GS + 1) - f.gs;
+    f.sum0 = readlane64(B, SB_K);
+    f.tb = B;
+    f.lold = f.cnt0 > 0 ? min(W, f.kg) : 0;
+    f.hi = wave_incl_add(min(f.k, W));
+    f.lo = f.hi - min(W, f.c);
+    f.cb = (f.k > 0 && f.c < W && f.lold) ? f.c : 0;
+    f.whole = f.k >= W && f.k >= SB_HEAVY_MIN;
+    f.need_x = ballot(f.k > 0 && !f.whole) != 0;
+    f.any_whole = ballot(f.whole) != 0;
+    return f;
+}
+
+// Lane b's result of batch b for group g (s: its window sum), and, by the
+// lane of the group's last batch, the group's final state.
+__device__ __forceinline__ void apply_emit(const State &st, const Out *outs, int g,
+                                           const ApplyFacts &f, long long s) {
+    const int b = lane_id();
+    if (b >= SB_K || f.k <= 0) return;
     const int32_t W = st.W;
-    ApplyGroup q;
-    q.kg = 0;
-#pragma unroll
-    for (int b = 0; b < SB_K; ++b) {
-        const int32_t k = __builtin_amdgcn_readlane(A, AF_K + b);
-        q.k[b] = (b < in.K && valid[b]) ? k : 0;
-        q.tix[b] = __builtin_amdgcn_readlane(A, AF_TIX + b);
-        q.kg += q.k[b];
+    emit_one(outs[b], f.tix, g, s, (int32_t)min((int64_t)W, (int64_t)f.cnt0 + f.c));
+    if (b == f.last) {
+        st.sum[g] = s;
+        st.pos[g] = (int32_t)(((uint32_t)f.pos0 + (uint32_t)f.kg) % (uint32_t)W);
+        st.cnt[g] = (int32_t)min((int64_t)W, (int64_t)f.cnt0 + f.kg);
     }
-    if (q.kg == 0) return;
-    q.pos0 = __builtin_amdgcn_readlane(A, AF_POS);
-    q.cnt0 = __builtin_amdgcn_readlane(A, AF_CNT);
-    q.gs = __builtin_amdgcn_readlane(A, AF_GS);
-    q.m = __builtin_amdgcn_readlane(A, AF_GS + 1) - q.gs;
-    q.sum0 = readlane64(B, SB_K);
-    q.lold = q.cnt0 > 0 ? min(W, q.kg) : 0;
-    int32_t lo[SB_K], hi[SB_K], cb[SB_K];
-    bool whole[SB_K];  // the batch's own survivors are the window: its sum is known
-    bool need_x = false;
-    {
-        int32_t c = 0, e = 0;
+}
+
+// One wave's pass over elements [e0, e1) of a sequence, 64 a round and
+// RU rounds' loads issued before any is used: load(e) reads element e,
+// use(e, loaded) does what follows (stores) and gives its value.  Each
+// lane's points q[j] inside (e0, e1] get the sum of the elements [e0, q[j])
+// in pre[j] (others keep theirs), from the round's inclusive prefix sum at
+// q[j] - 1 plus the rounds before; returns the sum of [e0, e1).
+template <int NP, class Load, class Use>
+__device__ __forceinline__ long long apply_run(int32_t e0, int32_t e1, const int32_t (&q)[NP],
+                                               long long (&pre)[NP], Load &&load, Use &&use) {
+    constexpr int RU = 8;
+    const int lane = lane_id();
+    long long carry = 0;
+    for (int32_t r0 = e0; r0 < e1; r0 += RU * 64) {
+        decltype(load(0)) t[RU];
 #pragma unroll
-        for (int b = 0; b < SB_K; ++b) {
-            const int32_t k = q.k[b];
-            c += k;
-            e += min(k, W);
-            hi[b] = e;
-            lo[b] = e - min(W, c);
-            cb[b] = (k > 0 && c < W && q.lold) ? c : 0;
-            whole[b] = k >= W && k >= SB_HEAVY_MIN;
-            need_x |= k > 0 && !whole[b];
+        for (int u = 0; u < RU; ++u) t[u] = load(min(r0 + u * 64 + lane, e1 - 1));
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int32_t base = r0 + u * 64;
+            if (base >= e1) break;
+            const int32_t e = base + lane;
+            const long long x = e < e1 ? use(e, t[u]) : 0LL;
+            const long long S = wave_incl_add64(x);
+            bool here[NP], any = false;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                here[j] = (uint32_t)(q[j] - 1 - base) < 64u && q[j] <= e1;
+                any |= here[j];
+            }
+            if (ballot(any)) {
+#pragma unroll
+                for (int j = 0; j < NP; ++j) {
+                    const long long v = __shfl(S, (q[j] - 1 - base) & 63, 64);
+                    if (here[j]) pre[j] = carry + v;
+                }
+            }
+            carry += readlane64(S, 63);
         }
     }
-    long long acc[SB_K];
-#pragma unroll
-    for (int b = 0; b < SB_K; ++b) acc[b] = 0;
+    return carry;
+}
+
+// Group g by one wave, its facts in A and B (lanes AF_*).  Batch b's
+// window sum, in lane b: when every window of the call reaches back before
+// it (kg <= W, no batch whole), the sum before the call plus the
+// differences (new - old) of the group's tuples x < c_b, tuple x taking
+// slot pos0 + x mod W; otherwise the survivors at places [lo_b, hi_b) less
+// the old values [0, cb_b), plus the sum before the call while c_b < W.
+// Both are prefix sums of one sequence (the differences; the old values
+// then the survivors) read at each batch's points.
+__device__ void apply_wave(const State &st, const SbBufs &sb, const Out *outs, uint32_t vmask,
+                           int g, int32_t A, int64_t B) {
+    const int32_t W = st.W;
+    const ApplyFacts f = apply_unpack(A, B, vmask, W);
+    if (f.kg == 0) return;
     int32_t *ring = st.ring + (int64_t)g * W;
-    const int32_t unread = W - q.cnt0;
-    bool any_whole = false;
-#pragma unroll
-    for (int b = 0; b < SB_K; ++b) any_whole |= whole[b];
-    if (q.kg <= W && !any_whole) {
-        // Every window of the call reaches back before it: the group's new
-        // tuples x < kg are its survivors, in place x, and tuple x takes
-        // slot pos0 + x mod W, whose old value it evicts.  Batch b's window
-        // sum is the sum before the call plus the differences (new - old) of
-        // tuples x < C_b, so each difference goes to its own batch's segment
-        // (a run of 64 tuples mostly lies in one: that segment is found once
-        // for the run) and the segments are summed in batch order after.
-        int32_t C[SB_K];
-        {
-            int32_t c = 0;
-#pragma unroll
-            for (int b = 0; b < SB_K; ++b) {
-                c += q.k[b];
-                C[b] = c;
-            }
-        }
-        auto seg_of = [&](int32_t x) {  // batch of tuple x (x uniform)
-            int sg = 0;
-#pragma unroll
-            for (int b = 0; b < SB_K; ++b) sg += C[b] <= x ? 1 : 0;
-            return sg;
-        };
-        const int32_t n = q.kg;
-        constexpr int UP = 8;
-        for (int x0 = 0; x0 < n; x0 += UP * 64) {
-            int32_t nv[UP], ov[UP];
-#pragma unroll
-            for (int u = 0; u < UP; ++u) {
-                const int32_t x = min(x0 + u * 64 + lane, n - 1);
-                uint32_t slot = (uint32_t)q.pos0 + (uint32_t)x;
+    const int32_t *xs = sb.xs + f.gs;
+    const int32_t unread = W - f.cnt0;
+    const uint32_t pos0 = (uint32_t)f.pos0;
+    if (f.kg <= W && !f.any_whole) {
+        const int32_t q[1] = {f.k > 0 ? f.c : 0};
+        long long pre[1] = {0};
+        apply_run(
+            0, f.kg, q, pre,
+            [&](int32_t x) {
+                uint32_t slot = pos0 + (uint32_t)x;
                 slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
-                nv[u] = sb.xs[q.gs + x];
-                ov[u] = x >= unread ? ring[slot] : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < UP; ++u) {
-                const int32_t cb = x0 + u * 64;
-                if (cb >= n) break;
-                const int32_t x = cb + lane;
-                const bool in = x < n;
-                if (in) {
-                    uint32_t slot = (uint32_t)q.pos0 + (uint32_t)x;
-                    slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
-                    ring[slot] = nv[u];
-                }
-                const long long d = in ? (long long)nv[u] - (long long)ov[u] : 0LL;
-                const int slo = seg_of(cb), shi = seg_of(min(cb + 63, n - 1));
-                if (slo == shi) {
-#pragma unroll
-                    for (int b = 0; b < SB_K; ++b)
-                        if (b == slo) acc[b] += d;
-                } else {
-#pragma unroll
-                    for (int b = 0; b < SB_K; ++b)
-                        if (b >= slo && b <= shi) {
-                            const int32_t lo_b = b ? C[b - 1] : 0;
-                            acc[b] += (x >= lo_b && x < C[b]) ? d : 0LL;
-                        }
-                }
-            }
-        }
-#pragma unroll
-        for (int h = SB_K / 2, off = 32; h >= 1; h >>= 1, off >>= 1) {
-            const bool up = lane & off;
-#pragma unroll
-            for (int j = 0; j < h; ++j) {
-                const long long give = up ? acc[j] : acc[j + h];
-                const long long keep_ = up ? acc[j + h] : acc[j];
-                acc[j] = keep_ + __shfl_xor(give, off, 64);
-            }
-        }
-#pragma unroll
-        for (int off = LPB / 2; off >= 1; off >>= 1) acc[0] += __shfl_xor(acc[0], off, 64);
-        // window sums: the sum before the call plus the segments up to b
-        const int bl = lane / LPB;
-        long long run = q.sum0, mine = 0;
-#pragma unroll
-        for (int b = 0; b < SB_K; ++b) {
-            run += readlane64(acc[0], LPB * b);
-            mine = bl == b ? run : mine;
-        }
-        const LaneBatch lb = lane_batch(q, bl, W);
-        if (lane % LPB == 0) apply_emit_lane(st, sb, outs, q, g, lb, bl, mine, false);
+                return make_int2(*global_ptr(xs + x), x >= unread ? *global_ptr(ring + slot) : 0);
+            },
+            [&](int32_t x, int2 v) {
+                uint32_t slot = pos0 + (uint32_t)x;
+                slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
+                *global_ptr(ring + slot) = v.x;
+                return (long long)v.x - (long long)v.y;
+            });
+        apply_emit(st, outs, g, f, f.sum0 + pre[0]);
         return;
     }
-    // One pass over the old values [0, lold) and then the survivors [x_from,
-    // m), U per lane in flight: old value i sits in slot pos0 + i mod W
-    // (slots a window that never filled has not reached hold 0 and are not
-    // read); survivors at or past keep_from, the final window, go to the
-    // ring.  A round's loads are all issued before any of its stores, and
-    // every old value comes before every survivor, so no old value is read
-    // after its slot was written.
-    const int32_t keep_from = q.m - min(W, q.kg);
-    const int32_t x_from = need_x ? 0 : keep_from;
-    const int32_t ne = q.lold + (q.m - x_from);
+    // The old values [0, lold) and then the survivors [x_from, m) as one
+    // sequence e: old value i sits in slot pos0 + i mod W (slots a window
+    // that never filled has not reached hold 0 and are not read); survivors
+    // at or past keep_from, the final window, go to the ring.  A round's
+    // loads are all issued before any of its stores, and every old value
+    // comes before every survivor, so no old value is read after its slot
+    // was written.
+    const int32_t keep_from = f.m - min(W, f.kg);
+    const int32_t x_from = f.need_x ? 0 : keep_from;
+    const int32_t lold = f.lold;
     const uint32_t slot0 =
-        (uint32_t)(((int64_t)q.pos0 + q.kg - min(W, q.kg)) % (int64_t)W);  // of keep_from
-    constexpr int U = 8;
-    for (int e0 = lane; e0 < ne; e0 += U * 64) {
-        int32_t v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t e = min(e0 + u * 64, ne - 1);
-            const bool old = e < q.lold;
-            uint32_t slot = (uint32_t)q.pos0 + (uint32_t)e;
+        (uint32_t)(((int64_t)f.pos0 + f.kg - min(W, f.kg)) % (int64_t)W);  // of keep_from
+    const bool sums = f.k > 0 && !f.whole;
+    const int32_t q[3] = {sums ? lold + f.hi - x_from : 0, sums ? lold + f.lo - x_from : 0,
+                          sums ? f.cb : 0};
+    long long pre[3] = {0, 0, 0};
+    apply_run(
+        0, lold + (f.m - x_from), q, pre,
+        [&](int32_t e) {
+            uint32_t slot = pos0 + (uint32_t)e;
             slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
-            const int32_t *src = old ? ring + slot : sb.xs + q.gs + (x_from + e - q.lold);
-            v[u] = (old && e < unread) ? 0 : *src;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t e = e0 + u * 64;
-            if (e >= ne) break;
-            if (e < q.lold) {
-#pragma unroll
-                for (int b = 0; b < SB_K; ++b) acc[b] -= e < cb[b] ? v[u] : 0;
-            } else {
-                const int32_t p = x_from + e - q.lold;
-#pragma unroll
-                for (int b = 0; b < SB_K; ++b)
-                    acc[b] += (!whole[b] && p >= lo[b] && p < hi[b]) ? v[u] : 0;
+            const int32_t *src = e < lold ? ring + slot : xs + (x_from + e - lold);
+            return (e < lold && e < unread) ? 0 : *global_ptr(src);
+        },
+        [&](int32_t e, int32_t v) {
+            const int32_t p = x_from + e - lold;
+            if (e >= lold && p >= keep_from) {
+                uint32_t slot = slot0 + (uint32_t)(p - keep_from);
+                slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
+                *global_ptr(ring + slot) = v;
+            }
+            return (long long)v;
+        });
+    const long long s = f.whole ? (long long)f.tb
+                                : (f.c < W ? f.sum0 : 0LL) + pre[0] - pre[1] - pre[2];
+    apply_emit(st, outs, g, f, s);
+}
+
+// LDS of a workgroup's big group: per batch its prefix sums at its points
+// as the wave whose run holds the point found them (survivors to hi and to
+// lo, old values to cb), and each wave's run sums (old values, survivors).
+struct BigLds {
+    long long pre[3][SB_K];
+    long long tot[2][APPLY_THREADS / 64];
+};
+
+// Group g by a whole workgroup (its survivors plus old values read exceed
+// APPLY_BUDGET): the window sums of apply_wave's general case, with the
+// old values and then the survivors each cut into one run per wave; a
+// point's prefix sum is its run's part plus the sums of the runs before.
+__device__ void apply_big(const State &st, const SbBufs &sb, const SbBatches &in,
+                          const Out *outs, uint32_t vmask, int g, BigLds &bl) {
+    constexpr int NW = APPLY_THREADS / 64;
+    const int lane = lane_id(), wid = (int)threadIdx.x >> 6;
+    const int32_t W = st.W;
+    int32_t A;
+    int64_t B;
+    apply_facts(st, sb, in.K, g, A, B);
+    const ApplyFacts f = apply_unpack(A, B, vmask, W);
+    if ((int)threadIdx.x < 3 * SB_K) (&bl.pre[0][0])[threadIdx.x] = 0;
+    __syncthreads();
+    int32_t *ring = st.ring + (int64_t)g * W;
+    const int32_t *xs = sb.xs + f.gs;
+    const int32_t unread = W - f.cnt0;
+    const uint32_t pos0 = (uint32_t)f.pos0;
+    const int32_t keep_from = f.m - min(W, f.kg);
+    const int32_t x_from = f.need_x ? 0 : keep_from;
+    const int32_t lold = f.lold;
+    const bool sums = f.k > 0 && !f.whole;
+    // runs of whole rounds: wave w takes [a + w * L, a + (w + 1) * L) of [a, z)
+    auto run_of = [&](int32_t a, int32_t z, int w, int32_t &r0, int32_t &r1) {
+        const int32_t L = (z - a + NW * 64 - 1) / (NW * 64) * 64;
+        r0 = min(z, a + w * L);
+        r1 = min(z, r0 + L);
+    };
+    int32_t r0, r1;
+    run_of(0, lold, wid, r0, r1);
+    {
+        const int32_t q[1] = {sums ? f.cb : 0};
+        long long pre[1] = {0};
+        const long long t = apply_run(
+            r0, r1, q, pre,
+            [&](int32_t i) {
+                uint32_t slot = pos0 + (uint32_t)i;
+                slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
+                return i < unread ? 0 : *global_ptr(ring + slot);
+            },
+            [&](int32_t, int32_t v) { return (long long)v; });
+        if (lane < SB_K && (uint32_t)(q[0] - 1 - r0) < (uint32_t)(r1 - r0)) bl.pre[2][lane] = pre[0];
+        if (lane == 0) bl.tot[0][wid] = t;
+    }
+    __syncthreads();  // (every old value has been read: the ring may change now)
+    run_of(x_from, f.m, wid, r0, r1);
+    const uint32_t slot0 =
+        (uint32_t)(((int64_t)f.pos0 + f.kg - min(W, f.kg)) % (int64_t)W);  // of keep_from
+    {
+        const int32_t q[2] = {sums ? f.hi : 0, sums ? f.lo : 0};
+        long long pre[2] = {0, 0};
+        const long long t = apply_run(
+            r0, r1, q, pre, [&](int32_t p) { return *global_ptr(xs + p); },
+            [&](int32_t p, int32_t v) {
                 if (p >= keep_from) {
                     uint32_t slot = slot0 + (uint32_t)(p - keep_from);
                     slot = slot >= (uint32_t)W ? slot - (uint32_t)W : slot;
-                    ring[slot] = v[u];
+                    *global_ptr(ring + slot) = v;
                 }
+                return (long long)v;
+            });
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            if (lane < SB_K && (uint32_t)(q[j] - 1 - r0) < (uint32_t)(r1 - r0))
+                bl.pre[j][lane] = pre[j];
+        if (lane == 0) bl.tot[1][wid] = t;
+    }
+    __syncthreads();
+    if (wid == 0) {
+        // a point's prefix: its run's part plus the runs that end before it
+        auto prefix = [&](int ph, int j, int32_t a, int32_t z, int32_t qp) {
+            long long s = qp > a ? bl.pre[j][lane < SB_K ? lane : 0] : 0LL;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                int32_t w0, w1;
+                run_of(a, z, w, w0, w1);
+                s += w1 < qp ? bl.tot[ph][w] : 0LL;
             }
-        }
+            return s;
+        };
+        const long long s =
+            f.whole ? (long long)f.tb
+                    : (f.c < W ? f.sum0 : 0LL) + prefix(1, 0, x_from, f.m, f.hi) -
+                          prefix(1, 1, x_from, f.m, f.lo) - prefix(0, 2, 0, lold, f.cb);
+        apply_emit(st, outs, g, f, s);
     }
-    // halving: after the step over lane bit 5 a lane holds four batches'
-    // partial sums (0-3 or 4-7), after bit 4 two, after bit 3 one
-#pragma unroll
-    for (int h = SB_K / 2, off = 32; h >= 1; h >>= 1, off >>= 1) {
-        const bool up = lane & off;
-#pragma unroll
-        for (int j = 0; j < h; ++j) {
-            const long long give = up ? acc[j] : acc[j + h];
-            const long long keep_ = up ? acc[j + h] : acc[j];
-            acc[j] = keep_ + __shfl_xor(give, off, 64);
-        }
-    }
-#pragma unroll
-    for (int off = LPB / 2; off >= 1; off >>= 1) acc[0] += __shfl_xor(acc[0], off, 64);
-    // lane LPB * b: batch b (a whole batch's sum is in lane b's B)
-    const int bl = lane / LPB;
-    const LaneBatch lb = lane_batch(q, bl, W);
-    const long long tbl = __shfl(B, bl, 64);
-    if (lane % LPB == 0) apply_emit_lane(st, sb, outs, q, g, lb, bl, lb.whole ? tbl : acc[0]);
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(APPLY_THREADS, 4) void k_sb_apply(State st, Scratch base, SbBufs sb,
@@ -3162,10 +3002,8 @@ __global__ __launch_bounds__(APPLY_THREADS, 4) void k_sb_apply(State st, Scratch
 #pragma unroll
     for (int b = 0; b < SB_K; ++b)
         if ((int)threadIdx.x == b) outs[b] = in.out[b];
+    const uint32_t vmask = (uint32_t)ballot(lane < K && sb.sbad[lane < K ? lane : 0] != seq);
     __syncthreads();
-    bool valid[SB_K];
-#pragma unroll
-    for (int b = 0; b < SB_K; ++b) valid[b] = b < K && sb.sbad[b] != seq;
     phase_mark(base, PHASE_SB_APPLY, 0);
     // The groups over APPLY_BUDGET by whole workgroups, the last min(nbig,
     // grid) ones; every other group by one wave of the workgroups before
@@ -3177,7 +3015,7 @@ __global__ __launch_bounds__(APPLY_THREADS, 4) void k_sb_apply(State st, Scratch
     const int nbw = min(nbig, grid);
     const int bw = grid - 1 - (int)blockIdx.x;  // this workgroup's place from the top
     for (int i = bw; i < nbig; i += grid) {
-        apply_big(st, sb, in, outs, valid, sb.big[i], bigl);
+        apply_big(st, sb, in, outs, vmask, sb.big[i], bigl);
         if (i == bw) phase_mark(base, PHASE_SB_APPLY, 1);
     }
     phase_mark(base, PHASE_SB_APPLY, 2);
@@ -3187,33 +3025,18 @@ __global__ __launch_bounds__(APPLY_THREADS, 4) void k_sb_apply(State st, Scratch
         return;
     }
     const int NWV = wgs * (APPLY_THREADS / 64);
-    auto facts = [&](int g, int32_t &A, int64_t &B) {
-        g = min(g, G - 1);
-        const int b = lane % SB_K;
-        const int bb = b < K ? b : 0;
-        const int32_t *pa = lane < AF_TIX   ? sb.kh + (int64_t)g * SB_K + b
-                            : lane < AF_POS ? sb.tidx + (int64_t)bb * G + g
-                            : lane == AF_POS ? st.pos + g
-                            : lane == AF_CNT ? st.cnt + g
-                            : lane == AF_GS ? sb.gsb + g
-                            : lane == AF_GS + 1 ? sb.gsb + g + 1
-                                                : sb.gbig + g;
-        const int64_t *pb = lane < SB_K ? sb.tb + (int64_t)bb * G + g : st.sum + g;
-        A = *pa;
-        B = *pb;
-    };
     int g = (int)blockIdx.x * (APPLY_THREADS / 64) + ((int)threadIdx.x >> 6);
     int32_t A0;
     int64_t B0;
-    facts(g, A0, B0);
+    apply_facts(st, sb, K, g, A0, B0);
     for (; g < G; g += NWV) {
         int32_t A1;
         int64_t B1;
-        facts(g + NWV, A1, B1);
+        apply_facts(st, sb, K, g + NWV, A1, B1);
         keep(A0);
         keep(B0);
         if (!__builtin_amdgcn_readlane(A0, AF_BIG))  // (else a workgroup's)
-            apply_wave(st, sb, in, outs, valid, g, A0, B0);
+            apply_wave(st, sb, outs, vmask, g, A0, B0);
         A0 = A1;
         B0 = B1;
     }
@@ -3374,8 +3197,8 @@ hipError_t launch_sb_hist(State st, Scratch base, SbBufs sb, const SbBatches &in
                           hipStream_t s) {
     const int grid = in.htile0[in.K];
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sb_hist, dim3((unsigned)grid), dim3(HIST_THREADS), (size_t)st.G * 4, s,
-                       base, sb, in, (int32_t)st.G, seq);
+    hipLaunchKernelGGL(k_sb_hist, dim3((unsigned)grid), dim3(SBH_THREADS),
+                       (size_t)((st.G + 1) / 2) * 4, s, base, sb, in, (int32_t)st.G, seq);
     return hipGetLastError();
 }
 

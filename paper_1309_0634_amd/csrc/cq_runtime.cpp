@@ -544,7 +544,10 @@ int ensure_sb(cq_query *q) {
     return CQ_OK;
 }
 
-// cq_push_batches in groups of up to SB_K batches, five launches each.
+// cq_push_batches in groups of up to SB_K batches, six launches each; a
+// longer call is cut into ceil(count / SB_K) groups of near-equal size, so
+// that no group is left with a few batches to carry a whole chain's fixed
+// cost.
 int push_sb(cq_query *q, int32_t count, const int32_t *const *keys,
             const int32_t *const *values, const int64_t *n, int32_t *const *ids,
             int64_t *const *sums, int32_t *const *counts, double *const *avgs,
@@ -554,9 +557,10 @@ int push_sb(cq_query *q, int32_t count, const int32_t *const *keys,
     if (rc != CQ_OK) return rc;
     const Scratch base = set_of(q, 0);
     q->sb.fault = q->sc.fault;
-    for (int32_t c0 = 0; c0 < count && rc == CQ_OK; c0 += SB_K) {
+    const int32_t chains = (count + SB_K - 1) / SB_K;
+    for (int32_t c = 0, c0 = 0; c < chains && rc == CQ_OK; ++c) {
         SbBatches in{};
-        in.K = std::min<int32_t>(SB_K, count - c0);
+        in.K = count / chains + (c < count % chains ? 1 : 0);
         int32_t ht = 0, pt = 0;
         for (int b = 0; b < in.K; ++b) {
             const int32_t i = c0 + b;
@@ -587,6 +591,7 @@ int push_sb(cq_query *q, int32_t count, const int32_t *const *keys,
         if (rc == CQ_OK)
             rc = timed(q, CQ_KERNEL_APPLY, s,
                        [&] { return launch_sb_apply(q->st, base, q->sb, in, seq, s); });
+        c0 += in.K;
     }
     // cq_results, cq_status and cq_batch_plan read the last batch's plan,
     // which the several-batch plan also leaves in buffer set 0
