@@ -10,7 +10,7 @@ Reported: tuples/s and algorithmic HBM GB/s for s in {0, 0.5, 1, 1.5, 2},
 balanced vs static partition, p50/p99 batch latency, and the imbalance of
 the per-group phase (per-CU busy-time spread, per-workgroup tuple loads).
 The headline value is s=1.5, balanced, with the batches pushed up to
-sixteen per cq_push_batches call (--per-call; the timed batches are cut
+twenty per cq_push_batches call (--per-call; the timed batches are cut
 into calls of near-equal size): every batch's results are emitted into its
 own buffers, and a call's batches share one set of launches.  The same
 batches one cq_push_batch_results call each are reported beside it, and the
@@ -22,8 +22,9 @@ with idle time of their own.  The roofline object is for the
 longest-running kernel of the headline run (one launch processes one
 call's batches), beside the end-to-end fraction (algorithmic bytes over
 the whole time per batch); its `traffic` is the HBM bytes per launch
-recorded from rocprofv3 counters in profiles/traffic_<kind>.md, or null
-when that record was taken on other kernel sources; the whole path's
+from rocprofv3 counters recorded in profiles/traffic_<kind>.md (bytes per
+batch there, times this run's batches per launch), or null when that
+record was taken on other kernel sources; the whole path's
 counter bytes per batch (every launch's record) stand beside the
 algorithmic bytes.  The
 cpu_baseline is the CPU oracle timed on a bounded sample of the same
@@ -556,7 +557,8 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 
 def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` recorded from rocprofv3 FETCH_SIZE and
+    """HBM bytes per batch of `kernel` (its bytes per launch over the batches
+    each recorded launch processed), recorded from rocprofv3 FETCH_SIZE and
     WRITE_SIZE counters in profiles/traffic_<kernel>.md, or None when that
     record was taken on a different kernel source than the one built now."""
     path = os.path.join(PROFILES, f"traffic_{kernel}.md")
@@ -565,13 +567,14 @@ def measured_traffic(kernel: str):
     text = open(path).read()
     m_sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
     m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not (m_sha and m_b):
+    m_n = re.search(r"batches_per_launch:\s*([0-9]+)", text)
+    if not (m_sha and m_b and m_n):
         return None
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:  # the kernels' source and the headers they build on
         h.update(open(f, "rb").read())
     sha = h.hexdigest()
-    return float(m_b.group(1)) if sha == m_sha.group(1) else None
+    return float(m_b.group(1)) / int(m_n.group(1)) if sha == m_sha.group(1) else None
 
 
 def copy_calibration(torch, mib: int):
@@ -641,8 +644,9 @@ def main():
     ap.add_argument("--serving", default="10,50,100,250,500",
                     help="arrival rates (batches/s) of the serving loop ('' skips it)")
     ap.add_argument("--serving-seconds", type=float, default=3.0)
-    ap.add_argument("--per-call", type=int, default=16,
-                    help="batches per cq_push_batches call of the balanced partition")
+    ap.add_argument("--per-call", type=int, default=20,
+                    help="batches per cq_push_batches call of the balanced partition "
+                         "(20: one set of the library's launches, CQ_CHAIN_BATCHES)")
     ap.add_argument("--calibrate", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -731,14 +735,16 @@ def main():
     dom_ms, dom_launches = kern[dom]
     avg_bytes = timed_bytes / args.steps
     # one launch of each kernel processes one call's batches
-    per_launch = avg_bytes * args.steps / dom_launches
+    per_call = args.steps / dom_launches
+    per_launch = avg_bytes * per_call
     achieved = per_launch / (dom_ms / dom_launches * 1e-3) / 1e9
     traffic = measured_traffic(dom)
+    traffic = None if traffic is None else round(traffic * per_call)
     e2e = avg_bytes / (row["ms_per_batch"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom, "kernel_avg_us": round(1e3 * dom_ms / dom_launches, 2),
-                "batches_per_launch": row["batches_per_call"],
+                "batches_per_launch": round(per_call, 3),
                 "alg_bytes_per_launch": round(per_launch),
                 "end_to_end_GBps": round(e2e, 1),
                 "end_to_end_frac": round(e2e / HBM_PEAK_GBS, 4),
@@ -748,7 +754,7 @@ def main():
     # every record matches the kernels built now
     recs = [measured_traffic(k) for k in kern]
     if all(t is not None for t in recs):
-        path_b = sum(recs) / row["batches_per_call"]
+        path_b = sum(recs)
         roofline["path_traffic_bytes_per_batch"] = round(path_b)
         roofline["alg_bytes_per_batch"] = round(avg_bytes)
         roofline["path_traffic_over_alg"] = round(path_b / avg_bytes, 3)

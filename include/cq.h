@@ -287,7 +287,11 @@ int cq_push_batch_tuples(cq_query *q, const int32_t *keys, const int32_t *values
  *   ids[i], sums[i], counts[i], avgs[i], n_touched[i] : batch i's result
  *                        buffers as for cq_results (the four arrays of
  *                        pointers may be NULL, n_touched[i] may not)
- * Consecutive batches use two sets of batch-local buffers, so batch i+1's
+ * With the balanced partition and at most 16384 groups, up to
+ * CQ_CHAIN_BATCHES batches share one set of six launches (histogram, two
+ * plan launches, reorder, survivors, apply); a longer call is cut into
+ * ceil(count / CQ_CHAIN_BATCHES) sets of near-equal size.  Otherwise
+ * consecutive batches use two sets of batch-local buffers, so batch i+1's
  * key histogram is computed by extra workgroups of batch i's per-group
  * launch: two launches per batch instead of three.  Stream-ordered on
  * `stream`; returns without waiting for the device.  A batch with a bad key
@@ -298,6 +302,7 @@ int cq_push_batch_tuples(cq_query *q, const int32_t *keys, const int32_t *values
  * or CQ_ERR_HIP.
  */
 #define CQ_PIPE_MAX 1048576 /* 2^20 tuples per batch */
+#define CQ_CHAIN_BATCHES 20 /* batches per set of launches of cq_push_batches */
 int cq_push_batches(cq_query *q, int32_t count, const int32_t *const *keys,
                     const int32_t *const *values, const int64_t *n, int32_t *const *ids,
                     int64_t *const *sums, int32_t *const *counts, double *const *avgs,

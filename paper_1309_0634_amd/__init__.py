@@ -32,6 +32,7 @@ TUPLE_MAX_GROUPS = 1 << 21
 MAX_BATCH = 1 << 30
 MAX_WINDOW = (1 << 22) - 1
 PIPE_MAX = 1 << 20
+CHAIN_BATCHES = 20
 NOALLOC_MAX_BATCH = 1 << 18
 NOALLOC_MAX_GROUPS = 16384
 

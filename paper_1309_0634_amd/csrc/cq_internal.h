@@ -170,7 +170,7 @@ struct Out {
 // each batch, which are the only ones any emitted window holds -- get
 // consecutive places per group (batch by batch, arrival order), so that
 // every batch's window sums are differences of prefix sums.
-constexpr int SB_K = 16;
+constexpr int SB_K = CQ_CHAIN_BATCHES;
 // The several-batch path's buckets: a group with at least SB_HEAVY_MIN
 // tuples of a batch is heavy, the others are packed into buckets of about
 // SB_LIGHT_BUDGET tuples (fewer than SB_LIGHT_CAP).  Fewer, larger buckets

@@ -1900,8 +1900,9 @@ __device__ __forceinline__ int sb_batch_of(const int32_t *tile0, int K, int t) {
     return b;
 }
 
-// One histogram tile of one batch per block: its SBH_TILE keys (all of a
-// thread's loads in flight together) counted in LDS as pairs of 16-bit
+// One histogram tile of one batch per block: its SBH_TILE keys (a thread's
+// in chunks of SBH_CHUNK, each chunk's loads in flight together, so that
+// registers allow three blocks per CU) counted in LDS as pairs of 16-bit
 // counters, group 2i in the low half of word i and 2i + 1 in the high half
 // (a tile's count of a group fits 16 bits, so a half never carries into the
 // other), the previous call's two most frequent groups in registers; the
@@ -1909,7 +1910,8 @@ __device__ __forceinline__ int sb_batch_of(const int32_t *tile0, int K, int t) {
 __global__ __launch_bounds__(SBH_THREADS) void k_sb_hist(Scratch base, SbBufs sb,
                                                          SbBatches in, int32_t G,
                                                          int32_t seq) {
-    static_assert(SBH_KPT % 4 == 0, "keys loaded four at a time");
+    constexpr int SBH_CHUNK = 32;
+    static_assert(SBH_KPT % SBH_CHUNK == 0 && SBH_CHUNK % 4 == 0, "keys loaded four at a time");
     extern __shared__ uint32_t cpair[];
     const int t = (int)blockIdx.x, tid = (int)threadIdx.x;
     const int b = sb_batch_of(in.htile0, in.K, t);
@@ -1921,36 +1923,38 @@ __global__ __launch_bounds__(SBH_THREADS) void k_sb_hist(Scratch base, SbBufs sb
     phase_mark(base, PHASE_HIST_PLAN, 0);
     const int32_t hot0 = base.hot[0], hot1 = base.hot[1];
     for (int i = tid; i < words; i += SBH_THREADS) cpair[i] = 0;
-    const int64_t i0 = (int64_t)tile * SBH_TILE;
-    int32_t v[SBH_KPT];
-#pragma unroll
-    for (int j = 0; j < SBH_KPT / 4; ++j) {
-        const int64_t i = i0 + 4 * ((int64_t)j * SBH_THREADS + tid);
-        if (vec && i + 3 < n) {
-            const int4 x = *reinterpret_cast<const int4 *>(keys + i);
-            v[4 * j] = x.x; v[4 * j + 1] = x.y; v[4 * j + 2] = x.z; v[4 * j + 3] = x.w;
-        } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) v[4 * j + e] = (i + e < n) ? keys[i + e] : 0;
-        }
-    }
-    if (base.kmod) {
-#pragma unroll
-        for (int j = 0; j < SBH_KPT; ++j) v[j] = view_key(v[j], base.kmod, G);
-    }
-    __syncthreads();
     int bad = 0, c0 = 0, c1 = 0;
+    for (int ch = 0; ch < SBH_KPT / SBH_CHUNK; ++ch) {
+        const int64_t i0 = (int64_t)tile * SBH_TILE + (int64_t)ch * SBH_THREADS * SBH_CHUNK;
+        int32_t v[SBH_CHUNK];
 #pragma unroll
-    for (int j = 0; j < SBH_KPT / 4; ++j) {
-        const int64_t i = i0 + 4 * ((int64_t)j * SBH_THREADS + tid);
+        for (int j = 0; j < SBH_CHUNK / 4; ++j) {
+            const int64_t i = i0 + 4 * ((int64_t)j * SBH_THREADS + tid);
+            if (vec && i + 3 < n) {
+                const int4 x = *reinterpret_cast<const int4 *>(keys + i);
+                v[4 * j] = x.x; v[4 * j + 1] = x.y; v[4 * j + 2] = x.z; v[4 * j + 3] = x.w;
+            } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            if (i + e >= n) continue;
-            const int32_t key = v[4 * j + e];
-            if (key < 0 || key >= G) bad = 1;
-            else if (key == hot0) ++c0;
-            else if (key == hot1) ++c1;
-            else atomicAdd(&cpair[key >> 1], 1u << ((key & 1) << 4));
+                for (int e = 0; e < 4; ++e) v[4 * j + e] = (i + e < n) ? keys[i + e] : 0;
+            }
+        }
+        if (base.kmod) {
+#pragma unroll
+            for (int j = 0; j < SBH_CHUNK; ++j) v[j] = view_key(v[j], base.kmod, G);
+        }
+        if (ch == 0) __syncthreads();  // (the counters are cleared)
+#pragma unroll
+        for (int j = 0; j < SBH_CHUNK / 4; ++j) {
+            const int64_t i = i0 + 4 * ((int64_t)j * SBH_THREADS + tid);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (i + e >= n) continue;
+                const int32_t key = v[4 * j + e];
+                if (key < 0 || key >= G) bad = 1;
+                else if (key == hot0) ++c0;
+                else if (key == hot1) ++c1;
+                else atomicAdd(&cpair[key >> 1], 1u << ((key & 1) << 4));
+            }
         }
     }
     c0 = wave_total(wave_incl_add(c0));
@@ -2323,7 +2327,7 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
 struct SbTile {
     int32_t n, b, tile;
 };
-constexpr int SB_PASS_PER = 8;  // tiles per reorder workgroup at most
+constexpr int SB_PASS_PER = (SB_K * PASS_TILES_MAX + SB_PASS_GRID - 1) / SB_PASS_GRID;  // tiles per reorder workgroup at most
 static_assert(SB_K * PASS_TILES_MAX <= SB_PASS_PER * SB_PASS_GRID,
               "every workgroup's tiles fit its table");
 

@@ -104,6 +104,7 @@ def test_header_constants_match_binding():
     assert val("CQ_ERR_KEY_RANGE") == cq.ERR_KEY_RANGE
     assert val("CQ_PARTITION_STATIC") == cq.PARTITION_STATIC
     assert val("CQ_PIPE_MAX") == cq.PIPE_MAX
+    assert val("CQ_CHAIN_BATCHES") == cq.CHAIN_BATCHES
     assert val("CQ_KERNEL_KINDS") == len(cq.KERNEL_KINDS)
     assert val("CQ_KERNEL_TUPLES") == cq.KERNEL_KINDS.index("tuples")
     assert val("CQ_TUPLE_MAX_WINDOW") == cq.TUPLE_MAX_WINDOW

@@ -1,5 +1,5 @@
 """GPU parity of cq_push_batches on its several-batch path (up to 16384
-groups, balanced partition): up to sixteen consecutive batches share one
+groups, balanced partition): up to CHAIN_BATCHES (20) consecutive batches share one
 histogram, plan, reorder, survivor and apply launch, and every batch's
 results must equal the CPU oracle's bit for bit.  The cases aim at the
 path's own structure: windows that span several batches of a call, groups
@@ -48,7 +48,7 @@ def test_windows_across_batches(W):
     G = 300
     q, o = cq.Query(G, W), RingOracle(G, W)
     for call in range(4):
-        per = [1, 3, 8, 16][call]
+        per = [1, 3, 8, cq.CHAIN_BATCHES][call]
         bs = [_rb(rng, G, int(rng.integers(1, 9000)), -10 ** 6, 10 ** 6,
                   zipf=1.3 if call % 2 else None) for _ in range(per)]
         check_against_oracle(q, o, G, bs, f"W={W} call {call}")
@@ -56,10 +56,10 @@ def test_windows_across_batches(W):
     q.close(), o.close()
 
 
-@pytest.mark.parametrize("count", [17, 35])
+@pytest.mark.parametrize("count", [cq.CHAIN_BATCHES + 1, 2 * cq.CHAIN_BATCHES + 5])
 def test_call_longer_than_one_set_of_launches(count):
     """A call of more batches than one set of launches takes: cut into
-    near-equal groups (17 = 9 + 8, 35 = 12 + 12 + 11)."""
+    near-equal groups (21 = 11 + 10, 45 = 15 + 15 + 15)."""
     note(f"case: several-batch path, {count} batches in one call")
     rng = np.random.default_rng(count)
     G, W = 1000, 64
@@ -73,7 +73,7 @@ def test_call_longer_than_one_set_of_launches(count):
 @pytest.mark.parametrize("W,n", [(1000, 60000), (3000, 60000), (200, 200000)])
 def test_groups_over_one_apply_range(W, n):
     """Few groups with many tuples: a group's survivors over the call (up to
-    sixteen windows) plus its old window exceed one apply range and the group
+    twenty windows) plus its old window exceed one apply range and the group
     is summed alone; with W=3000 the windows also reach back across
     batches and into the window before the call."""
     note(f"case: several-batch path, big groups W={W} n={n}")
@@ -82,7 +82,7 @@ def test_groups_over_one_apply_range(W, n):
     q, o = cq.Query(G, W), RingOracle(G, W)
     for call in range(3):
         bs = [_rb(rng, G, n + int(rng.integers(0, 999)), zipf=1.1 if call == 1 else None)
-              for _ in range(8 if call == 2 else 16)]
+              for _ in range(8 if call == 2 else cq.CHAIN_BATCHES)]
         check_against_oracle(q, o, G, bs, f"W={W} call {call}")
     _no_fault(q)
     q.close(), o.close()
@@ -149,22 +149,23 @@ def test_key_mod_and_results_after_the_call():
 
 
 @pytest.mark.parametrize("s", [0.0, 0.5, 1.0, 1.5, 2.0])
-def test_bench_arrays_sixteen_per_call(s):
+def test_bench_arrays_whole_chains_per_call(s):
     """The benchmark's timed configuration: its 200 device-drawn batches of
     the 10,000-group, W=1000, 2^20-tuple Zipf stream in the order it cycles
-    them (200, then the first 10 again), sixteen per call, every batch's
-    results against the oracle's."""
+    them (200, then the first 10 again), CHAIN_BATCHES per call, every
+    batch's results against the oracle's."""
     import torch
     from workloads import DeviceStream
-    note(f"case: bench arrays s={s}, 16 batches per call")
+    note(f"case: bench arrays s={s}, {cq.CHAIN_BATCHES} batches per call")
     cfg = skew(s)
     ds = DeviceStream(cfg, device())
     q = cq.Query(cfg.groups, cfg.window)
     o = RingOracle(cfg.groups, cfg.window, threads=4)
     dev = device()
     seqn = list(range(cfg.batches)) + list(range(10))
-    for c0 in range(0, len(seqn), 16):
-        idx = seqn[c0:c0 + 16]
+    pc = cq.CHAIN_BATCHES
+    for c0 in range(0, len(seqn), pc):
+        idx = seqn[c0:c0 + pc]
         dbs = [ds.batch(b) for b in idx]
         outs = [(torch.empty(cfg.groups, dtype=torch.int32, device=dev),
                  torch.empty(cfg.groups, dtype=torch.int64, device=dev),
@@ -189,7 +190,7 @@ def test_degenerate_shapes(G, W):
     note(f"case: several-batch path, G={G} W={W}")
     rng = np.random.default_rng([G, W])
     q, o = cq.Query(G, W), RingOracle(G, W)
-    sizes = [0, 1, 1 << 20, 5, 0, 70000, 1, 3, 2, 0, 1 << 20, 1, 9000, 0, 4, 1]
+    sizes = [0, 1, 1 << 20, 5, 0, 70000, 1, 3, 2, 0, 1 << 20, 1, 9000, 0, 4, 1, 7, 0, 1, 2]
     bs = [(rng.integers(0, G, n).astype(np.int32), rng.integers(-10 ** 6, 10 ** 6, n).astype(np.int32))
           for n in sizes]
     check_against_oracle(q, o, G, bs, f"G={G} W={W}")
@@ -209,7 +210,7 @@ def test_every_group_touched_at_the_group_limit():
         q, o = cq.Query(G, W), RingOracle(G, W)
         pk, pv = probe_batch(G)
         bs = []
-        for i in range(16):
+        for i in range(cq.CHAIN_BATCHES):
             k = np.concatenate([pk, rng.integers(0, G, 40000).astype(np.int32)])
             v = np.concatenate([pv, rng.integers(0, 10 ** 6, 40000).astype(np.int32)])
             bs.append((k, v))
