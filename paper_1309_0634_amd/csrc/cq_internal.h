@@ -207,9 +207,9 @@ static_assert(SBP_PART % 2 == 0, "the top-two words of a block's partials are 8-
 constexpr int APPLY_BUDGET = 2048;
 constexpr int APPLY_THREADS = 256;
 // Workgroups of the reorder, survivor and apply launches, which loop over
-// their items: as many as the device runs at once (256 CUs; two, four and
+// their items: as many as the device runs at once (256 CUs; two, three and
 // four per CU fit their registers and LDS).
-constexpr int SB_PREP_GRID = 1024;
+constexpr int SB_PREP_GRID = 768;
 constexpr int SB_PASS_GRID = 512;
 constexpr int SB_APPLY_GRID = 1024;
 

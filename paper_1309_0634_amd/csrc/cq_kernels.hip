@@ -2783,21 +2783,22 @@ __device__ __forceinline__ void apply_emit(const State &st, const Out *outs, int
 }
 
 // One wave's pass over elements [e0, e1) of a sequence, 64 a round and
-// RU rounds' loads issued before any is used: load(e) reads element e,
+// RU rounds' loads issued before any is used (more rounds in flight for
+// longer runs): load(e) reads element e,
 // use(e, loaded) does what follows (stores) and gives its value.  Each
 // lane's points q[j] inside (e0, e1] get the sum of the elements [e0, q[j])
 // in pre[j] (others keep theirs), from the round's inclusive prefix sum at
 // q[j] - 1 plus the rounds before; returns the sum of [e0, e1).
-template <int NP, class Load, class Use>
+template <int RU, int NP, class Load, class Use>
 __device__ __forceinline__ long long apply_run(int32_t e0, int32_t e1, const int32_t (&q)[NP],
                                                long long (&pre)[NP], Load &&load, Use &&use) {
-    constexpr int RU = 8;
     const int lane = lane_id();
     long long carry = 0;
     for (int32_t r0 = e0; r0 < e1; r0 += RU * 64) {
         decltype(load(0)) t[RU];
 #pragma unroll
-        for (int u = 0; u < RU; ++u) t[u] = load(min(r0 + u * 64 + lane, e1 - 1));
+        for (int u = 0; u < RU; ++u)  // (rounds past the run are not loaded)
+            if (r0 + u * 64 < e1) t[u] = load(min(r0 + u * 64 + lane, e1 - 1));
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             const int32_t base = r0 + u * 64;
@@ -2844,7 +2845,7 @@ __device__ void apply_wave(const State &st, const SbBufs &sb, const Out *outs, u
     if (f.kg <= W && !f.any_whole) {
         const int32_t q[1] = {f.k > 0 ? f.c : 0};
         long long pre[1] = {0};
-        apply_run(
+        apply_run<8>(
             0, f.kg, q, pre,
             [&](int32_t x) {
                 uint32_t slot = pos0 + (uint32_t)x;
@@ -2876,7 +2877,7 @@ __device__ void apply_wave(const State &st, const SbBufs &sb, const Out *outs, u
     const int32_t q[3] = {sums ? lold + f.hi - x_from : 0, sums ? lold + f.lo - x_from : 0,
                           sums ? f.cb : 0};
     long long pre[3] = {0, 0, 0};
-    apply_run(
+    apply_run<8>(
         0, lold + (f.m - x_from), q, pre,
         [&](int32_t e) {
             uint32_t slot = pos0 + (uint32_t)e;
@@ -2940,7 +2941,7 @@ __device__ void apply_big(const State &st, const SbBufs &sb, const SbBatches &in
     {
         const int32_t q[1] = {sums ? f.cb : 0};
         long long pre[1] = {0};
-        const long long t = apply_run(
+        const long long t = apply_run<16>(
             r0, r1, q, pre,
             [&](int32_t i) {
                 uint32_t slot = pos0 + (uint32_t)i;
@@ -2958,7 +2959,7 @@ __device__ void apply_big(const State &st, const SbBufs &sb, const SbBatches &in
     {
         const int32_t q[2] = {sums ? f.hi : 0, sums ? f.lo : 0};
         long long pre[2] = {0, 0};
-        const long long t = apply_run(
+        const long long t = apply_run<16>(
             r0, r1, q, pre, [&](int32_t p) { return *global_ptr(xs + p); },
             [&](int32_t p, int32_t v) {
                 if (p >= keep_from) {
