@@ -272,7 +272,8 @@ __host__ __device__ inline Scratch sb_set(const SbBufs &sb, const Scratch &base,
     s.trace = nullptr;
     return s;
 }
-// The five launches of `in.K` batches (seq: the call's sequence number).
+// The launches of `in.K` batches, six in all (the plan is two; seq: the
+// call's sequence number).
 hipError_t launch_sb_hist(State st, Scratch base, SbBufs sb, const SbBatches &in, int32_t seq,
                           hipStream_t s);
 hipError_t launch_sb_plan(State st, Scratch base, SbBufs sb, const SbBatches &in, int32_t seq,

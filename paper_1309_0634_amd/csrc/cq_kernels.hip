@@ -1869,10 +1869,11 @@ __global__ void k_reset_totals(Scratch sc) {
 }
 
 // ======================================================= several batches --
-// Up to SB_K consecutive batches of one query share five launches:
+// Up to SB_K consecutive batches of one query share six launches:
 //
 //   k_sb_hist   every batch's key histogram (the tiles of all batches).
-//   k_sb_plan   every batch's own balanced plan (buckets, output positions),
+//   k_sb_sums, k_sb_plan
+//               every batch's own balanced plan (buckets, output positions),
 //               and the places of the survivors: a tuple can be in a window
 //               emitted for its own batch or a later one only if it is
 //               among its group's last W tuples of its batch (a tuple that
