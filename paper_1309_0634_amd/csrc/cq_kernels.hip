@@ -2065,6 +2065,9 @@ __global__ __launch_bounds__(SBS_THREADS) void k_sb_sums(State st, Scratch base,
     const int32_t W = st.W;
     const int g0 = (int)blockIdx.x * SBS_GROUPS;
     phase_mark(base, PHASE_HIST_PLAN, 3);
+    // (each lane's group's window count, for the fields after the barrier,
+    // loaded now beside the tile counts)
+    const int32_t cnt0 = g0 + lane < G ? st.cnt[g0 + lane] : 0;
     {
         const int pair = tid % (SBS_GROUPS / 2), b = tid / (SBS_GROUPS / 2);
         int nt = 0;
@@ -2106,21 +2109,27 @@ __global__ __launch_bounds__(SBS_THREADS) void k_sb_sums(State st, Scratch base,
             sb.cut[(gl + 1) * SB_K + b] = (uint8_t)(hi >= SB_HEAVY_MIN ? chi : 0);
     }
     __syncthreads();
-    if (tid >= 64) return;
-    const int g = g0 + tid;
+    // four waves, a lane per group: every wave forms the fields, wave w
+    // sums those with f mod 4 = w; wave 0 stores the counts, wave 1 keeps
+    // the two most frequent groups
+    constexpr int FW = 4;
+    static_assert(FW * 64 <= SBS_THREADS, "the block has four waves");
+    const int wv = tid >> 6;
+    if (wv >= FW) return;
+    const int g = g0 + lane;
     bool valid[SB_K];
 #pragma unroll
     for (int b = 0; b < SB_K; ++b) valid[b] = b < K && sb.sbad[b] != seq;
     SbGroup own;
 #pragma unroll
-    for (int b = 0; b < SB_K; ++b) own.k[b] = (g < G && valid[b]) ? kc[b][tid] : 0;
-    own.cnt0 = g < G ? st.cnt[g] : 0;
-    if (g < G) {
+    for (int b = 0; b < SB_K; ++b) own.k[b] = (g < G && valid[b]) ? kc[b][lane] : 0;
+    own.cnt0 = cnt0;
+    if (wv == 0 && g < G) {
         int4 *kp = reinterpret_cast<int4 *>(sb.kh + (int64_t)g * SB_K);
 #pragma unroll
         for (int j = 0; j < SB_K / 4; ++j)
-            kp[j] = make_int4(kc[4 * j][tid], kc[4 * j + 1][tid], kc[4 * j + 2][tid],
-                              kc[4 * j + 3][tid]);
+            kp[j] = make_int4(kc[4 * j][lane], kc[4 * j + 1][lane], kc[4 * j + 2][lane],
+                              kc[4 * j + 3][lane]);
     }
     int x[SBP_F];
     int32_t kg;
@@ -2128,52 +2137,72 @@ __global__ __launch_bounds__(SBS_THREADS) void k_sb_sums(State st, Scratch base,
     int32_t *part = sb.part + (int64_t)blockIdx.x * SBP_PART;
 #pragma unroll
     for (int f = 0; f < SBP_F; ++f) {
+        if (f % FW != wv) continue;
         const int t = wave_total(wave_incl_add(x[f]));
         if (lane == 0) part[f] = t;
     }
-    Top2 top;
-    if (kg > 0) top.add(((unsigned long long)(uint32_t)kg << 32) | (uint32_t)g);
-    top2_wave(top);
-    if (lane == 0) {
-        reinterpret_cast<unsigned long long *>(part + SBP_F)[0] = top.a;
-        reinterpret_cast<unsigned long long *>(part + SBP_F)[1] = top.b;
+    if (wv == 1) {
+        Top2 top;
+        if (kg > 0) top.add(((unsigned long long)(uint32_t)kg << 32) | (uint32_t)g);
+        top2_wave(top);
+        if (lane == 0) {
+            reinterpret_cast<unsigned long long *>(part + SBP_F)[0] = top.a;
+            reinterpret_cast<unsigned long long *>(part + SBP_F)[1] = top.b;
+        }
     }
     phase_mark(base, PHASE_HIST_PLAN, 4);
 }
 
 // Plan, second launch: every batch's own balanced plan and the survivors'
 // places, one group per thread, from the blocks' sums (those of the blocks
-// before this one give its carries, all of them the totals).
-__global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base, SbBufs sb,
-                                                         SbBatches in, int32_t seq) {
+// before this one give its carries, all of them the totals).  The batches
+// are split over PLAN_SPLIT rows of blocks (blockIdx.y): row Q takes
+// batches [Q * PLAN_KQ, (Q + 1) * PLAN_KQ) and so scans only their fields
+// and the two per group; row 0 also writes the per-group places.
+constexpr int PLAN_SPLIT = 4, PLAN_KQ = SB_K / PLAN_SPLIT, PLAN_NF = 2 * PLAN_KQ + 2;
+static_assert(SB_K % PLAN_SPLIT == 0, "the plan's rows take equal shares of the batches");
+
+// LDS of a plan block (row-local field i: batch fields 2 b0 + i, then the
+// survivors and big-group fields).
+struct PlanLds {
+    int wown[SBP_THREADS / 64][PLAN_NF];
+    int wbase[SBP_THREADS / 64][PLAN_NF];  // exclusive field values at each wave's first group
+    int ftot[PLAN_NF];                     // field totals over all groups
+    int bpre[PLAN_NF];                     // field sums of the blocks before this one
+    __align__(8) int32_t parts[SBS_BLOCKS_MAX * SBP_PART];  // every sums block's
+};
+
+template <int Q>
+__device__ __forceinline__ void sb_plan_row(const State &st, const Scratch &base,
+                                            const SbBufs &sb, const SbBatches &in, int32_t seq,
+                                            PlanLds &L) {
     constexpr int NW = SBP_THREADS / 64;
-    __shared__ int wown[NW][SBP_F];
-    __shared__ int wbase[NW][SBP_F];  // exclusive field values at each wave's first group
-    __shared__ int ftot[SBP_F];       // field totals over all groups
-    __shared__ int bpre[SBP_F];       // field sums of the blocks before this one
-    __shared__ __align__(8) int32_t parts[SBS_BLOCKS_MAX * SBP_PART];  // every sums block's
+    constexpr int B0 = Q * PLAN_KQ;
+    // the global field of row-local field i
+    auto gf = [](int i) { return i < 2 * PLAN_KQ ? 2 * B0 + i : 2 * SB_K + (i - 2 * PLAN_KQ); };
     const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
     const int K = in.K;
+    if (Q > 0 && B0 >= K) return;  // (no batch of this row in the call)
     const int G = (int)st.G;
     const int32_t W = st.W;
     const int nblk = (G + SBS_GROUPS - 1) / SBS_GROUPS;  // sums blocks
     const int kfirst = (int)blockIdx.x * (SBP_THREADS / SBS_GROUPS);  // this block's first
     const int gb = (int)blockIdx.x * SBP_THREADS, g = gb + tid;
-    phase_mark(base, PHASE_HIST_PLAN, 5);
     bool valid[SB_K];
 #pragma unroll
     for (int b = 0; b < SB_K; ++b) valid[b] = b < K && sb.sbad[b] != seq;
     SbGroup own[1];
     sb_load_groups<1>(sb, st, valid, K, g, 0, G, own);
-    // a heavy item's dropped tiles per batch (a group's SB_K bytes
-    // together), loaded here with the rest rather than in the per-batch loop
+    // a heavy item's dropped tiles per batch of the row (a group's SB_K
+    // bytes together), loaded here with the rest rather than in the loop
     static_assert(SB_K % 4 == 0, "a group's dropped-tile counts load as words");
     uint32_t cutw[SB_K / 4];
     {
         const uint32_t *cp =
             reinterpret_cast<const uint32_t *>(sb.cut + (int64_t)min(g, G - 1) * SB_K);
 #pragma unroll
-        for (int j = 0; j < SB_K / 4; ++j) cutw[j] = cp[j];
+        for (int j = 0; j < SB_K / 4; ++j)
+            if (4 * j + 3 >= B0 && 4 * j < B0 + PLAN_KQ) cutw[j] = cp[j];
     }
     {  // every block's partials, loaded together
         constexpr int PER = (SBS_BLOCKS_MAX * SBP_PART + SBP_THREADS - 1) / SBP_THREADS;
@@ -2183,69 +2212,78 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
         for (int j = 0; j < PER; ++j) v[j] = sb.part[min(tid + j * SBP_THREADS, np - 1)];
 #pragma unroll
         for (int j = 0; j < PER; ++j)
-            if (tid + j * SBP_THREADS < np) parts[tid + j * SBP_THREADS] = v[j];
+            if (tid + j * SBP_THREADS < np) L.parts[tid + j * SBP_THREADS] = v[j];
     }
     __syncthreads();
-    // field f summed over the sums blocks before this block and over all,
-    // by wave f mod NW, its lanes striding over the blocks
-    for (int f = wv; f < SBP_F; f += NW) {
+    // row field i summed over the sums blocks before this block and over
+    // all, by wave i mod NW, its lanes striding over the blocks
+#pragma unroll
+    for (int i = 0; i < PLAN_NF; ++i) {
+        if (i % NW != wv) continue;
         int p = 0, t = 0;
 #pragma unroll
         for (int j = 0; j < SBS_BLOCKS_MAX / 64; ++j) {
             const int k = lane + 64 * j;
-            const int v = k < nblk ? parts[k * SBP_PART + f] : 0;
+            const int v = k < nblk ? L.parts[k * SBP_PART + gf(i)] : 0;
             p += k < kfirst ? v : 0;
             t += v;
         }
         p = wave_total(wave_incl_add(p));
         t = wave_total(wave_incl_add(t));
         if (lane == 0) {
-            bpre[f] = p;
-            ftot[f] = t;
+            L.bpre[i] = p;
+            L.ftot[i] = t;
         }
     }
-    int wex[SBP_F];
+    int wex[PLAN_NF];
     int32_t own_big;
     {
         int x[SBP_F];
         int32_t kg;
         sb_fields(own[0], K, W, x, kg);
 #pragma unroll
-        for (int f = 0; f < SBP_F; ++f) {
-            const int incl = wave_incl_add(x[f]);
-            if (lane == 63) wown[wv][f] = incl;
-            wex[f] = incl - x[f];
+        for (int i = 0; i < PLAN_NF; ++i) {
+            const int incl = wave_incl_add(x[gf(i)]);
+            if (lane == 63) L.wown[wv][i] = incl;
+            wex[i] = incl - x[gf(i)];
         }
         own_big = x[2 * SB_K + 1];
     }
     __syncthreads();
-    if (tid < SBP_F) {  // thread f: field f's value at each wave's start
-        const int f = tid;
-        int run = bpre[f];
+    if (tid < PLAN_NF) {  // thread i: field i's value at each wave's start
+        const int i = tid;
+        int run = L.bpre[i];
         for (int w = 0; w < NW; ++w) {
-            wbase[w][f] = run;
-            run += wown[w][f];
+            L.wbase[w][i] = run;
+            run += L.wown[w][i];
         }
     }
     __syncthreads();
-    auto ex = [&](int f) { return wbase[wv][f] + wex[f]; };
-    auto tot = [&](int f) { return ftot[f]; };
+    // (by row-local field)
+    auto ex = [&](int i) { return L.wbase[wv][i] + wex[i]; };
+    auto tot = [&](int i) { return L.ftot[i]; };
+    constexpr int FS = 2 * PLAN_KQ, FB = 2 * PLAN_KQ + 1;  // survivors, big groups
     phase_mark(base, PHASE_HIST_PLAN, 6);
     if (g < G) {
         int m_before = 0;  // survivors of this group in the batches before b
 #pragma unroll
-        for (int b = 0; b < SB_K; ++b) {
+        for (int b = 0; b < B0; ++b) m_before += min(own[0].k[b], W);
+#pragma unroll
+        for (int bl = 0; bl < PLAN_KQ; ++bl) {
+            const int b = B0 + bl;
             if (b >= K || !valid[b]) continue;
             const Scratch sc = sb_set(sb, base, b, G);
             const int32_t k = own[0].k[b];
-            const int exl = ex(2 * b), exh = ex(2 * b + 1) & 0xfff, ext = ex(2 * b + 1) >> 12;
-            const int32_t nl = (tot(2 * b) + SB_LIGHT_BUDGET - 1) / SB_LIGHT_BUDGET;
+            const int exl = ex(2 * bl), exh = ex(2 * bl + 1) & 0xfff,
+                      ext = ex(2 * bl + 1) >> 12;
+            const int32_t nl = (tot(2 * bl) + SB_LIGHT_BUDGET - 1) / SB_LIGHT_BUDGET;
             sc.lpre[g] = exl;
-            sb.so[(int64_t)b * G + g] = ex(2 * SB_K) + m_before;
+            sb.so[(int64_t)b * G + g] = ex(FS) + m_before;
             if (k > 0) {
                 sc.tidx[g] = ext;
                 if (k >= SB_HEAVY_MIN) {
-                    sc.bucket[g] = (nl + exh) | (int32_t)(((cutw[b / 4] >> (8 * (b % 4))) & 0xffu) << 16);
+                    sc.bucket[g] =
+                        (nl + exh) | (int32_t)(((cutw[b / 4] >> (8 * (b % 4))) & 0xffu) << 16);
                     if ((uint32_t)exh < (uint32_t)SB_NB_MAX) sc.hkey[exh] = g;
                 } else {
                     sc.bucket[g] = (exl + k - 1) / SB_LIGHT_BUDGET;
@@ -2259,42 +2297,45 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
             }
             m_before += min(k, W);
         }
-        sb.gsb[g] = ex(2 * SB_K);
-        sb.gbig[g] = own_big;
-        if (own_big) sb.big[ex(2 * SB_K + 1)] = g;
-    }
-    {
-        // batch b's totals by thread 0 of block b mod grid, so that no block
-        // writes many (an unrolled loop: the batches' arguments are indexed
-        // by constants)
-        const int grid = (int)gridDim.x;
-#pragma unroll
-        for (int b = 0; b < SB_K; ++b) {
-            if (tid != 0 || b >= K || b % grid != (int)blockIdx.x) continue;
-            const Scratch sc = sb_set(sb, base, b, G);
-            PlanTotals t;
-            const int32_t nl = (tot(2 * b) + SB_LIGHT_BUDGET - 1) / SB_LIGHT_BUDGET;
-            t.n_light_buckets = valid[b] ? nl : 0;
-            t.n_heavy = valid[b] ? tot(2 * b + 1) & 0xfff : 0;
-            t.light_tuples = valid[b] ? tot(2 * b) : 0;
-            t.n_touched = valid[b] ? tot(2 * b + 1) >> 12 : 0;
-            t.status = valid[b] ? 0 : CQ_ERR_KEY_RANGE;
-            t.n_buckets = t.n_light_buckets + t.n_heavy;
-            t.tiles = (int32_t)((in.n[b] + PASS_TILE - 1) / PASS_TILE);
-            t.sub_touched = t.n_touched;
-            *sc.tot = t;
-            if (valid[b]) {
-                sc.lpre[G] = t.light_tuples;
-                sc.bstart[nl] = G;
-            }
-            if (in.out[b].n_touched) *in.out[b].n_touched = t.status ? t.status : t.n_touched;
-            if (b == K - 1) *base.tot = t;
-            if (t.n_buckets > SB_NB_MAX) atomicOr(base.fault, FAULT_BUCKETS);
+        if (Q == 0) {
+            sb.gsb[g] = ex(FS);
+            sb.gbig[g] = own_big;
+            if (own_big) sb.big[ex(FB)] = g;
         }
+    }
+    // batch b's totals by thread 0 of block b mod grid of its row, so that
+    // no block writes many (an unrolled loop: the batches' arguments are
+    // indexed by constants)
+    const int grid = (int)gridDim.x;
+#pragma unroll
+    for (int bl = 0; bl < PLAN_KQ; ++bl) {
+        const int b = B0 + bl;
+        if (tid != 0 || b >= K || b % grid != (int)blockIdx.x) continue;
+        const Scratch sc = sb_set(sb, base, b, G);
+        PlanTotals t;
+        const int32_t nl = (tot(2 * bl) + SB_LIGHT_BUDGET - 1) / SB_LIGHT_BUDGET;
+        t.n_light_buckets = valid[b] ? nl : 0;
+        t.n_heavy = valid[b] ? tot(2 * bl + 1) & 0xfff : 0;
+        t.light_tuples = valid[b] ? tot(2 * bl) : 0;
+        t.n_touched = valid[b] ? tot(2 * bl + 1) >> 12 : 0;
+        t.status = valid[b] ? 0 : CQ_ERR_KEY_RANGE;
+        t.n_buckets = t.n_light_buckets + t.n_heavy;
+        t.tiles = (int32_t)((in.n[b] + PASS_TILE - 1) / PASS_TILE);
+        t.sub_touched = t.n_touched;
+        *sc.tot = t;
+        if (valid[b]) {
+            sc.lpre[G] = t.light_tuples;
+            sc.bstart[nl] = G;
+        }
+        if (in.out[b].n_touched) *in.out[b].n_touched = t.status ? t.status : t.n_touched;
+        if (b == K - 1) *base.tot = t;
+        if (t.n_buckets > SB_NB_MAX) atomicOr(base.fault, FAULT_BUCKETS);
+    }
+    if (Q == 0) {
         if (blockIdx.x == 0 && tid == 64) {
-            sb.gsb[G] = tot(2 * SB_K);
-            sb.ntot[0] = tot(2 * SB_K + 1);
-            sb.ntot[1] = tot(2 * SB_K);
+            sb.gsb[G] = tot(FS);
+            sb.ntot[0] = tot(FB);
+            sb.ntot[1] = tot(FS);
         }
         // the call's two most frequent groups, for the next histogram, by the
         // last wave of the last block
@@ -2305,7 +2346,7 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
                 const int k = lane + 64 * j;
                 if (k < nblk) {
                     const unsigned long long *p = reinterpret_cast<const unsigned long long *>(
-                        parts + k * SBP_PART + SBP_F);
+                        L.parts + k * SBP_PART + SBP_F);
                     top.add(p[0]);
                     top.add(p[1]);
                 }
@@ -2316,6 +2357,19 @@ __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base,
                 base.hot[1] = top.b ? (int32_t)(uint32_t)top.b : -1;
             }
         }
+    }
+}
+
+__global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base, SbBufs sb,
+                                                         SbBatches in, int32_t seq) {
+    __shared__ PlanLds L;
+    phase_mark(base, PHASE_HIST_PLAN, 5);
+    static_assert(PLAN_SPLIT == 4, "one case per row");
+    switch (blockIdx.y) {
+        case 0: sb_plan_row<0>(st, base, sb, in, seq, L); break;
+        case 1: sb_plan_row<1>(st, base, sb, in, seq, L); break;
+        case 2: sb_plan_row<2>(st, base, sb, in, seq, L); break;
+        default: sb_plan_row<3>(st, base, sb, in, seq, L); break;
     }
     phase_mark(base, PHASE_HIST_PLAN, 7);
 }
@@ -3218,8 +3272,8 @@ hipError_t launch_sb_plan(State st, Scratch base, SbBufs sb, const SbBatches &in
     const int64_t gp = (st.G + SBP_THREADS - 1) / SBP_THREADS;
     hipLaunchKernelGGL(k_sb_sums, dim3((unsigned)gs), dim3(SBS_THREADS), 0, s, st, base, sb, in,
                        seq);
-    hipLaunchKernelGGL(k_sb_plan, dim3((unsigned)gp), dim3(SBP_THREADS), 0, s, st, base, sb, in,
-                       seq);
+    hipLaunchKernelGGL(k_sb_plan, dim3((unsigned)gp, PLAN_SPLIT), dim3(SBP_THREADS), 0, s, st,
+                       base, sb, in, seq);
     return hipGetLastError();
 }
 
