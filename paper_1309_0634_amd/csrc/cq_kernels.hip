@@ -2159,7 +2159,9 @@ __global__ __launch_bounds__(SBS_THREADS) void k_sb_sums(State st, Scratch base,
 // are split over PLAN_SPLIT rows of blocks (blockIdx.y): row Q takes
 // batches [Q * PLAN_KQ, (Q + 1) * PLAN_KQ) and so scans only their fields
 // and the two per group; row 0 also writes the per-group places.
-constexpr int PLAN_SPLIT = 4, PLAN_KQ = SB_K / PLAN_SPLIT, PLAN_NF = 2 * PLAN_KQ + 2;
+constexpr int PLAN_SPLIT = 5;
+constexpr int PLAN_KQ = SB_K / PLAN_SPLIT;
+constexpr int PLAN_NF = 2 * PLAN_KQ + 2;
 static_assert(SB_K % PLAN_SPLIT == 0, "the plan's rows take equal shares of the batches");
 
 // LDS of a plan block (row-local field i: batch fields 2 b0 + i, then the
@@ -2360,17 +2362,23 @@ __device__ __forceinline__ void sb_plan_row(const State &st, const Scratch &base
     }
 }
 
+// Row y's plan (the row index a template argument, so that its batches'
+// fields are indexed by constants).
+template <int Q>
+__device__ __forceinline__ void sb_plan_rows(int y, const State &st, const Scratch &base,
+                                             const SbBufs &sb, const SbBatches &in, int32_t seq,
+                                             PlanLds &L) {
+    if (y == Q)
+        sb_plan_row<Q>(st, base, sb, in, seq, L);
+    else if constexpr (Q + 1 < PLAN_SPLIT)
+        sb_plan_rows<Q + 1>(y, st, base, sb, in, seq, L);
+}
+
 __global__ __launch_bounds__(SBP_THREADS) void k_sb_plan(State st, Scratch base, SbBufs sb,
                                                          SbBatches in, int32_t seq) {
     __shared__ PlanLds L;
     phase_mark(base, PHASE_HIST_PLAN, 5);
-    static_assert(PLAN_SPLIT == 4, "one case per row");
-    switch (blockIdx.y) {
-        case 0: sb_plan_row<0>(st, base, sb, in, seq, L); break;
-        case 1: sb_plan_row<1>(st, base, sb, in, seq, L); break;
-        case 2: sb_plan_row<2>(st, base, sb, in, seq, L); break;
-        default: sb_plan_row<3>(st, base, sb, in, seq, L); break;
-    }
+    sb_plan_rows<0>((int)blockIdx.y, st, base, sb, in, seq, L);
     phase_mark(base, PHASE_HIST_PLAN, 7);
 }
 
