@@ -287,10 +287,11 @@ class Query:
 
     def push_batches_into(self, batches, outputs, stream=None):
         """Enqueue several consecutive batches in one call, overlapped inside
-        the library (cq_push_batches).  batches: list of (keys, values)
-        device tensors (at most PIPE_MAX tuples each); outputs: list of
-        (ids, sums, counts, avgs, n_touched) device tensors, one per batch
-        (any of the first four may be None)."""
+        the library (cq_push_batches; up to CHAIN_BATCHES of them share one
+        set of launches).  batches: list of (keys, values) device tensors
+        (at most PIPE_MAX tuples each); outputs: list of (ids, sums, counts,
+        avgs, n_touched) device tensors, one per batch (any of the first
+        four may be None)."""
         m = len(batches)
         if len(outputs) != m:
             raise ValueError("one output tuple per batch")
